@@ -1,0 +1,433 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: the paper's
+worked examples (tests/golden/worked_examples.txt), closed forms of analytic
+fields, brute-force dense marching, central finite differences and an
+independent autograd evaluation.  A plausible mistake in the oracle (a dropped
+term, a wrong sign, a swapped operand, an off-by-one step count) fails one of
+these.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dist_inputs as di
+from oracle import dist_oracle as O
+from conftest import load_golden
+
+
+def _prm(**kw):
+    p = di.TraceParams()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+# ----------------------------------------------------------------------------
+# Paper worked examples (App. A.1, App. A.2, Sec. 3.2)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("alpha", [1.0, 1.5])
+def test_kmin_worked_example_through_march(alpha):
+    """App. A.1: plane SDF, d=1, eps=5e-5, theta=10deg -> 52 (alpha 1) / 33 (alpha 1.5) steps.
+
+    Runs the oracle's own march loop on one ray against a plane; the number of
+    position updates before the converging query must equal the paper's count.
+    """
+    g = load_golden("worked_examples.txt")
+    th = math.radians(g["kmin.theta_deg"])
+    d0, eps = g["kmin.d"], g["kmin.eps"]
+    want = int(g["kmin.steps.alpha%.1f" % alpha])
+    # plane z = 0, ray starting at height d0 with angle theta to the plane
+    Ov = np.array([[0.0, 0.0, d0]])
+    D = np.array([[math.cos(th), 0.0, -math.sin(th)]])
+
+    def plane(idx, P):
+        return P[:, 2]
+
+    st = O.new_state(Ov, D, np.zeros(1), np.array([-1e9]), np.array([1e9]),
+                     np.array([O.ACTIVE]), 1, np.array([np.inf]))
+    O.march(plane, st, 0, 200, alpha, eps, 200)
+    assert st.status[0] == O.HIT
+    updates = int(st.nsteps[0]) - 1       # queries minus the converging one
+    assert updates == want
+    assert math.ceil(O.k_min(eps, d0, alpha, th)) == want
+
+
+def test_eps_worked_example():
+    """App. A.2: eps = d_min S cos^2 / (2 f R) ~ 0.5e-4 m; Sec. 3.2: 2 eps ~ 1e-4 m."""
+    g = load_golden("worked_examples.txt")
+    e = O.eps_for_camera(g["eps.dmin_m"], g["eps.sensor_m"], g["eps.focal_m"], int(g["eps.res"]))
+    assert abs(e - g["eps.approx_m"]) / g["eps.approx_m"] < 0.05
+    assert abs(2 * e - g["spacing.approx_m"]) / g["spacing.approx_m"] < 0.05
+    assert abs(e - 5.2083333e-5) < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Analytic base field: output layer zeroed -> f = 0.5 (|p| - 0.5)
+# ----------------------------------------------------------------------------
+def _base_decoder(spec=di.C1_SPEC):
+    Ws, bs = di.make_decoder(spec, seed=0)
+    Ws[-1][:] = 0.0
+    return O.Decoder(spec, Ws, bs)
+
+
+@pytest.mark.parametrize("c2f,alpha,H", [(0, 1.0, 32), (2, 1.5, 32), (1, 1.5, 24)])
+def test_base_field_closed_forms(c2f, alpha, H):
+    spec = di.C1_SPEC
+    dec = _base_decoder(spec)
+    z = di.make_latents(1, spec.latent_dim)
+    cam = di.front_camera(H, H)
+    prm = _prm(alpha=alpha, eps=1e-3, max_steps=40, c2f_levels=c2f, want_normals=1)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    depth_t, normal_t, sil_t = di.sphere_target_maps(cam, 0.5)
+
+    hit = r.status == O.HIT
+    assert hit.sum() > 50
+    # fg <=> S < 0 <=> HIT (the silhouette sign rule of Sec. 3.3)
+    assert np.array_equal(r.sil < 0, hit)
+    # |f| at every hit < eps, and the hit point is within 2 eps of the 0.5-sphere
+    R = cam.R_wc.astype(np.float64)
+    c = cam.c.astype(np.float64)
+    d = r.dist[hit]
+    dirs = r.dirs.reshape(H, H, 3)[hit]
+    P = c + d[:, None] * dirs
+    assert np.all(np.abs(np.linalg.norm(P, axis=1) - 0.5) < 2.0 * prm.eps * (1 + 1e-9))
+    # depth = camera-frame z of the hit point (independent of the 1/sqrt formula)
+    zc = ((P - c) @ R)[:, 2]
+    np.testing.assert_allclose(r.depth[hit], zc, rtol=0, atol=1e-12)
+    # closed-form sphere depth: |d - t*| <= 2 eps / s with s = -v . p_hat at the root
+    t_star = depth_t[hit].astype(np.float64) * np.sqrt(r.xt.reshape(H, H)[hit] ** 2 + r.yt.reshape(H, H)[hit] ** 2 + 1)
+    proot = c + t_star[:, None] * dirs
+    s = -np.sum(dirs * proot / 0.5, axis=1)
+    ok = s > 0.05
+    assert np.all(np.abs(d - t_star)[ok] <= 2.0 * prm.eps / s[ok] + 1e-6)
+    # hit pixels off the closed-form sphere are the eps-dilation of App. A.2: their
+    # ray passes the origin closer than 0.5 + 2 eps
+    off = sil_t[hit] < 0.5
+    perp_h = c - (dirs @ c)[:, None] * dirs
+    assert np.all(np.linalg.norm(perp_h[off], axis=1) < 0.5 + 2 * prm.eps)
+    # normals: central differences of 0.5|p| point along p
+    n = r.normal[hit]
+    cosang = np.sum(n * P / np.linalg.norm(P, axis=1, keepdims=True), axis=1)
+    assert np.all(cosang > 1 - 1e-6)
+    # MISS: S + 1 = distance of the ray line from the origin = |c - (c.v) v|
+    miss = r.status == O.MISS
+    assert miss.sum() > 0
+    dm = r.dirs.reshape(H, H, 3)[miss]
+    perp = c - (dm @ c)[:, None] * dm
+    np.testing.assert_allclose(r.sil[miss] + 1.0, np.linalg.norm(perp, axis=1), rtol=0, atol=1e-12)
+    # S inside the sphere is min |f| - eps over the pixel's queries, and min |f| >= 0
+    ins = ~miss
+    assert np.all(r.sil[ins] >= -prm.eps)
+    # per-step query counts add up
+    assert sum(r.queries_per_step) == r.queries
+
+
+def test_base_field_trajectory_is_monotone_and_bounded():
+    """On f0 = 0.5(|p| - 0.5) with alpha * Lip(f0) = 0.75 < 1 the march is a
+    contraction towards the first root: t increases and never passes the root."""
+    dec = _base_decoder()
+    cam = di.front_camera(16, 16)
+    prm = _prm(alpha=1.5, eps=1e-4, max_steps=60, c2f_levels=0, want_normals=0)
+    z = di.make_latents(1, 64)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    depth_t, _, _ = di.sphere_target_maps(cam, 0.5)
+    hit = r.status == O.HIT
+    t_star = depth_t[hit] * np.sqrt(r.xt.reshape(16, 16)[hit] ** 2 + r.yt.reshape(16, 16)[hit] ** 2 + 1)
+    # the last query t stays in front of the root (f > 0 side) for head-on rays
+    rec_t = r.rec_t[0].reshape(16, 16)[hit]
+    assert np.all(rec_t <= t_star + 1e-9)
+    # and the number of queries follows the scalar contraction |f_{n+1}| <= 0.75 |f_n| bound
+    assert np.all(r.nsteps[hit] <= 60)
+
+
+# ----------------------------------------------------------------------------
+# Linear-regime decoder: m(z, p) = a + u.z exactly -> sphere of radius R(z)
+# ----------------------------------------------------------------------------
+def _linear_decoder(spec):
+    rng = np.random.Generator(np.random.PCG64(7))
+    Ws, bs = di.make_decoder(spec, seed=0)
+    L = spec.latent_dim
+    Ws2, bs2 = [], []
+    for l, (W, b) in enumerate(zip(Ws, bs)):
+        W = np.abs(W).astype(np.float64) * 0.3
+        if l == 0:
+            W[:, L:] = 0.0                                  # no point dependence
+        if spec.skip_layer is not None and l == spec.skip_layer:
+            W[:, -3:] = 0.0
+        b = 0.5 + rng.random(W.shape[0])
+        if l == len(Ws) - 1:
+            b = np.array([0.0])
+        Ws2.append(W)
+        bs2.append(b)
+    dec = O.Decoder(spec, Ws2, bs2)
+    # scale the output layer so that m(0) = 0.3: tanh stays in its sloped range
+    m0, _, _ = dec.layer_inputs(np.zeros((1, L)), np.zeros((1, 3)), keep=False)
+    dec.W[-1] *= 0.1 / m0[0]
+    dec.b[-1][:] = 0.2
+    return dec
+
+
+@pytest.mark.parametrize("spec", [di.C1_SPEC, di.DEEPSDF_SPEC], ids=["c1", "deepsdf"])
+def test_linear_regime_depth_and_gradient_closed_form(spec):
+    dec = _linear_decoder(spec)
+    L = spec.latent_dim
+    z = di.make_latents(1, L, sigma=0.01)
+    z64 = z[0].astype(np.float64)
+    # m is affine in z: recover (a, u) from the forward at z = 0 and z = e_j (exact for affine maps)
+    P0 = np.zeros((L + 1, 3))
+    Zs = np.vstack([np.zeros(L), np.eye(L)])
+    m_all, _, _ = dec.layer_inputs(Zs, P0, keep=False)
+    a = m_all[0]
+    u = m_all[1:] - a
+    mz = a + u @ z64
+    Rz = 0.5 - 0.1 * math.tanh(mz)
+    # f = 0.5(|p| - 0.5) + 0.05 tanh(mz) = 0.5 (|p| - Rz): a sphere of radius Rz
+    H = 24
+    cam = di.front_camera(H, H)
+    prm = _prm(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=1, want_normals=0, k_samples=1)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    depth_t, _, sil_t = di.sphere_target_maps(cam, Rz)
+    hit = r.status == O.HIT
+    assert hit.sum() > 100
+    nrm = np.sqrt(r.xt.reshape(H, H) ** 2 + r.yt.reshape(H, H) ** 2 + 1)
+    t_star = depth_t[hit] * nrm[hit]
+    dirs = r.dirs.reshape(H, H, 3)[hit]
+    proot = cam.c.astype(np.float64) + t_star[:, None] * dirs
+    s = -np.sum(dirs * proot / Rz, axis=1)
+    ok = s > 0.1
+    assert np.all(np.abs(r.dist[hit] - t_star)[ok] <= 2 * prm.eps / s[ok] + 1e-6)
+    # paper gradient of an L1 depth loss (K = 1): every hit pixel contributes
+    # alpha * g_d / |(xt,yt,1)| * df/dz with df/dz = 0.05 sech^2(mz) u for all p.
+    dt = np.where(sil_t > 0.5, depth_t + 0.01, np.inf).astype(np.float32)
+    _, g_d, g_n, g_s = O.loss_and_grads(r, dt, np.zeros((H, H, 3)), sil_t, w_d=10.0, w_s=0.0)
+    gz, _, _ = O.backward(dec, z, [r], [(0, 0)], prm, [(g_d, g_n, g_s)], want_theta=False)
+    seed_sum = prm.alpha * np.sum(g_d[hit] / nrm[hit])
+    expect = 0.05 * (1 - math.tanh(mz) ** 2) * u * seed_sum
+    np.testing.assert_allclose(gz[0], expect, rtol=1e-9, atol=1e-15)
+    assert np.linalg.norm(expect) > 0
+
+
+# ----------------------------------------------------------------------------
+# Brute force: dense marching on tiny images
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("spec,H,dt", [(di.C1_SPEC, 16, 2e-3), (di.DEEPSDF_SPEC, 8, 4e-3)],
+                         ids=["c1-16", "deepsdf-8"])
+def test_brute_force_dense_march(spec, H, dt):
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    z = di.make_latents(1, spec.latent_dim)
+    cam = di.front_camera(H, H)
+    prm = _prm(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=0, want_normals=0)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    c = cam.c.astype(np.float64)
+    zz = z[0].astype(np.float64)
+
+    def f(P):
+        return dec.sdf(np.broadcast_to(zz, (P.shape[0], zz.size)), P)
+
+    D = r.dirs
+    b = D @ c
+    disc = b * b - (c @ c - 1)
+    n_checked = 0
+    for i in range(H * H):
+        if disc[i] <= 0:
+            assert r.status.reshape(-1)[i] == O.MISS
+            continue
+        t0, t1 = -b[i] - math.sqrt(disc[i]), -b[i] + math.sqrt(disc[i])
+        ts = np.arange(t0, t1, dt)
+        fv = f(c + ts[:, None] * D[i])
+        sc = np.nonzero(np.sign(fv[:-1]) != np.sign(fv[1:]))[0]
+        st = r.status.reshape(-1)[i]
+        if sc.size == 0:
+            # no crossing: the ray may only be foreground if it came within eps of the surface
+            if st == O.HIT:
+                assert np.min(np.abs(fv)) < 5 * prm.eps
+            continue
+        lo, hi = ts[sc[0]], ts[sc[0] + 1]
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            if np.sign(f((c + mid * D[i])[None])[0]) == np.sign(fv[sc[0]]):
+                lo = mid
+            else:
+                hi = mid
+        t_bf = 0.5 * (lo + hi)
+        if st != O.HIT:
+            continue       # erosion at grazing rays (App. A.2) is allowed
+        g = np.zeros(3)
+        p = c + t_bf * D[i]
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = 1e-5
+            g[k] = (f((p + e)[None])[0] - f((p - e)[None])[0]) / 2e-5
+        s = abs(g @ D[i])
+        assert abs(r.dist.reshape(-1)[i] - t_bf) <= (prm.eps / s) * (1 + s) + 1e-9
+        n_checked += 1
+    assert n_checked > H * H // 8
+
+
+# ----------------------------------------------------------------------------
+# VJP: hand-derived chain rule vs central differences and vs torch autograd
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("spec", [di.C1_SPEC, di.DEEPSDF_SPEC], ids=["c1", "deepsdf"])
+def test_vjp_against_central_differences(spec):
+    Ws, bs = di.make_decoder(spec, seed=0)
+    rng = np.random.Generator(np.random.PCG64(11))
+    bs = [(rng.standard_normal(b.shape) * 0.05).astype(np.float32) for b in bs]
+    dec = O.Decoder(spec, Ws, bs)
+    n = 16
+    Z = rng.standard_normal((n, spec.latent_dim)) * 0.3
+    P = rng.uniform(-0.6, 0.6, (n, 3))
+    seeds = rng.standard_normal(n)
+    gZ, gW, gb = dec.sdf_vjp(Z, P, seeds)
+    h = 1e-6
+    for j in rng.choice(spec.latent_dim, 8, replace=False):
+        Zp, Zm = Z.copy(), Z.copy()
+        Zp[:, j] += h
+        Zm[:, j] -= h
+        fd = (dec.sdf(Zp, P) - dec.sdf(Zm, P)) / (2 * h) * seeds
+        np.testing.assert_allclose(gZ[:, j], fd, rtol=1e-6, atol=1e-9)
+    # weights and biases of every layer, a few entries each
+    for l in range(dec.nl):
+        for _ in range(3):
+            o = rng.integers(dec.W[l].shape[0])
+            i = rng.integers(dec.W[l].shape[1])
+            Wsave = dec.W[l][o, i]
+            dec.W[l][o, i] = Wsave + h
+            fp = dec.sdf(Z, P) @ seeds
+            dec.W[l][o, i] = Wsave - h
+            fm = dec.sdf(Z, P) @ seeds
+            dec.W[l][o, i] = Wsave
+            assert abs((fp - fm) / (2 * h) - gW[l][o, i]) <= 1e-6 * max(1.0, abs(gW[l][o, i]))
+        o = rng.integers(dec.b[l].shape[0])
+        bsave = dec.b[l][o]
+        dec.b[l][o] = bsave + h
+        fp = dec.sdf(Z, P) @ seeds
+        dec.b[l][o] = bsave - h
+        fm = dec.sdf(Z, P) @ seeds
+        dec.b[l][o] = bsave
+        assert abs((fp - fm) / (2 * h) - gb[l][o]) <= 1e-6 * max(1.0, abs(gb[l][o]))
+
+
+def test_vjp_against_torch_autograd():
+    torch = pytest.importorskip("torch")
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    rng = np.random.Generator(np.random.PCG64(12))
+    n = 32
+    Z = rng.standard_normal((n, spec.latent_dim)) * 0.1
+    P = rng.uniform(-0.6, 0.6, (n, 3))
+    seeds = rng.standard_normal(n)
+    gZ, gW, _ = dec.sdf_vjp(Z, P, seeds)
+    Zt = torch.tensor(Z, requires_grad=True)
+    Pt = torch.tensor(P)
+    Wt = [torch.tensor(W.astype(np.float64), requires_grad=True) for W in Ws]
+    x = torch.cat([Zt, Pt], 1)
+    h = x
+    for l, W in enumerate(Wt):
+        inp = torch.cat([h, Zt, Pt], 1) if l == spec.skip_layer else h
+        a = inp @ W.T
+        h = torch.relu(a) if l < len(Wt) - 1 else a
+    f = 0.5 * (Pt.norm(dim=1) - 0.5) + 0.05 * torch.tanh(h[:, 0])
+    (f * torch.tensor(seeds)).sum().backward()
+    np.testing.assert_allclose(gZ, Zt.grad.numpy(), rtol=1e-10, atol=1e-14)
+    for l in range(len(Wt)):
+        np.testing.assert_allclose(gW[l], Wt[l].grad.numpy(), rtol=1e-10, atol=1e-14)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(3))
+    x = np.concatenate([rng.standard_normal(5000) * 10 ** rng.uniform(-6, 3, 5000),
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 0.0])])
+    ref = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(O._bf16_round(x), ref)
+
+
+# ----------------------------------------------------------------------------
+# Seeds of the silhouette loss (App. A.3) and the sample rule (Sec. 3.4)
+# ----------------------------------------------------------------------------
+def test_silhouette_hinge_gradient_by_finite_differences():
+    """dL/dS of the hinge loss of App. A.3 against central differences of the loss."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    H = 8
+    S = rng.uniform(-0.1, 0.1, (H, H))
+    St = (rng.random((H, H)) > 0.5).astype(np.float64)
+    r = O.Render(H=H, W=H, depth=np.ones((H, H)), dist=np.ones((H, H)),
+                 normal=np.zeros((H, H, 3)), nraw=np.zeros((H, H, 3)), sil=S,
+                 status=np.full((H, H), O.ESCAPED, np.int8), nsteps=np.zeros((H, H), np.int32),
+                 margin=np.zeros((H, H)), xt=np.zeros(H * H), yt=np.zeros(H * H), dirs=np.zeros((H * H, 3)),
+                 c=np.zeros(3), rec_absf=np.zeros((1, H * H)), rec_t=np.zeros((1, H * H)),
+                 rec_f=np.zeros((1, H * H)), rec_n=np.zeros((1, H * H), np.int32), queries=0)
+    L0, _, _, g_s = O.loss_and_grads(r, np.zeros((H, H)), np.zeros((H, H, 3)), St, w_d=0, w_s=1.0)
+    h = 1e-7
+    for _ in range(10):
+        i, j = rng.integers(H), rng.integers(H)
+        r.sil[i, j] += h
+        Lp = O.loss_and_grads(r, np.zeros((H, H)), np.zeros((H, H, 3)), St, w_d=0, w_s=1.0)[0]
+        r.sil[i, j] -= 2 * h
+        Lm = O.loss_and_grads(r, np.zeros((H, H)), np.zeros((H, H, 3)), St, w_d=0, w_s=1.0)[0]
+        r.sil[i, j] += h
+        assert abs((Lp - Lm) / (2 * h) - g_s[i, j]) < 1e-6
+
+
+def test_normal_seeds_match_finite_differences_of_normal_loss():
+    """The six normal samples with seeds +-(I - nn^T) g / (|n| 2 delta) reproduce the
+    derivative of the normal loss -n~ . n~* through the central-difference normal."""
+    spec = di.C1_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    H = 12
+    cam = di.front_camera(H, H)
+    z = di.make_latents(1, spec.latent_dim)
+    prm = _prm(alpha=1.5, eps=1e-3, max_steps=30, c2f_levels=0, want_normals=1)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    _, nt, st = di.sphere_target_maps(cam, 0.5)
+    _, g_d, g_n, g_s = O.loss_and_grads(r, np.zeros((H, H)), nt, st, w_d=0.0, w_s=0.0, w_n=1.0)
+    gz, _, _ = O.backward(dec, z, [r], [(0, 0)], prm, [(np.zeros_like(g_d), g_n, np.zeros_like(g_s))],
+                          want_theta=False)
+    # surrogate: points frozen, normals recomputed from the decoder at z +- h e_j
+    hit = (r.status == O.HIT).reshape(-1)
+    p = r.c + r.dist.reshape(-1)[hit, None] * r.dirs[hit]
+    fg = ((r.sil < 0) & (st > 0.5)).reshape(-1)[hit]
+    ntf = nt.reshape(-1, 3)[hit]
+
+    def loss(zv):
+        fn = lambda P: dec.sdf(np.broadcast_to(zv, (P.shape[0], zv.size)), P)
+        n = O.surface_normals(fn, p, prm.normal_delta)
+        n = n / np.linalg.norm(n, axis=1, keepdims=True)
+        return -(np.sum(n * ntf, axis=1) * fg).sum() / (H * H)
+
+    h = 1e-6      # small enough that no ReLU kink is crossed by the perturbation
+    z0 = z[0].astype(np.float64)
+    for j in range(0, spec.latent_dim, 9):
+        zp, zm = z0.copy(), z0.copy()
+        zp[j] += h
+        zm[j] -= h
+        fd = (loss(zp) - loss(zm)) / (2 * h)
+        assert abs(fd - gz[0, j]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9
+
+
+def test_subset_render_equals_full_render():
+    """Tracing only a subset of pixels (with their coarse ancestors) reproduces
+    the full render exactly at those pixels (self-consistency of the C2F chain)."""
+    spec = di.C1_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    z = di.make_latents(1, spec.latent_dim)
+    cam = di.front_camera(32, 32)
+    prm = _prm(alpha=1.5, eps=5e-4, max_steps=30, c2f_levels=2, want_normals=1, k_samples=3)
+    full = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    pix = np.random.Generator(np.random.PCG64(1)).choice(32 * 32, 50, replace=False)
+    sub = O.render(dec, z, [cam], [(0, 0)], prm, pixels=[pix])[0]
+    # discrete decisions exactly; values up to BLAS rounding order (batch size differs)
+    for name in ("status", "nsteps"):
+        np.testing.assert_array_equal(getattr(sub, name).reshape(-1)[pix], getattr(full, name).reshape(-1)[pix])
+    np.testing.assert_array_equal(sub.rec_n[:, pix], full.rec_n[:, pix])
+    for name in ("depth", "sil"):
+        np.testing.assert_allclose(getattr(sub, name).reshape(-1)[pix], getattr(full, name).reshape(-1)[pix],
+                                   rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(sub.rec_t[:, pix], full.rec_t[:, pix], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(sub.normal.reshape(-1, 3)[pix], full.normal.reshape(-1, 3)[pix], rtol=0, atol=1e-9)
