@@ -1,0 +1,257 @@
+/*
+ * dist.h -- C ABI of the MI355X differentiable sphere tracer.
+ *
+ * The library renders DeepSDF-style implicit signed distance functions with
+ * the differentiable sphere tracing of Liu et al., "DIST: Rendering Deep
+ * Implicit Signed Distance Function with Differentiable Sphere Tracing"
+ * (CVPR 2020, arXiv 1911.13225), and back-propagates image-space losses to
+ * the latent codes and decoder weights with the paper's approximate gradient.
+ *
+ * Conventions (all entry points):
+ *   - Every array argument marked "device" is caller-owned GPU memory
+ *     (contiguous, row-major, float32 unless stated).  The library never frees
+ *     or retains it beyond the call, except dist_submit (see there).
+ *   - "host" arrays are read during the call only.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Render calls are
+ *     stream-ordered and do not synchronise the host unless stated.
+ *   - Return value: DIST_OK (0) on success, DIST_PENDING (1) from dist_poll
+ *     when the request is not finished, a negative DIST_E* code on error.
+ *     dist_last_error() returns a message for the last error of the calling
+ *     thread.
+ *   - A context is used by one host thread at a time for fwd/bwd/eval calls;
+ *     dist_submit and dist_poll may be called from any thread.
+ */
+#ifndef DIST_H_
+#define DIST_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define DIST_OK           0
+#define DIST_PENDING      1
+#define DIST_EINVAL      (-1)   /* bad argument, shape or parameter                */
+#define DIST_ENOMEM      (-2)   /* request exceeds the context's HBM budget        */
+#define DIST_EBUSY       (-3)   /* serving queue full                              */
+#define DIST_ENOTFOUND   (-4)   /* unknown ticket                                  */
+#define DIST_ECANCELLED  (-5)   /* request cancelled or context shut down          */
+#define DIST_EHIP        (-6)   /* HIP runtime error                               */
+#define DIST_ENUMERIC    (-7)   /* a non-finite signed distance was produced       */
+
+/* ---- per-pixel ray status (output `status`) ------------------------------
+ * Termination cases of sphere tracing (paper Alg. 1 and Sec. 3.2):
+ *   HIT          |f| < eps at some query: foreground, depth finite.
+ *   MISS         the pixel ray does not meet the unit sphere (Sec. 3.2
+ *                "Initialization"): background, no queries.
+ *   ESCAPED      the ray left the unit sphere while marching: background.
+ *   UNCONVERGED  max_steps reached without convergence: background (the
+ *                erosion effect of App. A.2).                                */
+#define DIST_ACTIVE       0
+#define DIST_HIT          1
+#define DIST_MISS         2
+#define DIST_ESCAPED      3
+#define DIST_UNCONVERGED  4
+
+/* ---- precision ----------------------------------------------------------- */
+#define DIST_FP32  0   /* every decoder product in float32                       */
+#define DIST_BF16  1   /* hidden-layer products with bfloat16 weights/activations
+                          and float32 accumulation; layer-0 and skip point terms,
+                          biases, the output layer, t and the convergence test
+                          stay float32.  Normal queries and the recompute of the
+                          backward use DIST_BF16X3, the VJP itself bfloat16.      */
+#define DIST_BF16X3 2  /* split bfloat16: x = hi + lo, products hi*hi + lo*hi +
+                          hi*lo with float32 accumulation (about 16 significant
+                          bits per product, float32-class decoder values)         */
+
+typedef struct dist_ctx dist_ctx;      /* opaque, library-owned */
+typedef struct dist_saved dist_saved;  /* opaque, library-owned forward state  */
+
+/* Pinhole camera (OpenCV axes: x right, y down, z forward).  A pixel (u, v)
+ * (u = column) is traced through its centre (u + 1/2, v + 1/2); the ray
+ * direction is R_wc * K^-1 (u + 1/2, v + 1/2, 1), normalised, and depth is
+ * z_c = d / sqrt(xt^2 + yt^2 + 1) with (xt, yt, 1) = K^-1 (x, y, 1)
+ * (paper Sec. 3.3).  The camera centre must lie outside the unit sphere. */
+typedef struct {
+  float fx, fy, cx, cy;
+  float R_wc[9];   /* camera-to-world rotation, row-major */
+  float c[3];      /* camera centre in world coordinates   */
+  int32_t H, W;
+} dist_camera;
+
+/* Tracing parameters (paper Sec. 3.2, App. A, App. B.4).
+ *   alpha        aggressive-marching factor: t += alpha * f  (paper: 1.5)
+ *   eps          convergence threshold: stop when |f| < eps (paper: 5e-5)
+ *   normal_delta central-difference step of the normal (Sec. 3.3)
+ *   near_, far_  clip range of t; must satisfy near_ <= |c| - 1 and
+ *                far_ >= |c| + 1 for every camera (they then never bind)
+ *   max_steps    number of marching steps (1..255), coarse steps included
+ *   c2f_levels   coarse-to-fine levels L (0..2): tracing starts at
+ *                1/2^L resolution per side and splits every ray into four
+ *                after every 3 steps; H and W must be multiples of 2^L and
+ *                max_steps > 3 L
+ *   k_samples    K (1..4): number of minimum-|f| queries per ray that carry
+ *                the depth gradient (Sec. 3.4, App. B.4)
+ *   precision    DIST_FP32, DIST_BF16 or DIST_BF16X3
+ *   want_normals 1 to compute normals (6 float32 queries per hit) */
+typedef struct {
+  float alpha, eps, normal_delta, near_, far_;
+  int32_t max_steps, c2f_levels, k_samples, precision, want_normals;
+} dist_trace_params;
+
+/* DeepSDF-style decoder (paper App. B.1): n_layers fully connected layers;
+ * layer 0 reads [z, p] (latent_dim + 3 values), layer `skip_layer` (or -1)
+ * reads [h, z, p], hidden layers use ReLU and the last layer has width 1.
+ * The signed distance is f(p) = 0.5 (|p| - 0.5) + 0.05 tanh(m(z, p)).
+ * out_dims: host array of n_layers output widths (last = 1).  Hidden widths
+ * up to 512, latent_dim up to 512, n_layers up to 12. */
+typedef struct {
+  int32_t n_layers;
+  int32_t latent_dim;
+  int32_t skip_layer;
+  const int32_t* out_dims;
+} dist_decoder_desc;
+
+/* Create a context.  W[l] and b[l] (host arrays of n_layers device pointers)
+ * hold layer l's weights [out][in] and bias [out] in float32; they are copied
+ * into the library's packed layouts and not retained.  hbm_budget_bytes caps
+ * the device memory the context allocates (0 = no cap).  stream orders the
+ * weight packing.  On success *out owns the context until dist_destroy. */
+int dist_create(dist_ctx** out, const dist_decoder_desc* desc,
+                const float* const* W, const float* const* b,
+                size_t hbm_budget_bytes, void* stream);
+
+/* Replace the decoder weights (same shapes as at creation). */
+int dist_set_weights(dist_ctx* ctx, const float* const* W, const float* const* b, void* stream);
+
+/* Destroy a context; stops its serving thread and frees its memory.  Any
+ * dist_saved created from it must be freed first. */
+int dist_destroy(dist_ctx* ctx);
+
+/* Forward render (paper Sec. 3): sphere-trace n_images images, image i
+ * being the pair (view pairs[2i], latent pairs[2i+1]).  pairs may be NULL,
+ * meaning all n_views x n_latents pairs with image i = (i / n_latents,
+ * i % n_latents).  All views must share H and W.
+ *   cams     host [n_views]
+ *   z        device [n_latents, latent_dim]
+ * Outputs (device, caller-owned, each may be NULL), per image [H, W](x3):
+ *   depth    z_c, +inf for background                      (Sec. 3.3)
+ *   dist     ray distance d of Eq. 1, +inf for background
+ *   normal   [H, W, 3] unit normal from central differences, 0 for background
+ *   sil      soft silhouette: min|f| - eps along the pixel's ray, or
+ *            (distance of the ray from the origin) - 1 for rays that miss
+ *            the unit sphere; negative means foreground (Sec. 3.3, App. A.3)
+ *   status   uint8 DIST_HIT / DIST_MISS / DIST_ESCAPED / DIST_UNCONVERGED
+ *   nsteps   uint8 number of global marching steps taken (0 for MISS)
+ *   queries  device int64 [n_images]: decoder queries spent marching
+ * saved: if non-NULL receives the state dist_render_bwd needs; the caller
+ *   frees it with dist_saved_free.  z must stay unchanged until then.
+ * Errors: DIST_EINVAL for bad shapes/parameters, DIST_ENOMEM beyond the
+ * budget, DIST_EHIP for runtime failures. */
+int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n_views,
+                    const float* z, int32_t n_latents,
+                    const int32_t* pairs, int32_t n_images,
+                    const dist_trace_params* prm,
+                    float* depth, float* dist, float* normal, float* sil,
+                    uint8_t* status, uint8_t* nsteps, int64_t* queries,
+                    dist_saved** saved, void* stream);
+
+/* Backward of a forward render with the paper's approximate gradient
+ * (Sec. 3.4, Eq. 2 first term; App. B.2 recompute): given dL/d(depth),
+ * dL/d(normal) and dL/d(sil) (device, shaped like the forward outputs, each
+ * may be NULL = zero), re-evaluate the decoder at the detached samples -- the
+ * K minimum-|f| queries of each hit ray (seed alpha * dL/dz_c / sqrt(xt^2 +
+ * yt^2 + 1)), the minimum-|f| query of each ray inside the unit sphere
+ * (seed dL/dS * sign f) and the six central-difference points of each hit
+ * (seeds +-(I - n n^T) dL/dn / (|n| 2 delta)) -- and accumulate
+ *   g_z  device [n_latents, latent_dim]  (overwritten)
+ *   g_W, g_b  host arrays of n_layers device pointers shaped like the weights
+ *        (overwritten); pass NULL to skip the weight gradient.
+ * The reduction order is fixed, so results are bitwise reproducible. */
+int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved,
+                    const float* g_depth, const float* g_normal, const float* g_sil,
+                    float* g_z, float* const* g_W, float* const* g_b, void* stream);
+
+/* Free a forward state. */
+int dist_saved_free(dist_saved* saved);
+
+/* Decoder query (one network feed-forward per point, paper Sec. 3.2):
+ * f[i] = f(points[i], z[latent_ids[i]]).  points device [n, 3], latent_ids
+ * device int32 [n] in [0, n_latents), z device [n_latents, latent_dim],
+ * f device [n].  precision DIST_FP32, DIST_BF16 or DIST_BF16X3. */
+int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
+                  const float* z, int32_t n_latents, int64_t n, int32_t precision,
+                  float* f, void* stream);
+
+/* Vector-Jacobian product of the decoder at detached points (the per-sample
+ * term of Eq. 2): g_z[l] = sum_{i: latent_ids[i] = l} seeds[i] df(points[i],
+ * z_l)/dz_l, and optionally the weight gradient.  precision DIST_FP32
+ * (float32 throughout) or DIST_BF16 / DIST_BF16X3 (split-bf16 recompute,
+ * bf16 back-propagation).  Synchronises the host (it stages the grouping of
+ * samples by latent). */
+int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
+                 const float* seeds, const float* z, int32_t n_latents, int64_t n,
+                 int32_t precision, float* g_z, float* const* g_W, float* const* g_b,
+                 void* stream);
+
+/* ---- serving: continuous batching of render and inverse-optimisation ---- */
+#define DIST_REQ_RENDER 0
+#define DIST_REQ_ZOPT   1
+
+/* A request.  Buffers are device memory owned by the caller and must stay
+ * alive until dist_poll reports completion.
+ *   cams/n_views  host, copied at submit; all views share H, W
+ *   z             device [latent_dim]: RENDER reads it; ZOPT reads it as the
+ *                 initial code and writes the optimised code into z_out
+ *   depth/sil/normal/status  optional outputs [n_views, H, W](x3)
+ *   ZOPT: target_depth/target_sil device [n_views, H, W] (sil in {0,1}),
+ *         iters Adam iterations with learning rate lr (paper App. B.4:
+ *         Adam, 1e-2), loss w_depth * L1 depth + w_sil * silhouette hinge
+ *         (App. A.3), z_out device [latent_dim]. */
+typedef struct {
+  int32_t kind;
+  int32_t n_views;
+  const dist_camera* cams;
+  dist_trace_params prm;
+  const float* z;
+  float* depth;
+  float* sil;
+  float* normal;
+  uint8_t* status;
+  const float* target_depth;
+  const float* target_sil;
+  int32_t iters;
+  float lr, w_depth, w_sil;
+  float* z_out;
+} dist_request;
+
+typedef struct {
+  int32_t status;        /* DIST_OK, DIST_ECANCELLED, DIST_ENUMERIC, ...   */
+  int64_t latency_ns;    /* submit -> completion                           */
+  int64_t queries;       /* decoder queries spent marching                 */
+  float final_loss;      /* ZOPT: loss at the last iteration               */
+} dist_result;
+
+/* Queue a request; returns a ticket.  Admission waits for slots and memory
+ * (HBM budget); DIST_EBUSY if the queue is full, DIST_ENOMEM if the request
+ * can never fit the budget, DIST_EINVAL for malformed requests. */
+int dist_submit(dist_ctx* ctx, const dist_request* req, uint64_t* ticket);
+
+/* Wait up to timeout_us (0 = just check, <0 = forever) for a ticket.
+ * DIST_OK with *res filled when done (the ticket is then released),
+ * DIST_PENDING if still running, DIST_ENOTFOUND for unknown tickets. */
+int dist_poll(dist_ctx* ctx, uint64_t ticket, dist_result* res, int64_t timeout_us);
+
+/* Thread-local message describing the last error. */
+const char* dist_last_error(void);
+
+/* Library version string. */
+const char* dist_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIST_H_ */

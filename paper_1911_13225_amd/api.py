@@ -1,0 +1,217 @@
+"""Thin Python binding over the C ABI: argument marshalling only.
+
+Every computation of the tracer runs in the HIP library; PyTorch provides
+device memory (tensors) and the current stream.  If the library is missing
+the calls raise -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _native as N
+from ._native import check
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous GPU tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_camera(cam) -> N.dist_camera:
+    """Convert an object with fx, fy, cx, cy, R_wc [3,3], c [3], H, W to the C struct."""
+    c = N.dist_camera()
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R_wc, np.float32).reshape(9)
+    for i in range(9):
+        c.R_wc[i] = float(R[i])
+    cc = np.asarray(cam.c, np.float32).reshape(3)
+    for i in range(3):
+        c.c[i] = float(cc[i])
+    c.H, c.W = int(cam.H), int(cam.W)
+    return c
+
+
+def make_params(p) -> N.dist_trace_params:
+    q = N.dist_trace_params()
+    q.alpha, q.eps, q.normal_delta = float(p.alpha), float(p.eps), float(p.normal_delta)
+    q.near_, q.far_ = float(p.near), float(p.far)
+    q.max_steps, q.c2f_levels, q.k_samples = int(p.max_steps), int(p.c2f_levels), int(p.k_samples)
+    q.precision, q.want_normals = int(p.precision), int(p.want_normals)
+    return q
+
+
+class Context:
+    """A decoder resident on the GPU (dist_create / dist_destroy)."""
+
+    def __init__(self, out_dims: Sequence[int], latent_dim: int, skip_layer: Optional[int],
+                 Ws: Sequence[torch.Tensor], bs: Sequence[torch.Tensor], hbm_budget: int = 0):
+        self.lib = N.load()
+        self.out_dims = list(out_dims)
+        self.latent_dim = int(latent_dim)
+        self.skip_layer = -1 if skip_layer is None else int(skip_layer)
+        self._Ws = [w.detach().float().contiguous().cuda() for w in Ws]
+        self._bs = [b.detach().float().contiguous().cuda() for b in bs]
+        dims = (ctypes.c_int32 * len(self.out_dims))(*self.out_dims)
+        desc = N.dist_decoder_desc(len(self.out_dims), self.latent_dim, self.skip_layer, dims)
+        Wp = (ctypes.c_void_p * len(self._Ws))(*[w.data_ptr() for w in self._Ws])
+        bp = (ctypes.c_void_p * len(self._bs))(*[b.data_ptr() for b in self._bs])
+        h = ctypes.c_void_p()
+        check(self.lib.dist_create(ctypes.byref(h), ctypes.byref(desc), Wp, bp, int(hbm_budget), _stream()))
+        self.handle = h
+
+    @classmethod
+    def from_spec(cls, spec, Ws, bs, hbm_budget: int = 0, device="cuda"):
+        Wt = [torch.as_tensor(np.asarray(w), dtype=torch.float32, device=device) for w in Ws]
+        bt = [torch.as_tensor(np.asarray(b), dtype=torch.float32, device=device) for b in bs]
+        return cls(spec.out_dims, spec.latent_dim, spec.skip_layer, Wt, bt, hbm_budget)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(self.lib.dist_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, Ws, bs):
+        self._Ws = [w.detach().float().contiguous().cuda() for w in Ws]
+        self._bs = [b.detach().float().contiguous().cuda() for b in bs]
+        Wp = (ctypes.c_void_p * len(self._Ws))(*[w.data_ptr() for w in self._Ws])
+        bp = (ctypes.c_void_p * len(self._bs))(*[b.data_ptr() for b in self._bs])
+        check(self.lib.dist_set_weights(self.handle, Wp, bp, _stream()))
+
+
+class Saved:
+    """Owner of a dist_saved handle."""
+
+    def __init__(self, lib, handle):
+        self.lib, self.handle = lib, handle
+
+    def free(self):
+        if self.handle:
+            check(self.lib.dist_saved_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def dist_render_fwd(ctx: Context, cams, z: torch.Tensor, params, pairs=None, save: bool = False):
+    """Render; returns a dict of output tensors (and a Saved handle if save)."""
+    cams_c = (N.dist_camera * len(cams))(*[make_camera(c) for c in cams])
+    n_lat = z.shape[0]
+    if pairs is None:
+        n_img = len(cams) * n_lat
+        pairs_c = None
+    else:
+        pairs = np.asarray(pairs, np.int32).reshape(-1, 2)
+        n_img = pairs.shape[0]
+        pairs_c = (ctypes.c_int32 * (2 * n_img))(*pairs.reshape(-1).tolist())
+    H, W = int(cams[0].H), int(cams[0].W)
+    dev = z.device
+    out = dict(
+        depth=torch.empty(n_img, H, W, device=dev), dist=torch.empty(n_img, H, W, device=dev),
+        normal=torch.empty(n_img, H, W, 3, device=dev), sil=torch.empty(n_img, H, W, device=dev),
+        status=torch.empty(n_img, H, W, dtype=torch.uint8, device=dev),
+        nsteps=torch.empty(n_img, H, W, dtype=torch.uint8, device=dev),
+        queries=torch.empty(n_img, dtype=torch.int64, device=dev))
+    if not int(params.want_normals):
+        out["normal"].zero_()
+    prm = make_params(params)
+    sv = ctypes.c_void_p()
+    zc = z.detach().float().contiguous()
+    check(ctx.lib.dist_render_fwd(ctx.handle, cams_c, len(cams), _ptr(zc), n_lat, pairs_c, n_img, ctypes.byref(prm),
+                                  _ptr(out["depth"]), _ptr(out["dist"]),
+                                  _ptr(out["normal"]) if int(params.want_normals) else None,
+                                  _ptr(out["sil"]), _ptr(out["status"]), _ptr(out["nsteps"]), _ptr(out["queries"]),
+                                  ctypes.byref(sv) if save else None, _stream()))
+    if save:
+        out["saved"] = Saved(ctx.lib, sv)
+        out["_z"] = zc          # keep the latent buffer alive for the backward
+    return out
+
+
+def dist_render_bwd(ctx: Context, saved: Saved, g_depth=None, g_normal=None, g_sil=None, n_latents=None):
+    """Paper gradient w.r.t. the latent codes; returns g_z [n_latents, L]."""
+    g_z = torch.empty(n_latents, ctx.latent_dim, device="cuda")
+    args = [None if g is None else g.detach().float().contiguous() for g in (g_depth, g_normal, g_sil)]
+    check(ctx.lib.dist_render_bwd(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_z), None, None,
+                                  _stream()))
+    return g_z
+
+
+def dist_sdf_eval(ctx: Context, points: torch.Tensor, latent_ids: torch.Tensor, z: torch.Tensor, precision: int):
+    n = points.shape[0]
+    f = torch.empty(n, device=points.device)
+    pts = points.detach().float().contiguous()
+    ids = latent_ids.to(torch.int32).contiguous()
+    zc = z.detach().float().contiguous()
+    check(ctx.lib.dist_sdf_eval(ctx.handle, _ptr(pts), _ptr(ids), _ptr(zc), z.shape[0], n, int(precision), _ptr(f),
+                                _stream()))
+    return f
+
+
+def dist_sdf_vjp(ctx: Context, points, latent_ids, seeds, z, precision: int):
+    n = points.shape[0]
+    g_z = torch.empty(z.shape[0], ctx.latent_dim, device=points.device)
+    pts = points.detach().float().contiguous()
+    ids = latent_ids.to(torch.int32).contiguous()
+    sd = seeds.detach().float().contiguous()
+    zc = z.detach().float().contiguous()
+    check(ctx.lib.dist_sdf_vjp(ctx.handle, _ptr(pts), _ptr(ids), _ptr(sd), _ptr(zc), z.shape[0], n, int(precision),
+                               _ptr(g_z), None, None, _stream()))
+    return g_z
+
+
+class DistRender(torch.autograd.Function):
+    """Differentiable render of depth, normal and soft silhouette w.r.t. z.
+
+    forward(z, ctx, cams, params, pairs) -> (depth, normal, sil, status)
+    backward applies the paper's approximate gradient via dist_render_bwd.
+    """
+
+    @staticmethod
+    def forward(actx, z, ctx, cams, params, pairs=None):
+        out = dist_render_fwd(ctx, cams, z, params, pairs=pairs, save=True)
+        actx.saved_handle = out["saved"]
+        actx.ctx = ctx
+        actx.n_lat = z.shape[0]
+        actx.keep = out["_z"]
+        actx.mark_non_differentiable(out["status"])
+        return out["depth"], out["normal"], out["sil"], out["status"]
+
+    @staticmethod
+    def backward(actx, g_depth, g_normal, g_sil, g_status):
+        g_z = dist_render_bwd(actx.ctx, actx.saved_handle, g_depth, g_normal, g_sil, n_latents=actx.n_lat)
+        actx.saved_handle.free()
+        return g_z, None, None, None, None
+
+
+def render_loss(depth, normal, sil, depth_t, normal_t, sil_t, w_d=10.0, w_s=1.0, w_n=0.0):
+    """L1 depth on the rendered-and-target foreground, the silhouette hinge of
+    App. A.3 and the negative normal dot product, each normalised by H*W."""
+    HW = depth.shape[-1] * depth.shape[-2]
+    fg = (sil < 0) & (sil_t > 0.5)
+    diff = torch.where(fg, depth - torch.where(fg, depth_t, torch.zeros_like(depth_t)), torch.zeros_like(depth))
+    L = w_d / HW * diff.abs().sum()
+    L = L + w_s / HW * (sil_t * torch.relu(sil) + (1 - sil_t) * torch.relu(-sil)).sum()
+    if w_n:
+        L = L + w_n / HW * (-(normal * normal_t).sum(-1) * fg).sum()
+    return L

@@ -1,0 +1,97 @@
+// Host-side state of a context, its workspaces and saved forward states.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "dist.h"
+#include "dist_internal.h"
+
+namespace dist {
+struct Server;
+}
+
+// Buffers of one backward pass (gradient samples and partial sums).
+struct BwdSpace {
+  char* mem = nullptr;
+  size_t bytes = 0;
+  int cap_samples = 0, cap_blocks = 0, cap_lat = 0, tile = 0;
+  size_t mask_words = 0;
+  float4* samples = nullptr;
+  int* sample_lat = nullptr;
+  float* partial = nullptr;
+  int *bsum = nullptr, *boff = nullptr;
+  int *seg_base = nullptr, *seg_total = nullptr, *seg_padded = nullptr;
+  int* n_samples = nullptr;
+  unsigned* mask_ws = nullptr;
+};
+
+// Buffers of one forward render (ray pool, lists, counters, outputs staging).
+struct Workspace {
+  char* mem = nullptr;
+  size_t bytes = 0;
+  int cap_rays = 0, cap_pix = 0, cap_img = 0, cap_lat = 0, cap_steps = 0;
+  dist::RayPool pool{};
+  dist::ImgDesc* imgs = nullptr;
+  int* imgs_list = nullptr;
+  int* img_order = nullptr;
+  int* img_latent = nullptr;
+  int* list[2] = {nullptr, nullptr};
+  int* counters = nullptr;
+  unsigned long long* qcount = nullptr;
+  float* bias0_lat = nullptr;
+  float* biasS_lat = nullptr;
+  int* hits = nullptr;
+  float* fv = nullptr;
+  float4* nraw = nullptr;
+  // pinned staging of the per-call descriptors
+  dist::ImgDesc* h_imgs = nullptr;
+  int* h_ints = nullptr;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  BwdSpace* bw = nullptr;
+};
+
+struct dist_ctx {
+  int device = 0;
+  int n_cu = 256;
+  int nl = 0, L = 0, skip = -1, kmax = 0;
+  std::vector<int> out_dims, in_dims, wpad, kpad;
+  size_t budget = 0, used = 0;
+  std::mutex mem_mu;
+  std::vector<std::pair<void*, size_t>> owned;
+  std::vector<float*> Wf, bf;            // float32 master copies [out][in], [out]
+  std::vector<float*> bias_pad;          // padded hidden biases
+  float* w0p = nullptr;                  // [3][wpad0]
+  float* w0z = nullptr;                  // [wpad0][L]
+  float* wsp = nullptr;                  // [3][wpad_skip]
+  float* wsz = nullptr;                  // [wpad_skip][L]
+  float* wlast = nullptr;                // [wpad[nl-2]]
+  std::vector<void*> wpack[2], wpackT[2], wpacklo;
+  dist::NetDev net[3];          // float32, bfloat16, split bfloat16
+  std::mutex ws_mu;
+  std::vector<Workspace*> ws_free;
+  dist::Server* server = nullptr;
+  std::mutex server_mu;
+};
+
+struct dist_saved {
+  dist_ctx* ctx = nullptr;
+  Workspace* ws = nullptr;
+  int n_img = 0, hw = 0, n_lat = 0;
+  dist_trace_params prm{};
+  std::vector<int> img_latent, order;
+};
+
+int dist_set_error(int code, const char* fmt, ...);
+int ctx_alloc(dist_ctx* ctx, void** p, size_t bytes);
+void ctx_free(dist_ctx* ctx, void* p, size_t bytes);
+int slots_per_image(int hw, int levels);
+int fold_biases(dist_ctx* ctx, Workspace* w, const float* z, int n_lat, hipStream_t st);
+int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, hipStream_t st);
+int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, float* depth,
+                 float* dist, float* normal, float* sil, uint8_t* status, uint8_t* nsteps, hipStream_t st);
+void ws_put(dist_ctx* ctx, Workspace* w);

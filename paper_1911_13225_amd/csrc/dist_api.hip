@@ -1,0 +1,820 @@
+// Host side of the C ABI (include/dist.h): validation, packed weights,
+// workspaces and the launch sequence of the forward and backward passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "dist.h"
+#include "dist_internal.h"
+#include "ray_kernels.h"
+#include "ctx.h"
+#include "serve.h"
+
+using namespace dist;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+int dist_set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return dist_set_error(DIST_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+extern "C" const char* dist_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* dist_version(void) { return "dist-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+static int pad_width(int w) { return w <= 128 ? 128 : (w <= 256 ? 256 : 512); }
+
+int ctx_alloc(dist_ctx* ctx, void** p, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+      return dist_set_error(DIST_ENOMEM, "allocation of %zu bytes exceeds the HBM budget (%zu of %zu used)", bytes,
+                            ctx->used, ctx->budget);
+    ctx->used += bytes;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    ctx->used -= bytes;
+    return dist_set_error(DIST_EHIP, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return DIST_OK;
+}
+
+void ctx_free(dist_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  bytes = (bytes + 255) & ~(size_t)255;
+  (void)hipFree(p);
+  std::lock_guard<std::mutex> lk(ctx->mem_mu);
+  ctx->used -= bytes;
+}
+
+static int pack_weights(dist_ctx* ctx, const float* const* W, const float* const* b, hipStream_t st) {
+  const int nl = ctx->nl, L = ctx->L, skip = ctx->skip;
+  // float32 master copies
+  for (int l = 0; l < nl; ++l) {
+    HIPCHK(hipMemcpyAsync(ctx->Wf[l], W[l], sizeof(float) * ctx->out_dims[l] * ctx->in_dims[l],
+                          hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(ctx->bf[l], b[l], sizeof(float) * ctx->out_dims[l], hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  // host copies of the small pieces
+  std::vector<float> W0(ctx->out_dims[0] * ctx->in_dims[0]);
+  HIPCHK(hipMemcpy(W0.data(), W[0], W0.size() * 4, hipMemcpyDeviceToHost));
+  const int w0 = ctx->wpad[0];
+  std::vector<float> w0p(3 * w0, 0.f), w0z((size_t)w0 * L, 0.f);
+  for (int n = 0; n < ctx->out_dims[0]; ++n) {
+    for (int j = 0; j < L; ++j) w0z[(size_t)n * L + j] = W0[(size_t)n * ctx->in_dims[0] + j];
+    for (int a = 0; a < 3; ++a) w0p[a * w0 + n] = W0[(size_t)n * ctx->in_dims[0] + L + a];
+  }
+  HIPCHK(hipMemcpy(ctx->w0p, w0p.data(), w0p.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->w0z, w0z.data(), w0z.size() * 4, hipMemcpyHostToDevice));
+  if (skip >= 0) {
+    const int ws = ctx->wpad[skip], nh = ctx->out_dims[skip - 1], in = ctx->in_dims[skip];
+    std::vector<float> Ws((size_t)ctx->out_dims[skip] * in);
+    HIPCHK(hipMemcpy(Ws.data(), W[skip], Ws.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<float> wsp(3 * ws, 0.f), wsz((size_t)ws * L, 0.f);
+    for (int n = 0; n < ctx->out_dims[skip]; ++n) {
+      for (int j = 0; j < L; ++j) wsz[(size_t)n * L + j] = Ws[(size_t)n * in + nh + j];
+      for (int a = 0; a < 3; ++a) wsp[a * ws + n] = Ws[(size_t)n * in + nh + L + a];
+    }
+    HIPCHK(hipMemcpy(ctx->wsp, wsp.data(), wsp.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->wsz, wsz.data(), wsz.size() * 4, hipMemcpyHostToDevice));
+  }
+  // padded biases of hidden layers
+  for (int l = 0; l < nl - 1; ++l) {
+    std::vector<float> bb(ctx->wpad[l], 0.f);
+    HIPCHK(hipMemcpy(bb.data(), b[l], ctx->out_dims[l] * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ctx->bias_pad[l], bb.data(), bb.size() * 4, hipMemcpyHostToDevice));
+  }
+  // output layer
+  {
+    const int lo = nl - 1;
+    std::vector<float> wl(ctx->wpad[nl - 2], 0.f);
+    HIPCHK(hipMemcpy(wl.data(), W[lo], ctx->in_dims[lo] * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ctx->wlast, wl.data(), wl.size() * 4, hipMemcpyHostToDevice));
+    float bl = 0.f;
+    HIPCHK(hipMemcpy(&bl, b[lo], 4, hipMemcpyDeviceToHost));
+    ctx->net[0].blast = ctx->net[1].blast = ctx->net[2].blast = bl;
+  }
+  // MFMA fragments
+  for (int l = 1; l <= nl - 2; ++l) {
+    const int out = ctx->out_dims[l], in = ctx->in_dims[l];
+    const int ncols = (l == skip) ? ctx->out_dims[l - 1] : in;
+    for (int p = 0; p < 2; ++p) {
+      launch_pack_w(p, false, ctx->Wf[l], out, in, ncols, ctx->wpad[l], ctx->kpad[l], ctx->wpack[p][l], st);
+      launch_pack_w(p, true, ctx->Wf[l], out, in, ncols, ctx->wpad[l], ctx->kpad[l], ctx->wpackT[p][l], st);
+    }
+    launch_pack_w(kPrecSplit, false, ctx->Wf[l], out, in, ncols, ctx->wpad[l], ctx->kpad[l], ctx->wpacklo[l], st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return DIST_OK;
+}
+
+extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const float* const* W,
+                           const float* const* b, size_t hbm_budget_bytes, void* stream) {
+  if (!out || !desc || !W || !b || !desc->out_dims) return dist_set_error(DIST_EINVAL, "null argument");
+  const int nl = desc->n_layers, L = desc->latent_dim, skip = desc->skip_layer;
+  if (nl < 3 || nl > kMaxLayers) return dist_set_error(DIST_EINVAL, "n_layers must be in [3, %d]", kMaxLayers);
+  if (L < 1 || L > 512) return dist_set_error(DIST_EINVAL, "latent_dim must be in [1, 512]");
+  if (skip != -1 && (skip < 1 || skip >= nl - 2))
+    return dist_set_error(DIST_EINVAL, "skip_layer must be -1 or in [1, n_layers-3]");
+  if (desc->out_dims[nl - 1] != 1) return dist_set_error(DIST_EINVAL, "the last layer must have width 1");
+  for (int l = 0; l < nl - 1; ++l)
+    if (desc->out_dims[l] < 1 || desc->out_dims[l] > kMaxWidth)
+      return dist_set_error(DIST_EINVAL, "hidden widths must be in [1, %d]", kMaxWidth);
+  for (int l = 0; l < nl; ++l)
+    if (!W[l] || !b[l]) return dist_set_error(DIST_EINVAL, "null weight pointer for layer %d", l);
+  hipStream_t st = (hipStream_t)stream;
+
+  dist_ctx* ctx = new dist_ctx();
+  ctx->nl = nl;
+  ctx->L = L;
+  ctx->skip = skip;
+  ctx->budget = hbm_budget_bytes;
+  ctx->out_dims.assign(desc->out_dims, desc->out_dims + nl);
+  ctx->in_dims.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    ctx->in_dims[l] = (l == 0) ? L + 3 : ctx->out_dims[l - 1] + ((l == skip) ? L + 3 : 0);
+  }
+  if (hipGetDevice(&ctx->device) != hipSuccess) { delete ctx; return dist_set_error(DIST_EHIP, "no HIP device"); }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || ncu <= 0)
+    ncu = 256;
+  ctx->n_cu = ncu;
+  ctx->wpad.assign(nl, 0);
+  ctx->kpad.assign(nl, 0);
+  int kmax = 0;
+  for (int l = 0; l < nl - 1; ++l) {
+    ctx->wpad[l] = pad_width(ctx->out_dims[l]);
+    kmax = std::max(kmax, ctx->wpad[l]);
+  }
+  for (int l = 1; l <= nl - 2; ++l) ctx->kpad[l] = ctx->wpad[l - 1];
+  ctx->kmax = kmax;
+
+  int rc = DIST_OK;
+  auto A = [&](void** p, size_t bytes) {
+    if (rc == DIST_OK) {
+      rc = ctx_alloc(ctx, p, bytes);
+      if (rc == DIST_OK) ctx->owned.push_back({*p, bytes});
+    }
+  };
+  ctx->Wf.assign(nl, nullptr);
+  ctx->bf.assign(nl, nullptr);
+  for (int l = 0; l < nl; ++l) {
+    A((void**)&ctx->Wf[l], sizeof(float) * ctx->out_dims[l] * ctx->in_dims[l]);
+    A((void**)&ctx->bf[l], sizeof(float) * ctx->out_dims[l]);
+  }
+  A((void**)&ctx->w0p, sizeof(float) * 3 * ctx->wpad[0]);
+  A((void**)&ctx->w0z, sizeof(float) * ctx->wpad[0] * L);
+  if (skip >= 0) {
+    A((void**)&ctx->wsp, sizeof(float) * 3 * ctx->wpad[skip]);
+    A((void**)&ctx->wsz, sizeof(float) * ctx->wpad[skip] * L);
+  }
+  ctx->bias_pad.assign(nl, nullptr);
+  for (int l = 0; l < nl - 1; ++l) A((void**)&ctx->bias_pad[l], sizeof(float) * ctx->wpad[l]);
+  A((void**)&ctx->wlast, sizeof(float) * ctx->wpad[nl - 2]);
+  for (int p = 0; p < 2; ++p) {
+    ctx->wpack[p].assign(nl, nullptr);
+    ctx->wpackT[p].assign(nl, nullptr);
+    const size_t es = p ? 2 : 4;
+    for (int l = 1; l <= nl - 2; ++l) {
+      A(&ctx->wpack[p][l], es * ctx->wpad[l] * ctx->kpad[l]);
+      A(&ctx->wpackT[p][l], es * ctx->wpad[l] * ctx->kpad[l]);
+    }
+  }
+  ctx->wpacklo.assign(nl, nullptr);
+  for (int l = 1; l <= nl - 2; ++l) A(&ctx->wpacklo[l], 2 * ctx->wpad[l] * ctx->kpad[l]);
+  if (rc != DIST_OK) { dist_destroy(ctx); return rc; }
+  for (int p = 0; p < 3; ++p) {
+    const int q = p == 0 ? 0 : 1;      // split precision shares the bf16 packs (hi parts)
+    NetDev& nd = ctx->net[p];
+    memset(&nd, 0, sizeof nd);
+    nd.nl = nl;
+    nd.L = L;
+    nd.skip = skip;
+    nd.kmax = kmax;
+    for (int l = 0; l < nl; ++l) {
+      nd.wpad[l] = ctx->wpad[l];
+      nd.kpad[l] = ctx->kpad[l];
+      nd.wp[l] = ctx->wpack[q][l];
+      nd.wpT[l] = ctx->wpackT[q][l];
+      nd.wplo[l] = p == 2 ? ctx->wpacklo[l] : nullptr;
+      nd.bias[l] = ctx->bias_pad[l];
+    }
+    nd.w0p = ctx->w0p;
+    nd.wsp = ctx->wsp;
+    nd.wlast = ctx->wlast;
+  }
+  rc = pack_weights(ctx, W, b, st);
+  if (rc == DIST_OK) {
+    for (int p = 0; p < 3; ++p) {
+      hipError_t e = mlp_setup(p, ctx->net[p]);
+      if (e != hipSuccess) {
+        rc = dist_set_error(DIST_EHIP, "raising the LDS limit failed: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+  }
+  if (rc != DIST_OK) { dist_destroy(ctx); return rc; }
+  *out = ctx;
+  return DIST_OK;
+}
+
+extern "C" int dist_set_weights(dist_ctx* ctx, const float* const* W, const float* const* b, void* stream) {
+  if (!ctx || !W || !b) return dist_set_error(DIST_EINVAL, "null argument");
+  for (int l = 0; l < ctx->nl; ++l)
+    if (!W[l] || !b[l]) return dist_set_error(DIST_EINVAL, "null weight pointer for layer %d", l);
+  return pack_weights(ctx, W, b, (hipStream_t)stream);
+}
+
+static void ws_release_all(dist_ctx* ctx);
+
+extern "C" int dist_destroy(dist_ctx* ctx) {
+  if (!ctx) return dist_set_error(DIST_EINVAL, "null context");
+  serve_shutdown(ctx);
+  (void)hipDeviceSynchronize();
+  ws_release_all(ctx);
+  for (auto& o : ctx->owned) ctx_free(ctx, o.first, o.second);
+  delete ctx;
+  return DIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces: one device allocation carved into the buffers of a render
+// ---------------------------------------------------------------------------
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = (T*)(base ? base + off : nullptr);
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+static void ws_layout(Workspace& w, Carver& c) {
+  const size_t cap = w.cap_rays;
+  w.pool.d = c.take<float4>(cap);
+  w.pool.b = c.take<float2>(cap);
+  w.pool.img = c.take<int>(cap);
+  w.pool.st = c.take<uint8_t>(cap);
+  w.pool.n = c.take<uint8_t>(cap);
+  w.pool.flast = c.take<float>(cap);
+  w.pool.rec_f = c.take<float>(cap * kMaxK);
+  w.pool.rec_t = c.take<float>(cap * kMaxK);
+  w.pool.rec_n = c.take<uint8_t>(cap * kMaxK);
+  w.pool.cap = (int)cap;
+  w.imgs = c.take<ImgDesc>(w.cap_img);
+  w.imgs_list = c.take<int>(w.cap_img);
+  w.img_order = c.take<int>(w.cap_img);
+  w.img_latent = c.take<int>(w.cap_img);
+  w.list[0] = c.take<int>(cap);
+  w.list[1] = c.take<int>(cap);
+  w.counters = c.take<int>(w.cap_steps + 8);
+  w.qcount = c.take<unsigned long long>(w.cap_img);
+  w.bias0_lat = c.take<float>((size_t)w.cap_lat * kMaxWidth);
+  w.biasS_lat = c.take<float>((size_t)w.cap_lat * kMaxWidth);
+  w.hits = c.take<int>(w.cap_pix);
+  w.fv = c.take<float>((size_t)w.cap_pix * 6);
+  w.nraw = c.take<float4>(w.cap_pix);
+}
+
+static void bw_layout(BwdSpace& w, Carver& c) {
+  w.samples = c.take<float4>(w.cap_samples);
+  w.sample_lat = c.take<int>(w.cap_samples);
+  w.partial = c.take<float>((size_t)(w.cap_samples / w.tile + 1) * 4 * kMaxWidth);
+  w.bsum = c.take<int>(w.cap_blocks);
+  w.boff = c.take<int>(w.cap_blocks);
+  w.seg_base = c.take<int>(w.cap_lat);
+  w.seg_total = c.take<int>(w.cap_lat);
+  w.seg_padded = c.take<int>(w.cap_lat);
+  w.n_samples = c.take<int>(4);
+  w.mask_ws = c.take<unsigned>(w.mask_words);
+}
+
+static int ws_get(dist_ctx* ctx, int cap_rays, int cap_pix, int cap_img, int cap_lat, int cap_steps,
+                  Workspace** out) {
+  {
+    std::lock_guard<std::mutex> lk(ctx->ws_mu);
+    for (size_t i = 0; i < ctx->ws_free.size(); ++i) {
+      Workspace* w = ctx->ws_free[i];
+      if (w->cap_rays >= cap_rays && w->cap_pix >= cap_pix && w->cap_img >= cap_img && w->cap_lat >= cap_lat &&
+          w->cap_steps >= cap_steps) {
+        ctx->ws_free.erase(ctx->ws_free.begin() + i);
+        *out = w;
+        return DIST_OK;
+      }
+    }
+  }
+  Workspace* w = new Workspace();
+  w->cap_rays = cap_rays;
+  w->cap_pix = cap_pix;
+  w->cap_img = cap_img;
+  w->cap_lat = cap_lat;
+  w->cap_steps = cap_steps;
+  Carver c;
+  ws_layout(*w, c);
+  w->bytes = c.off + 256;
+  int rc = ctx_alloc(ctx, (void**)&w->mem, w->bytes);
+  if (rc != DIST_OK) {
+    // free cached workspaces and retry once
+    ws_release_all(ctx);
+    rc = ctx_alloc(ctx, (void**)&w->mem, w->bytes);
+    if (rc != DIST_OK) { delete w; return rc; }
+  }
+  c.base = w->mem;
+  c.off = 0;
+  ws_layout(*w, c);
+  if (hipHostMalloc((void**)&w->h_imgs, sizeof(ImgDesc) * cap_img) != hipSuccess ||
+      hipHostMalloc((void**)&w->h_ints, sizeof(int) * 3 * cap_img) != hipSuccess ||
+      hipEventCreateWithFlags(&w->staged, hipEventDisableTiming) != hipSuccess) {
+    ctx_free(ctx, w->mem, w->bytes);
+    delete w;
+    return dist_set_error(DIST_EHIP, "pinned staging allocation failed");
+  }
+  w->staged_pending = false;
+  *out = w;
+  return DIST_OK;
+}
+
+void ws_put(dist_ctx* ctx, Workspace* w) {
+  std::lock_guard<std::mutex> lk(ctx->ws_mu);
+  ctx->ws_free.push_back(w);
+}
+
+static void ws_destroy(dist_ctx* ctx, Workspace* w) {
+  if (w->staged_pending) (void)hipEventSynchronize(w->staged);
+  (void)hipEventDestroy(w->staged);
+  (void)hipHostFree(w->h_imgs);
+  (void)hipHostFree(w->h_ints);
+  ctx_free(ctx, w->mem, w->bytes);
+  if (w->bw) {
+    ctx_free(ctx, w->bw->mem, w->bw->bytes);
+    delete w->bw;
+  }
+  delete w;
+}
+
+static void ws_release_all(dist_ctx* ctx) {
+  std::vector<Workspace*> v;
+  {
+    std::lock_guard<std::mutex> lk(ctx->ws_mu);
+    v.swap(ctx->ws_free);
+  }
+  if (!v.empty()) (void)hipDeviceSynchronize();
+  for (Workspace* w : v) ws_destroy(ctx, w);
+}
+
+static int bw_get(dist_ctx* ctx, Workspace* w, int cap_samples, int cap_blocks, int cap_lat, int tile,
+                  size_t mask_words) {
+  BwdSpace* b = w->bw;
+  if (b && b->cap_samples >= cap_samples && b->cap_blocks >= cap_blocks && b->cap_lat >= cap_lat && b->tile == tile &&
+      b->mask_words >= mask_words)
+    return DIST_OK;
+  if (b) {
+    ctx_free(ctx, b->mem, b->bytes);
+    delete b;
+    w->bw = nullptr;
+  }
+  b = new BwdSpace();
+  b->cap_samples = cap_samples;
+  b->cap_blocks = cap_blocks;
+  b->cap_lat = cap_lat;
+  b->tile = tile;
+  b->mask_words = mask_words;
+  Carver c;
+  bw_layout(*b, c);
+  b->bytes = c.off + 256;
+  int rc = ctx_alloc(ctx, (void**)&b->mem, b->bytes);
+  if (rc != DIST_OK) { delete b; return rc; }
+  c.base = b->mem;
+  c.off = 0;
+  bw_layout(*b, c);
+  w->bw = b;
+  return DIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// forward render
+// ---------------------------------------------------------------------------
+static int validate_params(const dist_trace_params* p, int H, int W) {
+  if (!(p->alpha > 0.f) || !(p->eps > 0.f) || !(p->normal_delta > 0.f))
+    return dist_set_error(DIST_EINVAL, "alpha, eps and normal_delta must be positive");
+  if (p->max_steps < 1 || p->max_steps > 255) return dist_set_error(DIST_EINVAL, "max_steps must be in [1, 255]");
+  if (p->c2f_levels < 0 || p->c2f_levels > 2) return dist_set_error(DIST_EINVAL, "c2f_levels must be 0, 1 or 2");
+  if (p->max_steps <= 3 * p->c2f_levels)
+    return dist_set_error(DIST_EINVAL, "max_steps must exceed 3 * c2f_levels");
+  if (p->k_samples < 1 || p->k_samples > kMaxK) return dist_set_error(DIST_EINVAL, "k_samples must be in [1, 4]");
+  if (p->precision != DIST_FP32 && p->precision != DIST_BF16 && p->precision != DIST_BF16X3)
+    return dist_set_error(DIST_EINVAL, "precision must be DIST_FP32, DIST_BF16 or DIST_BF16X3");
+  const int m = 1 << p->c2f_levels;
+  if (H < 1 || W < 1 || H % m || W % m || (long long)H * W > (1 << 22))
+    return dist_set_error(DIST_EINVAL, "H and W must be positive multiples of 2^c2f_levels (at most 4M pixels)");
+  return DIST_OK;
+}
+
+static int validate_camera(const dist_camera& c, const dist_trace_params* p) {
+  const double r = std::sqrt((double)c.c[0] * c.c[0] + (double)c.c[1] * c.c[1] + (double)c.c[2] * c.c[2]);
+  if (!(r > 1.0)) return dist_set_error(DIST_EINVAL, "camera centre must lie outside the unit sphere");
+  if (!(p->near_ <= r - 1.0) || !(p->far_ >= r + 1.0))
+    return dist_set_error(DIST_EINVAL, "near/far must not clip the unit sphere (near <= |c|-1, far >= |c|+1)");
+  if (!(c.fx > 0.f) || !(c.fy > 0.f)) return dist_set_error(DIST_EINVAL, "focal lengths must be positive");
+  return DIST_OK;
+}
+
+static void fill_desc(ImgDesc& d, const dist_camera& c, const dist_trace_params* p, int latent, int slot_base,
+                      int out_base) {
+  memset(&d, 0, sizeof d);
+  d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+  for (int i = 0; i < 9; ++i) d.R[i] = c.R_wc[i];
+  for (int i = 0; i < 3; ++i) d.c[i] = c.c[i];
+  d.alpha = p->alpha; d.eps = p->eps; d.near_ = p->near_; d.far_ = p->far_;
+  d.H = c.H; d.W = c.W; d.levels = p->c2f_levels; d.latent = latent;
+  d.max_steps = p->max_steps; d.K = p->k_samples; d.cur_level = p->c2f_levels;
+  d.slot_base = slot_base;
+  const int hw = c.H * c.W;
+  d.lvl_off[0] = 0;
+  d.lvl_off[1] = hw;
+  d.lvl_off[2] = hw + hw / 4;
+  d.out_base = out_base;
+}
+
+int slots_per_image(int hw, int levels) {
+  int s = 0;
+  for (int l = 0; l <= levels; ++l) s += hw >> (2 * l);
+  // keep the level offsets of fill_desc valid whatever the level count
+  return std::max(s, hw + hw / 4 + (levels >= 2 ? hw / 16 : 0));
+}
+
+// Stage image descriptors and the per-image index arrays (pinned -> device).
+static int stage_images(Workspace* w, const std::vector<ImgDesc>& d, const std::vector<int>& order,
+                        const std::vector<int>& lat, hipStream_t st) {
+  if (w->staged_pending) HIPCHK(hipEventSynchronize(w->staged));
+  const int n = (int)d.size();
+  memcpy(w->h_imgs, d.data(), sizeof(ImgDesc) * n);
+  for (int i = 0; i < n; ++i) {
+    w->h_ints[i] = i;
+    w->h_ints[n + i] = order[i];
+    w->h_ints[2 * n + i] = lat[i];
+  }
+  HIPCHK(hipMemcpyAsync(w->imgs, w->h_imgs, sizeof(ImgDesc) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w->imgs_list, w->h_ints, sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w->img_order, w->h_ints + n, sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w->img_latent, w->h_ints + 2 * n, sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(w->staged, st));
+  w->staged_pending = true;
+  return DIST_OK;
+}
+
+int fold_biases(dist_ctx* ctx, Workspace* w, const float* z, int n_lat, hipStream_t st) {
+  launch_fold_bias(ctx->bf[0], ctx->w0z, z, n_lat, ctx->L, ctx->out_dims[0], ctx->wpad[0], w->bias0_lat, st);
+  if (ctx->skip >= 0)
+    launch_fold_bias(ctx->bf[ctx->skip], ctx->wsz, z, n_lat, ctx->L, ctx->out_dims[ctx->skip],
+                     ctx->wpad[ctx->skip], w->biasS_lat, st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+static int mlp_grid(dist_ctx* ctx, long long rows, int prec) {
+  const long long tiles = (rows + mlp_tile_rows(prec) - 1) / mlp_tile_rows(prec);
+  return (int)std::max(1LL, std::min<long long>(tiles, ctx->n_cu));
+}
+
+// March all images of a workspace from their coarsest level to completion.
+int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, hipStream_t st) {
+  const int L = prm->c2f_levels, prec = prm->precision;
+  launch_fill_i32(w->counters, 0, prm->max_steps + 8, st);
+  launch_fill_u64(w->qcount, n_img, st);
+  launch_init_level(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * L), w->list[0], w->counters, st);
+  MarchArgs ma{};
+  ma.net = ctx->net[prec];
+  ma.pool = w->pool;
+  ma.imgs = w->imgs;
+  ma.bias0_lat = w->bias0_lat;
+  ma.biasS_lat = w->biasS_lat;
+  for (int n = 0; n < prm->max_steps; ++n) {
+    const int lv = std::max(L - n / 3, 0);
+    const long long rays = (long long)n_img * (hw >> (2 * lv));
+    ma.list = w->list[n & 1];
+    ma.count = w->counters + n;
+    launch_march(prec, ma, mlp_grid(ctx, rays, prec), st);
+    int* nxt = w->list[(n + 1) & 1];
+    int* ncnt = w->counters + n + 1;
+    if (n % 3 == 2 && lv > 0)
+      launch_split(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * (lv - 1)), lv - 1, n + 1, nxt, ncnt, st);
+    launch_compact(w->pool, w->imgs, w->list[n & 1], w->counters + n, (int)rays, nxt, ncnt, w->qcount, st);
+  }
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+// Finalise outputs and compute normals with float32 queries.
+int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, float* depth,
+                 float* dist, float* normal, float* sil, uint8_t* status, uint8_t* nsteps, hipStream_t st) {
+  FinalizeOut fo{};
+  fo.depth = depth;
+  fo.dist = dist;
+  fo.sil = sil;
+  fo.normal = normal;
+  fo.status = status;
+  fo.nsteps = nsteps;
+  fo.nraw = w->nraw;
+  fo.hits = w->hits;
+  fo.hit_count = w->counters + prm->max_steps + 4;
+  fo.want_hits = prm->want_normals ? 1 : 0;
+  launch_fill_i32(fo.hit_count, 0, 1, st);
+  launch_finalize(w->pool, w->imgs, n_img, hw, fo, st);
+  if (prm->want_normals) {
+    // normal queries: float32, or split bf16 (float32-class accuracy) on the bf16 paths
+    const int np = prm->precision == DIST_FP32 ? kPrecF32 : kPrecSplit;
+    EvalArgs ea{};
+    ea.net = ctx->net[np];
+    ea.bias0_lat = w->bias0_lat;
+    ea.biasS_lat = w->biasS_lat;
+    ea.mode = 1;
+    ea.hits = w->hits;
+    ea.hit_count = fo.hit_count;
+    ea.pool = w->pool;
+    ea.imgs = w->imgs;
+    ea.delta = prm->normal_delta;
+    ea.f_out = w->fv;
+    launch_eval(np, ea, mlp_grid(ctx, 6LL * n_img * hw, np), st);
+    launch_normals(w->pool, w->imgs, w->hits, fo.hit_count, n_img * hw, w->fv, prm->normal_delta, normal, w->nraw,
+                   st);
+  }
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+__global__ void k_u64_to_i64(const unsigned long long* a, int64_t* b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int64_t)a[i];
+}
+
+extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n_views, const float* z,
+                               int32_t n_latents, const int32_t* pairs, int32_t n_images,
+                               const dist_trace_params* prm, float* depth, float* dist, float* normal, float* sil,
+                               uint8_t* status, uint8_t* nsteps, int64_t* queries, dist_saved** saved,
+                               void* stream) {
+  if (!ctx || !cams || !z || !prm) return dist_set_error(DIST_EINVAL, "null argument");
+  if (n_views < 1 || n_latents < 1) return dist_set_error(DIST_EINVAL, "n_views and n_latents must be positive");
+  const int n_img = pairs ? n_images : n_views * n_latents;
+  if (n_img < 1 || n_img > 65536) return dist_set_error(DIST_EINVAL, "n_images must be in [1, 65536]");
+  const int H = cams[0].H, W = cams[0].W;
+  for (int v = 0; v < n_views; ++v) {
+    if (cams[v].H != H || cams[v].W != W) return dist_set_error(DIST_EINVAL, "all views must share H and W");
+    int rc = validate_camera(cams[v], prm);
+    if (rc) return rc;
+  }
+  int rc = validate_params(prm, H, W);
+  if (rc) return rc;
+  std::vector<int> vi(n_img), li(n_img);
+  for (int i = 0; i < n_img; ++i) {
+    vi[i] = pairs ? pairs[2 * i] : i / n_latents;
+    li[i] = pairs ? pairs[2 * i + 1] : i % n_latents;
+    if (vi[i] < 0 || vi[i] >= n_views || li[i] < 0 || li[i] >= n_latents)
+      return dist_set_error(DIST_EINVAL, "pair %d out of range", i);
+  }
+  if (saved) *saved = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  const int hw = H * W;
+  const int spi = slots_per_image(hw, prm->c2f_levels);
+  const long long cap_rays = (long long)n_img * spi;
+  if (cap_rays > (1LL << 30)) return dist_set_error(DIST_EINVAL, "too many rays in one call");
+  Workspace* w = nullptr;
+  rc = ws_get(ctx, (int)cap_rays, n_img * hw, n_img, n_latents, prm->max_steps, &w);
+  if (rc) return rc;
+  std::vector<ImgDesc> d(n_img);
+  for (int i = 0; i < n_img; ++i) fill_desc(d[i], cams[vi[i]], prm, li[i], i * spi, i * hw);
+  std::vector<int> order(n_img);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return li[a] < li[b]; });
+  rc = stage_images(w, d, order, li, st);
+  if (!rc) rc = fold_biases(ctx, w, z, n_latents, st);
+  if (!rc) rc = run_trace(ctx, w, n_img, hw, prm, st);
+  if (!rc) rc = run_finalize(ctx, w, n_img, hw, prm, depth, dist, normal, sil, status, nsteps, st);
+  if (!rc && queries) hipLaunchKernelGGL(k_u64_to_i64, dim3((n_img + 255) / 256), dim3(256), 0, st, w->qcount, queries, n_img);
+  if (rc) {
+    ws_put(ctx, w);
+    return rc;
+  }
+  if (saved) {
+    dist_saved* s = new dist_saved();
+    s->ctx = ctx;
+    s->ws = w;
+    s->n_img = n_img;
+    s->hw = hw;
+    s->n_lat = n_latents;
+    s->prm = *prm;
+    s->img_latent = li;
+    s->order = order;
+    *saved = s;
+  } else {
+    ws_put(ctx, w);
+  }
+  return DIST_OK;
+}
+
+extern "C" int dist_saved_free(dist_saved* s) {
+  if (!s) return dist_set_error(DIST_EINVAL, "null saved state");
+  ws_put(s->ctx, s->ws);
+  delete s;
+  return DIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+// The adjoint of a bf16 render recomputes the forward in split precision (the
+// ReLU pattern must match the float32 network; a bf16 recompute flips units
+// near zero) and back-propagates in bf16.
+static int adj_prec(int render_prec) { return render_prec == DIST_FP32 ? kPrecF32 : kPrecSplit; }
+
+static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, int n_lat, float* g_z,
+                                  hipStream_t st) {
+  AdjArgs aa{};
+  aa.net = ctx->net[prec];
+  aa.bias0_lat = w->bias0_lat;
+  aa.biasS_lat = w->biasS_lat;
+  aa.samples = b->samples;
+  aa.sample_lat = b->sample_lat;
+  aa.n_samples = b->n_samples;
+  aa.mask_ws = b->mask_ws;
+  aa.partial = b->partial;
+  const int grid = mlp_grid(ctx, b->cap_samples, prec);
+  launch_adjoint(prec, aa, grid, st);
+  const int w0 = ctx->wpad[0];
+  const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
+  launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->seg_base, b->seg_padded, n_lat, w0, w0 == 128 ? 2 : 1,
+                   ctx->w0z, ws, ws == 128 ? 2 : 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const float* g_depth, const float* g_normal,
+                               const float* g_sil, float* g_z, float* const* g_W, float* const* g_b, void* stream) {
+  if (!ctx || !saved || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (saved->ctx != ctx) return dist_set_error(DIST_EINVAL, "saved state belongs to another context");
+  if (g_W || g_b) return dist_set_error(DIST_EINVAL, "weight gradients are not available in this build");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = saved->ws;
+  const int prec = adj_prec(saved->prm.precision);
+  const int tile = adj_tile_rows(prec);
+  const int n_img = saved->n_img, hw = saved->hw, n_lat = saved->n_lat;
+  const long long cap = (long long)n_img * hw * (saved->prm.k_samples + 6) + (long long)n_lat * tile;
+  if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
+  const int bpi = (hw + 255) / 256;
+  const int grid = mlp_grid(ctx, cap, prec);
+  int rc = bw_get(ctx, w, (int)cap, n_img * bpi, n_lat, tile, adj_mask_words(prec, ctx->net[prec]) * grid);
+  if (rc) return rc;
+  BwdSpace* b = w->bw;
+  SeedIn in{};
+  in.g_depth = g_depth;
+  in.g_normal = saved->prm.want_normals ? g_normal : nullptr;
+  in.g_sil = g_sil;
+  in.nraw = w->nraw;
+  in.delta = saved->prm.normal_delta;
+  launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, tile, in, b->bsum, b->boff,
+                 b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st);
+  HIPCHK(hipGetLastError());
+  return run_adjoint_and_reduce(ctx, w, b, prec, n_lat, g_z, st);
+}
+
+// ---------------------------------------------------------------------------
+// decoder queries at explicit points
+// ---------------------------------------------------------------------------
+extern "C" int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* latent_ids, const float* z,
+                             int32_t n_latents, int64_t n, int32_t precision, float* f, void* stream) {
+  if (!ctx || !points || !latent_ids || !z || !f) return dist_set_error(DIST_EINVAL, "null argument");
+  if (n < 0 || n > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "n out of range");
+  if (n_latents < 1) return dist_set_error(DIST_EINVAL, "n_latents must be positive");
+  if (precision < 0 || precision > 2) return dist_set_error(DIST_EINVAL, "bad precision");
+  if (n == 0) return DIST_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = nullptr;
+  int rc = ws_get(ctx, 1, 1, 1, n_latents, 1, &w);
+  if (rc) return rc;
+  rc = fold_biases(ctx, w, z, n_latents, st);
+  if (!rc) {
+    EvalArgs ea{};
+    ea.net = ctx->net[precision];
+    ea.bias0_lat = w->bias0_lat;
+    ea.biasS_lat = w->biasS_lat;
+    ea.mode = 0;
+    ea.pts = points;
+    ea.lat = latent_ids;
+    ea.n = n;
+    ea.n_lat = n_latents;
+    ea.f_out = f;
+    launch_eval(precision, ea, mlp_grid(ctx, n, precision), st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = dist_set_error(DIST_EHIP, "eval launch failed: %s", hipGetErrorString(e));
+  }
+  ws_put(ctx, w);
+  return rc;
+}
+
+extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* latent_ids, const float* seeds,
+                            const float* z, int32_t n_latents, int64_t n, int32_t precision, float* g_z,
+                            float* const* g_W, float* const* g_b, void* stream) {
+  if (!ctx || !points || !latent_ids || !seeds || !z || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (n < 0 || n > (1LL << 28)) return dist_set_error(DIST_EINVAL, "n out of range");
+  if (n_latents < 1) return dist_set_error(DIST_EINVAL, "n_latents must be positive");
+  if (precision < 0 || precision > 2) return dist_set_error(DIST_EINVAL, "bad precision");
+  if (g_W || g_b) return dist_set_error(DIST_EINVAL, "weight gradients are not available in this build");
+  precision = adj_prec(precision);
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<float> hp(3 * n), hs(n);
+  std::vector<int> hl(n);
+  if (n) {
+    HIPCHK(hipMemcpy(hp.data(), points, 12 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hs.data(), seeds, 4 * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hl.data(), latent_ids, 4 * n, hipMemcpyDeviceToHost));
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (hl[i] < 0 || hl[i] >= n_latents) return dist_set_error(DIST_EINVAL, "latent id out of range");
+  const int tile = adj_tile_rows(precision);
+  // group by latent (stable), pad each group to a multiple of the tile
+  std::vector<std::vector<int64_t>> groups(n_latents);
+  for (int64_t i = 0; i < n; ++i) groups[hl[i]].push_back(i);
+  std::vector<int> sb(n_latents), stt(n_latents), sp(n_latents);
+  long long pos = 0;
+  for (int l = 0; l < n_latents; ++l) {
+    sb[l] = (int)pos;
+    stt[l] = (int)groups[l].size();
+    sp[l] = (int)((groups[l].size() + tile - 1) / tile * tile);
+    pos += sp[l];
+  }
+  std::vector<float> smp(4 * std::max<long long>(pos, 1), 0.f);
+  std::vector<int> slat(std::max<long long>(pos, 1), 0);
+  for (int l = 0; l < n_latents; ++l) {
+    for (int k = 0; k < sp[l]; ++k) {
+      const long long o = sb[l] + k;
+      slat[o] = l;
+      if (k < stt[l]) {
+        const int64_t i = groups[l][k];
+        smp[4 * o] = hp[3 * i];
+        smp[4 * o + 1] = hp[3 * i + 1];
+        smp[4 * o + 2] = hp[3 * i + 2];
+        smp[4 * o + 3] = hs[i];
+      }
+    }
+  }
+  Workspace* w = nullptr;
+  int rc = ws_get(ctx, 1, 1, 1, n_latents, 1, &w);
+  if (rc) return rc;
+  const int grid = mlp_grid(ctx, std::max<long long>(pos, 1), precision);
+  rc = bw_get(ctx, w, (int)std::max<long long>(pos, tile), 1, n_latents, tile,
+              adj_mask_words(precision, ctx->net[precision]) * grid);
+  if (rc) { ws_put(ctx, w); return rc; }
+  BwdSpace* b = w->bw;
+  int np = (int)pos;
+  rc = fold_biases(ctx, w, z, n_latents, st);
+  if (!rc) {
+    if (pos) {
+      HIPCHK(hipMemcpyAsync(b->samples, smp.data(), 16 * pos, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(b->sample_lat, slat.data(), 4 * pos, hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(b->seg_base, sb.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->seg_total, stt.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->seg_padded, sp.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->n_samples, &np, 4, hipMemcpyHostToDevice, st));
+    rc = run_adjoint_and_reduce(ctx, w, b, precision, n_latents, g_z, st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  ws_put(ctx, w);
+  return rc;
+}

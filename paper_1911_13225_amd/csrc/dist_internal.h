@@ -1,0 +1,127 @@
+// Internal data structures of the MI355X sphere tracer (host + device).
+//
+// Memory layout in HBM
+//   * Ray pool (structure of arrays, one slot per ray of every coarse-to-fine
+//     level of every image):  d = (dir.xyz, t) float4, b = (t_lo, t_hi)
+//     float2, img int32, st/n uint8 (status, next global step), flast float,
+//     and K records of the smallest-|f| queries (rec_f signed f, rec_t, rec_n)
+//     stored record-major [K][cap].  An image owns slots
+//     [slot_base, slot_base + H*W*(1 + 1/4 + 1/16)): level 0 first, then the
+//     coarser levels.
+//   * Packed decoder: every hidden-layer weight matrix is stored as MFMA
+//     A-operand fragments, fragment-major, so that one wave's fragment is one
+//     contiguous 1 KB block (coalesced 16-byte loads, L2 resident).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dist {
+
+constexpr int kMaxLayers = 12;
+constexpr int kMaxK = 4;
+constexpr int kMaxWidth = 512;
+constexpr int kThreads = 512;          // 8 waves of 64 per MLP workgroup
+
+enum : uint8_t { ST_ACTIVE = 0, ST_HIT = 1, ST_MISS = 2, ST_ESCAPED = 3, ST_UNCONVERGED = 4 };
+
+// One rendered image: camera, latent, tracing parameters and ray-slot bases.
+struct ImgDesc {
+  float fx, fy, cx, cy;
+  float R[9];                 // camera-to-world rotation, row-major
+  float c[3];                 // camera centre
+  float alpha, eps, near_, far_;
+  int H, W, levels, latent;
+  int max_steps, K, cur_level, slot_base;
+  int lvl_off[3];             // slot offset of level 0, 1, 2 from slot_base
+  int out_base;               // first output pixel of this image
+};
+
+struct RayPool {
+  float4* d;
+  float2* b;
+  int* img;
+  uint8_t* st;
+  uint8_t* n;
+  float* flast;
+  float* rec_f;
+  float* rec_t;
+  uint8_t* rec_n;
+  int cap;
+};
+
+// Device view of a packed decoder for one precision.
+struct NetDev {
+  int nl, L, skip;                 // layers, latent width, skip layer (-1: none)
+  int kmax;                        // widest padded activation row
+  int wpad[kMaxLayers];            // padded output width of layers 0 .. nl-2
+  int kpad[kMaxLayers];            // padded hidden-part input width of layers 1 .. nl-2
+  const void* wp[kMaxLayers];      // W_l packed as A fragments (rows = outputs)
+  const void* wpT[kMaxLayers];     // W_l^T packed as A fragments (rows = inputs)
+  const void* wplo[kMaxLayers];    // split precision: bf16(W_l - bf16(W_l)) fragments
+  const float* bias[kMaxLayers];   // padded biases (float32)
+  const float* w0p;                // [3][wpad0]: point columns of layer 0
+  const float* wsp;                // [3][wpad_skip]: point columns of the skip layer
+  const float* wlast;              // [wpad[nl-2]] output-layer weights
+  float blast;                     // output-layer bias
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+struct MarchArgs {
+  NetDev net;
+  RayPool pool;
+  const ImgDesc* imgs;
+  const float* bias0_lat;          // [n_lat][wpad0]  b0 + W0_z z
+  const float* biasS_lat;          // [n_lat][wpad_skip]
+  const int* list;                 // active ray slots
+  const int* count;                // number of entries in list
+};
+
+struct EvalArgs {
+  NetDev net;
+  const float* bias0_lat;
+  const float* biasS_lat;
+  int mode;                        // 0: explicit points, 1: normal stencil of hits
+  const float* pts;                // mode 0: [n][3]
+  const int* lat;                  // mode 0: [n]
+  long long n;                     // mode 0: count
+  int n_lat;                       // mode 0: latent ids are clamped to [0, n_lat)
+  const int* hits;                 // mode 1: hit ray slots
+  const int* hit_count;            // mode 1: device count of hits
+  RayPool pool;
+  const ImgDesc* imgs;
+  float delta;
+  float* f_out;
+};
+
+struct AdjArgs {
+  NetDev net;
+  const float* bias0_lat;
+  const float* biasS_lat;
+  const float4* samples;           // (p.xyz, seed), grouped by latent, padded per latent
+  const int* sample_lat;           // latent of each sample
+  const int* n_samples;            // device count (multiple of the tile size)
+  unsigned* mask_ws;               // per-workgroup ReLU mask scratch
+  float* partial;                  // [tile][2][2][kmax] column sums (S0, Sskip) x m-groups
+};
+
+// Precision codes of the decoder kernels: 0 float32, 1 bfloat16, 2 split
+// bfloat16 (x = hi + lo, products hi*hi + lo*hi + hi*lo, float32 accumulation).
+constexpr int kPrecF32 = 0, kPrecBF16 = 1, kPrecSplit = 2;
+
+int mlp_tile_rows(int precision);                 // rays per MLP tile
+int adj_tile_rows(int precision);                 // samples per adjoint tile
+size_t mlp_smem_bytes(int precision, const NetDev& net);
+size_t adj_mask_words(int precision, const NetDev& net);   // per workgroup
+hipError_t mlp_setup(int precision, const NetDev& net);    // raise LDS limits
+
+void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t s);
+void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t s);
+void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
+
+// packing / folding
+void launch_pack_w(int precision, bool transpose, const float* W, int out, int in_stride, int ncols,
+                   int npad, int kpad, void* dst, hipStream_t s);
+void launch_fold_bias(const float* b, const float* Wz, const float* z, int n_lat, int L, int nout,
+                      int npad, float* dst, hipStream_t s);
+
+}  // namespace dist

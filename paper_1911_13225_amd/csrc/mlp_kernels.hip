@@ -1,0 +1,788 @@
+// Fused decoder kernels for CDNA4 (gfx950): one workgroup evaluates the whole
+// DeepSDF-style MLP (paper App. B.1) for a tile of rays or sample points.
+//
+// Layout of one tile (M rows = rays, 8 waves):
+//   * The activation tile lives in LDS, row-major [M][kmax] (bf16 or f32),
+//     16-byte chunks XOR-swizzled by (row & 15) so that the MFMA operand reads
+//     and the epilogue writes are bank-conflict free.
+//   * Hidden layers are computed as D[n][m] = sum_k W[n][k] act[m][k] with the
+//     weights as the MFMA A operand (pre-packed fragments streamed from L2)
+//     and the activations as the B operand (from LDS).  An accumulator lane
+//     then holds 4 consecutive output features of one ray, which the
+//     epilogue (bias, ReLU, rounding) writes back as one 8/16-byte chunk.
+//   * Layer 0 and the point columns of the skip layer are 3-wide products done
+//     in float32 on the vector ALUs; the latent part of both is folded into a
+//     per-latent bias once per call (z is constant for an image).
+//   * The 1-wide output layer is a float32 dot product reduced across waves
+//     in a fixed order, then f = 0.5 (|p| - 0.5) + 0.05 tanh(m).
+#include "dist_internal.h"
+
+namespace dist {
+
+typedef __bf16 bf16;
+typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int P> struct Cfg;
+template <> struct Cfg<1> {           // bf16 x bf16 -> f32, v_mfma_f32_32x32x16_bf16
+  static constexpr int M = 128, MT = 4, ES = 2, EPC = 8;
+};
+template <> struct Cfg<0> {           // f32 x f32 -> f32, v_mfma_f32_32x32x2_f32
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 4;
+};
+template <> struct Cfg<2> {           // split bf16: x = hi + lo; hi*hi + lo*hi + hi*lo, f32 accumulation
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 8;   // a row holds interleaved hi/lo 16-byte chunks
+};
+
+__host__ __device__ inline int rows_for(int P) { return P == 1 ? 128 : 64; }
+__host__ __device__ inline size_t smem_bytes_for(int P, int kmax) {
+  const int M = rows_for(P);
+  const int ES = P == 1 ? 2 : 4;
+  return (size_t)M * kmax * ES + (size_t)M * (16 + 4 + 4 + 4 + 4) + (size_t)8 * M * 4;
+}
+
+template <int P> struct Sm {
+  char* act;
+  float4* pts;
+  int* lat;
+  int* rid;
+  float* fval;
+  float* gm;
+  float* part;
+  int rowb;
+  __device__ Sm(char* base, int kmax) {
+    constexpr int M = Cfg<P>::M;
+    rowb = kmax * Cfg<P>::ES;
+    act = base;
+    size_t off = (size_t)M * rowb;
+    pts = (float4*)(base + off); off += (size_t)M * 16;
+    lat = (int*)(base + off);    off += (size_t)M * 4;
+    rid = (int*)(base + off);    off += (size_t)M * 4;
+    fval = (float*)(base + off); off += (size_t)M * 4;
+    gm = (float*)(base + off);   off += (size_t)M * 4;
+    part = (float*)(base + off);
+  }
+  __device__ __forceinline__ char* chunk(int m, int ch) const {
+    return act + (size_t)m * rowb + ((ch ^ (m & 15)) << 4);
+  }
+};
+
+extern __shared__ __attribute__((aligned(16))) char dyn_smem[];
+
+// ---------------------------------------------------------------------------
+// Layer 0: h0 = relu(W0_p p + (b0 + W0_z z)), float32 VALU, written to LDS.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float layer0_pre(const NetDev& net, const float* b0l, int n, float4 p) {
+  const int N0 = net.wpad[0];
+  return fmaf(net.w0p[n], p.x, fmaf(net.w0p[N0 + n], p.y, fmaf(net.w0p[2 * N0 + n], p.z, b0l[n])));
+}
+
+template <int P>
+__device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid) {
+  constexpr int M = Cfg<P>::M, EPC = Cfg<P>::EPC;
+  const int N0 = net.wpad[0];
+  const int cpr = N0 / EPC;
+  for (int c = tid; c < M * cpr; c += kThreads) {
+    const int m = c / cpr, ch = c - m * cpr;
+    const int n = ch * EPC;
+    const float4 p = s.pts[m];
+    const float* b0l = bias0_lat + (size_t)s.lat[m] * N0;
+    float v[EPC];
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) v[e] = fmaxf(layer0_pre(net, b0l, n + e, p), 0.f);
+    if constexpr (P == 1) {
+      bf16x8 w;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w[e] = (bf16)v[e];
+      *(bf16x8*)s.chunk(m, ch) = w;
+    } else if constexpr (P == 2) {
+      bf16x8 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        hi[e] = (bf16)v[e];
+        lo[e] = (bf16)(v[e] - (float)hi[e]);
+      }
+      *(bf16x8*)s.chunk(m, 2 * ch) = hi;
+      *(bf16x8*)s.chunk(m, 2 * ch + 1) = lo;
+    } else {
+      *(f32x4*)s.chunk(m, ch) = f32x4{v[0], v[1], v[2], v[3]};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level GEMM: acc[i][j] (m-tile mt0+i, n-tile nt0+j) = sum_k A[n][k] B[k][m]
+// ---------------------------------------------------------------------------
+template <int MTW, int NTW>
+__device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& s, const bf16x8* __restrict__ wp,
+                                          int ksteps, int nt0, int mt0, int lane) {
+  const int r = lane & 31, g = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  const bf16x8* wrow[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
+  const char* arow[MTW];
+  int sw[MTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int m = (mt0 + i) * 32 + r;
+    arow[i] = s.act + (size_t)m * s.rowb;
+    sw[i] = m & 15;
+  }
+  bf16x8 an[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) an[j] = wrow[j][0];
+  for (int ks = 0; ks < ksteps; ++ks) {
+    bf16x8 a[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) a[j] = an[j];
+    if (ks + 1 < ksteps) {
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) an[j] = wrow[j][(size_t)(ks + 1) * 64];
+    }
+    bf16x8 b[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) b[i] = *(const bf16x8*)(arow[i] + (((2 * ks + g) ^ sw[i]) << 4));
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+      for (int j = 0; j < NTW; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[i], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Split precision: with X3 the product is hi*hi + lo*hi + hi*lo (A = weights,
+// B = activations); without X3 only the hi planes are used (bf16 product).
+template <int MTW, int NTW, bool X3>
+__device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>& s, const bf16x8* __restrict__ wp,
+                                           const bf16x8* __restrict__ wlo, int ksteps, int nt0, int mt0, int lane) {
+  const int r = lane & 31, g = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  const char* arow[MTW];
+  int sw[MTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int m = (mt0 + i) * 32 + r;
+    arow[i] = s.act + (size_t)m * s.rowb;
+    sw[i] = m & 15;
+  }
+  for (int ks = 0; ks < ksteps; ++ks) {
+    bf16x8 ah[NTW], al[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+      const size_t off = ((size_t)(nt0 + j) * ksteps + ks) * 64 + lane;
+      ah[j] = wp[off];
+      if constexpr (X3) al[j] = wlo[off];
+    }
+    const int c = 2 * (2 * ks + g);
+    bf16x8 bh[MTW], bl[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      bh[i] = *(const bf16x8*)(arow[i] + ((c ^ sw[i]) << 4));
+      if constexpr (X3) bl[i] = *(const bf16x8*)(arow[i] + (((c + 1) ^ sw[i]) << 4));
+    }
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[j], bh[i], acc[i][j], 0, 0, 0);
+        if constexpr (X3) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[j], bh[i], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[j], bl[i], acc[i][j], 0, 0, 0);
+        }
+      }
+  }
+}
+
+template <int MTW, int NTW>
+__device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s, const f32x4* __restrict__ wp,
+                                         int ksteps, int nt0, int mt0, int lane) {
+  const int r = lane & 31, g = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  const f32x4* wrow[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
+  const char* arow[MTW];
+  int sw[MTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int m = (mt0 + i) * 32 + r;
+    arow[i] = s.act + (size_t)m * s.rowb;
+    sw[i] = m & 15;
+  }
+  f32x4 an[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) an[j] = wrow[j][0];
+  for (int ks = 0; ks < ksteps; ++ks) {
+    f32x4 a[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) a[j] = an[j];
+    if (ks + 1 < ksteps) {
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) an[j] = wrow[j][(size_t)(ks + 1) * 64];
+    }
+    f32x4 b[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) b[i] = *(const f32x4*)(arow[i] + (((2 * ks + g) ^ sw[i]) << 4));
+#pragma unroll
+    for (int sidx = 0; sidx < 4; ++sidx)
+#pragma unroll
+      for (int i = 0; i < MTW; ++i)
+#pragma unroll
+        for (int j = 0; j < NTW; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j][sidx], b[i][sidx], acc[i][j], 0, 0, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues
+// ---------------------------------------------------------------------------
+enum { EP_ACT = 0, EP_LAST = 1, EP_ACT_MASK = 2, EP_LAST_ADJ = 3, EP_VJP = 4 };
+
+struct EpCtx {
+  const float* bias;        // per-layer bias (non-skip) or null
+  const float* biasS_lat;   // folded skip bias [n_lat][wpad]
+  const float* bias0_lat;   // folded layer-0 bias (for the layer-0 mask of the VJP)
+  const float* wsp;         // skip point columns [3][wpad]
+  int wpad;                 // output width of this layer (stride of biasS/wsp)
+  bool skip;                // this layer reads [h, z, p]
+  int layer;                // index of the layer whose output this epilogue produces
+  unsigned* mask;           // mask scratch of this workgroup
+  int ntmax;                // words per mask row
+  float* partial;           // adjoint column-sum output of this tile (or null)
+  int which;                // 0: S0, 1: Sskip, -1: none
+  bool write_act;
+  int kmax;
+};
+
+template <int P>
+__device__ __forceinline__ void store4(const Sm<P>& s, int m, int n, int g, const float (&v)[4], bool hi_only = false) {
+  if constexpr (P == 1) {
+    bf16x4 w = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+    *(bf16x4*)(s.chunk(m, n >> 3) + 8 * g) = w;
+  } else if constexpr (P == 2) {
+    bf16x4 h = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+    *(bf16x4*)(s.chunk(m, 2 * (n >> 3)) + 8 * g) = h;
+    if (!hi_only) {
+      bf16x4 l = {(bf16)(v[0] - (float)h[0]), (bf16)(v[1] - (float)h[1]), (bf16)(v[2] - (float)h[2]),
+                  (bf16)(v[3] - (float)h[3])};
+      *(bf16x4*)(s.chunk(m, 2 * (n >> 3) + 1) + 8 * g) = l;
+    }
+  } else {
+    *(f32x4*)s.chunk(m, n >> 2) = f32x4{v[0], v[1], v[2], v[3]};
+  }
+}
+
+template <int P, int MTW, int NTW>
+__device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
+                                         const Sm<P>& s, int nt0, int mt0, int nw, int mg, int lane) {
+  constexpr int M = Cfg<P>::M;
+  const int r = lane & 31, g = lane >> 5;
+  if (mode == EP_ACT || mode == EP_ACT_MASK) {
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      const int m = (mt0 + i) * 32 + r;
+      const float4 p = s.pts[m];
+      const float* bl = ec.skip ? ec.biasS_lat + (size_t)s.lat[m] * ec.wpad : ec.bias;
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        const int nb = (nt0 + j) * 32;
+        unsigned bits = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int n = nb + 8 * q + 4 * g;
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float x = acc[i][j][4 * q + e];
+            if (ec.skip) {
+              x += fmaf(ec.wsp[n + e], p.x, fmaf(ec.wsp[ec.wpad + n + e], p.y,
+                        fmaf(ec.wsp[2 * ec.wpad + n + e], p.z, bl[n + e])));
+            } else {
+              x += bl[n + e];
+            }
+            bits |= (x > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
+            v[e] = fmaxf(x, 0.f);
+          }
+          store4<P>(s, m, n, g, v);
+        }
+        if (mode == EP_ACT_MASK) {
+          bits |= __shfl_xor(bits, 32);
+          if (g == 0) ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + (nb >> 5)] = bits;
+        }
+      }
+    }
+    return;
+  }
+  if (mode == EP_LAST || mode == EP_LAST_ADJ) {
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      const int m = (mt0 + i) * 32 + r;
+      const float4 p = s.pts[m];
+      const float* bl = ec.skip ? ec.biasS_lat + (size_t)s.lat[m] * ec.wpad : ec.bias;
+      float sum = 0.f;
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        const int nb = (nt0 + j) * 32;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int n = nb + 8 * q + 4 * g;
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float x = acc[i][j][4 * q + e];
+            if (ec.skip) {
+              x += fmaf(ec.wsp[n + e], p.x, fmaf(ec.wsp[ec.wpad + n + e], p.y,
+                        fmaf(ec.wsp[2 * ec.wpad + n + e], p.z, bl[n + e])));
+            } else {
+              x += bl[n + e];
+            }
+            const float wl = net.wlast[n + e];
+            sum = fmaf(wl, fmaxf(x, 0.f), sum);
+            v[e] = x > 0.f ? wl : 0.f;           // d m / d(pre-activation)
+          }
+          if (mode == EP_LAST_ADJ) store4<P>(s, m, n, g, v, true);
+        }
+      }
+      sum += __shfl_xor(sum, 32);
+      if (g == 0) s.part[nw * M + m] = sum;
+    }
+    return;
+  }
+  // EP_VJP: acc = W^T delta for the output of layer ec.layer; apply its ReLU mask
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int m = (mt0 + i) * 32 + r;
+    const float4 p = s.pts[m];
+    const float* b0l = ec.bias0_lat + (size_t)s.lat[m] * net.wpad[0];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+      const int nb = (nt0 + j) * 32;
+      unsigned bits;
+      if (ec.layer == 0) {
+        bits = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int n = nb + 8 * q + 4 * g + e;
+            bits |= (layer0_pre(net, b0l, n, p) > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
+          }
+      } else {
+        bits = ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + (nb >> 5)];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (!((bits >> (8 * q + 4 * g + e)) & 1u)) acc[i][j][4 * q + e] = 0.f;
+      if (ec.write_act) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v[4] = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+          store4<P>(s, m, nb + 8 * q + 4 * g, g, v, true);
+        }
+      }
+    }
+  }
+  if (ec.which >= 0) {
+    // column sums over the tile's rows, each row scaled by its seed gm[m]
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+      const int nb = (nt0 + j) * 32;
+      float cs[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cs[e] = 0.f;
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        const float w = s.gm[(mt0 + i) * 32 + r];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) cs[e] = fmaf(w, acc[i][j][e], cs[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        float x = cs[e];
+        x += __shfl_xor(x, 16);
+        x += __shfl_xor(x, 8);
+        x += __shfl_xor(x, 4);
+        x += __shfl_xor(x, 2);
+        x += __shfl_xor(x, 1);
+        cs[e] = x;
+      }
+      if (r == 0) {
+        float* dst = ec.partial + ((size_t)(ec.which * 2 + mg)) * ec.kmax;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) dst[nb + 8 * q + 4 * g + e] = cs[4 * q + e];
+      }
+    }
+  }
+}
+
+// Run one layer (GEMM + barrier + epilogue + barrier) for an output width N
+// (128, 256 or 512 after padding): 8 waves split N into WN groups and the
+// tile rows into 8/WN groups.
+template <int P, int MTW, int NTW, int WN>
+__device__ __forceinline__ void layer_run(int mode, const NetDev& net, const EpCtx& ec, const Sm<P>& s,
+                                          const void* wp, const void* wlo, int ksteps, int wave, int lane) {
+  const int nw = wave % WN, mg = wave / WN;
+  const int nt0 = nw * NTW, mt0 = mg * MTW;
+  f32x16 acc[MTW][NTW];
+  if constexpr (P == 1) {
+    gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane);
+  } else if constexpr (P == 2) {
+    if (mode == EP_VJP) gemm_split<MTW, NTW, false>(acc, s, (const bf16x8*)wp, nullptr, ksteps, nt0, mt0, lane);
+    else gemm_split<MTW, NTW, true>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane);
+  } else {
+    gemm_f32<MTW, NTW>(acc, s, (const f32x4*)wp, ksteps, nt0, mt0, lane);
+  }
+  __syncthreads();
+  epilogue<P, MTW, NTW>(mode, net, ec, acc, s, nt0, mt0, nw, mg, lane);
+  __syncthreads();
+}
+
+template <int P>
+__device__ __forceinline__ int layer(int mode, const NetDev& net, const EpCtx& ec, const Sm<P>& s,
+                                     const void* wp, const void* wlo, int N, int K, int wave, int lane) {
+  constexpr int MT = Cfg<P>::MT;
+  const int ksteps = K / (P ? 16 : 8);
+  if (N == 512) { layer_run<P, MT, 2, 8>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 8; }
+  if (N == 256) { layer_run<P, MT, 1, 8>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 8; }
+  layer_run<P, MT / 2, 1, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane);
+  return 4;
+}
+
+__device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_lat, int l) {
+  EpCtx ec{};
+  ec.bias = net.bias[l];
+  ec.biasS_lat = biasS_lat;
+  ec.wsp = net.wsp;
+  ec.wpad = net.wpad[l];
+  ec.skip = (l == net.skip);
+  ec.layer = l;
+  ec.which = -1;
+  ec.kmax = net.kmax;
+  ec.ntmax = net.kmax / 32;
+  return ec;
+}
+
+// Forward through all hidden layers; leaves the output-layer partial sums in
+// s.part and returns the number of partial groups.
+template <int P>
+__device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat, const Sm<P>& s,
+                           int tid, int wave, int lane, unsigned* mask, bool adj) {
+  layer0_fill<P>(net, bias0_lat, s, tid);
+  __syncthreads();
+  int wn = 8;
+  for (int l = 1; l <= net.nl - 2; ++l) {
+    EpCtx ec = fwd_ctx(net, biasS_lat, l);
+    ec.mask = mask;
+    const bool last = (l == net.nl - 2);
+    const int mode = last ? (adj ? EP_LAST_ADJ : EP_LAST) : (adj ? EP_ACT_MASK : EP_ACT);
+    wn = layer<P>(mode, net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l], wave, lane);
+  }
+  return wn;
+}
+
+__device__ __forceinline__ float sdf_from_m(float4 p, float m) {
+  const float r = sqrtf(fmaf(p.x, p.x, fmaf(p.y, p.y, p.z * p.z)));
+  return 0.5f * (r - 0.5f) + 0.05f * tanhf(m);
+}
+
+// ---------------------------------------------------------------------------
+// March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_march(MarchArgs a) {
+  constexpr int M = Cfg<P>::M;
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int count = *a.count;
+  const int K = 0;
+  (void)K;
+  for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
+    if (tid < M) {
+      const int idx = tile * M + tid;
+      float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+      int lt = 0, r = -1;
+      if (idx < count) {
+        r = a.list[idx];
+        const ImgDesc& im = a.imgs[a.pool.img[r]];
+        const float4 d = a.pool.d[r];
+        p = make_float4(fmaf(d.w, d.x, im.c[0]), fmaf(d.w, d.y, im.c[1]), fmaf(d.w, d.z, im.c[2]), 0.f);
+        lt = im.latent;
+      }
+      s.pts[tid] = p;
+      s.lat[tid] = lt;
+      s.rid[tid] = r;
+    }
+    __syncthreads();
+    const int wn = mlp_forward<P>(a.net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, nullptr, false);
+    if (tid < M && s.rid[tid] >= 0) {
+      float m = a.net.blast;
+      for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
+      const float4 p = s.pts[tid];
+      const float f = sdf_from_m(p, m);
+      const int r = s.rid[tid];
+      const RayPool& pl = a.pool;
+      const ImgDesc& im = a.imgs[pl.img[r]];
+      const int n = pl.n[r];
+      float4 d = pl.d[r];
+      const float t = d.w;
+      // running K smallest |f| (ties keep the earlier step)
+      const float af = fabsf(f);
+      const int Kr = im.K;
+      int pos = 0;
+      for (int k = 0; k < Kr; ++k) pos += (fabsf(pl.rec_f[(size_t)k * pl.cap + r]) <= af) ? 1 : 0;
+      for (int k = Kr - 1; k > pos; --k) {
+        pl.rec_f[(size_t)k * pl.cap + r] = pl.rec_f[(size_t)(k - 1) * pl.cap + r];
+        pl.rec_t[(size_t)k * pl.cap + r] = pl.rec_t[(size_t)(k - 1) * pl.cap + r];
+        pl.rec_n[(size_t)k * pl.cap + r] = pl.rec_n[(size_t)(k - 1) * pl.cap + r];
+      }
+      if (pos < Kr) {
+        pl.rec_f[(size_t)pos * pl.cap + r] = f;
+        pl.rec_t[(size_t)pos * pl.cap + r] = t;
+        pl.rec_n[(size_t)pos * pl.cap + r] = (uint8_t)n;
+      }
+      pl.flast[r] = f;
+      uint8_t st;
+      if (!(af == af) || af == INFINITY) {
+        st = ST_UNCONVERGED;                   // non-finite query: stop the ray
+      } else if (af < im.eps) {
+        st = ST_HIT;
+      } else if (n == im.max_steps - 1) {
+        st = ST_UNCONVERGED;
+      } else {
+        const float tn = fmaf(im.alpha, f, t);
+        const float2 b = pl.b[r];
+        st = (tn > b.y || tn < b.x) ? ST_ESCAPED : ST_ACTIVE;
+        d.w = tn;
+        pl.d[r] = d;
+      }
+      pl.st[r] = st;
+      pl.n[r] = (uint8_t)(n + 1);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain decoder queries (explicit points, or the 6-point normal stencil)
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_eval(EvalArgs a) {
+  constexpr int M = Cfg<P>::M;
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long long count = a.mode == 0 ? a.n : 6ll * (long long)(*a.hit_count);
+  for (long long tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
+    if (tid < M) {
+      const long long idx = tile * M + tid;
+      float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+      int lt = 0, valid = 0;
+      if (idx < count) {
+        valid = 1;
+        if (a.mode == 0) {
+          p = make_float4(a.pts[3 * idx], a.pts[3 * idx + 1], a.pts[3 * idx + 2], 0.f);
+          lt = min(max(a.lat[idx], 0), a.n_lat - 1);
+        } else {
+          const int h = (int)(idx / 6), j = (int)(idx - 6ll * h);
+          const int r = a.hits[h];
+          const ImgDesc& im = a.imgs[a.pool.img[r]];
+          const float4 d = a.pool.d[r];
+          const float dd = d.w + a.pool.flast[r];          // Eq. 1 ray distance
+          float q[3] = {fmaf(dd, d.x, im.c[0]), fmaf(dd, d.y, im.c[1]), fmaf(dd, d.z, im.c[2])};
+          const int ax = j >> 1;
+          q[ax] = (j & 1) ? q[ax] - a.delta : q[ax] + a.delta;
+          p = make_float4(q[0], q[1], q[2], 0.f);
+          lt = im.latent;
+        }
+      }
+      s.pts[tid] = p;
+      s.lat[tid] = lt;
+      s.rid[tid] = valid;
+    }
+    __syncthreads();
+    const int wn = mlp_forward<P>(a.net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, nullptr, false);
+    if (tid < M && s.rid[tid]) {
+      float m = a.net.blast;
+      for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
+      a.f_out[tile * M + tid] = sdf_from_m(s.pts[tid], m);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint: recompute the decoder at detached samples and back-propagate the
+// per-sample seeds (Eq. 2 first term, recompute of App. B.2).  Each tile holds
+// samples of one latent; it writes the column sums of delta at layer 0 (S0)
+// and at the skip layer (Sskip); dL/dz = W0_z^T S0 + Wskip_z^T Sskip.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
+  constexpr int M = Cfg<P>::M;
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const NetDev& net = a.net;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int count = *a.n_samples;
+  const int ntmax = net.kmax / 32;
+  unsigned* mask = a.mask_ws + (size_t)blockIdx.x * (size_t)(net.nl) * M * ntmax;
+  for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
+    if (tid < M) {
+      const int idx = tile * M + tid;
+      const float4 smp = a.samples[idx];
+      s.pts[tid] = make_float4(smp.x, smp.y, smp.z, 0.f);
+      s.fval[tid] = smp.w;
+      s.lat[tid] = a.sample_lat[idx];
+    }
+    __syncthreads();
+    const int wn = mlp_forward<P>(net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, mask, true);
+    if (tid < M) {
+      float m = net.blast;
+      for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
+      const float th = tanhf(m);
+      s.gm[tid] = s.fval[tid] * 0.05f * (1.f - th * th);
+    }
+    __syncthreads();
+    float* part = a.partial + (size_t)tile * 4 * net.kmax;
+    for (int l = net.nl - 2; l >= 1; --l) {
+      EpCtx ec{};
+      ec.bias0_lat = a.bias0_lat;
+      ec.layer = l - 1;
+      ec.mask = mask;
+      ec.ntmax = ntmax;
+      ec.partial = part;
+      ec.kmax = net.kmax;
+      ec.which = (l - 1 == 0) ? 0 : ((l - 1 == net.skip) ? 1 : -1);
+      ec.write_act = (l - 1 != 0);
+      layer<P>(EP_VJP, net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l], wave, lane);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side helpers
+// ---------------------------------------------------------------------------
+int mlp_tile_rows(int precision) { return rows_for(precision); }
+int adj_tile_rows(int precision) { return mlp_tile_rows(precision); }
+size_t mlp_smem_bytes(int precision, const NetDev& net) { return smem_bytes_for(precision, net.kmax); }
+size_t adj_mask_words(int precision, const NetDev& net) {
+  return (size_t)net.nl * mlp_tile_rows(precision) * (net.kmax / 32);
+}
+
+template <int P>
+static hipError_t setup_p(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_march<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_eval<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_adjoint<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t mlp_setup(int precision, const NetDev& net) {
+  const int bytes = (int)mlp_smem_bytes(precision, net);
+  if (precision == 1) return setup_p<1>(bytes);
+  if (precision == 2) return setup_p<2>(bytes);
+  return setup_p<0>(bytes);
+}
+
+#define DIST_DISPATCH(KERNEL, ARGS)                                                                    \
+  do {                                                                                                 \
+    const size_t sm = mlp_smem_bytes(precision, ARGS.net);                                             \
+    if (precision == 1) hipLaunchKernelGGL(KERNEL<1>, dim3(grid), dim3(kThreads), sm, st, ARGS);       \
+    else if (precision == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(grid), dim3(kThreads), sm, st, ARGS);  \
+    else hipLaunchKernelGGL(KERNEL<0>, dim3(grid), dim3(kThreads), sm, st, ARGS);                      \
+  } while (0)
+
+void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_march, a); }
+void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_eval, a); }
+void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_adjoint, a); }
+
+// ---------------------------------------------------------------------------
+// Weight packing into MFMA A-operand fragments.
+//   bf16: fragment (rt, ks) = 64 lanes x 8 values, lane l holds row rt*32 + l%32,
+//         columns ks*16 + (l/32)*8 + 0..7
+//   f32 : fragment (rt, ks) = 64 lanes x 4 values, lane l holds row rt*32 + l%32,
+//         columns ks*8 + (l/32)*4 + 0..3
+// Rows are output features (or input features when transposed), columns the
+// contracted dimension; entries outside the matrix are zero.
+// ---------------------------------------------------------------------------
+__global__ void k_pack(int precision, int transpose, const float* __restrict__ W, int out, int in_stride,
+                       int ncols, int rows_pad, int cols_pad, void* dst) {
+  const long long total = (long long)rows_pad * cols_pad;
+  const int kfrag = precision ? 16 : 8;
+  const int per = precision ? 8 : 4;
+  const int ksteps = cols_pad / kfrag;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+    const int e = (int)(i % per);
+    const long long fl = i / per;
+    const int lane = (int)(fl % 64);
+    const long long frag = fl / 64;
+    const int ks = (int)(frag % ksteps);
+    const int rt = (int)(frag / ksteps);
+    const int row = rt * 32 + (lane & 31);
+    const int col = ks * kfrag + (lane >> 5) * per + e;
+    // matrix A[row][col]: W[row][col] or, transposed, W[col][row]
+    const int n = transpose ? col : row;   // output feature of W
+    const int k = transpose ? row : col;   // input feature of W (hidden part)
+    float v = 0.f;
+    if (n < out && k < ncols) v = W[(size_t)n * in_stride + k];
+    if (precision == 2) v = v - (float)(bf16)v;          // low part of the split
+    if (precision) ((bf16*)dst)[i] = (bf16)v;
+    else ((float*)dst)[i] = v;
+  }
+}
+
+void launch_pack_w(int precision, bool transpose, const float* W, int out, int in_stride, int ncols,
+                   int npad, int kpad, void* dst, hipStream_t st) {
+  // not transposed: rows = npad (outputs), cols = kpad (inputs); transposed: rows = kpad, cols = npad
+  const int rows_pad = transpose ? kpad : npad;
+  const int cols_pad = transpose ? npad : kpad;
+  const long long total = (long long)rows_pad * cols_pad;
+  const int grid = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, precision, transpose ? 1 : 0, W, out, in_stride, ncols,
+                     rows_pad, cols_pad, dst);
+}
+
+// dst[l][n] = b[n] + sum_j Wz[n][j] z[l][j]  (rows n >= nout are zero)
+__global__ void k_fold_bias(const float* __restrict__ b, const float* __restrict__ Wz, const float* __restrict__ z,
+                            int n_lat, int L, int nout, int npad, float* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_lat * npad) return;
+  const int l = i / npad, n = i - l * npad;
+  float acc = 0.f;
+  if (n < nout) {
+    acc = b[n];
+    const float* w = Wz + (size_t)n * L;
+    const float* zz = z + (size_t)l * L;
+    for (int j = 0; j < L; ++j) acc = fmaf(w[j], zz[j], acc);
+  }
+  dst[i] = acc;
+}
+
+void launch_fold_bias(const float* b, const float* Wz, const float* z, int n_lat, int L, int nout, int npad,
+                      float* dst, hipStream_t st) {
+  const int total = n_lat * npad;
+  hipLaunchKernelGGL(k_fold_bias, dim3((total + 255) / 256), dim3(256), 0, st, b, Wz, z, n_lat, L, nout, npad, dst);
+}
+
+}  // namespace dist

@@ -1,0 +1,48 @@
+// Launchers of the ray bookkeeping kernels (ray_kernels.hip).
+#pragma once
+#include "dist_internal.h"
+
+namespace dist {
+
+struct FinalizeOut {
+  float* depth;
+  float* dist;
+  float* sil;
+  float* normal;
+  uint8_t* status;
+  uint8_t* nsteps;
+  float4* nraw;      // per pixel (nx, ny, nz, |n|), zeroed here, filled by the normal pass
+  int* hits;
+  int* hit_count;
+  int want_hits;
+};
+
+struct SeedIn {
+  const float* g_depth;
+  const float* g_normal;
+  const float* g_sil;
+  const float4* nraw;
+  float delta;
+};
+
+void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_rays, int* list,
+                       int* counter, hipStream_t s);
+void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_children,
+                  int child_lvl, int child_step, int* list, int* counter, hipStream_t s);
+void launch_compact(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count,
+                    int max_items, int* out_list, int* out_count, unsigned long long* qcount, hipStream_t s);
+void launch_finalize(const RayPool& pl, const ImgDesc* imgs, int n_img, int hw, const FinalizeOut& o, hipStream_t s);
+void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, const int* hit_count, int max_hits,
+                    const float* fv, float delta, float* normal, float4* nraw, hipStream_t s);
+void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
+                    int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
+                    int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s);
+void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
+                        int* sample_lat, hipStream_t s);
+void launch_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base, const int* seg_padded,
+                      int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs, const float* Wsz, int L,
+                      float* gz, hipStream_t s);
+void launch_fill_i32(int* p, int v, int n, hipStream_t s);
+void launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
+
+}  // namespace dist

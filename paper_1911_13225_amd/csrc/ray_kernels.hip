@@ -1,0 +1,519 @@
+// Ray bookkeeping kernels: generation and unit-sphere initialisation, the
+// coarse-to-fine split, active-ray compaction, finalisation of the rendered
+// maps, normals, and the gradient-sample list of the backward pass.  All of
+// them are memory-bound (a few tens of bytes per ray) and use wave64 ballots
+// with one atomic per workgroup for list appends.
+#include "dist_internal.h"
+#include "ray_kernels.h"
+
+namespace dist {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+// Append `value` to list for every thread with flag set; one atomic per
+// 256-thread block.  Must be called by all threads of the block.
+__device__ __forceinline__ void block_append(bool flag, int value, int* list, int* counter) {
+  __shared__ int wcnt[4];
+  __shared__ int base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int within = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) wcnt[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    base = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
+  int off = base;
+  for (int i = 0; i < w; ++i) off += wcnt[i];
+  if (flag) list[off + within] = value;
+  __syncthreads();
+}
+
+// Level-`lvl` ray through the centre of block (U, V): unit world direction and
+// the normalised image coordinates (xt, yt) = K^-1 (x, y) of that centre.
+__device__ __forceinline__ void level_ray(const ImgDesc& im, int lvl, int U, int V, float3& d, float& xt, float& yt) {
+  const float sc = (float)(1 << lvl);
+  const float u = sc * (float)U + 0.5f * sc;
+  const float v = sc * (float)V + 0.5f * sc;
+  xt = (u - im.cx) / im.fx;
+  yt = (v - im.cy) / im.fy;
+  const float nrm = sqrtf(xt * xt + yt * yt + 1.f);
+  const float a = xt / nrm, b = yt / nrm, c = 1.f / nrm;
+  d.x = im.R[0] * a + im.R[1] * b + im.R[2] * c;
+  d.y = im.R[3] * a + im.R[4] * b + im.R[5] * c;
+  d.z = im.R[6] * a + im.R[7] * b + im.R[8] * c;
+}
+
+// Unit-sphere interval of the ray c + t d (Sec. 3.2 initialisation).
+__device__ __forceinline__ bool sphere_interval(const ImgDesc& im, float3 d, float& t_lo, float& t_hi) {
+  const float b = im.c[0] * d.x + im.c[1] * d.y + im.c[2] * d.z;
+  const float cc = im.c[0] * im.c[0] + im.c[1] * im.c[1] + im.c[2] * im.c[2];
+  const float disc = b * b - (cc - 1.f);
+  const float sq = sqrtf(fmaxf(disc, 0.f));
+  t_lo = fmaxf(-b - sq, im.near_);
+  t_hi = fminf(-b + sq, im.far_);
+  return disc > 0.f;
+}
+
+__device__ __forceinline__ void init_ray(const RayPool& pl, const ImgDesc& im, int img, int r, float3 d, float t,
+                                         float t_lo, float t_hi, bool inside, int step) {
+  pl.d[r] = make_float4(d.x, d.y, d.z, t);
+  pl.b[r] = make_float2(t_lo, t_hi);
+  pl.img[r] = img;
+  pl.st[r] = inside ? ST_ACTIVE : ST_MISS;
+  pl.n[r] = (uint8_t)step;
+  pl.flast[r] = 0.f;
+  for (int k = 0; k < im.K; ++k) {
+    pl.rec_f[(size_t)k * pl.cap + r] = INFINITY;
+    pl.rec_t[(size_t)k * pl.cap + r] = 0.f;
+    pl.rec_n[(size_t)k * pl.cap + r] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: one ray per 2^L x 2^L block, starting at the sphere entry.
+// grid: (blocks over rays of the largest image, n_images in `imgs_list`)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init_level(RayPool pl, ImgDesc* imgs, const int* imgs_list,
+                                                    int* list, int* counter) {
+  const int img = imgs_list[blockIdx.y];
+  const ImgDesc& im = imgs[img];
+  const int lvl = im.levels;
+  const int Wl = im.W >> lvl, Hl = im.H >> lvl;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = false;
+  int r = 0;
+  if (i < Wl * Hl) {
+    const int V = i / Wl, U = i - V * Wl;
+    float3 d;
+    float xt, yt, t_lo, t_hi;
+    level_ray(im, lvl, U, V, d, xt, yt);
+    const bool inside = sphere_interval(im, d, t_lo, t_hi);
+    r = im.slot_base + im.lvl_off[lvl] + i;
+    init_ray(pl, im, img, r, d, t_lo, t_lo, t_hi, inside, 0);
+    act = inside;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) imgs[img].cur_level = lvl;
+  block_append(act, r, list, counter);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-to-fine split (Sec. 3.2, Fig. 3a): every ray of level lvl+1 becomes
+// four rays of level lvl.  A child starts from the parent's t clamped into its
+// own unit-sphere interval (from its own entry if the parent missed) and is
+// re-activated whatever the parent's state; its records start empty.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_split(RayPool pl, ImgDesc* imgs, const int* imgs_list, int child_lvl,
+                                               int child_step, int* list, int* counter) {
+  const int img = imgs_list[blockIdx.y];
+  const ImgDesc& im = imgs[img];
+  const int Wl = im.W >> child_lvl, Hl = im.H >> child_lvl;
+  const int Wp = im.W >> (child_lvl + 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = false;
+  int r = 0;
+  if (i < Wl * Hl) {
+    const int V = i / Wl, U = i - V * Wl;
+    float3 d;
+    float xt, yt, t_lo, t_hi;
+    level_ray(im, child_lvl, U, V, d, xt, yt);
+    const bool inside = sphere_interval(im, d, t_lo, t_hi);
+    const int pr = im.slot_base + im.lvl_off[child_lvl + 1] + (V >> 1) * Wp + (U >> 1);
+    const float tp = pl.st[pr] == ST_MISS ? t_lo : pl.d[pr].w;
+    const float t = fminf(fmaxf(tp, t_lo), t_hi);
+    r = im.slot_base + im.lvl_off[child_lvl] + i;
+    init_ray(pl, im, img, r, d, t, t_lo, t_hi, inside, child_step);
+    act = inside;
+  }
+  block_append(act, r, list, counter);
+}
+
+__global__ void k_set_level(ImgDesc* imgs, const int* imgs_list, int n, int lvl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) imgs[imgs_list[i]].cur_level = lvl;
+}
+
+// ---------------------------------------------------------------------------
+// Compaction (dynamic synchronized inference, Sec. 3.2 / App. B.2): keep the
+// rays that are still ACTIVE at their image's current level, and count the
+// queries each image spent in the step just marched.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_compact(RayPool pl, const ImgDesc* imgs, const int* in_list,
+                                                 const int* in_count, int* out_list, int* out_count,
+                                                 unsigned long long* qcount) {
+  const int count = *in_count;
+  const int lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * 256; base < count; base += gridDim.x * 256) {
+    const int i = base + threadIdx.x;
+    bool keep = false, valid = i < count;
+    int r = 0, img = -1;
+    if (valid) {
+      r = in_list[i];
+      img = pl.img[r];
+      const ImgDesc& im = imgs[img];
+      const int off = r - im.slot_base;
+      const int hw = im.H * im.W;
+      const int lvl = off < hw ? 0 : (off < hw + (hw >> 2) ? 1 : 2);
+      keep = pl.st[r] == ST_ACTIVE && lvl == im.cur_level;
+    }
+    // per-image query counts, one atomic per distinct image in the wave
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int li = __shfl(img, leader);
+      const unsigned long long same = __ballot(valid && img == li);
+      if (lane == leader) atomicAdd(&qcount[li], (unsigned long long)__popcll(same));
+      todo &= ~same;
+    }
+    block_append(keep, r, out_list, out_count);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finalise level-0 rays into the output maps (Sec. 3.3, App. A.3).
+// grid: (blocks over H*W, n_images)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* imgs, FinalizeOut o) {
+  const int img = blockIdx.y;
+  const ImgDesc& im = imgs[img];
+  const int hw = im.H * im.W;
+  const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+  bool hit = false;
+  int r = 0;
+  if (pix < hw) {
+    r = im.slot_base + im.lvl_off[0] + pix;
+    const uint8_t st = pl.st[r];
+    const size_t q = (size_t)im.out_base + pix;
+    const int V = pix / im.W, U = pix - V * im.W;
+    float3 dd;
+    float xt, yt;
+    level_ray(im, 0, U, V, dd, xt, yt);
+    const float4 d = pl.d[r];
+    hit = st == ST_HIT;
+    float depth = INFINITY, dist = INFINITY, sil;
+    if (hit) {
+      dist = d.w + pl.flast[r];
+      depth = dist / sqrtf(xt * xt + yt * yt + 1.f);
+    }
+    if (st == ST_MISS) {
+      const float b = im.c[0] * d.x + im.c[1] * d.y + im.c[2] * d.z;
+      const float cc = im.c[0] * im.c[0] + im.c[1] * im.c[1] + im.c[2] * im.c[2];
+      sil = sqrtf(fmaxf(cc - b * b, 0.f)) - 1.f;
+    } else {
+      sil = fabsf(pl.rec_f[r]) - im.eps;
+    }
+    if (o.depth) o.depth[q] = depth;
+    if (o.dist) o.dist[q] = dist;
+    if (o.sil) o.sil[q] = sil;
+    if (o.status) o.status[q] = st;
+    if (o.nsteps) o.nsteps[q] = st == ST_MISS ? 0 : pl.n[r];
+    if (o.normal && !hit) { o.normal[3 * q] = 0.f; o.normal[3 * q + 1] = 0.f; o.normal[3 * q + 2] = 0.f; }
+    if (o.nraw) o.nraw[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  block_append(hit && o.want_hits, r, o.hits, o.hit_count);
+}
+
+// Normals from the six central-difference queries of each hit (Sec. 3.3).
+__global__ void k_normals(const RayPool pl, const ImgDesc* imgs, const int* hits, const int* hit_count,
+                          const float* fv, float delta, float* normal, float4* nraw) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= *hit_count) return;
+  const int r = hits[h];
+  const ImgDesc& im = imgs[pl.img[r]];
+  const int pix = r - im.slot_base - im.lvl_off[0];
+  const size_t q = (size_t)im.out_base + pix;
+  const float* f = fv + 6ll * h;
+  const float inv = 1.f / (2.f * delta);
+  const float nx = (f[0] - f[1]) * inv, ny = (f[2] - f[3]) * inv, nz = (f[4] - f[5]) * inv;
+  const float len = sqrtf(nx * nx + ny * ny + nz * nz);
+  if (nraw) nraw[q] = make_float4(nx, ny, nz, len);
+  if (normal) {
+    const float s = len > 0.f ? 1.f / len : 0.f;
+    normal[3 * q] = nx * s;
+    normal[3 * q + 1] = ny * s;
+    normal[3 * q + 2] = nz * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: gradient samples (Sec. 3.4 Eq. 2 first term; App. B.2)
+// ---------------------------------------------------------------------------
+struct PixSamples {
+  int nd, base, nn;      // depth records used, samples at records, normal samples
+};
+
+__device__ __forceinline__ PixSamples pixel_samples(const RayPool& pl, const ImgDesc& im, int r, size_t q,
+                                                    const SeedIn& in) {
+  PixSamples ps{0, 0, 0};
+  const uint8_t st = pl.st[r];
+  if (st == ST_MISS) return ps;
+  const float gd = in.g_depth ? in.g_depth[q] : 0.f;
+  const float gs = in.g_sil ? in.g_sil[q] : 0.f;
+  if (st == ST_HIT && gd != 0.f) {
+    for (int k = 0; k < im.K; ++k) ps.nd += (pl.rec_f[(size_t)k * pl.cap + r] != INFINITY) ? 1 : 0;
+  }
+  const int ns = (gs != 0.f && pl.rec_f[r] != INFINITY) ? 1 : 0;
+  ps.base = ps.nd > ns ? ps.nd : ns;
+  if (st == ST_HIT && in.g_normal && in.nraw) {
+    const float* g = in.g_normal + 3 * q;
+    if ((g[0] != 0.f || g[1] != 0.f || g[2] != 0.f) && in.nraw[q].w > 0.f) ps.nn = 6;
+  }
+  return ps;
+}
+
+__global__ __launch_bounds__(256) void k_samples_count(RayPool pl, const ImgDesc* imgs, const int* img_order,
+                                                       SeedIn in, int* bsum) {
+  __shared__ int red[256];
+  const int img = img_order[blockIdx.y];
+  const ImgDesc& im = imgs[img];
+  const int hw = im.H * im.W;
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  int c = 0;
+  if (pix < hw) {
+    const PixSamples ps = pixel_samples(pl, im, im.slot_base + im.lvl_off[0] + pix, (size_t)im.out_base + pix, in);
+    c = ps.base + ps.nn;
+  }
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// One workgroup: exclusive scan of the block sums in image order, restarting
+// the padding at every latent segment so that each segment starts at a
+// multiple of the adjoint tile.  seg_* are indexed by latent id.
+__global__ __launch_bounds__(1024) void k_samples_scan(const int* bsum, int n_img, int bpi, const int* img_order,
+                                                       const int* img_latent, int tile, int n_lat, int* boff,
+                                                       int* seg_base, int* seg_total, int* seg_padded,
+                                                       int* n_samples) {
+  __shared__ int buf[1024];
+  __shared__ int carry_s;
+  const int tid = threadIdx.x;
+  for (int l = tid; l < n_lat; l += 1024) { seg_base[l] = 0; seg_total[l] = 0; seg_padded[l] = 0; }
+  __syncthreads();
+  int pos = 0;              // running padded offset (uniform)
+  int i0 = 0;
+  while (i0 < n_img) {
+    const int lat = img_latent[img_order[i0]];
+    int i1 = i0;
+    while (i1 < n_img && img_latent[img_order[i1]] == lat) ++i1;
+    // scan blocks of images [i0, i1)
+    const int nb = (i1 - i0) * bpi;
+    const int b0 = i0 * bpi;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nb; c0 += 1024) {
+      const int v = (c0 + tid < nb) ? bsum[b0 + c0 + tid] : 0;
+      buf[tid] = v;
+      __syncthreads();
+      for (int off = 1; off < 1024; off <<= 1) {
+        const int x = tid >= off ? buf[tid - off] : 0;
+        __syncthreads();
+        buf[tid] += x;
+        __syncthreads();
+      }
+      const int carry = carry_s;
+      if (c0 + tid < nb) boff[b0 + c0 + tid] = pos + carry + buf[tid] - v;
+      __syncthreads();
+      if (tid == 1023) carry_s = carry + buf[1023];
+      __syncthreads();
+    }
+    const int total = carry_s;
+    const int padded = (total + tile - 1) / tile * tile;
+    if (tid == 0) { seg_base[lat] = pos; seg_total[lat] = total; seg_padded[lat] = padded; }
+    pos += padded;
+    i0 = i1;
+    __syncthreads();
+  }
+  if (tid == 0) *n_samples = pos;
+}
+
+__global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc* imgs, const int* img_order,
+                                                       SeedIn in, const int* boff, float4* samples,
+                                                       int* sample_lat) {
+  __shared__ int buf[256];
+  const int img = img_order[blockIdx.y];
+  const ImgDesc& im = imgs[img];
+  const int hw = im.H * im.W;
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  PixSamples ps{0, 0, 0};
+  int r = 0;
+  size_t q = 0;
+  if (pix < hw) {
+    r = im.slot_base + im.lvl_off[0] + pix;
+    q = (size_t)im.out_base + pix;
+    ps = pixel_samples(pl, im, r, q, in);
+  }
+  const int c = ps.base + ps.nn;
+  buf[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int x = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+    __syncthreads();
+    buf[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int o = boff[blockIdx.y * gridDim.x + blockIdx.x] + buf[threadIdx.x] - c;
+  if (c == 0) return;
+  const float4 d = pl.d[r];
+  const float cx = im.c[0], cy = im.c[1], cz = im.c[2];
+  const int V = pix / im.W, U = pix - V * im.W;
+  float3 dd;
+  float xt, yt;
+  level_ray(im, 0, U, V, dd, xt, yt);
+  const float gd = in.g_depth ? in.g_depth[q] : 0.f;
+  const float gs = in.g_sil ? in.g_sil[q] : 0.f;
+  const float dseed = im.alpha * gd / sqrtf(xt * xt + yt * yt + 1.f);
+  for (int k = 0; k < ps.base; ++k) {
+    const float tk = pl.rec_t[(size_t)k * pl.cap + r];
+    float seed = k < ps.nd ? dseed : 0.f;
+    if (k == 0 && gs != 0.f) {
+      const float f0 = pl.rec_f[r];
+      seed += gs * (f0 > 0.f ? 1.f : (f0 < 0.f ? -1.f : 0.f));
+    }
+    samples[o] = make_float4(fmaf(tk, d.x, cx), fmaf(tk, d.y, cy), fmaf(tk, d.z, cz), seed);
+    sample_lat[o] = im.latent;
+    ++o;
+  }
+  if (ps.nn) {
+    const float4 nr = in.nraw[q];
+    const float inv = 1.f / nr.w;
+    const float nx = nr.x * inv, ny = nr.y * inv, nz = nr.z * inv;
+    const float* g = in.g_normal + 3 * q;
+    const float gn = g[0] * nx + g[1] * ny + g[2] * nz;
+    const float gv[3] = {(g[0] - gn * nx) * inv, (g[1] - gn * ny) * inv, (g[2] - gn * nz) * inv};
+    const float dist = d.w + pl.flast[r];
+    const float p[3] = {fmaf(dist, d.x, cx), fmaf(dist, d.y, cy), fmaf(dist, d.z, cz)};
+    const float s2 = 1.f / (2.f * in.delta);
+    for (int j = 0; j < 6; ++j) {
+      const int ax = j >> 1;
+      float qv[3] = {p[0], p[1], p[2]};
+      qv[ax] = (j & 1) ? qv[ax] - in.delta : qv[ax] + in.delta;
+      const float seed = (j & 1) ? -gv[ax] * s2 : gv[ax] * s2;
+      samples[o] = make_float4(qv[0], qv[1], qv[2], seed);
+      sample_lat[o] = im.latent;
+      ++o;
+    }
+  }
+}
+
+// Padding samples (zero seed) at the end of each latent segment.
+__global__ void k_samples_pad(const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
+                              int* sample_lat) {
+  const int l = blockIdx.x;
+  const int b = seg_base[l], t = seg_total[l], p = seg_padded[l];
+  for (int i = t + threadIdx.x; i < p; i += blockDim.x) {
+    samples[b + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    sample_lat[b + i] = l;
+  }
+}
+
+// g_z[l] = W0_z^T S0 + Ws_z^T Ss, with S = sum over the latent's tiles (fixed order).
+__global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base,
+                                                   const int* seg_padded, int w0, int mg0, const float* W0z,
+                                                   int ws, int mgs, const float* Wsz, int L, float* gz) {
+  __shared__ float S0[512];
+  __shared__ float Ss[512];
+  const int l = blockIdx.x;
+  const int t0 = seg_base[l] / tile, t1 = (seg_base[l] + seg_padded[l]) / tile;
+  for (int n = threadIdx.x; n < 512; n += blockDim.x) {
+    float a = 0.f, b = 0.f;
+    for (int t = t0; t < t1; ++t) {
+      const float* pt = partial + (size_t)t * 4 * kmax;
+      for (int g = 0; g < mg0; ++g) a += (n < w0) ? pt[g * kmax + n] : 0.f;
+      if (Wsz)
+        for (int g = 0; g < mgs; ++g) b += (n < ws) ? pt[(2 + g) * kmax + n] : 0.f;
+    }
+    S0[n] = a;
+    Ss[n] = b;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+    float acc = 0.f;
+    for (int n = 0; n < w0; ++n) acc = fmaf(W0z[(size_t)n * L + j], S0[n], acc);
+    if (Wsz)
+      for (int n = 0; n < ws; ++n) acc = fmaf(Wsz[(size_t)n * L + j], Ss[n], acc);
+    gz[(size_t)l * L + j] = acc;
+  }
+}
+
+__global__ void k_fill_i32(int* p, int v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_rays, int* list,
+                       int* counter, hipStream_t s) {
+  if (n_img <= 0 || max_rays <= 0) return;
+  hipLaunchKernelGGL(k_init_level, dim3(nblk(max_rays, 256), n_img), dim3(256), 0, s, pl, imgs, imgs_list, list,
+                     counter);
+}
+void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_children,
+                  int child_lvl, int child_step, int* list, int* counter, hipStream_t s) {
+  if (n_img <= 0 || max_children <= 0) return;
+  hipLaunchKernelGGL(k_split, dim3(nblk(max_children, 256), n_img), dim3(256), 0, s, pl, imgs, imgs_list,
+                     child_lvl, child_step, list, counter);
+  hipLaunchKernelGGL(k_set_level, dim3(nblk(n_img, 256)), dim3(256), 0, s, imgs, imgs_list, n_img, child_lvl);
+}
+void launch_compact(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count,
+                    int max_items, int* out_list, int* out_count, unsigned long long* qcount, hipStream_t s) {
+  if (max_items <= 0) return;
+  unsigned g = nblk(max_items, 256);
+  if (g > 2048) g = 2048;
+  hipLaunchKernelGGL(k_compact, dim3(g), dim3(256), 0, s, pl, imgs, in_list, in_count, out_list, out_count, qcount);
+}
+void launch_finalize(const RayPool& pl, const ImgDesc* imgs, int n_img, int hw, const FinalizeOut& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nblk(hw, 256), n_img), dim3(256), 0, s, pl, imgs, o);
+}
+void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, const int* hit_count, int max_hits,
+                    const float* fv, float delta, float* normal, float4* nraw, hipStream_t s) {
+  if (max_hits <= 0) return;
+  hipLaunchKernelGGL(k_normals, dim3(nblk(max_hits, 256)), dim3(256), 0, s, pl, imgs, hits, hit_count, fv, delta,
+                     normal, nraw);
+}
+void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
+                    int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
+                    int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s) {
+  const int bpi = (int)nblk(hw, 256);
+  hipLaunchKernelGGL(k_samples_count, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, bsum);
+  hipLaunchKernelGGL(k_samples_scan, dim3(1), dim3(1024), 0, s, bsum, n_img, bpi, img_order, img_latent, tile, n_lat,
+                     boff, seg_base, seg_total, seg_padded, n_samples);
+  hipLaunchKernelGGL(k_samples_write, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, boff, samples,
+                     sample_lat);
+  hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
+                     sample_lat);
+}
+void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
+                        int* sample_lat, hipStream_t s) {
+  hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
+                     sample_lat);
+}
+void launch_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base, const int* seg_padded,
+                      int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs, const float* Wsz, int L,
+                      float* gz, hipStream_t s) {
+  hipLaunchKernelGGL(k_gz_reduce, dim3(n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base, seg_padded, w0, mg0,
+                     W0z, ws, mgs, Wsz, L, gz);
+}
+void launch_fill_i32(int* p, int v, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
+}
+void launch_fill_u64(unsigned long long* p, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3(nblk(n, 256)), dim3(256), 0, s, p, n);
+}
+
+}  // namespace dist
