@@ -1,0 +1,219 @@
+"""Benchmark of the MI355X sphere tracer (one JSON line on stdout).
+
+A step is one pass of the whole hot path over one batch: forward render of
+8 views x 4 latents = 32 images of 256x256 with the DeepSDF-scale decoder in
+bf16 (coarse-to-fine, aggressive marching, compaction, normals), the image
+loss (10 L1 depth + silhouette hinge + normal term, torch), and the backward
+pass (the paper's approximate gradient w.r.t. the latent codes).  Inputs are
+seeded synthetic decoders, latents and cameras, resident on the GPU before the
+timed region.  The same workload is also timed with the float32 plain tracer,
+and a single 256x256 image (the float32 workload) is timed for latency.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SDF queries/s + 256^2 fwd+bwd frames/s, BF16 vs FP32 plain; serving p99 ms"
+# algorithmic work per decoder query of the DeepSDF-scale decoder with the
+# latent folded into per-image biases: 1,573,376 multiply-adds
+FLOP_PER_QUERY = 2 * 1_573_376
+# backward per sample: the recompute (as a query) + the VJP through the hidden
+# layers (5 x 512x512 + 2 x 253x512 multiply-adds)
+FLOP_PER_SAMPLE = FLOP_PER_QUERY + 2 * (5 * 512 * 512 + 2 * 253 * 512)
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(n_views=8, n_lat=4, H=256, precision=1):
+    import torch
+    import dist_inputs as di
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    ctx = api.Context.from_spec(spec, Ws, bs)
+    cams = [di.front_camera(H, H)] if n_views == 1 else di.random_sphere_cameras(n_views, H, H)
+    Z = torch.tensor(di.make_latents(n_lat, spec.latent_dim, sigma=0.01), device="cuda")
+    prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=2, k_samples=1,
+                         precision=precision, want_normals=1)
+    tg = [di.sphere_target_maps(c, 0.5) for c in cams]
+    # targets per image (image i = view i // n_lat)
+    dt = torch.tensor(np.stack([tg[i // n_lat][0] for i in range(n_views * n_lat)]), device="cuda")
+    nt = torch.tensor(np.stack([tg[i // n_lat][1] for i in range(n_views * n_lat)]), device="cuda")
+    st = torch.tensor(np.stack([tg[i // n_lat][2] for i in range(n_views * n_lat)]), device="cuda")
+    return dict(ctx=ctx, cams=cams, Z=Z, prm=prm, targets=(dt, nt, st), n_img=n_views * n_lat)
+
+
+def step(w):
+    """forward + loss + backward; returns (g_z, per-image query tensor)."""
+    import torch
+    from paper_1911_13225_amd import api
+    Z = w["Z"].clone().requires_grad_(True)
+    out = api.dist_render_fwd(w["ctx"], w["cams"], Z, w["prm"], save=True)
+    depth = out["depth"].requires_grad_(True)
+    normal = out["normal"].requires_grad_(True)
+    sil = out["sil"].requires_grad_(True)
+    dt, nt, st = w["targets"]
+    L = api.render_loss(depth, normal, sil, dt, nt, st, w_d=10.0, w_s=1.0, w_n=1.0)
+    gd, gn, gs = torch.autograd.grad(L, (depth, normal, sil))
+    g_z = api.dist_render_bwd(w["ctx"], out["saved"], gd, gn, gs, n_latents=Z.shape[0])
+    out["saved"].free()
+    return g_z, out["queries"]
+
+
+def time_steps(w, steps, warmup):
+    import torch
+    from paper_1911_13225_amd import api
+    for _ in range(warmup):
+        step(w)
+    torch.cuda.synchronize()
+    api.dist_timing_enable(w["ctx"], True)
+    torch.cuda.synchronize()
+    qs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, q = step(w)
+        qs.append(q)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {name: api.dist_timing_read(w["ctx"], k) for k, name in enumerate(("march", "eval", "adjoint"))}
+    api.dist_timing_enable(w["ctx"], False)
+    queries = int(sum(int(q.sum()) for q in qs))
+    return dict(sec=t1 - t0, steps=steps, queries=queries, kern=kern)
+
+
+def kernel_summary(r, dtype):
+    """Algorithmic FLOP/s of each kernel class from live HIP-event timing."""
+    out = {}
+    for name, (launches, ms, rows) in r["kern"].items():
+        if launches == 0 or ms <= 0:
+            continue
+        fl = FLOP_PER_SAMPLE if name == "adjoint" else FLOP_PER_QUERY
+        out[name] = dict(launches=launches, ms_total=round(ms, 3), ms_avg=round(ms / launches, 4), rows=rows,
+                         tflops=round(rows * fl / (ms * 1e-3) / 1e12, 2))
+    return out
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle on a bounded sample of the benchmark workload."""
+    import dist_inputs as di
+    from oracle import dist_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    cams = di.random_sphere_cameras(1, 256, 256)
+    Z = di.make_latents(1, spec.latent_dim, sigma=0.01)
+    prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=2, k_samples=1, precision=0,
+                         want_normals=1)
+    rng = np.random.Generator(np.random.PCG64(77))
+    n_pix = 2048
+    total_q, total_s, rounds = 0, 0.0, 0
+    while total_s < seconds_target and rounds < 64:
+        pix = rng.choice(256 * 256, n_pix, replace=False)
+        t0 = time.perf_counter()
+        r = O.render(dec, Z, cams, [(0, 0)], prm, pixels=[pix])[0]
+        dt, nt, st = di.sphere_target_maps(cams[0], 0.5)
+        _, g_d, g_n, g_s = O.loss_and_grads(r, dt, nt, st, w_d=10.0, w_s=1.0, w_n=1.0)
+        O.backward(dec, Z, [r], [(0, 0)], prm, [(g_d, g_n, g_s)], want_theta=False)
+        total_s += time.perf_counter() - t0
+        total_q += r.queries
+        rounds += 1
+    return {"value": round(total_q / total_s, 1), "unit": "queries/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{rounds} x {n_pix} random pixels of one 256x256 view (with their coarse-to-fine "
+                      f"ancestors), FP64 fwd + normals + loss + backward; {total_q} march queries in "
+                      f"{total_s:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: the tracer has no multi-GPU path (requested --gpus {a.gpus}); "
+              "images and requests are independent and would shard by image across GPUs.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+
+    log("[bench] bf16 32-image workload")
+    w = build_workload(precision=1)
+    r = time_steps(w, a.steps, a.warmup)
+    ms_step = 1e3 * r["sec"] / r["steps"]
+    qps = r["queries"] / r["sec"]
+    fps = w["n_img"] * r["steps"] / r["sec"]
+    ks = kernel_summary(r, "bf16")
+    log("[bench] bf16", round(ms_step, 2), "ms/step", ks)
+
+    res = {"metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "8 views x 4 latents = 32 images of 256x256 per step, DeepSDF 8x512 decoder "
+                                  "(Kaiming seed 0), alpha 1.5, eps 5e-4, 50 steps, coarse-to-fine from 64x64, "
+                                  "K=1, normals, loss 10 L1 + silhouette + normal, backward to z",
+                      "global_batch": w["n_img"], "resolution": 256, "precision": "bf16"},
+           "frames_per_s": round(fps, 2), "queries_per_step": r["queries"] // r["steps"], "kernels": ks}
+    # roofline of the dominant kernel (by measured time)
+    dom = max(ks.items(), key=lambda kv: kv[1]["ms_total"])
+    name, k = dom
+    achieved = k["tflops"]
+    res["roofline"] = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"] / 1e12,
+                       "unit": "TFLOP/s", "frac": round(achieved / (PEAK["bf16"] / 1e12), 4), "traffic": None}
+    del w
+    torch.cuda.empty_cache()
+
+    if not a.no_fp32:
+        log("[bench] fp32 plain 32-image workload")
+        w = build_workload(precision=0)
+        r2 = time_steps(w, max(1, a.steps // 5), 1)
+        q2 = r2["queries"] / r2["sec"]
+        ks2 = kernel_summary(r2, "fp32")
+        res["fp32_plain"] = {"queries_per_s": round(q2, 1), "frames_per_s": round(w["n_img"] * r2["steps"] / r2["sec"], 2),
+                             "ms_per_step": round(1e3 * r2["sec"] / r2["steps"], 2), "kernels": ks2,
+                             "march_frac_of_fp32_peak": round(ks2["march"]["tflops"] / (PEAK["fp32"] / 1e12), 4)
+                             if "march" in ks2 else None}
+        res["speedup_bf16_vs_fp32"] = round(qps / q2, 2)
+        del w
+        torch.cuda.empty_cache()
+        log("[bench] single 256x256 image, fp32 and bf16")
+        single = {}
+        for prec, nm in ((0, "fp32"), (1, "bf16")):
+            w = build_workload(n_views=1, n_lat=1, precision=prec)
+            r3 = time_steps(w, 3, 1)
+            single[nm] = {"ms_per_frame": round(1e3 * r3["sec"] / r3["steps"], 2),
+                          "queries_per_s": round(r3["queries"] / r3["sec"], 1)}
+            del w
+        res["single_image"] = single
+
+    if not a.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

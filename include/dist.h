@@ -245,6 +245,22 @@ int dist_submit(dist_ctx* ctx, const dist_request* req, uint64_t* ticket);
  * DIST_PENDING if still running, DIST_ENOTFOUND for unknown tickets. */
 int dist_poll(dist_ctx* ctx, uint64_t ticket, dist_result* res, int64_t timeout_us);
 
+/* ---- kernel timing ------------------------------------------------------
+ * When enabled, the library records a pair of HIP events on the caller's
+ * stream around every launch of its decoder kernels.  dist_timing_read
+ * synchronises on those events and returns, for one kernel class, the
+ * number of launches and their summed duration since timing was enabled.
+ * kernel: 0 = march step (decoder + march update), 1 = plain decoder queries
+ * (normals, dist_sdf_eval), 2 = adjoint (backward recompute + VJP). */
+typedef struct {
+  int64_t launches;
+  double ms;
+  int64_t rows;      /* decoder evaluations processed (rays, points or samples) */
+} dist_kernel_time;
+
+int dist_timing_enable(dist_ctx* ctx, int on);
+int dist_timing_read(dist_ctx* ctx, int32_t kernel, dist_kernel_time* out);
+
 /* Thread-local message describing the last error. */
 const char* dist_last_error(void);
 

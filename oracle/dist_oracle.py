@@ -502,8 +502,8 @@ def loss_and_grads(r: Render, depth_t, normal_t, sil_t, w_d=10.0, w_s=1.0, w_n=0
     L_d = w_d / HW * np.abs(diff).sum()
     # a term whose weight S* or 1 - S* is zero contributes zero even where S is
     # infinite (pixels left out of a partial render)
-    L_s = w_s / HW * (np.where(St > 0, St * np.maximum(S, 0), 0.0)
-                      + np.where(St < 1, (1 - St) * np.maximum(-S, 0), 0.0)).sum()
+    L_s = w_s / HW * (St * np.maximum(np.where(St > 0, S, 0.0), 0)
+                      + (1 - St) * np.maximum(-np.where(St < 1, S, 0.0), 0)).sum()
     nt = np.asarray(normal_t, np.float64)
     L_n = w_n / HW * (-(r.normal * nt).sum(-1) * m).sum()
     g_depth = w_d / HW * np.sign(diff)

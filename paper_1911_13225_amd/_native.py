@@ -53,6 +53,10 @@ class dist_request(ctypes.Structure):
                 ("z_out", ctypes.c_void_p)]
 
 
+class dist_kernel_time(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("rows", ctypes.c_int64)]
+
+
 class dist_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("latency_ns", ctypes.c_int64), ("queries", ctypes.c_int64),
                 ("final_loss", ctypes.c_float)]
@@ -76,6 +80,8 @@ _SIGS = [
                                     ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
     ("dist_submit", ctypes.c_int, [_P, ctypes.POINTER(dist_request), ctypes.POINTER(ctypes.c_uint64)]),
     ("dist_poll", ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(dist_result), ctypes.c_int64]),
+    ("dist_timing_enable", ctypes.c_int, [_P, ctypes.c_int]),
+    ("dist_timing_read", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(dist_kernel_time)]),
     ("dist_last_error", ctypes.c_char_p, []),
     ("dist_version", ctypes.c_char_p, []),
 ]

@@ -76,6 +76,21 @@ struct dist_ctx {
   std::vector<Workspace*> ws_free;
   dist::Server* server = nullptr;
   std::mutex server_mu;
+  // kernel timing (see dist_timing_enable)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[3];
+  size_t tev_used[3] = {0, 0, 0};
+  unsigned long long* d_rows = nullptr;   // device accumulators of processed rows [3]
+};
+
+// Event pair around one launch of kernel class k (no-op unless timing is on).
+struct TimedLaunch {
+  dist_ctx* ctx;
+  int k;
+  hipStream_t st;
+  hipEvent_t end = nullptr;
+  TimedLaunch(dist_ctx* c, int kk, hipStream_t s, const int* rows = nullptr, int mul = 1);
+  ~TimedLaunch();
 };
 
 struct dist_saved {

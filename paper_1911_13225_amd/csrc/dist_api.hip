@@ -264,8 +264,72 @@ extern "C" int dist_destroy(dist_ctx* ctx) {
   serve_shutdown(ctx);
   (void)hipDeviceSynchronize();
   ws_release_all(ctx);
+  for (int k = 0; k < 3; ++k)
+    for (auto& pr : ctx->tev[k]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
   for (auto& o : ctx->owned) ctx_free(ctx, o.first, o.second);
   delete ctx;
+  return DIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+__global__ void k_acc_rows(const int* rows, int mul, unsigned long long* acc) {
+  if (threadIdx.x == 0) *acc += (unsigned long long)(*rows) * (unsigned long long)mul;
+}
+
+TimedLaunch::TimedLaunch(dist_ctx* c, int kk, hipStream_t s, const int* rows, int mul) : ctx(c), k(kk), st(s) {
+  if (!ctx->timing) return;
+  if (rows && ctx->d_rows) hipLaunchKernelGGL(k_acc_rows, dim3(1), dim3(64), 0, st, rows, mul, ctx->d_rows + k);
+  auto& v = ctx->tev[k];
+  if (ctx->tev_used[k] == v.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    v.push_back({a, b});
+  }
+  auto& pr = v[ctx->tev_used[k]++];
+  (void)hipEventRecord(pr.first, st);
+  end = pr.second;
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (end) (void)hipEventRecord(end, st);
+}
+
+extern "C" int dist_timing_enable(dist_ctx* ctx, int on) {
+  if (!ctx) return dist_set_error(DIST_EINVAL, "null context");
+  HIPCHK(hipDeviceSynchronize());
+  if (!ctx->d_rows) {
+    int rc = ctx_alloc(ctx, (void**)&ctx->d_rows, 3 * sizeof(unsigned long long));
+    if (rc) return rc;
+    ctx->owned.push_back({ctx->d_rows, 3 * sizeof(unsigned long long)});
+  }
+  HIPCHK(hipMemset(ctx->d_rows, 0, 3 * sizeof(unsigned long long)));
+  HIPCHK(hipDeviceSynchronize());
+  ctx->timing = on != 0;
+  for (int k = 0; k < 3; ++k) ctx->tev_used[k] = 0;
+  return DIST_OK;
+}
+
+extern "C" int dist_timing_read(dist_ctx* ctx, int32_t kernel, dist_kernel_time* out) {
+  if (!ctx || !out || kernel < 0 || kernel > 2) return dist_set_error(DIST_EINVAL, "bad argument");
+  double ms = 0.0;
+  for (size_t i = 0; i < ctx->tev_used[kernel]; ++i) {
+    auto& pr = ctx->tev[kernel][i];
+    HIPCHK(hipEventSynchronize(pr.second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, pr.first, pr.second));
+    ms += t;
+  }
+  unsigned long long rows = 0;
+  if (ctx->d_rows) HIPCHK(hipMemcpy(&rows, ctx->d_rows + kernel, sizeof rows, hipMemcpyDeviceToHost));
+  out->launches = (int64_t)ctx->tev_used[kernel];
+  out->ms = ms;
+  out->rows = (int64_t)rows;
   return DIST_OK;
 }
 
@@ -529,7 +593,10 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
     const long long rays = (long long)n_img * (hw >> (2 * lv));
     ma.list = w->list[n & 1];
     ma.count = w->counters + n;
-    launch_march(prec, ma, mlp_grid(ctx, rays, prec), st);
+    {
+      TimedLaunch tl(ctx, 0, st, ma.count, 1);
+      launch_march(prec, ma, mlp_grid(ctx, rays, prec), st);
+    }
     int* nxt = w->list[(n + 1) & 1];
     int* ncnt = w->counters + n + 1;
     if (n % 3 == 2 && lv > 0)
@@ -570,7 +637,10 @@ int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trac
     ea.imgs = w->imgs;
     ea.delta = prm->normal_delta;
     ea.f_out = w->fv;
-    launch_eval(np, ea, mlp_grid(ctx, 6LL * n_img * hw, np), st);
+    {
+      TimedLaunch tl(ctx, 1, st, fo.hit_count, 6);
+      launch_eval(np, ea, mlp_grid(ctx, 6LL * n_img * hw, np), st);
+    }
     launch_normals(w->pool, w->imgs, w->hits, fo.hit_count, n_img * hw, w->fv, prm->normal_delta, normal, w->nraw,
                    st);
   }
@@ -674,10 +744,14 @@ static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int 
   aa.mask_ws = b->mask_ws;
   aa.partial = b->partial;
   const int grid = mlp_grid(ctx, b->cap_samples, prec);
-  launch_adjoint(prec, aa, grid, st);
+  {
+    TimedLaunch tl(ctx, 2, st, b->n_samples, 1);
+    launch_adjoint(prec, aa, grid, st);
+  }
   const int w0 = ctx->wpad[0];
   const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
-  launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->seg_base, b->seg_padded, n_lat, w0, w0 == 128 ? 2 : 1,
+  launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg_base, b->seg_padded, n_lat,
+                   w0, w0 == 128 ? 2 : 1,
                    ctx->w0z, ws, ws == 128 ? 2 : 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
   HIPCHK(hipGetLastError());
   return DIST_OK;
@@ -738,7 +812,10 @@ extern "C" int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* 
     ea.n = n;
     ea.n_lat = n_latents;
     ea.f_out = f;
-    launch_eval(precision, ea, mlp_grid(ctx, n, precision), st);
+    {
+      TimedLaunch tl(ctx, 1, st);
+      launch_eval(precision, ea, mlp_grid(ctx, n, precision), st);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) rc = dist_set_error(DIST_EHIP, "eval launch failed: %s", hipGetErrorString(e));
   }

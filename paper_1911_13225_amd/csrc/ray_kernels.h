@@ -39,9 +39,9 @@ void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order
                     int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s);
 void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
                         int* sample_lat, hipStream_t s);
-void launch_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base, const int* seg_padded,
-                      int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs, const float* Wsz, int L,
-                      float* gz, hipStream_t s);
+void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
+                      const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,
+                      const float* Wsz, int L, float* gz, hipStream_t s);
 void launch_fill_i32(int* p, int v, int n, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 

@@ -414,18 +414,37 @@ __global__ void k_samples_pad(const int* seg_base, const int* seg_total, const i
   }
 }
 
-// g_z[l] = W0_z^T S0 + Ws_z^T Ss, with S = sum over the latent's tiles (fixed order).
+// g_z[l] = W0_z^T S0 + Ws_z^T Ss with S = sum over the latent's tiles.  The
+// sum runs in two fixed-order passes: k_gz_fold adds each run of 64 tiles into
+// the run's first tile, k_gz_reduce adds the run heads.  Bitwise reproducible.
+constexpr int kFold = 64;
+
+__global__ __launch_bounds__(512) void k_gz_fold(float* partial, int kmax, int tile, const int* seg_base,
+                                                 const int* seg_padded) {
+  const int l = blockIdx.y;
+  const int t0 = seg_base[l] / tile, nt = seg_padded[l] / tile;
+  const int c0 = blockIdx.x * kFold;
+  if (c0 >= nt) return;
+  const int c1 = min(c0 + kFold, nt);
+  const int width = 4 * kmax;
+  for (int i = threadIdx.x; i < width; i += blockDim.x) {
+    float a = 0.f;
+    for (int t = c0; t < c1; ++t) a += partial[(size_t)(t0 + t) * width + i];
+    partial[(size_t)(t0 + c0) * width + i] = a;
+  }
+}
+
 __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base,
                                                    const int* seg_padded, int w0, int mg0, const float* W0z,
                                                    int ws, int mgs, const float* Wsz, int L, float* gz) {
   __shared__ float S0[512];
   __shared__ float Ss[512];
   const int l = blockIdx.x;
-  const int t0 = seg_base[l] / tile, t1 = (seg_base[l] + seg_padded[l]) / tile;
+  const int t0 = seg_base[l] / tile, nt = seg_padded[l] / tile;
   for (int n = threadIdx.x; n < 512; n += blockDim.x) {
     float a = 0.f, b = 0.f;
-    for (int t = t0; t < t1; ++t) {
-      const float* pt = partial + (size_t)t * 4 * kmax;
+    for (int c = 0; c < nt; c += kFold) {
+      const float* pt = partial + (size_t)(t0 + c) * 4 * kmax;
       for (int g = 0; g < mg0; ++g) a += (n < w0) ? pt[g * kmax + n] : 0.f;
       if (Wsz)
         for (int g = 0; g < mgs; ++g) b += (n < ws) ? pt[(2 + g) * kmax + n] : 0.f;
@@ -503,9 +522,11 @@ void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, co
   hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
                      sample_lat);
 }
-void launch_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base, const int* seg_padded,
-                      int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs, const float* Wsz, int L,
-                      float* gz, hipStream_t s) {
+void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
+                      const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,
+                      const float* Wsz, int L, float* gz, hipStream_t s) {
+  hipLaunchKernelGGL(k_gz_fold, dim3(nblk(max_tiles, kFold), n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base,
+                     seg_padded);
   hipLaunchKernelGGL(k_gz_reduce, dim3(n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base, seg_padded, w0, mg0,
                      W0z, ws, mgs, Wsz, L, gz);
 }
