@@ -750,9 +750,9 @@ static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int 
   }
   const int w0 = ctx->wpad[0];
   const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
+  // every wave covers all rows of a tile, so each column sum has one row group
   launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg_base, b->seg_padded, n_lat,
-                   w0, w0 == 128 ? 2 : 1,
-                   ctx->w0z, ws, ws == 128 ? 2 : 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
+                   w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
   HIPCHK(hipGetLastError());
   return DIST_OK;
 }

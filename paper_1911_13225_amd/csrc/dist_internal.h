@@ -20,7 +20,7 @@ namespace dist {
 constexpr int kMaxLayers = 12;
 constexpr int kMaxK = 4;
 constexpr int kMaxWidth = 512;
-constexpr int kThreads = 512;          // 8 waves of 64 per MLP workgroup
+constexpr int kThreads = 256;          // 4 waves of 64 per MLP workgroup (one per SIMD)
 
 enum : uint8_t { ST_ACTIVE = 0, ST_HIT = 1, ST_MISS = 2, ST_ESCAPED = 3, ST_UNCONVERGED = 4 };
 

@@ -71,6 +71,15 @@ template <int P> struct Sm {
 
 extern __shared__ __attribute__((aligned(16))) char dyn_smem[];
 
+// An opaque copy of a lane-dependent value: addresses derived from it are
+// computed where they are used instead of being hoisted out of the layer and
+// tile loops (which would keep dozens of them alive across the GEMM).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+
 // ---------------------------------------------------------------------------
 // Layer 0: h0 = relu(W0_p p + (b0 + W0_z z)), float32 VALU, written to LDS.
 // ---------------------------------------------------------------------------
@@ -80,7 +89,8 @@ __device__ __forceinline__ float layer0_pre(const NetDev& net, const float* b0l,
 }
 
 template <int P>
-__device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid) {
+__device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_) {
+  const int tid = opaque(tid_);
   constexpr int M = Cfg<P>::M, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
   const int cpr = N0 / EPC;
@@ -115,6 +125,19 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
 // ---------------------------------------------------------------------------
 // Wave-level GEMM: acc[i][j] (m-tile mt0+i, n-tile nt0+j) = sum_k A[n][k] B[k][m]
 // ---------------------------------------------------------------------------
+// The k loop is software pipelined: weight fragments (from L2) are requested
+// kDepth k-steps before use in rotating register sets, and the activation
+// fragments of the next k-step (from LDS) are requested one step ahead, so the
+// MFMA pipe never waits on a single load round trip.  ksteps must be a
+// multiple of kDepth (the padded widths are multiples of 128).
+constexpr int kDepth = 4;
+
+template <class Frag, int MTW, int NTW>
+struct Pipe {
+  Frag a[kDepth][NTW];
+  Frag b[2][MTW];
+};
+
 template <int MTW, int NTW>
 __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& s, const bf16x8* __restrict__ wp,
                                           int ksteps, int nt0, int mt0, int lane) {
@@ -136,25 +159,36 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
     arow[i] = s.act + (size_t)m * s.rowb;
     sw[i] = m & 15;
   }
-  bf16x8 an[NTW];
+  Pipe<bf16x8, MTW, NTW> p;
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) an[j] = wrow[j][0];
-  for (int ks = 0; ks < ksteps; ++ks) {
-    bf16x8 a[NTW];
+  for (int d = 0; d < kDepth; ++d)
 #pragma unroll
-    for (int j = 0; j < NTW; ++j) a[j] = an[j];
-    if (ks + 1 < ksteps) {
+    for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)d * 64];
 #pragma unroll
-      for (int j = 0; j < NTW; ++j) an[j] = wrow[j][(size_t)(ks + 1) * 64];
+  for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const bf16x8*)(arow[i] + (((g) ^ sw[i]) << 4));
+  for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      const int ks = k0 + d;
+      const int cb = d & 1, nb = cb ^ 1;
+      {
+        const int kn = min(ks + 1, ksteps - 1);     // unconditional (the last one is redundant)
+#pragma unroll
+        for (int i = 0; i < MTW; ++i)
+          p.b[nb][i] = *(const bf16x8*)(arow[i] + (((2 * kn + g) ^ sw[i]) << 4));
+      }
+#pragma unroll
+      for (int i = 0; i < MTW; ++i)
+#pragma unroll
+        for (int j = 0; j < NTW; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p.a[d][j], p.b[cb][i], acc[i][j], 0, 0, 0);
+      {
+        const int kn = min(ks + kDepth, ksteps - 1);
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)kn * 64];
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
-    bf16x8 b[MTW];
-#pragma unroll
-    for (int i = 0; i < MTW; ++i) b[i] = *(const bf16x8*)(arow[i] + (((2 * ks + g) ^ sw[i]) << 4));
-#pragma unroll
-    for (int i = 0; i < MTW; ++i)
-#pragma unroll
-      for (int j = 0; j < NTW; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[i], acc[i][j], 0, 0, 0);
   }
 }
 
@@ -170,6 +204,13 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
     for (int j = 0; j < NTW; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  const bf16x8* wrow[NTW];
+  const bf16x8* lrow[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) {
+    wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
+    lrow[j] = X3 ? wlo + (size_t)(nt0 + j) * ksteps * 64 + lane : nullptr;
+  }
   const char* arow[MTW];
   int sw[MTW];
 #pragma unroll
@@ -178,31 +219,52 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
     arow[i] = s.act + (size_t)m * s.rowb;
     sw[i] = m & 15;
   }
-  for (int ks = 0; ks < ksteps; ++ks) {
-    bf16x8 ah[NTW], al[NTW];
+  Pipe<bf16x8, MTW, NTW> ph, pl;
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d)
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
-      const size_t off = ((size_t)(nt0 + j) * ksteps + ks) * 64 + lane;
-      ah[j] = wp[off];
-      if constexpr (X3) al[j] = wlo[off];
-    }
-    const int c = 2 * (2 * ks + g);
-    bf16x8 bh[MTW], bl[MTW];
-#pragma unroll
-    for (int i = 0; i < MTW; ++i) {
-      bh[i] = *(const bf16x8*)(arow[i] + ((c ^ sw[i]) << 4));
-      if constexpr (X3) bl[i] = *(const bf16x8*)(arow[i] + (((c + 1) ^ sw[i]) << 4));
+      ph.a[d][j] = wrow[j][(size_t)d * 64];
+      if constexpr (X3) pl.a[d][j] = lrow[j][(size_t)d * 64];
     }
 #pragma unroll
-    for (int i = 0; i < MTW; ++i)
+  for (int i = 0; i < MTW; ++i) {
+    ph.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g) ^ sw[i]) << 4));
+    if constexpr (X3) pl.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g + 1) ^ sw[i]) << 4));
+  }
+  for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
 #pragma unroll
-      for (int j = 0; j < NTW; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[j], bh[i], acc[i][j], 0, 0, 0);
-        if constexpr (X3) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[j], bh[i], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[j], bl[i], acc[i][j], 0, 0, 0);
+    for (int d = 0; d < kDepth; ++d) {
+      const int ks = k0 + d;
+      const int cb = d & 1, nb = cb ^ 1;
+      {
+        const int c = 2 * (2 * min(ks + 1, ksteps - 1) + g);
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) {
+          ph.b[nb][i] = *(const bf16x8*)(arow[i] + ((c ^ sw[i]) << 4));
+          if constexpr (X3) pl.b[nb][i] = *(const bf16x8*)(arow[i] + (((c + 1) ^ sw[i]) << 4));
         }
       }
+#pragma unroll
+      for (int i = 0; i < MTW; ++i)
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[d][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
+          if constexpr (X3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl.a[d][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[d][j], pl.b[cb][i], acc[i][j], 0, 0, 0);
+          }
+        }
+      {
+        const int kn = min(ks + kDepth, ksteps - 1);
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+          ph.a[d][j] = wrow[j][(size_t)kn * 64];
+          if constexpr (X3) pl.a[d][j] = lrow[j][(size_t)kn * 64];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
+    }
   }
 }
 
@@ -227,27 +289,38 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
     arow[i] = s.act + (size_t)m * s.rowb;
     sw[i] = m & 15;
   }
-  f32x4 an[NTW];
+  Pipe<f32x4, MTW, NTW> p;
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) an[j] = wrow[j][0];
-  for (int ks = 0; ks < ksteps; ++ks) {
-    f32x4 a[NTW];
+  for (int d = 0; d < kDepth; ++d)
 #pragma unroll
-    for (int j = 0; j < NTW; ++j) a[j] = an[j];
-    if (ks + 1 < ksteps) {
+    for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)d * 64];
 #pragma unroll
-      for (int j = 0; j < NTW; ++j) an[j] = wrow[j][(size_t)(ks + 1) * 64];
+  for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const f32x4*)(arow[i] + (((g) ^ sw[i]) << 4));
+  for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+      const int ks = k0 + d;
+      const int cb = d & 1, nb = cb ^ 1;
+      {
+        const int kn = min(ks + 1, ksteps - 1);
+#pragma unroll
+        for (int i = 0; i < MTW; ++i)
+          p.b[nb][i] = *(const f32x4*)(arow[i] + (((2 * kn + g) ^ sw[i]) << 4));
+      }
+#pragma unroll
+      for (int sidx = 0; sidx < 4; ++sidx)
+#pragma unroll
+        for (int i = 0; i < MTW; ++i)
+#pragma unroll
+          for (int j = 0; j < NTW; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(p.a[d][j][sidx], p.b[cb][i][sidx], acc[i][j], 0, 0, 0);
+      {
+        const int kn = min(ks + kDepth, ksteps - 1);
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)kn * 64];
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
-    f32x4 b[MTW];
-#pragma unroll
-    for (int i = 0; i < MTW; ++i) b[i] = *(const f32x4*)(arow[i] + (((2 * ks + g) ^ sw[i]) << 4));
-#pragma unroll
-    for (int sidx = 0; sidx < 4; ++sidx)
-#pragma unroll
-      for (int i = 0; i < MTW; ++i)
-#pragma unroll
-        for (int j = 0; j < NTW; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j][sidx], b[i][sidx], acc[i][j], 0, 0, 0);
   }
 }
 
@@ -292,8 +365,9 @@ __device__ __forceinline__ void store4(const Sm<P>& s, int m, int n, int g, cons
 
 template <int P, int MTW, int NTW>
 __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
-                                         const Sm<P>& s, int nt0, int mt0, int nw, int mg, int lane) {
+                                         const Sm<P>& s, int nt0, int mt0, int nw, int mg, int lane_) {
   constexpr int M = Cfg<P>::M;
+  const int lane = opaque(lane_);
   const int r = lane & 31, g = lane >> 5;
   if (mode == EP_ACT || mode == EP_ACT_MASK) {
 #pragma unroll
@@ -438,11 +512,16 @@ __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCt
 }
 
 // Run one layer (GEMM + barrier + epilogue + barrier) for an output width N
-// (128, 256 or 512 after padding): 8 waves split N into WN groups and the
-// tile rows into 8/WN groups.
+// (128, 256 or 512 after padding): the 4 waves split N into 4 groups of N/4
+// outputs and each covers all rows of the tile.
 template <int P, int MTW, int NTW, int WN>
 __device__ __forceinline__ void layer_run(int mode, const NetDev& net, const EpCtx& ec, const Sm<P>& s,
-                                          const void* wp, const void* wlo, int ksteps, int wave, int lane) {
+                                          const void* wp, const void* wlo, int ksteps, int wave_, int lane_) {
+  // lane-dependent addressing is recomputed per layer (see opaque())
+  const int t = opaque((int)threadIdx.x);
+  const int wave = t >> 6, lane = t & 63;
+  (void)wave_;
+  (void)lane_;
   const int nw = wave % WN, mg = wave / WN;
   const int nt0 = nw * NTW, mt0 = mg * MTW;
   f32x16 acc[MTW][NTW];
@@ -464,9 +543,9 @@ __device__ __forceinline__ int layer(int mode, const NetDev& net, const EpCtx& e
                                      const void* wp, const void* wlo, int N, int K, int wave, int lane) {
   constexpr int MT = Cfg<P>::MT;
   const int ksteps = K / (P ? 16 : 8);
-  if (N == 512) { layer_run<P, MT, 2, 8>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 8; }
-  if (N == 256) { layer_run<P, MT, 1, 8>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 8; }
-  layer_run<P, MT / 2, 1, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane);
+  if (N == 512) { layer_run<P, MT, 4, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 4; }
+  if (N == 256) { layer_run<P, MT, 2, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 4; }
+  layer_run<P, MT, 1, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane);
   return 4;
 }
 
@@ -491,7 +570,7 @@ __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0
                            int tid, int wave, int lane, unsigned* mask, bool adj) {
   layer0_fill<P>(net, bias0_lat, s, tid);
   __syncthreads();
-  int wn = 8;
+  int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
     EpCtx ec = fwd_ctx(net, biasS_lat, l);
     ec.mask = mask;
@@ -511,7 +590,7 @@ __device__ __forceinline__ float sdf_from_m(float4 p, float m) {
 // March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_march(MarchArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_march(MarchArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -588,7 +667,7 @@ __global__ __launch_bounds__(kThreads) void k_march(MarchArgs a) {
 // Plain decoder queries (explicit points, or the 6-point normal stencil)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_eval(EvalArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_eval(EvalArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -638,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void k_eval(EvalArgs a) {
 // and at the skip layer (Sskip); dL/dz = W0_z^T S0 + Wskip_z^T Sskip.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint(AdjArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
