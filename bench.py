@@ -143,6 +143,90 @@ def cpu_baseline(seconds_target=15.0):
                       f"{total_s:.1f} s"}
 
 
+def serving_run(rate=10.0, n_req=24, zopt_iters=50, seed=4000):
+    """Poisson stream of mixed requests through dist_submit/dist_poll."""
+    import torch
+    import dist_inputs as di
+    from paper_1911_13225_amd import api, _native as N
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    ctx = api.Context.from_spec(spec, Ws, bs, hbm_budget=64 << 30)
+    stream = di.poisson_requests(rate, n_req, seed=seed)
+    prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=2, k_samples=1, precision=1,
+                         want_normals=1)
+    reqs = []
+    for q in stream:
+        cams = di.random_sphere_cameras(q["n_views"], q["res"], q["res"], base_seed=q["latent_seed"])
+        z = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=q["latent_seed"])[0],
+                         device="cuda")
+        if q["kind"] == "zopt":
+            tg = [di.sphere_target_maps(c, 0.5) for c in cams]
+            td = torch.tensor(np.stack([np.where(np.isfinite(t[0]), t[0], 0.0) for t in tg]), device="cuda")
+            ts = torch.tensor(np.stack([t[2] for t in tg]), device="cuda")
+            r = api.ServeRequest(N.REQ_ZOPT, cams, z, prm, want_normals=False, targets=(td, ts),
+                                 iters=zopt_iters, lr=1e-2)
+        else:
+            r = api.ServeRequest(N.REQ_RENDER, cams, z, prm, want_normals=True)
+        reqs.append((q, r))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, r in reqs:
+        delay = q["t_arrive"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        api.dist_submit(ctx, r)
+    lat = {"render": [], "zopt": []}
+    queries = 0
+    for q, r in reqs:
+        res = api.dist_poll(ctx, r, 600_000_000)
+        assert res is not None and res["status"] == 0, res
+        lat[q["kind"]].append(res["latency_ms"])
+        queries += res["queries"]
+    wall = time.perf_counter() - t0
+    ctx.close()
+    allv = np.array(lat["render"] + lat["zopt"])
+    out = {"rate_req_per_s": rate, "requests": n_req, "completed_req_per_s": round(n_req / wall, 2),
+           "march_queries_per_s": round(queries / wall, 1), "p50_ms": round(float(np.percentile(allv, 50)), 2),
+           "p99_ms": round(float(np.percentile(allv, 99)), 2), "wall_s": round(wall, 2),
+           "mix": f"resolution uniform over {{64,128,256,512}}^2, 1-8 views, 10% z-opt jobs of {zopt_iters} "
+                  "Adam iterations; bf16; 64 GB admission budget"}
+    for k, v in lat.items():
+        if v:
+            out[k] = {"n": len(v), "p50_ms": round(float(np.percentile(v, 50)), 2),
+                      "p99_ms": round(float(np.percentile(v, 99)), 2)}
+    return out
+
+
+def kernel_micro(n=1 << 21):
+    """One decoder launch over n random points per precision (no march tail)."""
+    import torch
+    import dist_inputs as di
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    ctx = api.Context.from_spec(spec, Ws, bs)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    P = (torch.rand(n, 3, device="cuda", generator=g) - 0.5) * 1.2
+    lat = torch.zeros(n, dtype=torch.int32, device="cuda")
+    Z = torch.zeros(1, spec.latent_dim, device="cuda")
+    out = {}
+    for prec, name, peak in ((1, "bf16", PEAK["bf16"]), (2, "split_bf16", PEAK["bf16"] / 3), (0, "fp32", PEAK["fp32"])):
+        for _ in range(2):
+            api.dist_sdf_eval(ctx, P, lat, Z, prec)
+        torch.cuda.synchronize()
+        api.dist_timing_enable(ctx, True)
+        reps = 3
+        for _ in range(reps):
+            api.dist_sdf_eval(ctx, P, lat, Z, prec)
+        launches, ms, rows = api.dist_timing_read(ctx, 1)
+        api.dist_timing_enable(ctx, False)
+        tf = n * launches * FLOP_PER_QUERY / (ms * 1e-3) / 1e12
+        out[name] = {"points": n, "ms": round(ms / launches, 3), "tflops": round(tf, 1),
+                     "frac_of_peak": round(tf * 1e12 / peak, 4)}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +234,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=10.0)
+    ap.add_argument("--serve-requests", type=int, default=24)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: the tracer has no multi-GPU path (requested --gpus {a.gpus}); "
@@ -159,6 +246,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
+
+    log("[bench] decoder kernel alone")
+    micro = kernel_micro()
+    log("[bench] micro", micro)
 
     log("[bench] bf16 32-image workload")
     w = build_workload(precision=1)
@@ -176,7 +267,8 @@ def main():
                                   "(Kaiming seed 0), alpha 1.5, eps 5e-4, 50 steps, coarse-to-fine from 64x64, "
                                   "K=1, normals, loss 10 L1 + silhouette + normal, backward to z",
                       "global_batch": w["n_img"], "resolution": 256, "precision": "bf16"},
-           "frames_per_s": round(fps, 2), "queries_per_step": r["queries"] // r["steps"], "kernels": ks}
+           "frames_per_s": round(fps, 2), "queries_per_step": r["queries"] // r["steps"], "kernels": ks,
+           "decoder_kernel_alone": micro}
     # roofline of the dominant kernel (by measured time)
     dom = max(ks.items(), key=lambda kv: kv[1]["ms_total"])
     name, k = dom
@@ -208,6 +300,11 @@ def main():
                           "queries_per_s": round(r3["queries"] / r3["sec"], 1)}
             del w
         res["single_image"] = single
+
+    if not a.no_serve:
+        log("[bench] serving stream")
+        res["serving"] = serving_run(a.serve_rate, a.serve_requests)
+        log("[bench] serving", res["serving"])
 
     if not a.no_cpu:
         log("[bench] cpu baseline (oracle)")

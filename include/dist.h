@@ -169,7 +169,10 @@ int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n_views,
  * (seeds +-(I - n n^T) dL/dn / (|n| 2 delta)) -- and accumulate
  *   g_z  device [n_latents, latent_dim]  (overwritten)
  *   g_W, g_b  host arrays of n_layers device pointers shaped like the weights
- *        (overwritten); pass NULL to skip the weight gradient.
+ *        [out][in] and biases [out] (overwritten); pass both NULL to skip the
+ *        weight gradient.  Asking for it synchronises the host once (to size
+ *        the per-row capture buffers) and costs roughly one more decoder
+ *        pass per sample.
  * The reduction order is fixed, so results are bitwise reproducible. */
 int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved,
                     const float* g_depth, const float* g_normal, const float* g_sil,

@@ -159,10 +159,25 @@ def dist_render_fwd(ctx: Context, cams, z: torch.Tensor, params, pairs=None, sav
     return out
 
 
-def dist_render_bwd(ctx: Context, saved: Saved, g_depth=None, g_normal=None, g_sil=None, n_latents=None):
-    """Paper gradient w.r.t. the latent codes; returns g_z [n_latents, L]."""
+def _theta_buffers(ctx: Context):
+    gW = [torch.empty_like(w) for w in ctx._Ws]
+    gb = [torch.empty_like(b) for b in ctx._bs]
+    Wp = (ctypes.c_void_p * len(gW))(*[t.data_ptr() for t in gW])
+    bp = (ctypes.c_void_p * len(gb))(*[t.data_ptr() for t in gb])
+    return gW, gb, Wp, bp
+
+
+def dist_render_bwd(ctx: Context, saved: Saved, g_depth=None, g_normal=None, g_sil=None, n_latents=None,
+                    want_theta: bool = False):
+    """Paper gradient w.r.t. the latent codes (g_z [n_latents, L]); with
+    want_theta also w.r.t. the decoder weights: returns (g_z, gW list, gb list)."""
     g_z = torch.empty(n_latents, ctx.latent_dim, device="cuda")
     args = [None if g is None else g.detach().float().contiguous() for g in (g_depth, g_normal, g_sil)]
+    if want_theta:
+        gW, gb, Wp, bp = _theta_buffers(ctx)
+        check(ctx.lib.dist_render_bwd(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_z), Wp, bp,
+                                      _stream()))
+        return g_z, gW, gb
     check(ctx.lib.dist_render_bwd(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_z), None, None,
                                   _stream()))
     return g_z
@@ -179,13 +194,18 @@ def dist_sdf_eval(ctx: Context, points: torch.Tensor, latent_ids: torch.Tensor, 
     return f
 
 
-def dist_sdf_vjp(ctx: Context, points, latent_ids, seeds, z, precision: int):
+def dist_sdf_vjp(ctx: Context, points, latent_ids, seeds, z, precision: int, want_theta: bool = False):
     n = points.shape[0]
     g_z = torch.empty(z.shape[0], ctx.latent_dim, device=points.device)
     pts = points.detach().float().contiguous()
     ids = latent_ids.to(torch.int32).contiguous()
     sd = seeds.detach().float().contiguous()
     zc = z.detach().float().contiguous()
+    if want_theta:
+        gW, gb, Wp, bp = _theta_buffers(ctx)
+        check(ctx.lib.dist_sdf_vjp(ctx.handle, _ptr(pts), _ptr(ids), _ptr(sd), _ptr(zc), z.shape[0], n,
+                                   int(precision), _ptr(g_z), Wp, bp, _stream()))
+        return g_z, gW, gb
     check(ctx.lib.dist_sdf_vjp(ctx.handle, _ptr(pts), _ptr(ids), _ptr(sd), _ptr(zc), z.shape[0], n, int(precision),
                                _ptr(g_z), None, None, _stream()))
     return g_z
@@ -226,3 +246,65 @@ def render_loss(depth, normal, sil, depth_t, normal_t, sil_t, w_d=10.0, w_s=1.0,
     if w_n:
         L = L + w_n / HW * (-(normal * normal_t).sum(-1) * fg).sum()
     return L
+
+
+# ----------------------------------------------------------------------------
+# serving
+# ----------------------------------------------------------------------------
+class ServeRequest:
+    """Host-side holder of one submitted request and the buffers it references."""
+
+    def __init__(self, kind, cams, z, params, want_normals=True, targets=None, iters=0, lr=1e-2,
+                 w_depth=10.0, w_sil=1.0):
+        n = len(cams)
+        H, W = int(cams[0].H), int(cams[0].W)
+        dev = z.device
+        self.kind = kind
+        self.cams_c = (N.dist_camera * n)(*[make_camera(c) for c in cams])
+        self.z = z.detach().float().contiguous()
+        self.depth = torch.empty(n, H, W, device=dev)
+        self.sil = torch.empty(n, H, W, device=dev)
+        self.normal = torch.zeros(n, H, W, 3, device=dev) if want_normals else None
+        self.status = torch.empty(n, H, W, dtype=torch.uint8, device=dev)
+        self.targets = None if targets is None else tuple(t.float().contiguous() for t in targets)
+        self.z_out = torch.empty_like(self.z) if kind == N.REQ_ZOPT else None
+        r = N.dist_request()
+        r.kind = kind
+        r.n_views = n
+        r.cams = self.cams_c
+        r.prm = make_params(params)
+        r.prm.want_normals = 1 if want_normals else 0
+        r.z = self.z.data_ptr()
+        r.depth = self.depth.data_ptr()
+        r.sil = self.sil.data_ptr()
+        r.normal = self.normal.data_ptr() if want_normals else None
+        r.status = self.status.data_ptr()
+        if kind == N.REQ_ZOPT:
+            r.target_depth = self.targets[0].data_ptr()
+            r.target_sil = self.targets[1].data_ptr()
+            r.iters = int(iters)
+            r.lr, r.w_depth, r.w_sil = float(lr), float(w_depth), float(w_sil)
+            r.z_out = self.z_out.data_ptr()
+        self.c = r
+        self.ticket = None
+        self.result = None
+
+
+def dist_submit(ctx: Context, req: ServeRequest):
+    """Queue a request (buffers must be ready: the server reads them on its own stream)."""
+    torch.cuda.current_stream().synchronize()
+    t = ctypes.c_uint64()
+    check(ctx.lib.dist_submit(ctx.handle, ctypes.byref(req.c), ctypes.byref(t)))
+    req.ticket = t.value
+    return t.value
+
+
+def dist_poll(ctx: Context, req: ServeRequest, timeout_us: int = -1):
+    """Wait for a request; returns a dict (status, latency_ms, queries, final_loss) or None if pending."""
+    res = N.dist_result()
+    rc = check(ctx.lib.dist_poll(ctx.handle, ctypes.c_uint64(req.ticket), ctypes.byref(res), int(timeout_us)))
+    if rc == N.DIST_PENDING:
+        return None
+    req.result = dict(status=int(res.status), latency_ms=res.latency_ns / 1e6, queries=int(res.queries),
+                      final_loss=float(res.final_loss))
+    return req.result

@@ -96,12 +96,20 @@ struct TimedLaunch {
 struct dist_saved {
   dist_ctx* ctx = nullptr;
   Workspace* ws = nullptr;
+  const float* z = nullptr;          // the forward's latent codes (caller-owned)
   int n_img = 0, hw = 0, n_lat = 0;
   dist_trace_params prm{};
   std::vector<int> img_latent, order;
 };
 
 int dist_set_error(int code, const char* fmt, ...);
+
+#define HIPCHK_S(expr)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return dist_set_error(DIST_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
 int ctx_alloc(dist_ctx* ctx, void** p, size_t bytes);
 void ctx_free(dist_ctx* ctx, void* p, size_t bytes);
 int slots_per_image(int hw, int levels);

@@ -535,6 +535,15 @@ static void fill_desc(ImgDesc& d, const dist_camera& c, const dist_trace_params*
   d.out_base = out_base;
 }
 
+namespace dist {
+int validate_params_ext(const dist_trace_params* p, int H, int W) { return validate_params(p, H, W); }
+int validate_camera_ext(const dist_camera& c, const dist_trace_params* p) { return validate_camera(c, p); }
+void fill_desc_ext(ImgDesc& d, const dist_camera& c, const dist_trace_params* p, int latent, int slot_base,
+                   int out_base) {
+  fill_desc(d, c, p, latent, slot_base, out_base);
+}
+}  // namespace dist
+
 int slots_per_image(int hw, int levels) {
   int s = 0;
   for (int l = 0; l <= levels; ++l) s += hw >> (2 * l);
@@ -588,6 +597,7 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
   ma.imgs = w->imgs;
   ma.bias0_lat = w->bias0_lat;
   ma.biasS_lat = w->biasS_lat;
+  ma.qcount = w->qcount;
   for (int n = 0; n < prm->max_steps; ++n) {
     const int lv = std::max(L - n / 3, 0);
     const long long rays = (long long)n_img * (hw >> (2 * lv));
@@ -601,7 +611,7 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
     int* ncnt = w->counters + n + 1;
     if (n % 3 == 2 && lv > 0)
       launch_split(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * (lv - 1)), lv - 1, n + 1, nxt, ncnt, st);
-    launch_compact(w->pool, w->imgs, w->list[n & 1], w->counters + n, (int)rays, nxt, ncnt, w->qcount, st);
+    launch_compact(w->pool, w->imgs, w->list[n & 1], w->counters + n, (int)rays, nxt, ncnt, nullptr, st);
   }
   HIPCHK(hipGetLastError());
   return DIST_OK;
@@ -622,7 +632,7 @@ int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trac
   fo.hit_count = w->counters + prm->max_steps + 4;
   fo.want_hits = prm->want_normals ? 1 : 0;
   launch_fill_i32(fo.hit_count, 0, 1, st);
-  launch_finalize(w->pool, w->imgs, n_img, hw, fo, st);
+  launch_finalize(w->pool, w->imgs, nullptr, n_img, hw, fo, st);
   if (prm->want_normals) {
     // normal queries: float32, or split bf16 (float32-class accuracy) on the bf16 paths
     const int np = prm->precision == DIST_FP32 ? kPrecF32 : kPrecSplit;
@@ -708,6 +718,7 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
     s->hw = hw;
     s->n_lat = n_latents;
     s->prm = *prm;
+    s->z = z;
     s->img_latent = li;
     s->order = order;
     *saved = s;
@@ -731,6 +742,15 @@ extern "C" int dist_saved_free(dist_saved* s) {
 // ReLU pattern must match the float32 network; a bf16 recompute flips units
 // near zero) and back-propagates in bf16.
 static int adj_prec(int render_prec) { return render_prec == DIST_FP32 ? kPrecF32 : kPrecSplit; }
+
+static int reduce_only(dist_ctx* ctx, BwdSpace* b, int n_lat, float* g_z, hipStream_t st) {
+  const int w0 = ctx->wpad[0];
+  const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
+  launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg_base, b->seg_padded, n_lat,
+                   w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
 
 static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, int n_lat, float* g_z,
                                   hipStream_t st) {
@@ -757,11 +777,93 @@ static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int 
   return DIST_OK;
 }
 
+__global__ void k_zero_f32(float* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+// Weight gradient: adjoint over chunks of tiles capturing h and Delta per row,
+// then one fixed-order accumulation kernel per layer.  Synchronises once to
+// read the number of samples.
+static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const float* z, float* const* g_W,
+                     float* const* g_b, hipStream_t st) {
+  for (int l = 0; l < ctx->nl; ++l)
+    if (!g_W[l] || !g_b[l]) return dist_set_error(DIST_EINVAL, "null weight-gradient pointer for layer %d", l);
+  int ns = 0;
+  HIPCHK(hipMemcpyAsync(&ns, b->n_samples, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int l = 0; l < ctx->nl; ++l) {
+    hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, st, g_W[l],
+                       (long long)ctx->out_dims[l] * ctx->in_dims[l]);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, st, g_b[l], (long long)ctx->out_dims[l]);
+  }
+  const int tile = b->tile;
+  const int tiles = ns / tile;
+  if (tiles == 0) return DIST_OK;
+  const int chunk = std::max(1, std::min(tiles, 32768 / tile));
+  const size_t rows = (size_t)chunk * tile;
+  const size_t rstride = (size_t)(ctx->nl - 1) * ctx->kmax;
+  const size_t bytes = rows * rstride * 4 * 2 + rows * 4 + 1024;
+  void* mem = nullptr;
+  int rc = ctx_alloc(ctx, &mem, bytes);
+  if (rc) return rc;
+  float* hbuf = (float*)mem;
+  float* dbuf = hbuf + rows * rstride;
+  float* gmbuf = dbuf + rows * rstride;
+  AdjArgs aa{};
+  aa.net = ctx->net[prec];
+  aa.bias0_lat = w->bias0_lat;
+  aa.biasS_lat = w->biasS_lat;
+  aa.samples = b->samples;
+  aa.sample_lat = b->sample_lat;
+  aa.n_samples = b->n_samples;
+  aa.mask_ws = b->mask_ws;
+  aa.partial = b->partial;
+  aa.hbuf = hbuf;
+  aa.dbuf = dbuf;
+  aa.gmbuf = gmbuf;
+  for (int t0 = 0; t0 < tiles; t0 += chunk) {
+    const int t1 = std::min(tiles, t0 + chunk);
+    aa.tile_begin = t0;
+    aa.tile_end = t1;
+    {
+      TimedLaunch tl(ctx, 2, st);
+      launch_adjoint(prec, aa, std::max(1, std::min(t1 - t0, ctx->n_cu)), st);
+    }
+    for (int l = 0; l < ctx->nl; ++l) {
+      DwArgs d{};
+      d.layer = l;
+      d.nl = ctx->nl;
+      d.skip = ctx->skip;
+      d.L = ctx->L;
+      d.nh = l > 0 ? ctx->out_dims[l - 1] : 0;
+      d.kmax = ctx->kmax;
+      d.rstride = (int)rstride;
+      d.rows = (t1 - t0) * tile;
+      d.out = ctx->out_dims[l];
+      d.in = ctx->in_dims[l];
+      d.hbuf = hbuf;
+      d.dbuf = dbuf;
+      d.gmbuf = gmbuf;
+      d.pts = b->samples + (size_t)t0 * tile;
+      d.lat = b->sample_lat + (size_t)t0 * tile;
+      d.z = z;
+      d.gW = g_W[l];
+      d.gb = g_b[l];
+      launch_dw(d, st);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  ctx_free(ctx, mem, bytes);
+  return DIST_OK;
+}
+
 extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const float* g_depth, const float* g_normal,
                                const float* g_sil, float* g_z, float* const* g_W, float* const* g_b, void* stream) {
   if (!ctx || !saved || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
   if (saved->ctx != ctx) return dist_set_error(DIST_EINVAL, "saved state belongs to another context");
-  if (g_W || g_b) return dist_set_error(DIST_EINVAL, "weight gradients are not available in this build");
+  if ((g_W == nullptr) != (g_b == nullptr)) return dist_set_error(DIST_EINVAL, "pass both g_W and g_b, or neither");
   hipStream_t st = (hipStream_t)stream;
   Workspace* w = saved->ws;
   const int prec = adj_prec(saved->prm.precision);
@@ -783,6 +885,11 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, tile, in, b->bsum, b->boff,
                  b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st);
   HIPCHK(hipGetLastError());
+  if (g_W) {
+    rc = run_theta(ctx, w, b, prec, saved->z, g_W, g_b, st);
+    if (rc) return rc;
+    return reduce_only(ctx, b, n_lat, g_z, st);
+  }
   return run_adjoint_and_reduce(ctx, w, b, prec, n_lat, g_z, st);
 }
 
@@ -830,7 +937,7 @@ extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* l
   if (n < 0 || n > (1LL << 28)) return dist_set_error(DIST_EINVAL, "n out of range");
   if (n_latents < 1) return dist_set_error(DIST_EINVAL, "n_latents must be positive");
   if (precision < 0 || precision > 2) return dist_set_error(DIST_EINVAL, "bad precision");
-  if (g_W || g_b) return dist_set_error(DIST_EINVAL, "weight gradients are not available in this build");
+  if ((g_W == nullptr) != (g_b == nullptr)) return dist_set_error(DIST_EINVAL, "pass both g_W and g_b, or neither");
   precision = adj_prec(precision);
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipStreamSynchronize(st));
@@ -889,7 +996,12 @@ extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* l
     HIPCHK(hipMemcpyAsync(b->seg_total, stt.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->seg_padded, sp.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(b->n_samples, &np, 4, hipMemcpyHostToDevice, st));
-    rc = run_adjoint_and_reduce(ctx, w, b, precision, n_latents, g_z, st);
+    if (g_W) {
+      rc = run_theta(ctx, w, b, precision, z, g_W, g_b, st);
+      if (!rc) rc = reduce_only(ctx, b, n_latents, g_z, st);
+    } else {
+      rc = run_adjoint_and_reduce(ctx, w, b, precision, n_latents, g_z, st);
+    }
     HIPCHK(hipStreamSynchronize(st));
   }
   ws_put(ctx, w);

@@ -74,6 +74,7 @@ struct MarchArgs {
   const float* biasS_lat;          // [n_lat][wpad_skip]
   const int* list;                 // active ray slots
   const int* count;                // number of entries in list
+  unsigned long long* qcount;      // per-image decoder queries (or null)
 };
 
 struct EvalArgs {
@@ -102,11 +103,31 @@ struct AdjArgs {
   const int* n_samples;            // device count (multiple of the tile size)
   unsigned* mask_ws;               // per-workgroup ReLU mask scratch
   float* partial;                  // [tile][2][2][kmax] column sums (S0, Sskip) x m-groups
+  // weight gradient (optional): tiles [tile_begin, tile_end) write, per row,
+  // h_l (post-ReLU) and Delta_l = seed * dm/d(pre-activation of layer l) for
+  // every hidden layer, [row][nl-1][kmax], plus the row's seed factor gm
+  float* hbuf;
+  float* dbuf;
+  float* gmbuf;
+  int tile_begin, tile_end;
 };
 
 // Precision codes of the decoder kernels: 0 float32, 1 bfloat16, 2 split
 // bfloat16 (x = hi + lo, products hi*hi + lo*hi + hi*lo, float32 accumulation).
 constexpr int kPrecF32 = 0, kPrecBF16 = 1, kPrecSplit = 2;
+
+struct DwArgs {
+  int layer, nl, skip, L, nh, kmax, rstride, rows, out, in;
+  const float* hbuf;
+  const float* dbuf;
+  const float* gmbuf;
+  const float4* pts;
+  const int* lat;
+  const float* z;
+  float* gW;
+  float* gb;
+};
+void launch_dw(const DwArgs& a, hipStream_t s);
 
 int mlp_tile_rows(int precision);                 // rays per MLP tile
 int adj_tile_rows(int precision);                 // samples per adjoint tile

@@ -89,7 +89,8 @@ __device__ __forceinline__ float layer0_pre(const NetDev& net, const float* b0l,
 }
 
 template <int P>
-__device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_) {
+__device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_,
+                                            float* hcap = nullptr, int rstride = 0) {
   const int tid = opaque(tid_);
   constexpr int M = Cfg<P>::M, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
@@ -102,6 +103,10 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
     float v[EPC];
 #pragma unroll
     for (int e = 0; e < EPC; ++e) v[e] = fmaxf(layer0_pre(net, b0l, n + e, p), 0.f);
+    if (hcap) {
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) hcap[(size_t)m * rstride + n + e] = v[e];
+    }
     if constexpr (P == 1) {
       bf16x8 w;
 #pragma unroll
@@ -161,9 +166,11 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
   }
   Pipe<bf16x8, MTW, NTW> p;
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d)
+  for (int d = 0; d < kDepth; ++d) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)d * 64];
+    __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
+  }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const bf16x8*)(arow[i] + (((g) ^ sw[i]) << 4));
   for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
@@ -221,12 +228,14 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
   }
   Pipe<bf16x8, MTW, NTW> ph, pl;
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d)
+  for (int d = 0; d < kDepth; ++d) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
       ph.a[d][j] = wrow[j][(size_t)d * 64];
       if constexpr (X3) pl.a[d][j] = lrow[j][(size_t)d * 64];
     }
+    __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
+  }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
     ph.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g) ^ sw[i]) << 4));
@@ -291,9 +300,11 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
   }
   Pipe<f32x4, MTW, NTW> p;
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d)
+  for (int d = 0; d < kDepth; ++d) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)d * 64];
+    __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
+  }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const f32x4*)(arow[i] + (((g) ^ sw[i]) << 4));
   for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
@@ -343,6 +354,9 @@ struct EpCtx {
   int which;                // 0: S0, 1: Sskip, -1: none
   bool write_act;
   int kmax;
+  float* hrow;              // weight-gradient capture: h of this layer, row stride rstride (or null)
+  float* drow;              // weight-gradient capture: Delta of this layer (or null)
+  int rstride;
 };
 
 template <int P>
@@ -396,6 +410,7 @@ __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCt
             v[e] = fmaxf(x, 0.f);
           }
           store4<P>(s, m, n, g, v);
+          if (ec.hrow) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(v[0], v[1], v[2], v[3]);
         }
         if (mode == EP_ACT_MASK) {
           bits |= __shfl_xor(bits, 32);
@@ -431,6 +446,7 @@ __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCt
             const float wl = net.wlast[n + e];
             sum = fmaf(wl, fmaxf(x, 0.f), sum);
             v[e] = x > 0.f ? wl : 0.f;           // d m / d(pre-activation)
+            if (ec.hrow) ec.hrow[(size_t)m * ec.rstride + n + e] = fmaxf(x, 0.f);
           }
           if (mode == EP_LAST_ADJ) store4<P>(s, m, n, g, v, true);
         }
@@ -473,6 +489,14 @@ __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCt
           float v[4] = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
           store4<P>(s, m, nb + 8 * q + 4 * g, g, v, true);
         }
+      }
+      if (ec.drow) {
+        const float w = s.gm[m];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          *(float4*)(ec.drow + (size_t)m * ec.rstride + nb + 8 * q + 4 * g) =
+              make_float4(w * acc[i][j][4 * q], w * acc[i][j][4 * q + 1], w * acc[i][j][4 * q + 2],
+                          w * acc[i][j][4 * q + 3]);
       }
     }
   }
@@ -567,13 +591,18 @@ __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_l
 // s.part and returns the number of partial groups.
 template <int P>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat, const Sm<P>& s,
-                           int tid, int wave, int lane, unsigned* mask, bool adj) {
-  layer0_fill<P>(net, bias0_lat, s, tid);
+                           int tid, int wave, int lane, unsigned* mask, bool adj, float* hcap = nullptr) {
+  const int rstride = (net.nl - 1) * net.kmax;
+  layer0_fill<P>(net, bias0_lat, s, tid, hcap, rstride);
   __syncthreads();
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
     EpCtx ec = fwd_ctx(net, biasS_lat, l);
     ec.mask = mask;
+    if (hcap) {
+      ec.hrow = hcap + (size_t)l * net.kmax;
+      ec.rstride = rstride;
+    }
     const bool last = (l == net.nl - 2);
     const int mode = last ? (adj ? EP_LAST_ADJ : EP_LAST) : (adj ? EP_ACT_MASK : EP_ACT);
     wn = layer<P>(mode, net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l], wave, lane);
@@ -659,6 +688,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       pl.st[r] = st;
       pl.n[r] = (uint8_t)(n + 1);
     }
+    if (a.qcount && tid < M) {
+      // queries of this step per image, one atomic per distinct image in a wave
+      const int r = s.rid[tid];
+      const bool valid = r >= 0;
+      const int img = valid ? a.pool.img[r] : -1;
+      unsigned long long todo = __ballot(valid);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int li = __shfl(img, leader);
+        const unsigned long long same = __ballot(valid && img == li);
+        if (lane == leader) atomicAdd(&a.qcount[li], (unsigned long long)__popcll(same));
+        todo &= ~same;
+      }
+    }
     __syncthreads();
   }
 }
@@ -725,7 +768,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   const int count = *a.n_samples;
   const int ntmax = net.kmax / 32;
   unsigned* mask = a.mask_ws + (size_t)blockIdx.x * (size_t)(net.nl) * M * ntmax;
-  for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
+  const bool theta = a.hbuf != nullptr;
+  const int t_end = theta ? min(a.tile_end, (count + M - 1) / M) : (count + M - 1) / M;
+  const int rstride = (net.nl - 1) * net.kmax;
+  for (int tile = (theta ? a.tile_begin : 0) + blockIdx.x; tile < t_end; tile += gridDim.x) {
+    const size_t row0 = theta ? (size_t)(tile - a.tile_begin) * M : 0;
+    float* hcap = theta ? a.hbuf + row0 * rstride : nullptr;
     if (tid < M) {
       const int idx = tile * M + tid;
       const float4 smp = a.samples[idx];
@@ -734,14 +782,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.lat[tid] = a.sample_lat[idx];
     }
     __syncthreads();
-    const int wn = mlp_forward<P>(net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, mask, true);
+    const int wn = mlp_forward<P>(net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, mask, true, hcap);
     if (tid < M) {
       float m = net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
       const float th = tanhf(m);
       s.gm[tid] = s.fval[tid] * 0.05f * (1.f - th * th);
+      if (theta) a.gmbuf[row0 + tid] = s.gm[tid];
     }
     __syncthreads();
+    if (theta) {
+      // Delta of the last hidden layer: gm * w_last * [h > 0]
+      const int ll = net.nl - 2, W = net.wpad[ll];
+      for (int i = tid; i < M * W; i += kThreads) {
+        const int m = i / W, n = i - m * W;
+        const size_t o = (row0 + m) * rstride + (size_t)ll * net.kmax + n;
+        a.dbuf[o] = a.hbuf[o] > 0.f ? s.gm[m] * net.wlast[n] : 0.f;
+      }
+    }
     float* part = a.partial + (size_t)tile * 4 * net.kmax;
     for (int l = net.nl - 2; l >= 1; --l) {
       EpCtx ec{};
@@ -753,9 +811,70 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       ec.kmax = net.kmax;
       ec.which = (l - 1 == 0) ? 0 : ((l - 1 == net.skip) ? 1 : -1);
       ec.write_act = (l - 1 != 0);
+      if (theta) {
+        ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
+        ec.rstride = rstride;
+      }
       layer<P>(EP_VJP, net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l], wave, lane);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of one layer from captured rows (fixed summation order):
+//   gW[n][k] += sum_r Delta_l[r][n] * in_l(r, k),  gb[n] += sum_r Delta_l[r][n]
+// in_l is [z, p] for layer 0, [h, z, p] for the skip layer, h_{l-1} otherwise;
+// for the output layer Delta is the row's seed factor gm and in = h_{nl-2}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dw_in(const DwArgs& a, int r, int k) {
+  const size_t base = (size_t)r * a.rstride;
+  const int L = a.L;
+  if (a.layer == 0) {
+    if (k < L) return a.z[(size_t)a.lat[r] * L + k];
+    return (&a.pts[r].x)[k - L];
+  }
+  if (a.layer == a.skip) {
+    if (k < a.nh) return a.hbuf[base + (size_t)(a.layer - 1) * a.kmax + k];
+    if (k < a.nh + L) return a.z[(size_t)a.lat[r] * L + (k - a.nh)];
+    return (&a.pts[r].x)[k - a.nh - L];
+  }
+  return a.hbuf[base + (size_t)(a.layer - 1) * a.kmax + k];
+}
+
+__device__ __forceinline__ float dw_delta(const DwArgs& a, int r, int n) {
+  if (a.layer == a.nl - 1) return a.gmbuf[r];
+  return a.dbuf[(size_t)r * a.rstride + (size_t)a.layer * a.kmax + n];
+}
+
+__global__ __launch_bounds__(256) void k_dw(DwArgs a) {
+  __shared__ float Ds[32][17];
+  __shared__ float Is[32][17];
+  const int n0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+  const int tn = threadIdx.x >> 4, tk = threadIdx.x & 15;
+  const int n = n0 + tn, k = k0 + tk;
+  float acc = 0.f, accb = 0.f;
+  for (int r0 = 0; r0 < a.rows; r0 += 32) {
+    for (int i = threadIdx.x; i < 32 * 16; i += 256) {
+      const int rr = i >> 4, c = i & 15;
+      const int r = r0 + rr;
+      Ds[rr][c] = (r < a.rows && n0 + c < a.out) ? dw_delta(a, r, n0 + c) : 0.f;
+      Is[rr][c] = (r < a.rows && k0 + c < a.in) ? dw_in(a, r, k0 + c) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < 32; ++rr) {
+      acc = fmaf(Ds[rr][tn], Is[rr][tk], acc);
+      accb += Ds[rr][tn];
+    }
+    __syncthreads();
+  }
+  if (n < a.out && k < a.in) a.gW[(size_t)n * a.in + k] += acc;
+  if (blockIdx.x == 0 && tk == 0 && n < a.out) a.gb[n] += accb;
+}
+
+void launch_dw(const DwArgs& a, hipStream_t st) {
+  dim3 grid((a.in + 15) / 16, (a.out + 15) / 16);
+  hipLaunchKernelGGL(k_dw, grid, dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,13 @@ struct FinalizeOut {
   int want_hits;
 };
 
+// One image that starts rays this tick: split into level `lvl` (split = 1) or
+// (re)started at its coarsest level `lvl` (split = 0); its new rays occupy
+// positions [begin, begin + count) of the tick's new-ray range.
+struct AdvEntry {
+  int img, lvl, step, split, begin, count;
+};
+
 struct SeedIn {
   const float* g_depth;
   const float* g_normal;
@@ -31,17 +38,26 @@ void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_
                   int child_lvl, int child_step, int* list, int* counter, hipStream_t s);
 void launch_compact(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count,
                     int max_items, int* out_list, int* out_count, unsigned long long* qcount, hipStream_t s);
-void launch_finalize(const RayPool& pl, const ImgDesc* imgs, int n_img, int hw, const FinalizeOut& o, hipStream_t s);
+void launch_finalize(const RayPool& pl, const ImgDesc* imgs, const int* imgs_list, int n_img, int hw,
+                     const FinalizeOut& o, hipStream_t s);
 void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, const int* hit_count, int max_hits,
                     const float* fv, float delta, float* normal, float4* nraw, hipStream_t s);
 void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
                     int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
-                    int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s);
+                    int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s,
+                    int lat_fixed = 0);
 void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
                         int* sample_lat, hipStream_t s);
 void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
                       const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,
-                      const float* Wsz, int L, float* gz, hipStream_t s);
+                      const float* Wsz, int L, float* gz, hipStream_t s, int lat0 = 0);
+void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s);
+void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
+                    int* out_count, const AdvEntry* table, const int* hdr, int* img_active,
+                    unsigned long long* qcount, int grid, hipStream_t s);
+void launch_zopt_loss(const float* depth, const float* sil, const float* depth_t, const float* sil_t, int n,
+                      float inv_hw, float w_d, float w_s, float* g_depth, float* g_sil, float* loss, hipStream_t s);
+void launch_adam(float* z, float* m, float* v, const float* g, int L, float lr, int t, hipStream_t s);
 void launch_fill_i32(int* p, int v, int n, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 

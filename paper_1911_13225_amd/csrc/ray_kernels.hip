@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_compact(RayPool pl, const ImgDesc* imgs
       keep = pl.st[r] == ST_ACTIVE && lvl == im.cur_level;
     }
     // per-image query counts, one atomic per distinct image in the wave
-    unsigned long long todo = __ballot(valid);
+    unsigned long long todo = qcount ? __ballot(valid) : 0ull;
     while (todo) {
       const int leader = __ffsll((long long)todo) - 1;
       const int li = __shfl(img, leader);
@@ -176,8 +176,9 @@ __global__ __launch_bounds__(256) void k_compact(RayPool pl, const ImgDesc* imgs
 // Finalise level-0 rays into the output maps (Sec. 3.3, App. A.3).
 // grid: (blocks over H*W, n_images)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* imgs, FinalizeOut o) {
-  const int img = blockIdx.y;
+__global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* imgs, const int* imgs_list,
+                                                  FinalizeOut o) {
+  const int img = imgs_list ? imgs_list[blockIdx.y] : blockIdx.y;
   const ImgDesc& im = imgs[img];
   const int hw = im.H * im.W;
   const int pix = blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,8 +290,8 @@ __global__ __launch_bounds__(256) void k_samples_count(RayPool pl, const ImgDesc
 // the padding at every latent segment so that each segment starts at a
 // multiple of the adjoint tile.  seg_* are indexed by latent id.
 __global__ __launch_bounds__(1024) void k_samples_scan(const int* bsum, int n_img, int bpi, const int* img_order,
-                                                       const int* img_latent, int tile, int n_lat, int* boff,
-                                                       int* seg_base, int* seg_total, int* seg_padded,
+                                                       const int* img_latent, int lat_fixed, int tile, int n_lat,
+                                                       int* boff, int* seg_base, int* seg_total, int* seg_padded,
                                                        int* n_samples) {
   __shared__ int buf[1024];
   __shared__ int carry_s;
@@ -300,9 +301,9 @@ __global__ __launch_bounds__(1024) void k_samples_scan(const int* bsum, int n_im
   int pos = 0;              // running padded offset (uniform)
   int i0 = 0;
   while (i0 < n_img) {
-    const int lat = img_latent[img_order[i0]];
+    const int lat = img_latent ? img_latent[img_order[i0]] : lat_fixed;
     int i1 = i0;
-    while (i1 < n_img && img_latent[img_order[i1]] == lat) ++i1;
+    while (i1 < n_img && (img_latent ? img_latent[img_order[i1]] : lat_fixed) == lat) ++i1;
     // scan blocks of images [i0, i1)
     const int nb = (i1 - i0) * bpi;
     const int b0 = i0 * bpi;
@@ -420,8 +421,8 @@ __global__ void k_samples_pad(const int* seg_base, const int* seg_total, const i
 constexpr int kFold = 64;
 
 __global__ __launch_bounds__(512) void k_gz_fold(float* partial, int kmax, int tile, const int* seg_base,
-                                                 const int* seg_padded) {
-  const int l = blockIdx.y;
+                                                 const int* seg_padded, int lat0) {
+  const int l = lat0 + blockIdx.y;
   const int t0 = seg_base[l] / tile, nt = seg_padded[l] / tile;
   const int c0 = blockIdx.x * kFold;
   if (c0 >= nt) return;
@@ -436,10 +437,10 @@ __global__ __launch_bounds__(512) void k_gz_fold(float* partial, int kmax, int t
 
 __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base,
                                                    const int* seg_padded, int w0, int mg0, const float* W0z,
-                                                   int ws, int mgs, const float* Wsz, int L, float* gz) {
+                                                   int ws, int mgs, const float* Wsz, int L, float* gz, int lat0) {
   __shared__ float S0[512];
   __shared__ float Ss[512];
-  const int l = blockIdx.x;
+  const int l = lat0 + blockIdx.x;
   const int t0 = seg_base[l] / tile, nt = seg_padded[l] / tile;
   for (int n = threadIdx.x; n < 512; n += blockDim.x) {
     float a = 0.f, b = 0.f;
@@ -460,6 +461,130 @@ __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kma
       for (int n = 0; n < ws; ++n) acc = fmaf(Wsz[(size_t)n * L + j], Ss[n], acc);
     gz[(size_t)l * L + j] = acc;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Serving: one pass that builds the next pooled active list from (a) the rays
+// still active in the previous list, (b) the children of images that split
+// this tick and (c) the coarsest rays of newly (re)started images, and counts
+// per image the rays it has in the new list and the queries of the last tick.
+// ---------------------------------------------------------------------------
+__global__ void k_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr) {
+  const int n = hdr[0];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    imgs[table[i].img].cur_level = table[i].lvl;
+}
+
+__global__ __launch_bounds__(256) void k_advance(RayPool pl, const ImgDesc* imgs, const int* in_list,
+                                                 const int* in_count, int* out_list, int* out_count,
+                                                 const AdvEntry* table, const int* hdr, int* img_active,
+                                                 unsigned long long* qcount) {
+  const int n_old = *in_count;
+  const int n_tab = hdr[0], n_new = hdr[1];
+  const int total = n_old + n_new;
+  const int lane = threadIdx.x & 63;
+  for (int base = blockIdx.x * 256; base < total; base += gridDim.x * 256) {
+    const int i = base + threadIdx.x;
+    bool keep = false, old = false;
+    int r = 0, img = -1;
+    if (i < n_old) {
+      old = true;
+      r = in_list[i];
+      img = pl.img[r];
+      const ImgDesc& im = imgs[img];
+      const int off = r - im.slot_base;
+      const int hw = im.H * im.W;
+      const int lvl = off < hw ? 0 : (off < hw + (hw >> 2) ? 1 : 2);
+      keep = pl.st[r] == ST_ACTIVE && lvl == im.cur_level;
+    } else if (i < total) {
+      const int j = i - n_old;
+      int lo = 0, hi = n_tab - 1;          // last entry with begin <= j
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].begin <= j) lo = mid; else hi = mid - 1;
+      }
+      const AdvEntry e = table[lo];
+      img = e.img;
+      const ImgDesc& im = imgs[img];
+      const int c = j - e.begin;
+      const int lvl = e.lvl;
+      const int Wl = im.W >> lvl;
+      const int V = c / Wl, U = c - V * Wl;
+      float3 d;
+      float xt, yt, t_lo, t_hi;
+      level_ray(im, lvl, U, V, d, xt, yt);
+      const bool inside = sphere_interval(im, d, t_lo, t_hi);
+      float t = t_lo;
+      if (e.split) {
+        const int Wp = im.W >> (lvl + 1);
+        const int pr = im.slot_base + im.lvl_off[lvl + 1] + (V >> 1) * Wp + (U >> 1);
+        const float tp = pl.st[pr] == ST_MISS ? t_lo : pl.d[pr].w;
+        t = fminf(fmaxf(tp, t_lo), t_hi);
+      }
+      r = im.slot_base + im.lvl_off[lvl] + c;
+      init_ray(pl, im, img, r, d, t, t_lo, t_hi, inside, e.step);
+      keep = inside;
+    }
+    // queries of the last tick (old entries were all marched), if asked for
+    unsigned long long todo = qcount ? __ballot(old) : 0ull;
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int li = __shfl(img, leader);
+      const unsigned long long same = __ballot(old && img == li);
+      if (lane == leader) atomicAdd(&qcount[li], (unsigned long long)__popcll(same));
+      todo &= ~same;
+    }
+    // per-image count of rays in the new list
+    todo = __ballot(keep);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int li = __shfl(img, leader);
+      const unsigned long long same = __ballot(keep && img == li);
+      if (lane == leader) atomicAdd(&img_active[li], __popcll(same));
+      todo &= ~same;
+    }
+    block_append(keep, r, out_list, out_count);
+  }
+}
+
+// Inverse optimisation (App. B.4 losses): per-pixel gradient of
+// w_d/HW L1(depth) over the rendered-and-target foreground plus the
+// silhouette hinge of App. A.3, and the loss value.
+__global__ __launch_bounds__(256) void k_zopt_loss(const float* depth, const float* sil, const float* depth_t,
+                                                   const float* sil_t, int n, float inv_hw, float w_d, float w_s,
+                                                   float* g_depth, float* g_sil, float* loss) {
+  __shared__ float red[256];
+  float acc = 0.f;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const float S = sil[i], St = sil_t[i];
+    const bool fg = S < 0.f && St > 0.5f;
+    const float dd = fg ? depth[i] - depth_t[i] : 0.f;
+    g_depth[i] = w_d * inv_hw * (dd > 0.f ? 1.f : (dd < 0.f ? -1.f : 0.f));
+    g_sil[i] = w_s * inv_hw * (St * (S > 0.f ? 1.f : 0.f) - (1.f - St) * (S < 0.f ? 1.f : 0.f));
+    acc += w_d * inv_hw * fabsf(dd) + w_s * inv_hw * (St * fmaxf(S, 0.f) + (1.f - St) * fmaxf(-S, 0.f));
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, red[0]);
+}
+
+// Adam (paper App. B.4: Adam, learning rate 1e-2) on one latent code.
+__global__ void k_adam(float* z, float* m, float* v, const float* g, int L, float lr, float b1, float b2, float eps,
+                       int t) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= L) return;
+  const float gj = g[j];
+  const float mj = b1 * m[j] + (1.f - b1) * gj;
+  const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+  m[j] = mj;
+  v[j] = vj;
+  const float mh = mj / (1.f - powf(b1, (float)t));
+  const float vh = vj / (1.f - powf(b2, (float)t));
+  z[j] -= lr * mh / (sqrtf(vh) + eps);
 }
 
 __global__ void k_fill_i32(int* p, int v, int n) {
@@ -496,8 +621,9 @@ void launch_compact(const RayPool& pl, const ImgDesc* imgs, const int* in_list, 
   if (g > 2048) g = 2048;
   hipLaunchKernelGGL(k_compact, dim3(g), dim3(256), 0, s, pl, imgs, in_list, in_count, out_list, out_count, qcount);
 }
-void launch_finalize(const RayPool& pl, const ImgDesc* imgs, int n_img, int hw, const FinalizeOut& o, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(nblk(hw, 256), n_img), dim3(256), 0, s, pl, imgs, o);
+void launch_finalize(const RayPool& pl, const ImgDesc* imgs, const int* imgs_list, int n_img, int hw,
+                     const FinalizeOut& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nblk(hw, 256), n_img), dim3(256), 0, s, pl, imgs, imgs_list, o);
 }
 void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, const int* hit_count, int max_hits,
                     const float* fv, float delta, float* normal, float4* nraw, hipStream_t s) {
@@ -507,11 +633,12 @@ void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, con
 }
 void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
                     int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
-                    int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s) {
+                    int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s,
+                    int lat_fixed) {
   const int bpi = (int)nblk(hw, 256);
   hipLaunchKernelGGL(k_samples_count, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, bsum);
-  hipLaunchKernelGGL(k_samples_scan, dim3(1), dim3(1024), 0, s, bsum, n_img, bpi, img_order, img_latent, tile, n_lat,
-                     boff, seg_base, seg_total, seg_padded, n_samples);
+  hipLaunchKernelGGL(k_samples_scan, dim3(1), dim3(1024), 0, s, bsum, n_img, bpi, img_order, img_latent, lat_fixed,
+                     tile, n_lat, boff, seg_base, seg_total, seg_padded, n_samples);
   hipLaunchKernelGGL(k_samples_write, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, boff, samples,
                      sample_lat);
   hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
@@ -524,12 +651,33 @@ void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, co
 }
 void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
                       const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,
-                      const float* Wsz, int L, float* gz, hipStream_t s) {
+                      const float* Wsz, int L, float* gz, hipStream_t s, int lat0) {
   hipLaunchKernelGGL(k_gz_fold, dim3(nblk(max_tiles, kFold), n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base,
-                     seg_padded);
+                     seg_padded, lat0);
   hipLaunchKernelGGL(k_gz_reduce, dim3(n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base, seg_padded, w0, mg0,
-                     W0z, ws, mgs, Wsz, L, gz);
+                     W0z, ws, mgs, Wsz, L, gz, lat0);
 }
+void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_levels, dim3(nblk(max_entries > 0 ? max_entries : 1, 256)), dim3(256), 0, s, imgs, table,
+                     hdr);
+}
+void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
+                    int* out_count, const AdvEntry* table, const int* hdr, int* img_active,
+                    unsigned long long* qcount, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(grid), dim3(256), 0, s, pl, imgs, in_list, in_count, out_list, out_count, table,
+                     hdr, img_active, qcount);
+}
+void launch_zopt_loss(const float* depth, const float* sil, const float* depth_t, const float* sil_t, int n,
+                      float inv_hw, float w_d, float w_s, float* g_depth, float* g_sil, float* loss, hipStream_t s) {
+  unsigned g = nblk(n, 256);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_zopt_loss, dim3(g), dim3(256), 0, s, depth, sil, depth_t, sil_t, n, inv_hw, w_d, w_s, g_depth,
+                     g_sil, loss);
+}
+void launch_adam(float* z, float* m, float* v, const float* g, int L, float lr, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(nblk(L, 256)), dim3(256), 0, s, z, m, v, g, L, lr, 0.9f, 0.999f, 1e-8f, t);
+}
+
 void launch_fill_i32(int* p, int v, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
 }

@@ -1,14 +1,721 @@
-// Serving loop: continuous batching of render and z-optimisation requests.
+// Serving loop: continuous batching of render and latent-optimisation
+// requests over one pooled sphere tracer.
+//
+// One persistent ray pool holds the rays of every admitted request.  Each
+// tick replays a captured hipGraph on the server stream:
+//     clear counters -> apply level changes -> advance (previous active list
+//     + coarse-to-fine splits + newly started images -> next active list)
+//     -> march (the bf16 decoder on every active ray of every request)
+// so requests of different resolutions share every decoder launch, and a
+// request that arrives while others are marching joins at the next tick.
+// Between ticks the scheduler thread reads the per-image active counts,
+// finalises finished requests (maps, normals), and for latent-optimisation
+// requests computes the loss, the paper's approximate gradient (adjoint) and
+// an Adam step before restarting their images in the pool.
+//
+// Admission is limited by free ray slots, image/latent slots and the
+// context's HBM budget (request buffers are charged against it); a request
+// waits in the queue until resources free up.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "ray_kernels.h"
 #include "serve.h"
 
-void serve_shutdown(dist_ctx* ctx) { (void)ctx; }
+namespace dist {
+
+int validate_params_ext(const dist_trace_params* p, int H, int W);
+int validate_camera_ext(const dist_camera& c, const dist_trace_params* p);
+void fill_desc_ext(ImgDesc& d, const dist_camera& c, const dist_trace_params* p, int latent, int slot_base,
+                   int out_base);
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator of contiguous ray-slot ranges.
+struct SlotAlloc {
+  std::map<int, int> free_;     // begin -> count
+  void init(int cap) { free_.clear(); free_[0] = cap; }
+  int alloc(int n) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const int b = it->first, c = it->second;
+        free_.erase(it);
+        if (c > n) free_[b + n] = c - n;
+        return b;
+      }
+    }
+    return -1;
+  }
+  void release(int b, int n) {
+    auto it = free_.emplace(b, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  dist_request req{};
+  std::vector<dist_camera> cams;
+  int H = 0, W = 0, hw = 0, n_views = 0, levels = 0, spi = 0;
+  // pool resources
+  int slot_base = -1;
+  std::vector<int> imgs;        // pool image slots (view order)
+  int lat = -1;
+  // device buffers of this request (one block from the server cache)
+  char* mem = nullptr;
+  size_t mem_bytes = 0;
+  int* d_imgs = nullptr;
+  float *d_depth = nullptr, *d_sil = nullptr, *d_gd = nullptr, *d_gs = nullptr, *d_gz = nullptr, *d_loss = nullptr;
+  float* d_fv = nullptr;
+  float4* d_nraw = nullptr;
+  int *d_hits = nullptr, *d_hit_count = nullptr;
+  BwdSpace bw;
+  // progress
+  int step = 0, iter = 0;
+  std::vector<char> img_done;
+  bool finished = false;       // render / optimisation complete (scheduler thread)
+  bool done = false;           // result published (under the server lock)
+  int status = DIST_OK;
+  int64_t queries = 0;
+  float final_loss = 0.f;
+  Clock::time_point t_submit, t_done;
+};
+
+struct Server {
+  dist_ctx* ctx = nullptr;
+  hipStream_t st = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv_sub, cv_done;
+  bool stop = false;
+  std::deque<Request*> pending;
+  std::map<uint64_t, Request*> tickets;
+  std::vector<Request*> running;
+  uint64_t next_ticket = 1;
+  int max_pending = 4096;
+  // pool
+  int cap_rays = 0, cap_imgs = 0, cap_lat = 0;
+  char* mem = nullptr;
+  size_t mem_bytes = 0;
+  RayPool pool{};
+  ImgDesc* imgs = nullptr;
+  int* lists[2] = {nullptr, nullptr};
+  int* counters = nullptr;       // [2]
+  AdvEntry* table = nullptr;
+  int* hdr = nullptr;            // [0] entries, [1] new rays
+  int* img_active = nullptr;
+  unsigned long long* qcount = nullptr;
+  float *z_pool = nullptr, *bias0 = nullptr, *biasS = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+  // pinned staging
+  AdvEntry* h_table = nullptr;
+  int* h_hdr = nullptr;
+  int* h_active = nullptr;
+  unsigned long long* h_q = nullptr;
+  ImgDesc* h_desc = nullptr;
+  float* h_loss = nullptr;
+  SlotAlloc slots;
+  std::vector<int> free_imgs, free_lats;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int parity = 0;
+  int adv_grid = 1024;
+  // request buffer cache (size -> blocks), charged against the budget
+  std::multimap<size_t, char*> cache;
+  std::string init_error;
+  int init_rc = DIST_OK;
+};
+
+static size_t ray_bytes() {
+  return sizeof(float4) + sizeof(float2) + sizeof(int) + 2 + sizeof(float) + kMaxK * (4 + 4 + 1);
+}
+
+// ---------------------------------------------------------------------------
+// memory
+// ---------------------------------------------------------------------------
+static size_t round_block(size_t b) {
+  const size_t g = b < (1u << 20) ? 4096 : (1u << 20);
+  return (b + g - 1) / g * g;
+}
+
+static int buf_get(Server* s, size_t bytes, char** out) {
+  bytes = round_block(bytes);
+  auto it = s->cache.find(bytes);
+  if (it != s->cache.end()) {
+    *out = it->second;
+    s->cache.erase(it);
+    return DIST_OK;
+  }
+  void* p = nullptr;
+  int rc = ctx_alloc(s->ctx, &p, bytes);
+  if (rc == DIST_ENOMEM && !s->cache.empty()) {
+    (void)hipStreamSynchronize(s->st);
+    for (auto& kv : s->cache) ctx_free(s->ctx, kv.second, kv.first);
+    s->cache.clear();
+    rc = ctx_alloc(s->ctx, &p, bytes);
+  }
+  if (rc) return rc;
+  *out = (char*)p;
+  return DIST_OK;
+}
+
+static void buf_put(Server* s, char* p, size_t bytes) {
+  if (p) s->cache.emplace(round_block(bytes), p);
+}
+
+// ---------------------------------------------------------------------------
+// pool set-up and the captured tick
+// ---------------------------------------------------------------------------
+template <class T>
+static T* carve(char*& p, size_t n) {
+  p = (char*)(((uintptr_t)p + 255) & ~(uintptr_t)255);
+  T* r = (T*)p;
+  p += sizeof(T) * n;
+  return r;
+}
+
+static size_t pool_layout(Server* s, char* base) {
+  char* p = base;
+  const size_t cap = s->cap_rays;
+  RayPool pl{};
+  pl.d = carve<float4>(p, cap);
+  pl.b = carve<float2>(p, cap);
+  pl.img = carve<int>(p, cap);
+  pl.st = carve<uint8_t>(p, cap);
+  pl.n = carve<uint8_t>(p, cap);
+  pl.flast = carve<float>(p, cap);
+  pl.rec_f = carve<float>(p, cap * kMaxK);
+  pl.rec_t = carve<float>(p, cap * kMaxK);
+  pl.rec_n = carve<uint8_t>(p, cap * kMaxK);
+  pl.cap = (int)cap;
+  s->pool = pl;
+  s->imgs = carve<ImgDesc>(p, s->cap_imgs);
+  s->lists[0] = carve<int>(p, cap);
+  s->lists[1] = carve<int>(p, cap);
+  s->counters = carve<int>(p, 4);
+  s->table = carve<AdvEntry>(p, s->cap_imgs);
+  s->hdr = carve<int>(p, 4);
+  s->img_active = carve<int>(p, s->cap_imgs);
+  s->qcount = carve<unsigned long long>(p, s->cap_imgs);
+  const int L = s->ctx->L;
+  s->z_pool = carve<float>(p, (size_t)s->cap_lat * L);
+  s->bias0 = carve<float>(p, (size_t)s->cap_lat * kMaxWidth);
+  s->biasS = carve<float>(p, (size_t)s->cap_lat * kMaxWidth);
+  s->adam_m = carve<float>(p, (size_t)s->cap_lat * L);
+  s->adam_v = carve<float>(p, (size_t)s->cap_lat * L);
+  return (size_t)(p - base) + 256;
+}
+
+static int capture_tick(Server* s, int par) {
+  dist_ctx* ctx = s->ctx;
+  const int cur = par, nxt = par ^ 1;
+  HIPCHK_S(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+  launch_fill_i32(s->counters + nxt, 0, 1, s->st);
+  launch_fill_i32(s->img_active, 0, s->cap_imgs, s->st);
+  launch_apply_levels(s->imgs, s->table, s->hdr, s->cap_imgs, s->st);
+  launch_advance(s->pool, s->imgs, s->lists[cur], s->counters + cur, s->lists[nxt], s->counters + nxt, s->table,
+                 s->hdr, s->img_active, nullptr, s->adv_grid, s->st);
+  MarchArgs ma{};
+  ma.net = ctx->net[kPrecBF16];
+  ma.pool = s->pool;
+  ma.imgs = s->imgs;
+  ma.bias0_lat = s->bias0;
+  ma.biasS_lat = s->biasS;
+  ma.list = s->lists[nxt];
+  ma.count = s->counters + nxt;
+  ma.qcount = s->qcount;          // queries counted where they are made
+  launch_march(kPrecBF16, ma, ctx->n_cu, s->st);
+  hipGraph_t g = nullptr;
+  HIPCHK_S(hipStreamEndCapture(s->st, &g));
+  HIPCHK_S(hipGraphInstantiate(&s->exec[par], g, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(g);
+  return DIST_OK;
+}
+
+static int pool_init(Server* s) {
+  dist_ctx* ctx = s->ctx;
+  HIPCHK_S(hipSetDevice(ctx->device));
+  HIPCHK_S(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+  s->cap_imgs = 4096;
+  s->cap_lat = 1024;
+  long long cap = 1LL << 25;
+  if (ctx->budget) cap = std::min<long long>(cap * 2, (long long)(ctx->budget / 4 / ray_bytes()));
+  s->cap_rays = (int)std::max<long long>(cap, 1 << 16);
+  s->mem_bytes = pool_layout(s, nullptr);
+  void* p = nullptr;
+  int rc = ctx_alloc(ctx, &p, s->mem_bytes);
+  if (rc) return rc;
+  s->mem = (char*)p;
+  pool_layout(s, s->mem);
+  HIPCHK_S(hipMemsetAsync(s->mem, 0, s->mem_bytes, s->st));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_table, sizeof(AdvEntry) * s->cap_imgs));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_hdr, sizeof(int) * 4));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_active, sizeof(int) * s->cap_imgs));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_q, sizeof(unsigned long long) * s->cap_imgs));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_desc, sizeof(ImgDesc) * s->cap_imgs));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_loss, sizeof(float) * 4));
+  s->slots.init(s->cap_rays);
+  for (int i = s->cap_imgs - 1; i >= 0; --i) s->free_imgs.push_back(i);
+  for (int i = s->cap_lat - 1; i >= 0; --i) s->free_lats.push_back(i);
+  HIPCHK_S(hipStreamSynchronize(s->st));
+  for (int par = 0; par < 2; ++par) {
+    rc = capture_tick(s, par);
+    if (rc) return rc;
+  }
+  return DIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-request buffers
+// ---------------------------------------------------------------------------
+static size_t req_layout(Server* s, Request* r, char* base) {
+  char* p = base;
+  const size_t npx = (size_t)r->n_views * r->hw;
+  r->d_imgs = carve<int>(p, r->n_views);
+  r->d_depth = carve<float>(p, npx);
+  r->d_sil = carve<float>(p, npx);
+  r->d_hits = carve<int>(p, npx);
+  r->d_hit_count = carve<int>(p, 4);
+  r->d_fv = carve<float>(p, npx * 6);
+  r->d_nraw = carve<float4>(p, npx);
+  r->d_loss = carve<float>(p, 4);
+  if (r->req.kind == DIST_REQ_ZOPT) {
+    const int tile = adj_tile_rows(kPrecSplit);
+    const int K = r->req.prm.k_samples;
+    r->d_gd = carve<float>(p, npx);
+    r->d_gs = carve<float>(p, npx);
+    r->d_gz = carve<float>(p, (size_t)s->cap_lat * s->ctx->L);
+    BwdSpace& b = r->bw;
+    b.tile = tile;
+    b.cap_samples = (int)(npx * (K + 6) + tile);
+    b.cap_blocks = r->n_views * ((r->hw + 255) / 256);
+    b.cap_lat = s->cap_lat;
+    const int grid = std::max(1, std::min<int>((b.cap_samples + tile - 1) / tile, s->ctx->n_cu));
+    b.mask_words = adj_mask_words(kPrecSplit, s->ctx->net[kPrecSplit]) * grid;
+    b.samples = carve<float4>(p, b.cap_samples);
+    b.sample_lat = carve<int>(p, b.cap_samples);
+    b.partial = carve<float>(p, (size_t)(b.cap_samples / tile + 1) * 4 * kMaxWidth);
+    b.bsum = carve<int>(p, b.cap_blocks);
+    b.boff = carve<int>(p, b.cap_blocks);
+    b.seg_base = carve<int>(p, b.cap_lat);
+    b.seg_total = carve<int>(p, b.cap_lat);
+    b.seg_padded = carve<int>(p, b.cap_lat);
+    b.n_samples = carve<int>(p, 4);
+    b.mask_ws = carve<unsigned>(p, b.mask_words);
+  }
+  return (size_t)(p - base) + 256;
+}
+
+static void release(Server* s, Request* r) {
+  if (r->slot_base >= 0) s->slots.release(r->slot_base, r->n_views * r->spi);
+  r->slot_base = -1;
+  for (int i : r->imgs) s->free_imgs.push_back(i);
+  r->imgs.clear();
+  if (r->lat >= 0) s->free_lats.push_back(r->lat);
+  r->lat = -1;
+  buf_put(s, r->mem, r->mem_bytes);
+  r->mem = nullptr;
+}
+
+// Start (or restart, for the next z-opt iteration) the render of a request.
+static void start_render(Server* s, Request* r) {
+  r->step = 0;
+  std::fill(r->img_done.begin(), r->img_done.end(), 0);
+  const int L = s->ctx->L;
+  const float* z = s->z_pool + (size_t)r->lat * L;
+  launch_fold_bias(s->ctx->bf[0], s->ctx->w0z, z, 1, L, s->ctx->out_dims[0], s->ctx->wpad[0],
+                   s->bias0 + (size_t)r->lat * s->ctx->wpad[0], s->st);
+  if (s->ctx->skip >= 0)
+    launch_fold_bias(s->ctx->bf[s->ctx->skip], s->ctx->wsz, z, 1, L, s->ctx->out_dims[s->ctx->skip],
+                     s->ctx->wpad[s->ctx->skip], s->biasS + (size_t)r->lat * s->ctx->wpad[s->ctx->skip], s->st);
+}
+
+static bool try_admit(Server* s, Request* r) {
+  const int need = r->n_views * r->spi;
+  if ((int)s->free_imgs.size() < r->n_views || s->free_lats.empty()) return false;
+  r->mem_bytes = req_layout(s, r, nullptr);
+  if (buf_get(s, r->mem_bytes, &r->mem) != DIST_OK) return false;
+  const int base = s->slots.alloc(need);
+  if (base < 0) {
+    buf_put(s, r->mem, r->mem_bytes);
+    r->mem = nullptr;
+    return false;
+  }
+  r->slot_base = base;
+  req_layout(s, r, r->mem);
+  r->lat = s->free_lats.back();
+  s->free_lats.pop_back();
+  r->imgs.resize(r->n_views);
+  for (int v = 0; v < r->n_views; ++v) {
+    r->imgs[v] = s->free_imgs.back();
+    s->free_imgs.pop_back();
+  }
+  // descriptors and the latent code
+  for (int v = 0; v < r->n_views; ++v) {
+    ImgDesc& d = s->h_desc[r->imgs[v]];
+    fill_desc_ext(d, r->cams[v], &r->req.prm, r->lat, base + v * r->spi, v * r->hw);
+    (void)hipMemcpyAsync(s->imgs + r->imgs[v], &d, sizeof(ImgDesc), hipMemcpyHostToDevice, s->st);
+  }
+  (void)hipMemcpyAsync(r->d_imgs, r->imgs.data(), sizeof(int) * r->n_views, hipMemcpyHostToDevice, s->st);
+  for (int v = 0; v < r->n_views; ++v) launch_fill_u64(s->qcount + r->imgs[v], 1, s->st);
+  const int L = s->ctx->L;
+  (void)hipMemcpyAsync(s->z_pool + (size_t)r->lat * L, r->req.z, sizeof(float) * L, hipMemcpyDeviceToDevice, s->st);
+  launch_fill_i32((int*)(s->adam_m + (size_t)r->lat * L), 0, L, s->st);
+  launch_fill_i32((int*)(s->adam_v + (size_t)r->lat * L), 0, L, s->st);
+  // the synchronisation below makes the pinned descriptors reusable
+  (void)hipStreamSynchronize(s->st);
+  r->img_done.assign(r->n_views, 0);
+  start_render(s, r);
+  return true;
+}
+
+// Outputs, normals and (z-opt) loss + gradient + Adam for a finished render.
+static void complete_render(Server* s, Request* r) {
+  dist_ctx* ctx = s->ctx;
+  const dist_request& q = r->req;
+  const bool zopt = q.kind == DIST_REQ_ZOPT;
+  const bool last = !zopt || r->iter + 1 >= q.iters;
+  FinalizeOut fo{};
+  fo.depth = (last && q.depth) ? q.depth : r->d_depth;
+  fo.sil = (last && q.sil) ? q.sil : r->d_sil;
+  fo.status = last ? q.status : nullptr;
+  const bool normals = last && q.normal && q.prm.want_normals;
+  fo.normal = normals ? q.normal : nullptr;
+  fo.nraw = r->d_nraw;
+  fo.hits = r->d_hits;
+  fo.hit_count = r->d_hit_count;
+  fo.want_hits = normals ? 1 : 0;
+  launch_fill_i32(r->d_hit_count, 0, 1, s->st);
+  launch_finalize(s->pool, s->imgs, r->d_imgs, r->n_views, r->hw, fo, s->st);
+  if (normals) {
+    EvalArgs ea{};
+    ea.net = ctx->net[kPrecSplit];
+    ea.bias0_lat = s->bias0;
+    ea.biasS_lat = s->biasS;
+    ea.mode = 1;
+    ea.hits = r->d_hits;
+    ea.hit_count = r->d_hit_count;
+    ea.pool = s->pool;
+    ea.imgs = s->imgs;
+    ea.delta = q.prm.normal_delta;
+    ea.f_out = r->d_fv;
+    const long long rows = 6LL * r->n_views * r->hw;
+    launch_eval(kPrecSplit, ea, (int)std::max(1LL, std::min<long long>((rows + 63) / 64, ctx->n_cu)), s->st);
+    launch_normals(s->pool, s->imgs, r->d_hits, r->d_hit_count, r->n_views * r->hw, r->d_fv, q.prm.normal_delta,
+                   q.normal, r->d_nraw, s->st);
+  }
+  if (!zopt) {
+    r->finished = true;
+    return;
+  }
+  // loss and its gradient on the maps (depth L1 + silhouette hinge)
+  const int npx = r->n_views * r->hw;
+  launch_fill_i32((int*)r->d_loss, 0, 1, s->st);
+  launch_zopt_loss(fo.depth, fo.sil, q.target_depth, q.target_sil, npx, 1.f / r->hw, q.w_depth, q.w_sil, r->d_gd,
+                   r->d_gs, r->d_loss, s->st);
+  // gradient samples of this request's images and the adjoint
+  BwdSpace& b = r->bw;
+  SeedIn in{};
+  in.g_depth = r->d_gd;
+  in.g_sil = r->d_gs;
+  in.nraw = r->d_nraw;
+  in.delta = q.prm.normal_delta;
+  // image order = view order; all images carry the request's latent slot
+  launch_samples(s->pool, s->imgs, r->d_imgs, nullptr, r->n_views, r->hw, s->cap_lat, b.tile, in, b.bsum, b.boff,
+                 b.seg_base, b.seg_total, b.seg_padded, b.n_samples, b.samples, b.sample_lat, s->st, r->lat);
+  AdjArgs aa{};
+  aa.net = ctx->net[kPrecSplit];
+  aa.bias0_lat = s->bias0;
+  aa.biasS_lat = s->biasS;
+  aa.samples = b.samples;
+  aa.sample_lat = b.sample_lat;
+  aa.n_samples = b.n_samples;
+  aa.mask_ws = b.mask_ws;
+  aa.partial = b.partial;
+  const int grid = std::max(1, std::min<int>((b.cap_samples + b.tile - 1) / b.tile, ctx->n_cu));
+  launch_adjoint(kPrecSplit, aa, grid, s->st);
+  const int w0 = ctx->wpad[0];
+  const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
+  launch_gz_reduce(b.partial, ctx->kmax, b.tile, b.cap_samples / b.tile + 1, b.seg_base, b.seg_padded, 1, w0, 1,
+                   ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, r->d_gz, s->st, r->lat);
+  const int L = ctx->L;
+  launch_adam(s->z_pool + (size_t)r->lat * L, s->adam_m + (size_t)r->lat * L, s->adam_v + (size_t)r->lat * L,
+              r->d_gz + (size_t)r->lat * L, L, q.lr, r->iter + 1, s->st);
+  (void)hipMemcpyAsync(s->h_loss, r->d_loss, sizeof(float), hipMemcpyDeviceToHost, s->st);
+  (void)hipStreamSynchronize(s->st);
+  r->final_loss = s->h_loss[0];
+  r->iter += 1;
+  if (r->iter >= q.iters) {
+    (void)hipMemcpyAsync(q.z_out, s->z_pool + (size_t)r->lat * L, sizeof(float) * L, hipMemcpyDeviceToDevice, s->st);
+    r->finished = true;
+  } else {
+    start_render(s, r);
+  }
+}
+
+static void finish(Server* s, Request* r, int status) {
+  (void)hipStreamSynchronize(s->st);
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->status = status;
+  r->t_done = Clock::now();
+  r->finished = true;
+  release(s, r);
+  r->done = true;
+  s->cv_done.notify_all();
+}
+
+static void run(Server* s) {
+  dist_ctx* ctx = s->ctx;
+  (void)hipSetDevice(ctx->device);
+  while (true) {
+    // admission
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->stop) break;
+      if (s->running.empty() && s->pending.empty()) {
+        s->cv_sub.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+        if (s->stop) break;
+      }
+    }
+    while (true) {
+      Request* r = nullptr;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->pending.empty()) break;
+        r = s->pending.front();
+      }
+      if (!try_admit(s, r)) break;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->pending.pop_front();
+      s->running.push_back(r);
+    }
+    if (s->running.empty()) {
+      std::this_thread::sleep_for(std::chrono::microseconds(200));
+      continue;
+    }
+    // the tick's table of images that start rays
+    int n_tab = 0, n_new = 0;
+    for (Request* r : s->running) {
+      const int L = r->levels;
+      int lvl = -1, split = 0;
+      if (r->step == 0) {
+        lvl = L;
+      } else if (r->step % 3 == 0 && r->step / 3 <= L) {
+        lvl = L - r->step / 3;
+        split = 1;
+      }
+      if (lvl < 0) continue;
+      for (int v = 0; v < r->n_views; ++v) {
+        AdvEntry& e = s->h_table[n_tab++];
+        e.img = r->imgs[v];
+        e.lvl = lvl;
+        e.step = r->step;
+        e.split = split;
+        e.begin = n_new;
+        e.count = (r->H >> lvl) * (r->W >> lvl);
+        n_new += e.count;
+      }
+    }
+    s->h_hdr[0] = n_tab;
+    s->h_hdr[1] = n_new;
+    if (n_tab) (void)hipMemcpyAsync(s->table, s->h_table, sizeof(AdvEntry) * n_tab, hipMemcpyHostToDevice, s->st);
+    (void)hipMemcpyAsync(s->hdr, s->h_hdr, sizeof(int) * 2, hipMemcpyHostToDevice, s->st);
+    hipError_t e = hipGraphLaunch(s->exec[s->parity], s->st);
+    s->parity ^= 1;
+    (void)hipMemcpyAsync(s->h_active, s->img_active, sizeof(int) * s->cap_imgs, hipMemcpyDeviceToHost, s->st);
+    (void)hipMemcpyAsync(s->h_q, s->qcount, sizeof(unsigned long long) * s->cap_imgs, hipMemcpyDeviceToHost, s->st);
+    hipError_t e2 = hipStreamSynchronize(s->st);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      // runtime failure: fail every running request
+      std::vector<Request*> rs = s->running;
+      s->running.clear();
+      for (Request* r : rs) finish(s, r, DIST_EHIP);
+      continue;
+    }
+    // progress and completion
+    std::vector<Request*> keep;
+    for (Request* r : s->running) {
+      r->step += 1;
+      bool all = true;
+      for (int v = 0; v < r->n_views; ++v) {
+        const int img = r->imgs[v];
+        if (!r->img_done[v]) {
+          const bool no_more_splits = r->step > 3 * r->levels;
+          if (r->step >= r->req.prm.max_steps || (no_more_splits && s->h_active[img] == 0)) r->img_done[v] = 1;
+        }
+        all = all && r->img_done[v];
+      }
+      if (!all) {
+        keep.push_back(r);
+        continue;
+      }
+      complete_render(s, r);
+      if (r->finished) {
+        long long q = 0;
+        for (int img : r->imgs) q += (long long)s->h_q[img];
+        r->queries = q;
+        finish(s, r, DIST_OK);
+      } else {
+        keep.push_back(r);
+      }
+    }
+    s->running.swap(keep);
+  }
+  // cancel what is left
+  std::vector<Request*> rest;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    rest = s->running;
+    for (Request* r : s->pending) rest.push_back(r);
+    s->running.clear();
+    s->pending.clear();
+  }
+  for (Request* r : rest) finish(s, r, DIST_ECANCELLED);
+}
+
+}  // namespace dist
+
+using namespace dist;
+
+void serve_shutdown(dist_ctx* ctx) {
+  Server* s = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    s = ctx->server;
+    ctx->server = nullptr;
+  }
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_sub.notify_all();
+  if (s->th.joinable()) s->th.join();
+  (void)hipStreamSynchronize(s->st);
+  for (auto& kv : s->tickets) delete kv.second;
+  for (int p = 0; p < 2; ++p)
+    if (s->exec[p]) (void)hipGraphExecDestroy(s->exec[p]);
+  for (auto& kv : s->cache) ctx_free(ctx, kv.second, kv.first);
+  if (s->mem) ctx_free(ctx, s->mem, s->mem_bytes);
+  (void)hipHostFree(s->h_table);
+  (void)hipHostFree(s->h_hdr);
+  (void)hipHostFree(s->h_active);
+  (void)hipHostFree(s->h_q);
+  (void)hipHostFree(s->h_desc);
+  (void)hipHostFree(s->h_loss);
+  if (s->st) (void)hipStreamDestroy(s->st);
+  delete s;
+}
+
+static Server* get_server(dist_ctx* ctx, int* rc) {
+  std::lock_guard<std::mutex> lk(ctx->server_mu);
+  if (ctx->server) return ctx->server;
+  Server* s = new Server();
+  s->ctx = ctx;
+  *rc = pool_init(s);
+  if (*rc) {
+    if (s->mem) ctx_free(ctx, s->mem, s->mem_bytes);
+    if (s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+    return nullptr;
+  }
+  s->th = std::thread(run, s);
+  ctx->server = s;
+  return s;
+}
 
 extern "C" int dist_submit(dist_ctx* ctx, const dist_request* req, uint64_t* ticket) {
-  (void)ctx; (void)req; (void)ticket;
-  return dist_set_error(DIST_EINVAL, "serving is not available in this build");
+  if (!ctx || !req || !ticket) return dist_set_error(DIST_EINVAL, "null argument");
+  if (req->kind != DIST_REQ_RENDER && req->kind != DIST_REQ_ZOPT) return dist_set_error(DIST_EINVAL, "bad kind");
+  if (req->n_views < 1 || req->n_views > 64 || !req->cams) return dist_set_error(DIST_EINVAL, "n_views in [1, 64]");
+  if (!req->z) return dist_set_error(DIST_EINVAL, "null latent code");
+  if (req->prm.precision != DIST_BF16)
+    return dist_set_error(DIST_EINVAL, "serving marches pooled rays with the bf16 decoder (precision DIST_BF16)");
+  const int H = req->cams[0].H, W = req->cams[0].W;
+  for (int v = 0; v < req->n_views; ++v) {
+    if (req->cams[v].H != H || req->cams[v].W != W) return dist_set_error(DIST_EINVAL, "views must share H, W");
+    int rc = validate_camera_ext(req->cams[v], &req->prm);
+    if (rc) return rc;
+  }
+  int rc = validate_params_ext(&req->prm, H, W);
+  if (rc) return rc;
+  if (req->kind == DIST_REQ_ZOPT) {
+    if (!req->target_depth || !req->target_sil || !req->z_out || req->iters < 1)
+      return dist_set_error(DIST_EINVAL, "z-opt needs targets, z_out and iters >= 1");
+    if (!(req->lr > 0.f)) return dist_set_error(DIST_EINVAL, "lr must be positive");
+  }
+  Server* s = get_server(ctx, &rc);
+  if (!s) return rc ? rc : dist_set_error(DIST_EHIP, "server start failed");
+  Request* r = new Request();
+  r->req = *req;
+  r->cams.assign(req->cams, req->cams + req->n_views);
+  r->req.cams = r->cams.data();
+  r->H = H;
+  r->W = W;
+  r->hw = H * W;
+  r->n_views = req->n_views;
+  r->levels = req->prm.c2f_levels;
+  r->spi = slots_per_image(r->hw, r->levels);
+  r->t_submit = Clock::now();
+  if ((long long)r->n_views * r->spi > s->cap_rays) {
+    delete r;
+    return dist_set_error(DIST_ENOMEM, "request needs more ray slots than the pool holds");
+  }
+  const size_t need = round_block(req_layout(s, r, nullptr));
+  if (ctx->budget && need + s->mem_bytes > ctx->budget) {
+    delete r;
+    return dist_set_error(DIST_ENOMEM, "request can never fit the HBM budget (%zu bytes needed)", need);
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if ((int)s->pending.size() >= s->max_pending) {
+    delete r;
+    return dist_set_error(DIST_EBUSY, "serving queue full");
+  }
+  r->ticket = s->next_ticket++;
+  s->tickets[r->ticket] = r;
+  s->pending.push_back(r);
+  *ticket = r->ticket;
+  s->cv_sub.notify_all();
+  return DIST_OK;
 }
 
 extern "C" int dist_poll(dist_ctx* ctx, uint64_t ticket, dist_result* res, int64_t timeout_us) {
-  (void)ctx; (void)ticket; (void)res; (void)timeout_us;
-  return dist_set_error(DIST_ENOTFOUND, "unknown ticket");
+  if (!ctx || !res) return dist_set_error(DIST_EINVAL, "null argument");
+  Server* s = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(ctx->server_mu);
+    s = ctx->server;
+  }
+  if (!s) return dist_set_error(DIST_ENOTFOUND, "unknown ticket");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return dist_set_error(DIST_ENOTFOUND, "unknown ticket");
+  Request* r = it->second;
+  auto done = [&] { return r->done; };
+  if (!done()) {
+    if (timeout_us == 0) return DIST_PENDING;
+    if (timeout_us < 0) s->cv_done.wait(lk, done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) return DIST_PENDING;
+  }
+  res->status = r->status;
+  res->latency_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
+  res->queries = r->queries;
+  res->final_loss = r->final_loss;
+  s->tickets.erase(it);
+  delete r;
+  return DIST_OK;
 }

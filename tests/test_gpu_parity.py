@@ -142,6 +142,30 @@ def test_sdf_vjp(spec, prec, tol):
     assert rel <= tol
 
 
+@pytest.mark.parametrize("spec", [di.C1_SPEC, di.DEEPSDF_SPEC], ids=["c1", "deepsdf"])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)], ids=["fp32", "bf16"])
+def test_sdf_vjp_weights(spec, prec, tol):
+    """Weight and bias gradients of the per-sample term, every layer."""
+    from paper_1911_13225_amd import api
+    ctx = ctx_for(spec)
+    dec = oracle_decoder(spec)
+    n = 300
+    Z = di.make_latents(2, spec.latent_dim, sigma=0.1)
+    P = _rand_points(n, 13, -0.6, 0.6)
+    rng = np.random.Generator(np.random.PCG64(14))
+    seeds = rng.standard_normal(n).astype(np.float32)
+    lat = rng.integers(0, 2, n).astype(np.int32)
+    g, gW, gb = api.dist_sdf_vjp(ctx, torch.tensor(P, device="cuda"), torch.tensor(lat, device="cuda"),
+                                 torch.tensor(seeds, device="cuda"), torch.tensor(Z, device="cuda"), prec,
+                                 want_theta=True)
+    _, oW, ob = dec.sdf_vjp(Z[lat].astype(np.float64), P.astype(np.float64), seeds.astype(np.float64))
+    for l in range(len(oW)):
+        rw = np.linalg.norm(gW[l].cpu().numpy() - oW[l]) / np.linalg.norm(oW[l])
+        rb = np.linalg.norm(gb[l].cpu().numpy() - ob[l]) / max(np.linalg.norm(ob[l]), 1e-30)
+        _log("  layer", l, "dW rel", rw, "db rel", rb)
+        assert rw <= tol and rb <= tol
+
+
 # ----------------------------------------------------------------------------
 # forward render, FP32
 # ----------------------------------------------------------------------------
@@ -305,6 +329,36 @@ def test_backward_bf16():
     rel, g, go = _grad_case(spec, prm, 48, 2, 2, 1.0)
     _log("backward bf16 rel", rel)
     assert rel <= 1e-2
+
+
+def test_backward_weights_fp32():
+    """dL/dtheta of a rendered loss (paper gradient) against the oracle."""
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    prm = cfg_params("c2", precision=0, k_samples=2)
+    H = 32
+    cams = di.random_sphere_cameras(2, H, H)
+    Z = di.make_latents(1, spec.latent_dim, sigma=0.05)
+    ctx = ctx_for(spec)
+    out = api.dist_render_fwd(ctx, cams, torch.tensor(Z, device="cuda"), prm, save=True)
+    dec = oracle_decoder(spec)
+    pairs = [(0, 0), (1, 0)]
+    renders = O.render(dec, Z, cams, pairs, prm)
+    grads, gd, gn, gs = [], [], [], []
+    for r, (v, l) in zip(renders, pairs):
+        dt, nt, stt = di.sphere_target_maps(cams[v], 0.5)
+        _, g_d, g_n, g_s = O.loss_and_grads(r, dt, nt, stt, w_d=10.0, w_s=1.0, w_n=1.0)
+        grads.append((g_d, g_n, g_s)); gd.append(g_d); gn.append(g_n); gs.append(g_s)
+    _, oW, ob = O.backward(dec, Z, renders, pairs, prm, grads, want_theta=True)
+    T = lambda a: torch.tensor(np.stack(a).astype(np.float32), device="cuda")
+    g, gW, gb = api.dist_render_bwd(ctx, out["saved"], T(gd), T(gn), T(gs), n_latents=1, want_theta=True)
+    out["saved"].free()
+    worst = 0.0
+    for l in range(len(oW)):
+        rw = np.linalg.norm(gW[l].cpu().numpy() - oW[l]) / np.linalg.norm(oW[l])
+        worst = max(worst, rw)
+    _log("backward weights fp32 worst layer rel", worst)
+    assert worst <= 1e-3
 
 
 def test_backward_is_deterministic():
