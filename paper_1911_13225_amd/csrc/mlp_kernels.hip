@@ -83,29 +83,44 @@ __device__ __forceinline__ int opaque(int x) {
 // ---------------------------------------------------------------------------
 // Layer 0: h0 = relu(W0_p p + (b0 + W0_z z)), float32 VALU, written to LDS.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float layer0_pre(const NetDev& net, const float* b0l, int n, float4 p) {
-  const int N0 = net.wpad[0];
-  return fmaf(net.w0p[n], p.x, fmaf(net.w0p[N0 + n], p.y, fmaf(net.w0p[2 * N0 + n], p.z, b0l[n])));
-}
+__device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
 
-template <int P>
+// Each thread owns one chunk of EPC output features (its W0_p columns stay in
+// registers) and walks the rows of the tile; N0 / EPC divides kThreads.
+template <int P, bool CAP>
 __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_,
-                                            float* hcap = nullptr, int rstride = 0) {
+                                            float* hcap, int rstride) {
   const int tid = opaque(tid_);
   constexpr int M = Cfg<P>::M, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
   const int cpr = N0 / EPC;
-  for (int c = tid; c < M * cpr; c += kThreads) {
-    const int m = c / cpr, ch = c - m * cpr;
-    const int n = ch * EPC;
+  const int rpp = kThreads / cpr;
+  const int ch = tid % cpr;
+  const int n = ch * EPC;
+  float wx[EPC], wy[EPC], wz[EPC];
+#pragma unroll
+  for (int e = 0; e < EPC; e += 4) {
+    const float4 a = ld4(net.w0p + n + e), b = ld4(net.w0p + N0 + n + e), c = ld4(net.w0p + 2 * N0 + n + e);
+    wx[e] = a.x; wx[e + 1] = a.y; wx[e + 2] = a.z; wx[e + 3] = a.w;
+    wy[e] = b.x; wy[e + 1] = b.y; wy[e + 2] = b.z; wy[e + 3] = b.w;
+    wz[e] = c.x; wz[e + 1] = c.y; wz[e + 2] = c.z; wz[e + 3] = c.w;
+  }
+  for (int m = tid / cpr; m < M; m += rpp) {
     const float4 p = s.pts[m];
-    const float* b0l = bias0_lat + (size_t)s.lat[m] * N0;
+    const float* b0l = bias0_lat + (size_t)s.lat[m] * N0 + n;
     float v[EPC];
 #pragma unroll
-    for (int e = 0; e < EPC; ++e) v[e] = fmaxf(layer0_pre(net, b0l, n + e, p), 0.f);
-    if (hcap) {
+    for (int e = 0; e < EPC; e += 4) {
+      const float4 b = ld4(b0l + e);
+      const float bb[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-      for (int e = 0; e < EPC; ++e) hcap[(size_t)m * rstride + n + e] = v[e];
+      for (int u = 0; u < 4; ++u)
+        v[e + u] = fmaxf(fmaf(wx[e + u], p.x, fmaf(wy[e + u], p.y, fmaf(wz[e + u], p.z, bb[u]))), 0.f);
+    }
+    if constexpr (CAP) {
+#pragma unroll
+      for (int e = 0; e < EPC; e += 4)
+        *(float4*)(hcap + (size_t)m * rstride + n + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
     }
     if constexpr (P == 1) {
       bf16x8 w;
@@ -128,7 +143,7 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
 }
 
 // ---------------------------------------------------------------------------
-// Wave-level GEMM: acc[i][j] (m-tile mt0+i, n-tile nt0+j) = sum_k A[n][k] B[k][m]
+// Wave-level GEMM: acc[i][j] (m-tile mt0+i, n-tile nt0+j) += sum_k A[n][k] B[k][m]
 // ---------------------------------------------------------------------------
 // The k loop is software pipelined: weight fragments (from L2) are requested
 // kDepth k-steps before use in rotating register sets, and the activation
@@ -147,12 +162,6 @@ template <int MTW, int NTW>
 __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& s, const bf16x8* __restrict__ wp,
                                           int ksteps, int nt0, int mt0, int lane) {
   const int r = lane & 31, g = lane >> 5;
-#pragma unroll
-  for (int i = 0; i < MTW; ++i)
-#pragma unroll
-    for (int j = 0; j < NTW; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
   const bf16x8* wrow[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
@@ -205,12 +214,6 @@ template <int MTW, int NTW, bool X3>
 __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>& s, const bf16x8* __restrict__ wp,
                                            const bf16x8* __restrict__ wlo, int ksteps, int nt0, int mt0, int lane) {
   const int r = lane & 31, g = lane >> 5;
-#pragma unroll
-  for (int i = 0; i < MTW; ++i)
-#pragma unroll
-    for (int j = 0; j < NTW; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
   const bf16x8* wrow[NTW];
   const bf16x8* lrow[NTW];
 #pragma unroll
@@ -281,12 +284,6 @@ template <int MTW, int NTW>
 __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s, const f32x4* __restrict__ wp,
                                          int ksteps, int nt0, int mt0, int lane) {
   const int r = lane & 31, g = lane >> 5;
-#pragma unroll
-  for (int i = 0; i < MTW; ++i)
-#pragma unroll
-    for (int j = 0; j < NTW; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
   const f32x4* wrow[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
@@ -359,6 +356,10 @@ struct EpCtx {
   int rstride;
 };
 
+// Lane (r, g) of a wave holds in acc[i][j][4q + e] the output feature
+// n = (nt0 + j) * 32 + 8q + 4g + e of tile row m = (mt0 + i) * 32 + r.
+__device__ __forceinline__ int feat(int nt0, int j, int q, int g) { return (nt0 + j) * 32 + 8 * q + 4 * g; }
+
 template <int P>
 __device__ __forceinline__ void store4(const Sm<P>& s, int m, int n, int g, const float (&v)[4], bool hi_only = false) {
   if constexpr (P == 1) {
@@ -377,106 +378,191 @@ __device__ __forceinline__ void store4(const Sm<P>& s, int m, int n, int g, cons
   }
 }
 
+// relu(x) rounded to the tile's activation format and written to LDS.  For
+// bf16, rounding first and clearing negative codes (a signed 16-bit max with 0)
+// gives the same bits as rounding relu(x).
+template <int P>
+__device__ __forceinline__ void store4_relu(const Sm<P>& s, int m, int n, int g, const float (&x)[4]) {
+  if constexpr (P == 1) {
+    typedef short s16x4 __attribute__((ext_vector_type(4)));
+    const bf16x4 w = {(bf16)x[0], (bf16)x[1], (bf16)x[2], (bf16)x[3]};
+    const s16x4 c = __builtin_elementwise_max(__builtin_bit_cast(s16x4, w), (s16x4)0);
+    *(s16x4*)(s.chunk(m, n >> 3) + 8 * g) = c;
+  } else {
+    const float v[4] = {fmaxf(x[0], 0.f), fmaxf(x[1], 0.f), fmaxf(x[2], 0.f), fmaxf(x[3], 0.f)};
+    store4<P>(s, m, n, g, v);
+  }
+}
+
+template <int MTW, int NTW>
+__device__ __forceinline__ void acc_zero(f32x16 (&acc)[MTW][NTW]) {
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+}
+
+// Forward layers start the accumulation from the bias, so the epilogue only
+// applies the ReLU.  The skip layer's bias is the per-latent folded bias plus
+// the float32 point columns W_p p of the row.
 template <int P, int MTW, int NTW>
-__device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
-                                         const Sm<P>& s, int nt0, int mt0, int nw, int mg, int lane_) {
-  constexpr int M = Cfg<P>::M;
-  const int lane = opaque(lane_);
+__device__ __forceinline__ void acc_bias(f32x16 (&acc)[MTW][NTW], const EpCtx& ec, const Sm<P>& s, int nt0, int mt0,
+                                         int lane) {
   const int r = lane & 31, g = lane >> 5;
-  if (mode == EP_ACT || mode == EP_ACT_MASK) {
+  if (!ec.skip) {
 #pragma unroll
-    for (int i = 0; i < MTW; ++i) {
-      const int m = (mt0 + i) * 32 + r;
-      const float4 p = s.pts[m];
-      const float* bl = ec.skip ? ec.biasS_lat + (size_t)s.lat[m] * ec.wpad : ec.bias;
+    for (int j = 0; j < NTW; ++j)
 #pragma unroll
-      for (int j = 0; j < NTW; ++j) {
-        const int nb = (nt0 + j) * 32;
-        unsigned bits = 0;
+      for (int q = 0; q < 4; ++q) {
+        const float4 b = ld4(ec.bias + feat(nt0, j, q, g));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int n = nb + 8 * q + 4 * g;
-          float v[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float x = acc[i][j][4 * q + e];
-            if (ec.skip) {
-              x += fmaf(ec.wsp[n + e], p.x, fmaf(ec.wsp[ec.wpad + n + e], p.y,
-                        fmaf(ec.wsp[2 * ec.wpad + n + e], p.z, bl[n + e])));
-            } else {
-              x += bl[n + e];
-            }
-            bits |= (x > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
-            v[e] = fmaxf(x, 0.f);
-          }
-          store4<P>(s, m, n, g, v);
-          if (ec.hrow) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(v[0], v[1], v[2], v[3]);
-        }
-        if (mode == EP_ACT_MASK) {
-          bits |= __shfl_xor(bits, 32);
-          if (g == 0) ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + (nb >> 5)] = bits;
+        for (int i = 0; i < MTW; ++i) {
+          acc[i][j][4 * q] = b.x;
+          acc[i][j][4 * q + 1] = b.y;
+          acc[i][j][4 * q + 2] = b.z;
+          acc[i][j][4 * q + 3] = b.w;
         }
       }
-    }
     return;
   }
-  if (mode == EP_LAST || mode == EP_LAST_ADJ) {
-#pragma unroll
-    for (int i = 0; i < MTW; ++i) {
-      const int m = (mt0 + i) * 32 + r;
-      const float4 p = s.pts[m];
-      const float* bl = ec.skip ? ec.biasS_lat + (size_t)s.lat[m] * ec.wpad : ec.bias;
-      float sum = 0.f;
-#pragma unroll
-      for (int j = 0; j < NTW; ++j) {
-        const int nb = (nt0 + j) * 32;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int n = nb + 8 * q + 4 * g;
-          float v[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float x = acc[i][j][4 * q + e];
-            if (ec.skip) {
-              x += fmaf(ec.wsp[n + e], p.x, fmaf(ec.wsp[ec.wpad + n + e], p.y,
-                        fmaf(ec.wsp[2 * ec.wpad + n + e], p.z, bl[n + e])));
-            } else {
-              x += bl[n + e];
-            }
-            const float wl = net.wlast[n + e];
-            sum = fmaf(wl, fmaxf(x, 0.f), sum);
-            v[e] = x > 0.f ? wl : 0.f;           // d m / d(pre-activation)
-            if (ec.hrow) ec.hrow[(size_t)m * ec.rstride + n + e] = fmaxf(x, 0.f);
-          }
-          if (mode == EP_LAST_ADJ) store4<P>(s, m, n, g, v, true);
-        }
-      }
-      sum += __shfl_xor(sum, 32);
-      if (g == 0) s.part[nw * M + m] = sum;
-    }
-    return;
-  }
-  // EP_VJP: acc = W^T delta for the output of layer ec.layer; apply its ReLU mask
+  float4 p[MTW];
+  const float* bl[MTW];
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
     const int m = (mt0 + i) * 32 + r;
-    const float4 p = s.pts[m];
-    const float* b0l = ec.bias0_lat + (size_t)s.lat[m] * net.wpad[0];
+    p[i] = s.pts[m];
+    bl[i] = ec.biasS_lat + (size_t)s.lat[m] * ec.wpad;
+  }
+#pragma unroll
+  for (int j = 0; j < NTW; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = feat(nt0, j, q, g);
+      const float4 wx = ld4(ec.wsp + n), wy = ld4(ec.wsp + ec.wpad + n), wz = ld4(ec.wsp + 2 * ec.wpad + n);
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        const float4 b = ld4(bl[i] + n);
+        acc[i][j][4 * q] = fmaf(wx.x, p[i].x, fmaf(wy.x, p[i].y, fmaf(wz.x, p[i].z, b.x)));
+        acc[i][j][4 * q + 1] = fmaf(wx.y, p[i].x, fmaf(wy.y, p[i].y, fmaf(wz.y, p[i].z, b.y)));
+        acc[i][j][4 * q + 2] = fmaf(wx.z, p[i].x, fmaf(wy.z, p[i].y, fmaf(wz.z, p[i].z, b.z)));
+        acc[i][j][4 * q + 3] = fmaf(wx.w, p[i].x, fmaf(wy.w, p[i].y, fmaf(wz.w, p[i].z, b.w)));
+      }
+    }
+}
+
+// Hidden layer output: relu to LDS (+ ReLU mask bits for the adjoint, + a float32
+// copy of h for the weight gradient).
+template <int P, int MTW, int NTW, bool MASK, bool CAP>
+__device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s, int nt0, int mt0,
+                                       int lane) {
+  constexpr int M = Cfg<P>::M;
+  const int r = lane & 31, g = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int m = (mt0 + i) * 32 + r;
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
-      const int nb = (nt0 + j) * 32;
+      unsigned bits = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = feat(nt0, j, q, g);
+        const float x[4] = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+        if constexpr (MASK) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) bits |= (x[e] > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
+        }
+        store4_relu<P>(s, m, n, g, x);
+        if constexpr (CAP)
+          *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) =
+              make_float4(fmaxf(x[0], 0.f), fmaxf(x[1], 0.f), fmaxf(x[2], 0.f), fmaxf(x[3], 0.f));
+      }
+      if constexpr (MASK) {
+        bits |= __shfl_xor(bits, 32);
+        if (g == 0) ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + ((nt0 + j))] = bits;
+      }
+    }
+  }
+}
+
+// Last hidden layer: m-partial = sum_n w_last[n] relu(x[n]) per row (reduced
+// across the waves in a fixed order by the caller); with ADJ the seed
+// d m / d(pre-activation) = w_last [x > 0] is written to LDS.
+template <int P, int MTW, int NTW, bool ADJ, bool CAP>
+__device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
+                                        int nt0, int mt0, int nw, int lane) {
+  constexpr int M = Cfg<P>::M;
+  const int r = lane & 31, g = lane >> 5;
+  float sum[MTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) sum[i] = 0.f;
+#pragma unroll
+  for (int j = 0; j < NTW; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = feat(nt0, j, q, g);
+      const float4 w4 = ld4(net.wlast + n);
+      const float wl[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        const int m = (mt0 + i) * 32 + r;
+        float h[4], v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float x = acc[i][j][4 * q + e];
+          h[e] = fmaxf(x, 0.f);
+          sum[i] = fmaf(wl[e], h[e], sum[i]);
+          v[e] = x > 0.f ? wl[e] : 0.f;
+        }
+        if constexpr (ADJ) store4<P>(s, m, n, g, v, true);
+        if constexpr (CAP) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(h[0], h[1], h[2], h[3]);
+      }
+    }
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const float t = sum[i] + __shfl_xor(sum[i], 32);
+    if (g == 0) s.part[nw * M + (mt0 + i) * 32 + r] = t;
+  }
+}
+
+// VJP through one layer: acc = W^T delta for the output of layer ec.layer;
+// apply that layer's ReLU mask (recomputed in float32 for layer 0, whose
+// pre-activation is the same expression layer0_fill evaluates).
+template <int P, int MTW, int NTW, bool L0, bool CAP>
+__device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
+                                       int nt0, int mt0, int mg, int lane) {
+  constexpr int M = Cfg<P>::M;
+  const int r = lane & 31, g = lane >> 5;
+  const int N0 = net.wpad[0];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    const int m = (mt0 + i) * 32 + r;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float* b0l = nullptr;
+    if constexpr (L0) {
+      p = s.pts[m];
+      b0l = ec.bias0_lat + (size_t)s.lat[m] * N0;
+    }
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
       unsigned bits;
-      if (ec.layer == 0) {
+      if constexpr (L0) {
         bits = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q) {
+          const int n = feat(nt0, j, q, g);
+          const float4 wx = ld4(net.w0p + n), wy = ld4(net.w0p + N0 + n), wz = ld4(net.w0p + 2 * N0 + n);
+          const float4 b = ld4(b0l + n);
+          const float pre[4] = {fmaf(wx.x, p.x, fmaf(wy.x, p.y, fmaf(wz.x, p.z, b.x))),
+                                fmaf(wx.y, p.x, fmaf(wy.y, p.y, fmaf(wz.y, p.z, b.y))),
+                                fmaf(wx.z, p.x, fmaf(wy.z, p.y, fmaf(wz.z, p.z, b.z))),
+                                fmaf(wx.w, p.x, fmaf(wy.w, p.y, fmaf(wz.w, p.z, b.w)))};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int n = nb + 8 * q + 4 * g + e;
-            bits |= (layer0_pre(net, b0l, n, p) > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
-          }
+          for (int e = 0; e < 4; ++e) bits |= (pre[e] > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
+        }
       } else {
-        bits = ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + (nb >> 5)];
+        bits = ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + (nt0 + j)];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -487,14 +573,14 @@ __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCt
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float v[4] = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
-          store4<P>(s, m, nb + 8 * q + 4 * g, g, v, true);
+          store4<P>(s, m, feat(nt0, j, q, g), g, v, true);
         }
       }
-      if (ec.drow) {
+      if constexpr (CAP) {
         const float w = s.gm[m];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          *(float4*)(ec.drow + (size_t)m * ec.rstride + nb + 8 * q + 4 * g) =
+          *(float4*)(ec.drow + (size_t)m * ec.rstride + feat(nt0, j, q, g)) =
               make_float4(w * acc[i][j][4 * q], w * acc[i][j][4 * q + 1], w * acc[i][j][4 * q + 2],
                           w * acc[i][j][4 * q + 3]);
       }
@@ -504,7 +590,6 @@ __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCt
     // column sums over the tile's rows, each row scaled by its seed gm[m]
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
-      const int nb = (nt0 + j) * 32;
       float cs[16];
 #pragma unroll
       for (int e = 0; e < 16; ++e) cs[e] = 0.f;
@@ -529,47 +614,56 @@ __device__ __forceinline__ void epilogue(int mode, const NetDev& net, const EpCt
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) dst[nb + 8 * q + 4 * g + e] = cs[4 * q + e];
+          for (int e = 0; e < 4; ++e) dst[feat(nt0, j, q, g) + e] = cs[4 * q + e];
       }
     }
   }
 }
 
-// Run one layer (GEMM + barrier + epilogue + barrier) for an output width N
-// (128, 256 or 512 after padding): the 4 waves split N into 4 groups of N/4
-// outputs and each covers all rows of the tile.
-template <int P, int MTW, int NTW, int WN>
-__device__ __forceinline__ void layer_run(int mode, const NetDev& net, const EpCtx& ec, const Sm<P>& s,
-                                          const void* wp, const void* wlo, int ksteps, int wave_, int lane_) {
+// Run one layer (accumulator init + GEMM + barrier + epilogue + barrier) for an
+// output width N (128, 256 or 512 after padding): the 4 waves split N into 4
+// groups of N/4 outputs and each covers all rows of the tile.
+template <int P, int MTW, int NTW, int MODE, bool CAP>
+__device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
+                                          const void* wlo, int ksteps) {
+  constexpr int WN = 4;
   // lane-dependent addressing is recomputed per layer (see opaque())
   const int t = opaque((int)threadIdx.x);
   const int wave = t >> 6, lane = t & 63;
-  (void)wave_;
-  (void)lane_;
   const int nw = wave % WN, mg = wave / WN;
   const int nt0 = nw * NTW, mt0 = mg * MTW;
   f32x16 acc[MTW][NTW];
+  if constexpr (MODE == EP_VJP) acc_zero<MTW, NTW>(acc);
+  else acc_bias<P, MTW, NTW>(acc, ec, s, nt0, mt0, lane);
   if constexpr (P == 1) {
     gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane);
   } else if constexpr (P == 2) {
-    if (mode == EP_VJP) gemm_split<MTW, NTW, false>(acc, s, (const bf16x8*)wp, nullptr, ksteps, nt0, mt0, lane);
-    else gemm_split<MTW, NTW, true>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane);
+    gemm_split<MTW, NTW, MODE != EP_VJP>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane);
   } else {
     gemm_f32<MTW, NTW>(acc, s, (const f32x4*)wp, ksteps, nt0, mt0, lane);
   }
   __syncthreads();
-  epilogue<P, MTW, NTW>(mode, net, ec, acc, s, nt0, mt0, nw, mg, lane);
+  if constexpr (MODE == EP_ACT) ep_act<P, MTW, NTW, false, CAP>(ec, acc, s, nt0, mt0, lane);
+  if constexpr (MODE == EP_ACT_MASK) ep_act<P, MTW, NTW, true, CAP>(ec, acc, s, nt0, mt0, lane);
+  if constexpr (MODE == EP_LAST) ep_last<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
+  if constexpr (MODE == EP_LAST_ADJ) ep_last<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
+  if constexpr (MODE == EP_VJP) {
+    if (ec.layer == 0) ep_vjp<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, mg, lane);
+    else ep_vjp<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, mg, lane);
+  }
   __syncthreads();
 }
 
-template <int P>
-__device__ __forceinline__ int layer(int mode, const NetDev& net, const EpCtx& ec, const Sm<P>& s,
-                                     const void* wp, const void* wlo, int N, int K, int wave, int lane) {
+// One layer of output width N and contracted width K; returns the number of
+// wave groups that wrote output-layer partial sums.
+template <int P, int MODE, bool CAP>
+__device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
+                                     const void* wlo, int N, int K) {
   constexpr int MT = Cfg<P>::MT;
   const int ksteps = K / (P ? 16 : 8);
-  if (N == 512) { layer_run<P, MT, 4, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 4; }
-  if (N == 256) { layer_run<P, MT, 2, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane); return 4; }
-  layer_run<P, MT, 1, 4>(mode, net, ec, s, wp, wlo, ksteps, wave, lane);
+  if (N == 512) layer_run<P, MT, 4, MODE, CAP>(net, ec, s, wp, wlo, ksteps);
+  else if (N == 256) layer_run<P, MT, 2, MODE, CAP>(net, ec, s, wp, wlo, ksteps);
+  else layer_run<P, MT, 1, MODE, CAP>(net, ec, s, wp, wlo, ksteps);
   return 4;
 }
 
@@ -588,24 +682,27 @@ __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_l
 }
 
 // Forward through all hidden layers; leaves the output-layer partial sums in
-// s.part and returns the number of partial groups.
-template <int P>
-__device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat, const Sm<P>& s,
-                           int tid, int wave, int lane, unsigned* mask, bool adj, float* hcap = nullptr) {
+// s.part and returns the number of partial groups.  ADJ records the ReLU masks
+// and the output-layer seed for the adjoint; CAP keeps float32 copies of every
+// hidden activation in hcap for the weight gradient.
+template <int P, bool ADJ, bool CAP>
+__device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
+                                           const Sm<P>& s, int tid, unsigned* mask, float* hcap = nullptr) {
   const int rstride = (net.nl - 1) * net.kmax;
-  layer0_fill<P>(net, bias0_lat, s, tid, hcap, rstride);
+  layer0_fill<P, CAP>(net, bias0_lat, s, tid, hcap, rstride);
   __syncthreads();
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
     EpCtx ec = fwd_ctx(net, biasS_lat, l);
     ec.mask = mask;
-    if (hcap) {
+    if constexpr (CAP) {
       ec.hrow = hcap + (size_t)l * net.kmax;
       ec.rstride = rstride;
     }
-    const bool last = (l == net.nl - 2);
-    const int mode = last ? (adj ? EP_LAST_ADJ : EP_LAST) : (adj ? EP_ACT_MASK : EP_ACT);
-    wn = layer<P>(mode, net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l], wave, lane);
+    if (l == net.nl - 2)
+      wn = layer<P, ADJ ? EP_LAST_ADJ : EP_LAST, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
+    else
+      wn = layer<P, ADJ ? EP_ACT_MASK : EP_ACT, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
   }
   return wn;
 }
@@ -622,10 +719,8 @@ template <int P>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_march(MarchArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int count = *a.count;
-  const int K = 0;
-  (void)K;
   for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
     if (tid < M) {
       const int idx = tile * M + tid;
@@ -643,7 +738,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.rid[tid] = r;
     }
     __syncthreads();
-    const int wn = mlp_forward<P>(a.net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, nullptr, false);
+    const int wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, nullptr);
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -713,7 +808,7 @@ template <int P>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_eval(EvalArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x;
   const long long count = a.mode == 0 ? a.n : 6ll * (long long)(*a.hit_count);
   for (long long tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
     if (tid < M) {
@@ -743,7 +838,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.rid[tid] = valid;
     }
     __syncthreads();
-    const int wn = mlp_forward<P>(a.net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, nullptr, false);
+    const int wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, nullptr);
     if (tid < M && s.rid[tid]) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -764,7 +859,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x;
   const int count = *a.n_samples;
   const int ntmax = net.kmax / 32;
   unsigned* mask = a.mask_ws + (size_t)blockIdx.x * (size_t)(net.nl) * M * ntmax;
@@ -782,7 +877,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.lat[tid] = a.sample_lat[idx];
     }
     __syncthreads();
-    const int wn = mlp_forward<P>(net, a.bias0_lat, a.biasS_lat, s, tid, wave, lane, mask, true, hcap);
+    const int wn = theta ? mlp_forward<P, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mask, hcap)
+                         : mlp_forward<P, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mask);
     if (tid < M) {
       float m = net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -815,7 +911,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
         ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
         ec.rstride = rstride;
       }
-      layer<P>(EP_VJP, net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l], wave, lane);
+      if (theta) layer<P, EP_VJP, true>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
+      else layer<P, EP_VJP, false>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
     }
   }
 }

@@ -83,6 +83,7 @@ def test_served_render_alone_equals_mix_and_batch(ctx):
     assert torch.equal(out["depth"], a.depth)
     assert torch.equal(out["status"], a.status)
     assert torch.equal(out["normal"], a.normal)
+    assert int(out["queries"].sum()) == ra["queries"]
 
 
 def test_served_zopt_alone_equals_mix(ctx):
@@ -114,6 +115,7 @@ def test_served_zopt_alone_equals_mix(ctx):
         assert api.dist_poll(ctx, o, 120_000_000)["status"] == 0
     _log("zopt alone", ra, "mix", rb, "|dz|", float((a.z_out - z0).norm()))
     assert torch.equal(a.z_out, b.z_out)
+    assert ra["queries"] == rb["queries"]
     assert float((a.z_out - z0).norm()) > 0
     assert abs(ra["final_loss"] - rb["final_loss"]) <= 1e-6 * max(1.0, abs(ra["final_loss"]))
 
