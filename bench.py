@@ -31,7 +31,11 @@ METRIC = "SDF queries/s + 256^2 fwd+bwd frames/s, BF16 vs FP32 plain; serving p9
 FLOP_PER_QUERY = 2 * 1_573_376
 # backward per sample: the recompute (as a query) + the VJP through the hidden
 # layers (5 x 512x512 + 2 x 253x512 multiply-adds)
-FLOP_PER_SAMPLE = FLOP_PER_QUERY + 2 * (5 * 512 * 512 + 2 * 253 * 512)
+FLOP_VJP = 2 * (5 * 512 * 512 + 2 * 253 * 512)
+FLOP_PER_SAMPLE = FLOP_PER_QUERY + FLOP_VJP
+# per kernel class of dist_timing_read: algorithmic FLOP per processed row
+KERNEL_CLASSES = (("march", FLOP_PER_QUERY), ("eval", FLOP_PER_QUERY), ("adjoint", FLOP_PER_SAMPLE),
+                  ("vjp_saved", FLOP_VJP))
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}
 
 
@@ -90,7 +94,7 @@ def time_steps(w, steps, warmup):
         qs.append(q)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = {name: api.dist_timing_read(w["ctx"], k) for k, name in enumerate(("march", "eval", "adjoint"))}
+    kern = {name: api.dist_timing_read(w["ctx"], k) for k, (name, _) in enumerate(KERNEL_CLASSES)}
     api.dist_timing_enable(w["ctx"], False)
     queries = int(sum(int(q.sum()) for q in qs))
     return dict(sec=t1 - t0, steps=steps, queries=queries, kern=kern)
@@ -102,7 +106,7 @@ def kernel_summary(r, dtype):
     for name, (launches, ms, rows) in r["kern"].items():
         if launches == 0 or ms <= 0:
             continue
-        fl = FLOP_PER_SAMPLE if name == "adjoint" else FLOP_PER_QUERY
+        fl = dict(KERNEL_CLASSES)[name]
         out[name] = dict(launches=launches, ms_total=round(ms, 3), ms_avg=round(ms / launches, 4), rows=rows,
                          tflops=round(rows * fl / (ms * 1e-3) / 1e12, 2))
     return out

@@ -254,7 +254,9 @@ int dist_poll(dist_ctx* ctx, uint64_t ticket, dist_result* res, int64_t timeout_
  * synchronises on those events and returns, for one kernel class, the
  * number of launches and their summed duration since timing was enabled.
  * kernel: 0 = march step (decoder + march update), 1 = plain decoder queries
- * (normals, dist_sdf_eval), 2 = adjoint (backward recompute + VJP). */
+ * (normals, dist_sdf_eval), 2 = adjoint (backward recompute + VJP),
+ * 3 = VJP of the normal-stencil samples from the ReLU masks the forward
+ * saved (no recompute). */
 typedef struct {
   int64_t launches;
   double ms;

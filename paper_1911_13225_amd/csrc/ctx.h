@@ -14,6 +14,10 @@ namespace dist {
 struct Server;
 }
 
+// kernel classes of dist_timing_read: march, decoder queries, adjoint with
+// recompute, VJP from saved masks
+constexpr int kTimeClasses = 4;
+
 // Buffers of one backward pass (gradient samples and partial sums).
 struct BwdSpace {
   char* mem = nullptr;
@@ -25,8 +29,23 @@ struct BwdSpace {
   float* partial = nullptr;
   int *bsum = nullptr, *boff = nullptr;
   int *seg_base = nullptr, *seg_total = nullptr, *seg_padded = nullptr;
-  int* n_samples = nullptr;
+  int* n_samples = nullptr;       // [end of list 1, its length, end of list 2, its length]
   unsigned* mask_ws = nullptr;
+  // second list of the split layout (normal-stencil samples, VJP from saved masks)
+  int *bsum2 = nullptr, *boff2 = nullptr;
+  int *seg2_base = nullptr, *seg2_total = nullptr, *seg2_padded = nullptr;
+  int* sample_idx = nullptr;
+};
+
+// ReLU masks and 1 - tanh(m)^2 of the forward's normal-stencil queries, kept
+// for a backward that skips their recompute.
+struct NrmSave {
+  char* mem = nullptr;
+  size_t bytes = 0;
+  long long cap_samples = 0;
+  size_t words = 0;              // mask words per sample
+  unsigned* mask = nullptr;
+  float* dtanh = nullptr;
 };
 
 // Buffers of one forward render (ray pool, lists, counters, outputs staging).
@@ -47,6 +66,8 @@ struct Workspace {
   int* hits = nullptr;
   float* fv = nullptr;
   float4* nraw = nullptr;
+  int* hit_pix = nullptr;
+  NrmSave* ns = nullptr;
   // pinned staging of the per-call descriptors
   dist::ImgDesc* h_imgs = nullptr;
   int* h_ints = nullptr;
@@ -78,9 +99,9 @@ struct dist_ctx {
   std::mutex server_mu;
   // kernel timing (see dist_timing_enable)
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[3];
-  size_t tev_used[3] = {0, 0, 0};
-  unsigned long long* d_rows = nullptr;   // device accumulators of processed rows [3]
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[kTimeClasses];
+  size_t tev_used[kTimeClasses] = {0, 0, 0, 0};
+  unsigned long long* d_rows = nullptr;   // device accumulators of processed rows [kTimeClasses]
 };
 
 // Event pair around one launch of kernel class k (no-op unless timing is on).
@@ -100,6 +121,7 @@ struct dist_saved {
   int n_img = 0, hw = 0, n_lat = 0;
   dist_trace_params prm{};
   std::vector<int> img_latent, order;
+  bool masks_kept = false;           // the stencil queries kept their ReLU masks
 };
 
 int dist_set_error(int code, const char* fmt, ...);
@@ -116,5 +138,6 @@ int slots_per_image(int hw, int levels);
 int fold_biases(dist_ctx* ctx, Workspace* w, const float* z, int n_lat, hipStream_t st);
 int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, hipStream_t st);
 int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, float* depth,
-                 float* dist, float* normal, float* sil, uint8_t* status, uint8_t* nsteps, hipStream_t st);
+                 float* dist, float* normal, float* sil, uint8_t* status, uint8_t* nsteps, hipStream_t st,
+                 bool keep_masks = false);
 void ws_put(dist_ctx* ctx, Workspace* w);

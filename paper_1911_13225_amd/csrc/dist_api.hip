@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -264,7 +265,7 @@ extern "C" int dist_destroy(dist_ctx* ctx) {
   serve_shutdown(ctx);
   (void)hipDeviceSynchronize();
   ws_release_all(ctx);
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < kTimeClasses; ++k)
     for (auto& pr : ctx->tev[k]) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
@@ -304,19 +305,19 @@ extern "C" int dist_timing_enable(dist_ctx* ctx, int on) {
   if (!ctx) return dist_set_error(DIST_EINVAL, "null context");
   HIPCHK(hipDeviceSynchronize());
   if (!ctx->d_rows) {
-    int rc = ctx_alloc(ctx, (void**)&ctx->d_rows, 3 * sizeof(unsigned long long));
+    int rc = ctx_alloc(ctx, (void**)&ctx->d_rows, kTimeClasses * sizeof(unsigned long long));
     if (rc) return rc;
-    ctx->owned.push_back({ctx->d_rows, 3 * sizeof(unsigned long long)});
+    ctx->owned.push_back({ctx->d_rows, kTimeClasses * sizeof(unsigned long long)});
   }
-  HIPCHK(hipMemset(ctx->d_rows, 0, 3 * sizeof(unsigned long long)));
+  HIPCHK(hipMemset(ctx->d_rows, 0, kTimeClasses * sizeof(unsigned long long)));
   HIPCHK(hipDeviceSynchronize());
   ctx->timing = on != 0;
-  for (int k = 0; k < 3; ++k) ctx->tev_used[k] = 0;
+  for (int k = 0; k < kTimeClasses; ++k) ctx->tev_used[k] = 0;
   return DIST_OK;
 }
 
 extern "C" int dist_timing_read(dist_ctx* ctx, int32_t kernel, dist_kernel_time* out) {
-  if (!ctx || !out || kernel < 0 || kernel > 2) return dist_set_error(DIST_EINVAL, "bad argument");
+  if (!ctx || !out || kernel < 0 || kernel >= kTimeClasses) return dist_set_error(DIST_EINVAL, "bad argument");
   double ms = 0.0;
   for (size_t i = 0; i < ctx->tev_used[kernel]; ++i) {
     auto& pr = ctx->tev[kernel][i];
@@ -373,6 +374,7 @@ static void ws_layout(Workspace& w, Carver& c) {
   w.hits = c.take<int>(w.cap_pix);
   w.fv = c.take<float>((size_t)w.cap_pix * 6);
   w.nraw = c.take<float4>(w.cap_pix);
+  w.hit_pix = c.take<int>(w.cap_pix);
 }
 
 static void bw_layout(BwdSpace& w, Carver& c) {
@@ -386,6 +388,12 @@ static void bw_layout(BwdSpace& w, Carver& c) {
   w.seg_padded = c.take<int>(w.cap_lat);
   w.n_samples = c.take<int>(4);
   w.mask_ws = c.take<unsigned>(w.mask_words);
+  w.bsum2 = c.take<int>(w.cap_blocks);
+  w.boff2 = c.take<int>(w.cap_blocks);
+  w.seg2_base = c.take<int>(w.cap_lat);
+  w.seg2_total = c.take<int>(w.cap_lat);
+  w.seg2_padded = c.take<int>(w.cap_lat);
+  w.sample_idx = c.take<int>(w.cap_samples);
 }
 
 static int ws_get(dist_ctx* ctx, int cap_rays, int cap_pix, int cap_img, int cap_lat, int cap_steps,
@@ -448,6 +456,10 @@ static void ws_destroy(dist_ctx* ctx, Workspace* w) {
     ctx_free(ctx, w->bw->mem, w->bw->bytes);
     delete w->bw;
   }
+  if (w->ns) {
+    ctx_free(ctx, w->ns->mem, w->ns->bytes);
+    delete w->ns;
+  }
   delete w;
 }
 
@@ -487,6 +499,28 @@ static int bw_get(dist_ctx* ctx, Workspace* w, int cap_samples, int cap_blocks, 
   c.off = 0;
   bw_layout(*b, c);
   w->bw = b;
+  return DIST_OK;
+}
+
+// Buffers for the ReLU masks of up to cap_samples stencil queries.
+static int ns_get(dist_ctx* ctx, Workspace* w, long long cap_samples, size_t words) {
+  NrmSave* n = w->ns;
+  if (n && n->cap_samples >= cap_samples && n->words == words) return DIST_OK;
+  if (n) {
+    ctx_free(ctx, n->mem, n->bytes);
+    delete n;
+    w->ns = nullptr;
+  }
+  n = new NrmSave();
+  n->cap_samples = cap_samples;
+  n->words = words;
+  const size_t mbytes = ((size_t)cap_samples * words * 4 + 255) & ~(size_t)255;
+  n->bytes = mbytes + (size_t)cap_samples * 4 + 256;
+  int rc = ctx_alloc(ctx, (void**)&n->mem, n->bytes);
+  if (rc != DIST_OK) { delete n; return rc; }
+  n->mask = (unsigned*)n->mem;
+  n->dtanh = (float*)(n->mem + mbytes);
+  w->ns = n;
   return DIST_OK;
 }
 
@@ -619,7 +653,8 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
 
 // Finalise outputs and compute normals with float32 queries.
 int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, float* depth,
-                 float* dist, float* normal, float* sil, uint8_t* status, uint8_t* nsteps, hipStream_t st) {
+                 float* dist, float* normal, float* sil, uint8_t* status, uint8_t* nsteps, hipStream_t st,
+                 bool keep_masks) {
   FinalizeOut fo{};
   fo.depth = depth;
   fo.dist = dist;
@@ -631,6 +666,7 @@ int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trac
   fo.hits = w->hits;
   fo.hit_count = w->counters + prm->max_steps + 4;
   fo.want_hits = prm->want_normals ? 1 : 0;
+  fo.hit_pix = keep_masks ? w->hit_pix : nullptr;
   launch_fill_i32(fo.hit_count, 0, 1, st);
   launch_finalize(w->pool, w->imgs, nullptr, n_img, hw, fo, st);
   if (prm->want_normals) {
@@ -647,6 +683,10 @@ int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trac
     ea.imgs = w->imgs;
     ea.delta = prm->normal_delta;
     ea.f_out = w->fv;
+    if (keep_masks) {
+      ea.mask_out = w->ns->mask;
+      ea.dtanh_out = w->ns->dtanh;
+    }
     {
       TimedLaunch tl(ctx, 1, st, fo.hit_count, 6);
       launch_eval(np, ea, mlp_grid(ctx, 6LL * n_img * hw, np), st);
@@ -703,8 +743,15 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return li[a] < li[b]; });
   rc = stage_images(w, d, order, li, st);
   if (!rc) rc = fold_biases(ctx, w, z, n_latents, st);
+  // a forward whose state is saved keeps the ReLU masks of its normal-stencil
+  // queries, so that the backward skips their recompute
+  const int np = prm->precision == DIST_FP32 ? kPrecF32 : kPrecSplit;
+  const long long n_stencil = 6LL * n_img * hw;
+  const size_t mwords = (size_t)(ctx->nl - 1) * (ctx->net[np].kmax / 32);
+  bool keep = saved && prm->want_normals && n_stencil <= INT_MAX && n_stencil * (long long)mwords <= (1LL << 40);
+  if (!rc && keep && ns_get(ctx, w, n_stencil, mwords) != DIST_OK) keep = false;  // fall back to the recompute
   if (!rc) rc = run_trace(ctx, w, n_img, hw, prm, st);
-  if (!rc) rc = run_finalize(ctx, w, n_img, hw, prm, depth, dist, normal, sil, status, nsteps, st);
+  if (!rc) rc = run_finalize(ctx, w, n_img, hw, prm, depth, dist, normal, sil, status, nsteps, st, keep);
   if (!rc && queries) hipLaunchKernelGGL(k_u64_to_i64, dim3((n_img + 255) / 256), dim3(256), 0, st, w->qcount, queries, n_img);
   if (rc) {
     ws_put(ctx, w);
@@ -721,6 +768,7 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
     s->z = z;
     s->img_latent = li;
     s->order = order;
+    s->masks_kept = keep;
     *saved = s;
   } else {
     ws_put(ctx, w);
@@ -753,7 +801,7 @@ static int reduce_only(dist_ctx* ctx, BwdSpace* b, int n_lat, float* g_z, hipStr
 }
 
 static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, int n_lat, float* g_z,
-                                  hipStream_t st) {
+                                  bool split, hipStream_t st) {
   AdjArgs aa{};
   aa.net = ctx->net[prec];
   aa.bias0_lat = w->bias0_lat;
@@ -768,11 +816,24 @@ static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int 
     TimedLaunch tl(ctx, 2, st, b->n_samples, 1);
     launch_adjoint(prec, aa, grid, st);
   }
+  if (split) {
+    // the normal-stencil samples (second list): VJP from the masks the forward kept
+    aa.n_begin = b->n_samples;
+    aa.n_samples = b->n_samples + 2;
+    aa.sample_idx = b->sample_idx;
+    aa.smask = w->ns->mask;
+    aa.sdtanh = w->ns->dtanh;
+    TimedLaunch tl(ctx, 3, st, b->n_samples + 3, 1);
+    launch_vjp_saved(prec, aa, grid, st);
+  }
   const int w0 = ctx->wpad[0];
   const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
   // every wave covers all rows of a tile, so each column sum has one row group
   launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg_base, b->seg_padded, n_lat,
                    w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
+  if (split)
+    launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg2_base, b->seg2_padded,
+                     n_lat, w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st, 0, 1);
   HIPCHK(hipGetLastError());
   return DIST_OK;
 }
@@ -869,7 +930,10 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   const int prec = adj_prec(saved->prm.precision);
   const int tile = adj_tile_rows(prec);
   const int n_img = saved->n_img, hw = saved->hw, n_lat = saved->n_lat;
-  const long long cap = (long long)n_img * hw * (saved->prm.k_samples + 6) + (long long)n_lat * tile;
+  // the weight gradient captures every row's activations, so it recomputes the
+  // stencil samples too; g_z alone uses the masks the forward kept
+  const bool split = saved->masks_kept && !g_W && g_normal != nullptr;
+  const long long cap = (long long)n_img * hw * (saved->prm.k_samples + 6) + 2LL * n_lat * tile;
   if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
   const int bpi = (hw + 255) / 256;
   const int grid = mlp_grid(ctx, cap, prec);
@@ -882,15 +946,18 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   in.g_sil = g_sil;
   in.nraw = w->nraw;
   in.delta = saved->prm.normal_delta;
+  in.hit_pix = split ? w->hit_pix : nullptr;
+  const SplitList sl{b->bsum2, b->boff2, b->seg2_base, b->seg2_total, b->seg2_padded, b->sample_idx};
   launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, tile, in, b->bsum, b->boff,
-                 b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st);
+                 b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st, 0,
+                 split ? &sl : nullptr);
   HIPCHK(hipGetLastError());
   if (g_W) {
     rc = run_theta(ctx, w, b, prec, saved->z, g_W, g_b, st);
     if (rc) return rc;
     return reduce_only(ctx, b, n_lat, g_z, st);
   }
-  return run_adjoint_and_reduce(ctx, w, b, prec, n_lat, g_z, st);
+  return run_adjoint_and_reduce(ctx, w, b, prec, n_lat, g_z, split, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,7 +1067,7 @@ extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* l
       rc = run_theta(ctx, w, b, precision, z, g_W, g_b, st);
       if (!rc) rc = reduce_only(ctx, b, n_latents, g_z, st);
     } else {
-      rc = run_adjoint_and_reduce(ctx, w, b, precision, n_latents, g_z, st);
+      rc = run_adjoint_and_reduce(ctx, w, b, precision, n_latents, g_z, false, st);
     }
     HIPCHK(hipStreamSynchronize(st));
   }

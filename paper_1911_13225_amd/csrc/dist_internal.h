@@ -92,6 +92,11 @@ struct EvalArgs {
   const ImgDesc* imgs;
   float delta;
   float* f_out;
+  // mode 1, optional: per stencil sample i = 6 h + j, the ReLU mask bits of
+  // every hidden layer ([i][nl-1][kmax/32] words) and 1 - tanh(m)^2, for a
+  // backward that skips the recompute of these samples
+  unsigned* mask_out;
+  float* dtanh_out;
 };
 
 struct AdjArgs {
@@ -110,6 +115,13 @@ struct AdjArgs {
   float* dbuf;
   float* gmbuf;
   int tile_begin, tile_end;
+  // VJP from saved masks (k_vjp_saved): samples [n_begin[0], n_samples[0]),
+  // each with its stencil index in sample_idx; masks and 1 - tanh^2 as
+  // written by the forward's stencil queries
+  const int* n_begin;
+  const int* sample_idx;
+  const unsigned* smask;
+  const float* sdtanh;
 };
 
 // Precision codes of the decoder kernels: 0 float32, 1 bfloat16, 2 split
@@ -138,6 +150,7 @@ hipError_t mlp_setup(int precision, const NetDev& net);    // raise LDS limits
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t s);
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t s);
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
+void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t s);
 
 // packing / folding
 void launch_pack_w(int precision, bool transpose, const float* W, int out, int in_stride, int ncols,

@@ -337,6 +337,23 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
 // ---------------------------------------------------------------------------
 enum { EP_ACT = 0, EP_LAST = 1, EP_ACT_MASK = 2, EP_LAST_ADJ = 3, EP_VJP = 4 };
 
+// ReLU mask bits of a tile row: word w of layer l of row m is at
+// p[row * rs + l * ls + w], with row = m (per-workgroup scratch) or, with rid,
+// the row's sample index kept in s.rid (masks saved per sample; rows with a
+// negative index are not stored).
+struct MaskRef {
+  unsigned* p;
+  int rs, ls;
+  bool rid;
+};
+
+template <int P>
+__device__ __forceinline__ int mask_row(const MaskRef& mk, const Sm<P>& s, int m) { return mk.rid ? s.rid[m] : m; }
+
+__device__ __forceinline__ size_t mask_at(const MaskRef& mk, int row, int layer, int w) {
+  return (size_t)row * mk.rs + (size_t)layer * mk.ls + w;
+}
+
 struct EpCtx {
   const float* bias;        // per-layer bias (non-skip) or null
   const float* biasS_lat;   // folded skip bias [n_lat][wpad]
@@ -345,8 +362,8 @@ struct EpCtx {
   int wpad;                 // output width of this layer (stride of biasS/wsp)
   bool skip;                // this layer reads [h, z, p]
   int layer;                // index of the layer whose output this epilogue produces
-  unsigned* mask;           // mask scratch of this workgroup
-  int ntmax;                // words per mask row
+  MaskRef mk;               // where the ReLU mask bits of each row live
+  int ntmax;                // words per mask row of one layer
   float* partial;           // adjoint column-sum output of this tile (or null)
   int which;                // 0: S0, 1: Sskip, -1: none
   bool write_act;
@@ -457,11 +474,11 @@ __device__ __forceinline__ void acc_bias(f32x16 (&acc)[MTW][NTW], const EpCtx& e
 template <int P, int MTW, int NTW, bool MASK, bool CAP>
 __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s, int nt0, int mt0,
                                        int lane) {
-  constexpr int M = Cfg<P>::M;
   const int r = lane & 31, g = lane >> 5;
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
     const int m = (mt0 + i) * 32 + r;
+    const int row = MASK ? mask_row(ec.mk, s, m) : 0;
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
       unsigned bits = 0;
@@ -480,7 +497,7 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
       }
       if constexpr (MASK) {
         bits |= __shfl_xor(bits, 32);
-        if (g == 0) ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + ((nt0 + j))] = bits;
+        if (g == 0 && row >= 0) ec.mk.p[mask_at(ec.mk, row, ec.layer, nt0 + j)] = bits;
       }
     }
   }
@@ -495,8 +512,13 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
   constexpr int M = Cfg<P>::M;
   const int r = lane & 31, g = lane >> 5;
   float sum[MTW];
+  unsigned bits[MTW][NTW];
 #pragma unroll
-  for (int i = 0; i < MTW; ++i) sum[i] = 0.f;
+  for (int i = 0; i < MTW; ++i) {
+    sum[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) bits[i][j] = 0u;
+  }
 #pragma unroll
   for (int j = 0; j < NTW; ++j)
 #pragma unroll
@@ -514,6 +536,7 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
           h[e] = fmaxf(x, 0.f);
           sum[i] = fmaf(wl[e], h[e], sum[i]);
           v[e] = x > 0.f ? wl[e] : 0.f;
+          if constexpr (ADJ) bits[i][j] |= (x > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
         }
         if constexpr (ADJ) store4<P>(s, m, n, g, v, true);
         if constexpr (CAP) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(h[0], h[1], h[2], h[3]);
@@ -521,8 +544,17 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
     }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
+    const int m = (mt0 + i) * 32 + r;
     const float t = sum[i] + __shfl_xor(sum[i], 32);
-    if (g == 0) s.part[nw * M + (mt0 + i) * 32 + r] = t;
+    if (g == 0) s.part[nw * M + m] = t;
+    if constexpr (ADJ) {
+      const int row = mask_row(ec.mk, s, m);
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        const unsigned b = bits[i][j] | __shfl_xor(bits[i][j], 32);
+        if (g == 0 && row >= 0) ec.mk.p[mask_at(ec.mk, row, ec.layer, nt0 + j)] = b;
+      }
+    }
   }
 }
 
@@ -532,7 +564,6 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
 template <int P, int MTW, int NTW, bool L0, bool CAP>
 __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
                                        int nt0, int mt0, int mg, int lane) {
-  constexpr int M = Cfg<P>::M;
   const int r = lane & 31, g = lane >> 5;
   const int N0 = net.wpad[0];
 #pragma unroll
@@ -562,7 +593,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
           for (int e = 0; e < 4; ++e) bits |= (pre[e] > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
         }
       } else {
-        bits = ec.mask[((size_t)ec.layer * M + m) * ec.ntmax + (nt0 + j)];
+        bits = ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, m), 0), ec.layer, nt0 + j)];
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -687,14 +718,14 @@ __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_l
 // hidden activation in hcap for the weight gradient.
 template <int P, bool ADJ, bool CAP>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
-                                           const Sm<P>& s, int tid, unsigned* mask, float* hcap = nullptr) {
+                                           const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr) {
   const int rstride = (net.nl - 1) * net.kmax;
   layer0_fill<P, CAP>(net, bias0_lat, s, tid, hcap, rstride);
   __syncthreads();
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
     EpCtx ec = fwd_ctx(net, biasS_lat, l);
-    ec.mask = mask;
+    ec.mk = mk;
     if constexpr (CAP) {
       ec.hrow = hcap + (size_t)l * net.kmax;
       ec.rstride = rstride;
@@ -738,7 +769,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.rid[tid] = r;
     }
     __syncthreads();
-    const int wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, nullptr);
+    const int wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -810,13 +841,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x;
   const long long count = a.mode == 0 ? a.n : 6ll * (long long)(*a.hit_count);
+  // stencil queries may keep their ReLU masks for the backward (the host
+  // only asks for it when every stencil index fits an int)
+  const bool keep = a.mode == 1 && a.mask_out != nullptr;
+  const int ntmax = a.net.kmax / 32;
+  const MaskRef mk{a.mask_out, (a.net.nl - 1) * ntmax, ntmax, true};
   for (long long tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
     if (tid < M) {
       const long long idx = tile * M + tid;
       float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-      int lt = 0, valid = 0;
+      int lt = 0, row = -1;
       if (idx < count) {
-        valid = 1;
+        row = (int)min(idx, (long long)INT_MAX);
         if (a.mode == 0) {
           p = make_float4(a.pts[3 * idx], a.pts[3 * idx + 1], a.pts[3 * idx + 2], 0.f);
           lt = min(max(a.lat[idx], 0), a.n_lat - 1);
@@ -835,16 +871,46 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       }
       s.pts[tid] = p;
       s.lat[tid] = lt;
-      s.rid[tid] = valid;
+      s.rid[tid] = row;
     }
     __syncthreads();
-    const int wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, nullptr);
-    if (tid < M && s.rid[tid]) {
+    const int wn = keep ? mlp_forward<P, true, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, mk)
+                        : mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+    if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
       a.f_out[tile * M + tid] = sdf_from_m(s.pts[tid], m);
+      if (keep) {
+        const float th = tanhf(m);
+        a.dtanh_out[tile * M + tid] = 1.f - th * th;
+      }
     }
     __syncthreads();
+  }
+}
+
+// VJP through the hidden layers l = nl-2 .. 1 for the rows of a tile whose
+// output-layer seed is in LDS (unit-delta chain; every row is weighted by its
+// factor s.gm where the column sums are taken).
+template <int P, bool CAP>
+__device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, const MaskRef& mk, float* part,
+                                           size_t row0, int rstride) {
+  const NetDev& net = a.net;
+  for (int l = net.nl - 2; l >= 1; --l) {
+    EpCtx ec{};
+    ec.bias0_lat = a.bias0_lat;
+    ec.layer = l - 1;
+    ec.mk = mk;
+    ec.ntmax = net.kmax / 32;
+    ec.partial = part;
+    ec.kmax = net.kmax;
+    ec.which = (l - 1 == 0) ? 0 : ((l - 1 == net.skip) ? 1 : -1);
+    ec.write_act = (l - 1 != 0);
+    if constexpr (CAP) {
+      ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
+      ec.rstride = rstride;
+    }
+    layer<P, EP_VJP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
   }
 }
 
@@ -862,7 +928,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   const int tid = threadIdx.x;
   const int count = *a.n_samples;
   const int ntmax = net.kmax / 32;
-  unsigned* mask = a.mask_ws + (size_t)blockIdx.x * (size_t)(net.nl) * M * ntmax;
+  const MaskRef mk{a.mask_ws + (size_t)blockIdx.x * (size_t)(net.nl) * M * ntmax, ntmax, M * ntmax, false};
   const bool theta = a.hbuf != nullptr;
   const int t_end = theta ? min(a.tile_end, (count + M - 1) / M) : (count + M - 1) / M;
   const int rstride = (net.nl - 1) * net.kmax;
@@ -877,8 +943,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.lat[tid] = a.sample_lat[idx];
     }
     __syncthreads();
-    const int wn = theta ? mlp_forward<P, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mask, hcap)
-                         : mlp_forward<P, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mask);
+    const int wn = theta ? mlp_forward<P, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
+                         : mlp_forward<P, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
     if (tid < M) {
       float m = net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -897,23 +963,48 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       }
     }
     float* part = a.partial + (size_t)tile * 4 * net.kmax;
-    for (int l = net.nl - 2; l >= 1; --l) {
-      EpCtx ec{};
-      ec.bias0_lat = a.bias0_lat;
-      ec.layer = l - 1;
-      ec.mask = mask;
-      ec.ntmax = ntmax;
-      ec.partial = part;
-      ec.kmax = net.kmax;
-      ec.which = (l - 1 == 0) ? 0 : ((l - 1 == net.skip) ? 1 : -1);
-      ec.write_act = (l - 1 != 0);
-      if (theta) {
-        ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
-        ec.rstride = rstride;
-      }
-      if (theta) layer<P, EP_VJP, true>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
-      else layer<P, EP_VJP, false>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
+    if (theta) vjp_layers<P, true>(a, s, mk, part, row0, rstride);
+    else vjp_layers<P, false>(a, s, mk, part, 0, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the normal-stencil samples from the ReLU masks their forward
+// queries kept: same seeds and VJP as k_adjoint, without the recompute.  The
+// output-layer seed w_last [h > 0] is rebuilt from the saved bits of the last
+// hidden layer, and the forward's 1 - tanh(m)^2 gives the row factor.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_vjp_saved(AdjArgs a) {
+  constexpr int M = Cfg<P>::M;
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const NetDev& net = a.net;
+  const int tid = threadIdx.x;
+  const int t0 = *a.n_begin / M, t1 = *a.n_samples / M;
+  const int ntmax = net.kmax / 32;
+  const MaskRef mk{const_cast<unsigned*>(a.smask), (net.nl - 1) * ntmax, ntmax, true};
+  const int ll = net.nl - 2, q4 = net.wpad[ll] / 4;
+  for (int tile = t0 + blockIdx.x; tile < t1; tile += gridDim.x) {
+    if (tid < M) {
+      const int idx = tile * M + tid;
+      const float4 smp = a.samples[idx];
+      const int si = a.sample_idx[idx];
+      s.pts[tid] = make_float4(smp.x, smp.y, smp.z, 0.f);
+      s.lat[tid] = a.sample_lat[idx];
+      s.rid[tid] = si;
+      s.gm[tid] = smp.w * 0.05f * a.sdtanh[si];
     }
+    __syncthreads();
+    for (int i = tid; i < M * q4; i += kThreads) {
+      const int m = i / q4, n = 4 * (i - m * q4);
+      const unsigned word = a.smask[mask_at(mk, s.rid[m], ll, n >> 5)] >> (n & 31);
+      const float4 w4 = ld4(net.wlast + n);
+      const float v[4] = {(word & 1u) ? w4.x : 0.f, (word & 2u) ? w4.y : 0.f, (word & 4u) ? w4.z : 0.f,
+                          (word & 8u) ? w4.w : 0.f};
+      store4<P>(s, m, n, (n >> 2) & 1, v, true);
+    }
+    __syncthreads();
+    vjp_layers<P, false>(a, s, mk, a.partial + (size_t)tile * 4 * net.kmax, 0, 0);
   }
 }
 
@@ -990,6 +1081,8 @@ static hipError_t setup_p(int bytes) {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_eval<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_vjp_saved<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_adjoint<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -1011,6 +1104,7 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_march, a); }
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_eval, a); }
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_adjoint, a); }
+void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_vjp_saved, a); }
 
 // ---------------------------------------------------------------------------
 // Weight packing into MFMA A-operand fragments.

@@ -15,6 +15,7 @@ struct FinalizeOut {
   int* hits;
   int* hit_count;
   int want_hits;
+  int* hit_pix;      // per output pixel: its index in hits, -1 if none (or null)
 };
 
 // One image that starts rays this tick: split into level `lvl` (split = 1) or
@@ -30,6 +31,17 @@ struct SeedIn {
   const float* g_sil;
   const float4* nraw;
   float delta;
+  const int* hit_pix;  // split layout: per output pixel, its index in the forward's hit list
+};
+
+// Second sample list of the split layout (normal-stencil samples).
+struct SplitList {
+  int* bsum;
+  int* boff;
+  int* seg_base;
+  int* seg_total;
+  int* seg_padded;
+  int* sample_idx;
 };
 
 void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_rays, int* list,
@@ -45,12 +57,12 @@ void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, con
 void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
                     int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
                     int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s,
-                    int lat_fixed = 0);
+                    int lat_fixed = 0, const SplitList* split = nullptr);
 void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
                         int* sample_lat, hipStream_t s);
 void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
                       const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,
-                      const float* Wsz, int L, float* gz, hipStream_t s, int lat0 = 0);
+                      const float* Wsz, int L, float* gz, hipStream_t s, int lat0 = 0, int accumulate = 0);
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s);
 void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
                     int* out_count, const AdvEntry* table, const int* hdr, int* img_active,

@@ -12,8 +12,9 @@ namespace dist {
 // helpers
 // ---------------------------------------------------------------------------
 // Append `value` to list for every thread with flag set; one atomic per
-// 256-thread block.  Must be called by all threads of the block.
-__device__ __forceinline__ void block_append(bool flag, int value, int* list, int* counter) {
+// 256-thread block.  Must be called by all threads of the block.  Returns the
+// list position of a flagged thread's entry (-1 for the others).
+__device__ __forceinline__ int block_append(bool flag, int value, int* list, int* counter) {
   __shared__ int wcnt[4];
   __shared__ int base;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -30,6 +31,7 @@ __device__ __forceinline__ void block_append(bool flag, int value, int* list, in
   for (int i = 0; i < w; ++i) off += wcnt[i];
   if (flag) list[off + within] = value;
   __syncthreads();
+  return flag ? off + within : -1;
 }
 
 // Level-`lvl` ray through the centre of block (U, V): unit world direction and
@@ -214,7 +216,8 @@ __global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* img
     if (o.normal && !hit) { o.normal[3 * q] = 0.f; o.normal[3 * q + 1] = 0.f; o.normal[3 * q + 2] = 0.f; }
     if (o.nraw) o.nraw[q] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  block_append(hit && o.want_hits, r, o.hits, o.hit_count);
+  const int h = block_append(hit && o.want_hits, r, o.hits, o.hit_count);
+  if (o.hit_pix && pix < hw) o.hit_pix[(size_t)im.out_base + pix] = h;
 }
 
 // Normals from the six central-difference queries of each hit (Sec. 3.3).
@@ -265,40 +268,54 @@ __device__ __forceinline__ PixSamples pixel_samples(const RayPool& pl, const Img
   return ps;
 }
 
+// Per block of 256 pixels: the number of gradient samples.  With bsum2 (the
+// split layout) the record samples and the normal-stencil samples are counted
+// for two separate lists; otherwise a pixel's stencil samples follow its
+// record samples in one list.
 __global__ __launch_bounds__(256) void k_samples_count(RayPool pl, const ImgDesc* imgs, const int* img_order,
-                                                       SeedIn in, int* bsum) {
-  __shared__ int red[256];
+                                                       SeedIn in, int* bsum, int* bsum2) {
+  __shared__ int red[256], red2[256];
   const int img = img_order[blockIdx.y];
   const ImgDesc& im = imgs[img];
   const int hw = im.H * im.W;
   const int pix = blockIdx.x * 256 + threadIdx.x;
-  int c = 0;
+  int c = 0, c2 = 0;
   if (pix < hw) {
     const PixSamples ps = pixel_samples(pl, im, im.slot_base + im.lvl_off[0] + pix, (size_t)im.out_base + pix, in);
-    c = ps.base + ps.nn;
+    c = bsum2 ? ps.base : ps.base + ps.nn;
+    c2 = ps.nn;
   }
   red[threadIdx.x] = c;
+  red2[threadIdx.x] = c2;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if (threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      red2[threadIdx.x] += red2[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) bsum[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    if (bsum2) bsum2[blockIdx.y * gridDim.x + blockIdx.x] = red2[0];
+  }
 }
 
 // One workgroup: exclusive scan of the block sums in image order, restarting
 // the padding at every latent segment so that each segment starts at a
-// multiple of the adjoint tile.  seg_* are indexed by latent id.
+// multiple of the adjoint tile.  seg_* are indexed by latent id.  The list
+// starts at *pos0 (0 if null); n_out[0] receives its end, n_out[1] its length.
 __global__ __launch_bounds__(1024) void k_samples_scan(const int* bsum, int n_img, int bpi, const int* img_order,
                                                        const int* img_latent, int lat_fixed, int tile, int n_lat,
                                                        int* boff, int* seg_base, int* seg_total, int* seg_padded,
-                                                       int* n_samples) {
+                                                       const int* pos0, int* n_out) {
   __shared__ int buf[1024];
   __shared__ int carry_s;
   const int tid = threadIdx.x;
-  for (int l = tid; l < n_lat; l += 1024) { seg_base[l] = 0; seg_total[l] = 0; seg_padded[l] = 0; }
+  const int start = pos0 ? *pos0 : 0;
+  for (int l = tid; l < n_lat; l += 1024) { seg_base[l] = start; seg_total[l] = 0; seg_padded[l] = 0; }
   __syncthreads();
-  int pos = 0;              // running padded offset (uniform)
+  int pos = start;          // running padded offset (uniform)
   int i0 = 0;
   while (i0 < n_img) {
     const int lat = img_latent ? img_latent[img_order[i0]] : lat_fixed;
@@ -332,12 +349,32 @@ __global__ __launch_bounds__(1024) void k_samples_scan(const int* bsum, int n_im
     i0 = i1;
     __syncthreads();
   }
-  if (tid == 0) *n_samples = pos;
+  if (tid == 0) {
+    n_out[0] = pos;
+    n_out[1] = pos - start;
+  }
 }
 
+// Block-wide exclusive prefix of c over the 256 threads (all threads call).
+__device__ __forceinline__ int block_excl_scan(int c, int* buf) {
+  buf[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int x = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+    __syncthreads();
+    buf[threadIdx.x] += x;
+    __syncthreads();
+  }
+  return buf[threadIdx.x] - c;
+}
+
+// Writes each pixel's samples at the offsets of the scans.  With boff2 (split
+// layout) the stencil samples go to the second list, each with its stencil
+// index 6 h + j (h = the pixel's hit index in the forward's hit list), so that
+// their adjoint can use the masks the forward kept.
 __global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc* imgs, const int* img_order,
-                                                       SeedIn in, const int* boff, float4* samples,
-                                                       int* sample_lat) {
+                                                       SeedIn in, const int* boff, const int* boff2, float4* samples,
+                                                       int* sample_lat, int* sample_idx) {
   __shared__ int buf[256];
   const int img = img_order[blockIdx.y];
   const ImgDesc& im = imgs[img];
@@ -351,17 +388,15 @@ __global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc
     q = (size_t)im.out_base + pix;
     ps = pixel_samples(pl, im, r, q, in);
   }
-  const int c = ps.base + ps.nn;
-  buf[threadIdx.x] = c;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int x = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+  const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+  const int c = boff2 ? ps.base : ps.base + ps.nn;
+  int o = boff[blk] + block_excl_scan(c, buf);
+  int o2 = 0;
+  if (boff2) {
     __syncthreads();
-    buf[threadIdx.x] += x;
-    __syncthreads();
+    o2 = boff2[blk] + block_excl_scan(ps.nn, buf);
   }
-  int o = boff[blockIdx.y * gridDim.x + blockIdx.x] + buf[threadIdx.x] - c;
-  if (c == 0) return;
+  if (ps.base + ps.nn == 0) return;
   const float4 d = pl.d[r];
   const float cx = im.c[0], cy = im.c[1], cz = im.c[2];
   const int V = pix / im.W, U = pix - V * im.W;
@@ -392,26 +427,31 @@ __global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc
     const float dist = d.w + pl.flast[r];
     const float p[3] = {fmaf(dist, d.x, cx), fmaf(dist, d.y, cy), fmaf(dist, d.z, cz)};
     const float s2 = 1.f / (2.f * in.delta);
+    const int h = boff2 ? in.hit_pix[q] : 0;
     for (int j = 0; j < 6; ++j) {
       const int ax = j >> 1;
       float qv[3] = {p[0], p[1], p[2]};
       qv[ax] = (j & 1) ? qv[ax] - in.delta : qv[ax] + in.delta;
       const float seed = (j & 1) ? -gv[ax] * s2 : gv[ax] * s2;
-      samples[o] = make_float4(qv[0], qv[1], qv[2], seed);
-      sample_lat[o] = im.latent;
-      ++o;
+      const int at = boff2 ? o2++ : o++;
+      samples[at] = make_float4(qv[0], qv[1], qv[2], seed);
+      sample_lat[at] = im.latent;
+      if (boff2) sample_idx[at] = 6 * h + j;
     }
   }
 }
 
-// Padding samples (zero seed) at the end of each latent segment.
+// Padding samples (zero seed) at the end of each latent segment; their
+// stencil index (split layout) is 0, a valid entry whose contribution the zero
+// seed cancels.
 __global__ void k_samples_pad(const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
-                              int* sample_lat) {
+                              int* sample_lat, int* sample_idx) {
   const int l = blockIdx.x;
   const int b = seg_base[l], t = seg_total[l], p = seg_padded[l];
   for (int i = t + threadIdx.x; i < p; i += blockDim.x) {
     samples[b + i] = make_float4(0.f, 0.f, 0.f, 0.f);
     sample_lat[b + i] = l;
+    if (sample_idx) sample_idx[b + i] = 0;
   }
 }
 
@@ -437,7 +477,8 @@ __global__ __launch_bounds__(512) void k_gz_fold(float* partial, int kmax, int t
 
 __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base,
                                                    const int* seg_padded, int w0, int mg0, const float* W0z,
-                                                   int ws, int mgs, const float* Wsz, int L, float* gz, int lat0) {
+                                                   int ws, int mgs, const float* Wsz, int L, float* gz, int lat0,
+                                                   int accumulate) {
   __shared__ float S0[512];
   __shared__ float Ss[512];
   const int l = lat0 + blockIdx.x;
@@ -459,7 +500,7 @@ __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kma
     for (int n = 0; n < w0; ++n) acc = fmaf(W0z[(size_t)n * L + j], S0[n], acc);
     if (Wsz)
       for (int n = 0; n < ws; ++n) acc = fmaf(Wsz[(size_t)n * L + j], Ss[n], acc);
-    gz[(size_t)l * L + j] = acc;
+    gz[(size_t)l * L + j] = accumulate ? gz[(size_t)l * L + j] + acc : acc;
   }
 }
 
@@ -634,28 +675,37 @@ void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, con
 void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
                     int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
                     int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s,
-                    int lat_fixed) {
+                    int lat_fixed, const SplitList* sl) {
   const int bpi = (int)nblk(hw, 256);
-  hipLaunchKernelGGL(k_samples_count, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, bsum);
+  const bool split = sl != nullptr && in.hit_pix != nullptr;
+  hipLaunchKernelGGL(k_samples_count, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, bsum,
+                     split ? sl->bsum : nullptr);
   hipLaunchKernelGGL(k_samples_scan, dim3(1), dim3(1024), 0, s, bsum, n_img, bpi, img_order, img_latent, lat_fixed,
-                     tile, n_lat, boff, seg_base, seg_total, seg_padded, n_samples);
-  hipLaunchKernelGGL(k_samples_write, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, boff, samples,
-                     sample_lat);
+                     tile, n_lat, boff, seg_base, seg_total, seg_padded, nullptr, n_samples);
+  if (split)
+    hipLaunchKernelGGL(k_samples_scan, dim3(1), dim3(1024), 0, s, sl->bsum, n_img, bpi, img_order, img_latent,
+                       lat_fixed, tile, n_lat, sl->boff, sl->seg_base, sl->seg_total, sl->seg_padded, n_samples,
+                       n_samples + 2);
+  hipLaunchKernelGGL(k_samples_write, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, boff,
+                     split ? sl->boff : nullptr, samples, sample_lat, split ? sl->sample_idx : nullptr);
   hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
-                     sample_lat);
+                     sample_lat, nullptr);
+  if (split)
+    hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, sl->seg_base, sl->seg_total, sl->seg_padded,
+                       samples, sample_lat, sl->sample_idx);
 }
 void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
                         int* sample_lat, hipStream_t s) {
   hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
-                     sample_lat);
+                     sample_lat, nullptr);
 }
 void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
                       const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,
-                      const float* Wsz, int L, float* gz, hipStream_t s, int lat0) {
+                      const float* Wsz, int L, float* gz, hipStream_t s, int lat0, int accumulate) {
   hipLaunchKernelGGL(k_gz_fold, dim3(nblk(max_tiles, kFold), n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base,
                      seg_padded, lat0);
   hipLaunchKernelGGL(k_gz_reduce, dim3(n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base, seg_padded, w0, mg0,
-                     W0z, ws, mgs, Wsz, L, gz, lat0);
+                     W0z, ws, mgs, Wsz, L, gz, lat0, accumulate);
 }
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s) {
   hipLaunchKernelGGL(k_apply_levels, dim3(nblk(max_entries > 0 ? max_entries : 1, 256)), dim3(256), 0, s, imgs, table,

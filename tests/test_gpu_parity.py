@@ -378,6 +378,40 @@ def test_backward_is_deterministic():
     assert torch.equal(res[0][1], res[1][1])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_backward_saved_masks_match_recompute(precision):
+    """The normal-stencil adjoint from the masks the forward kept equals the
+    one that recomputes those samples (up to the order of the g_z sums), runs
+    the saved-mask kernel, and is bitwise reproducible."""
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    prm = cfg_params("c3", precision=precision)
+    cams = di.random_sphere_cameras(3, 48, 48)
+    Z = torch.tensor(di.make_latents(2, spec.latent_dim, sigma=0.05), device="cuda")
+    ctx = ctx_for(spec)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    runs = []
+    for _ in range(2):
+        out = api.dist_render_fwd(ctx, cams, Z, prm, save=True)
+        hit = (out["status"] == 1).float()
+        g_d = hit * torch.randn(out["depth"].shape, device="cuda", generator=gen) * 1e-2
+        g_n = hit[..., None] * torch.randn(out["normal"].shape, device="cuda", generator=gen) * 1e-2
+        g_s = torch.where(out["sil"] < 0, -1.0, 1.0) * 1e-3
+        gen.manual_seed(5)
+        api.dist_timing_enable(ctx, True)
+        g_saved = api.dist_render_bwd(ctx, out["saved"], g_d, g_n, g_s, n_latents=2)
+        n_vjp = api.dist_timing_read(ctx, 3)[0]
+        api.dist_timing_enable(ctx, False)
+        g_full = api.dist_render_bwd(ctx, out["saved"], g_d, g_n, g_s, n_latents=2, want_theta=True)[0]
+        out["saved"].free()
+        runs.append(g_saved.clone())
+        rel = float((g_saved - g_full).norm() / g_full.norm())
+        _log("saved-mask adjoint precision", precision, "vjp launches", n_vjp, "rel vs recompute", rel)
+        assert n_vjp == 1
+        assert rel <= 2e-5
+    assert torch.equal(runs[0], runs[1])
+
+
 # ----------------------------------------------------------------------------
 # full-size workload, sampled pixels
 # ----------------------------------------------------------------------------
