@@ -35,6 +35,7 @@ struct BwdSpace {
   int *bsum2 = nullptr, *boff2 = nullptr;
   int *seg2_base = nullptr, *seg2_total = nullptr, *seg2_padded = nullptr;
   int* sample_idx = nullptr;
+  float* partial2 = nullptr;       // column sums of the second list's tiles
 };
 
 // ReLU masks and 1 - tanh(m)^2 of the forward's normal-stencil queries, kept

@@ -394,6 +394,7 @@ static void bw_layout(BwdSpace& w, Carver& c) {
   w.seg2_total = c.take<int>(w.cap_lat);
   w.seg2_padded = c.take<int>(w.cap_lat);
   w.sample_idx = c.take<int>(w.cap_samples);
+  w.partial2 = c.take<float>((size_t)(w.cap_samples / w.tile + 1) * 4 * kMaxWidth);
 }
 
 static int ws_get(dist_ctx* ctx, int cap_rays, int cap_pix, int cap_img, int cap_lat, int cap_steps,
@@ -790,6 +791,7 @@ extern "C" int dist_saved_free(dist_saved* s) {
 // ReLU pattern must match the float32 network; a bf16 recompute flips units
 // near zero) and back-propagates in bf16.
 static int adj_prec(int render_prec) { return render_prec == DIST_FP32 ? kPrecF32 : kPrecSplit; }
+static int vjp_prec(int adj) { return adj == kPrecSplit ? kPrecBF16 : adj; }
 
 static int reduce_only(dist_ctx* ctx, BwdSpace* b, int n_lat, float* g_z, hipStream_t st) {
   const int w0 = ctx->wpad[0];
@@ -817,23 +819,32 @@ static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int 
     launch_adjoint(prec, aa, grid, st);
   }
   if (split) {
-    // the normal-stencil samples (second list): VJP from the masks the forward kept
+    // the normal-stencil samples (second list): VJP from the masks the forward
+    // kept, in the 128-row bf16 tile for bf16 renders (the VJP of the split
+    // recompute is a plain bf16 product either way)
+    const int vp = vjp_prec(prec);
+    aa.net = ctx->net[vp];
+    aa.partial = b->partial2;
     aa.n_begin = b->n_samples;
     aa.n_samples = b->n_samples + 2;
     aa.sample_idx = b->sample_idx;
     aa.smask = w->ns->mask;
     aa.sdtanh = w->ns->dtanh;
-    TimedLaunch tl(ctx, 3, st, b->n_samples + 3, 1);
-    launch_vjp_saved(prec, aa, grid, st);
+    {
+      TimedLaunch tl(ctx, 3, st, b->n_samples + 3, 1);
+      launch_vjp_saved(vp, aa, mlp_grid(ctx, b->cap_samples, vp), st);
+    }
   }
   const int w0 = ctx->wpad[0];
   const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
   // every wave covers all rows of a tile, so each column sum has one row group
   launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg_base, b->seg_padded, n_lat,
                    w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
-  if (split)
-    launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg2_base, b->seg2_padded,
-                     n_lat, w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st, 0, 1);
+  if (split) {
+    const int vt = adj_tile_rows(vjp_prec(prec));
+    launch_gz_reduce(b->partial2, ctx->kmax, vt, b->cap_samples / vt + 1, b->seg2_base, b->seg2_padded, n_lat, w0, 1,
+                     ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st, 0, 1);
+  }
   HIPCHK(hipGetLastError());
   return DIST_OK;
 }
@@ -933,7 +944,9 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   // the weight gradient captures every row's activations, so it recomputes the
   // stencil samples too; g_z alone uses the masks the forward kept
   const bool split = saved->masks_kept && !g_W && g_normal != nullptr;
-  const long long cap = (long long)n_img * hw * (saved->prm.k_samples + 6) + 2LL * n_lat * tile;
+  // sample lists are padded per latent to a multiple of both kernels' tiles
+  const int pad = split ? std::max(tile, adj_tile_rows(vjp_prec(prec))) : tile;
+  const long long cap = (long long)n_img * hw * (saved->prm.k_samples + 6) + 2LL * n_lat * pad;
   if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
   const int bpi = (hw + 255) / 256;
   const int grid = mlp_grid(ctx, cap, prec);
@@ -948,7 +961,7 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   in.delta = saved->prm.normal_delta;
   in.hit_pix = split ? w->hit_pix : nullptr;
   const SplitList sl{b->bsum2, b->boff2, b->seg2_base, b->seg2_total, b->seg2_padded, b->sample_idx};
-  launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, tile, in, b->bsum, b->boff,
+  launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, pad, in, b->bsum, b->boff,
                  b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st, 0,
                  split ? &sl : nullptr);
   HIPCHK(hipGetLastError());

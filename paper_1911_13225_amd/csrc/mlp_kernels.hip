@@ -373,6 +373,21 @@ struct EpCtx {
   int rstride;
 };
 
+// 1 if x > 0, else 0, as an integer clamp med3(bits, 0, 1) of the float's bits
+// (no compare, so no lane-mask registers; a NaN with a clear sign bit counts
+// as positive).  Written as one instruction: the compiler would turn the
+// equivalent min/max back into a compare and a select.
+__device__ __forceinline__ unsigned pos_bit(float x) {
+  unsigned r;
+  asm("v_med3_i32 %0, %1, 0, 1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// x if bit b of m is set, else 0 (a bit-field extract and an AND, no compare)
+__device__ __forceinline__ float keep_if(float x, unsigned m, int b) {
+  return __uint_as_float(__float_as_uint(x) & (0u - ((m >> b) & 1u)));
+}
+
 // Lane (r, g) of a wave holds in acc[i][j][4q + e] the output feature
 // n = (nt0 + j) * 32 + 8q + 4g + e of tile row m = (mt0 + i) * 32 + r.
 __device__ __forceinline__ int feat(int nt0, int j, int q, int g) { return (nt0 + j) * 32 + 8 * q + 4 * g; }
@@ -424,11 +439,11 @@ __device__ __forceinline__ void acc_zero(f32x16 (&acc)[MTW][NTW]) {
 // Forward layers start the accumulation from the bias, so the epilogue only
 // applies the ReLU.  The skip layer's bias is the per-latent folded bias plus
 // the float32 point columns W_p p of the row.
-template <int P, int MTW, int NTW>
+template <int P, int MTW, int NTW, bool SKIP>
 __device__ __forceinline__ void acc_bias(f32x16 (&acc)[MTW][NTW], const EpCtx& ec, const Sm<P>& s, int nt0, int mt0,
                                          int lane) {
   const int r = lane & 31, g = lane >> 5;
-  if (!ec.skip) {
+  if constexpr (!SKIP) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j)
 #pragma unroll
@@ -442,31 +457,31 @@ __device__ __forceinline__ void acc_bias(f32x16 (&acc)[MTW][NTW], const EpCtx& e
           acc[i][j][4 * q + 3] = b.w;
         }
       }
-    return;
-  }
-  float4 p[MTW];
-  const float* bl[MTW];
+  } else {
+    float4 p[MTW];
+    const float* bl[MTW];
 #pragma unroll
-  for (int i = 0; i < MTW; ++i) {
-    const int m = (mt0 + i) * 32 + r;
-    p[i] = s.pts[m];
-    bl[i] = ec.biasS_lat + (size_t)s.lat[m] * ec.wpad;
-  }
-#pragma unroll
-  for (int j = 0; j < NTW; ++j)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int n = feat(nt0, j, q, g);
-      const float4 wx = ld4(ec.wsp + n), wy = ld4(ec.wsp + ec.wpad + n), wz = ld4(ec.wsp + 2 * ec.wpad + n);
-#pragma unroll
-      for (int i = 0; i < MTW; ++i) {
-        const float4 b = ld4(bl[i] + n);
-        acc[i][j][4 * q] = fmaf(wx.x, p[i].x, fmaf(wy.x, p[i].y, fmaf(wz.x, p[i].z, b.x)));
-        acc[i][j][4 * q + 1] = fmaf(wx.y, p[i].x, fmaf(wy.y, p[i].y, fmaf(wz.y, p[i].z, b.y)));
-        acc[i][j][4 * q + 2] = fmaf(wx.z, p[i].x, fmaf(wy.z, p[i].y, fmaf(wz.z, p[i].z, b.z)));
-        acc[i][j][4 * q + 3] = fmaf(wx.w, p[i].x, fmaf(wy.w, p[i].y, fmaf(wz.w, p[i].z, b.w)));
-      }
+    for (int i = 0; i < MTW; ++i) {
+      const int m = (mt0 + i) * 32 + r;
+      p[i] = s.pts[m];
+      bl[i] = ec.biasS_lat + (size_t)s.lat[m] * ec.wpad;
     }
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = feat(nt0, j, q, g);
+        const float4 wx = ld4(ec.wsp + n), wy = ld4(ec.wsp + ec.wpad + n), wz = ld4(ec.wsp + 2 * ec.wpad + n);
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) {
+          const float4 b = ld4(bl[i] + n);
+          acc[i][j][4 * q] = fmaf(wx.x, p[i].x, fmaf(wy.x, p[i].y, fmaf(wz.x, p[i].z, b.x)));
+          acc[i][j][4 * q + 1] = fmaf(wx.y, p[i].x, fmaf(wy.y, p[i].y, fmaf(wz.y, p[i].z, b.y)));
+          acc[i][j][4 * q + 2] = fmaf(wx.z, p[i].x, fmaf(wy.z, p[i].y, fmaf(wz.z, p[i].z, b.z)));
+          acc[i][j][4 * q + 3] = fmaf(wx.w, p[i].x, fmaf(wy.w, p[i].y, fmaf(wz.w, p[i].z, b.w)));
+        }
+      }
+  }
 }
 
 // Hidden layer output: relu to LDS (+ ReLU mask bits for the adjoint, + a float32
@@ -488,7 +503,7 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
         const float x[4] = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
         if constexpr (MASK) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) bits |= (x[e] > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
+          for (int e = 0; e < 4; ++e) bits |= pos_bit(x[e]) << (8 * q + 4 * g + e);
         }
         store4_relu<P>(s, m, n, g, x);
         if constexpr (CAP)
@@ -535,8 +550,9 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
           const float x = acc[i][j][4 * q + e];
           h[e] = fmaxf(x, 0.f);
           sum[i] = fmaf(wl[e], h[e], sum[i]);
-          v[e] = x > 0.f ? wl[e] : 0.f;
-          if constexpr (ADJ) bits[i][j] |= (x > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
+          const unsigned b = pos_bit(x);
+          v[e] = __uint_as_float(__float_as_uint(wl[e]) & (0u - b));
+          if constexpr (ADJ) bits[i][j] |= b << (8 * q + 4 * g + e);
         }
         if constexpr (ADJ) store4<P>(s, m, n, g, v, true);
         if constexpr (CAP) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(h[0], h[1], h[2], h[3]);
@@ -590,7 +606,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
                                 fmaf(wx.z, p.x, fmaf(wy.z, p.y, fmaf(wz.z, p.z, b.z))),
                                 fmaf(wx.w, p.x, fmaf(wy.w, p.y, fmaf(wz.w, p.z, b.w)))};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) bits |= (pre[e] > 0.f ? 1u : 0u) << (8 * q + 4 * g + e);
+          for (int e = 0; e < 4; ++e) bits |= pos_bit(pre[e]) << (8 * q + 4 * g + e);
         }
       } else {
         bits = ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, m), 0), ec.layer, nt0 + j)];
@@ -598,8 +614,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (!((bits >> (8 * q + 4 * g + e)) & 1u)) acc[i][j][4 * q + e] = 0.f;
+        for (int e = 0; e < 4; ++e) acc[i][j][4 * q + e] = keep_if(acc[i][j][4 * q + e], bits, 8 * q + 4 * g + e);
       if (ec.write_act) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -654,7 +669,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
 // Run one layer (accumulator init + GEMM + barrier + epilogue + barrier) for an
 // output width N (128, 256 or 512 after padding): the 4 waves split N into 4
 // groups of N/4 outputs and each covers all rows of the tile.
-template <int P, int MTW, int NTW, int MODE, bool CAP>
+template <int P, int MTW, int NTW, int MODE, bool CAP, bool SKIP>
 __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                           const void* wlo, int ksteps) {
   constexpr int WN = 4;
@@ -665,7 +680,7 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   const int nt0 = nw * NTW, mt0 = mg * MTW;
   f32x16 acc[MTW][NTW];
   if constexpr (MODE == EP_VJP) acc_zero<MTW, NTW>(acc);
-  else acc_bias<P, MTW, NTW>(acc, ec, s, nt0, mt0, lane);
+  else acc_bias<P, MTW, NTW, SKIP>(acc, ec, s, nt0, mt0, lane);
   if constexpr (P == 1) {
     gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane);
   } else if constexpr (P == 2) {
@@ -687,14 +702,15 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
 
 // One layer of output width N and contracted width K; returns the number of
 // wave groups that wrote output-layer partial sums.
-template <int P, int MODE, bool CAP>
+// SKIP: the layer reads [h, z, p] (its bias is per latent plus W_p p).
+template <int P, int MODE, bool CAP, bool SKIP = false>
 __device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                      const void* wlo, int N, int K) {
   constexpr int MT = Cfg<P>::MT;
   const int ksteps = K / (P ? 16 : 8);
-  if (N == 512) layer_run<P, MT, 4, MODE, CAP>(net, ec, s, wp, wlo, ksteps);
-  else if (N == 256) layer_run<P, MT, 2, MODE, CAP>(net, ec, s, wp, wlo, ksteps);
-  else layer_run<P, MT, 1, MODE, CAP>(net, ec, s, wp, wlo, ksteps);
+  if (N == 512) layer_run<P, MT, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps);
+  else if (N == 256) layer_run<P, MT, 2, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps);
+  else layer_run<P, MT, 1, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps);
   return 4;
 }
 
@@ -730,8 +746,12 @@ __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0
       ec.hrow = hcap + (size_t)l * net.kmax;
       ec.rstride = rstride;
     }
+    // the skip layer is never the last hidden layer (skip <= nl - 3)
     if (l == net.nl - 2)
       wn = layer<P, ADJ ? EP_LAST_ADJ : EP_LAST, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
+    else if (l == net.skip)
+      wn = layer<P, ADJ ? EP_ACT_MASK : EP_ACT, CAP, true>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l],
+                                                           net.kpad[l]);
     else
       wn = layer<P, ADJ ? EP_ACT_MASK : EP_ACT, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
   }
@@ -843,7 +863,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
   const long long count = a.mode == 0 ? a.n : 6ll * (long long)(*a.hit_count);
   // stencil queries may keep their ReLU masks for the backward (the host
   // only asks for it when every stencil index fits an int)
-  const bool keep = a.mode == 1 && a.mask_out != nullptr;
+  const bool keep = P != kPrecBF16 && a.mode == 1 && a.mask_out != nullptr;
   const int ntmax = a.net.kmax / 32;
   const MaskRef mk{a.mask_out, (a.net.nl - 1) * ntmax, ntmax, true};
   for (long long tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
@@ -874,8 +894,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.rid[tid] = row;
     }
     __syncthreads();
-    const int wn = keep ? mlp_forward<P, true, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, mk)
-                        : mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+    int wn;
+    if constexpr (P != kPrecBF16)
+      wn = keep ? mlp_forward<P, true, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, mk)
+                : mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+    else
+      wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
