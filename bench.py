@@ -262,6 +262,51 @@ def kernel_micro(n=1 << 21):
     return out
 
 
+def zopt_run(iters=200, n_views=4, H=256, precision=1):
+    """Latent-code fitting: Adam (lr 1e-2) on z from N(0, 0.01^2) towards
+    depth/silhouette maps rendered from z* ~ N(0, 0.1^2); 10 L1 + silhouette."""
+    import torch
+    import dist_inputs as di
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    ctx = api.Context.from_spec(spec, Ws, bs)
+    cams = di.random_sphere_cameras(n_views, H, H)
+    prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=2, k_samples=1, precision=precision,
+                         want_normals=0)
+    zs = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.1, base_seed=3000), device="cuda")
+    tgt = api.dist_render_fwd(ctx, cams, zs, prm)
+    dt = torch.where(torch.isfinite(tgt["depth"]), tgt["depth"], torch.zeros_like(tgt["depth"]))
+    st = (tgt["sil"] < 0).float()
+    nz = torch.zeros(dt.shape + (3,), device="cuda")
+    z = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=1000), device="cuda",
+                     requires_grad=True)
+    d0 = float((z.detach() - zs).norm())
+    opt = torch.optim.Adam([z], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    curve = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(iters):
+        depth, _, sil, _ = api.DistRender.apply(z, ctx, cams, prm)
+        L = api.render_loss(depth, nz, sil, dt, nz, st, w_d=10.0, w_s=1.0, w_n=0.0)
+        opt.zero_grad()
+        L.backward()
+        opt.step()
+        if it in (0, 1, 10, 50, 100, iters - 1):
+            curve[it] = round(float(L), 6)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    with torch.no_grad():
+        out = api.dist_render_fwd(ctx, cams, z.detach(), prm)
+        fg = (out["sil"] < 0) & (st > 0.5)
+        derr = float((out["depth"] - dt).abs()[fg].mean()) if bool(fg.any()) else None
+    ctx.close()
+    return {"iters": iters, "views": n_views, "resolution": H, "precision": "bf16" if precision else "fp32",
+            "its_per_s": round(iters / sec, 2), "loss": curve,
+            "z_dist_rel": {"start": 1.0, "end": round(float((z.detach() - zs).norm()) / d0, 4)},
+            "final_depth_abs_err_fg": derr}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +318,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=10.0)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--no-micro", action="store_true")
+    ap.add_argument("--no-zopt", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (reference dispatch for HBM byte counters)")
     a = ap.parse_args()
@@ -352,6 +398,11 @@ def main():
                           "queries_per_s": round(r3["queries"] / r3["sec"], 1)}
             del w
         res["single_image"] = single
+
+    if not a.no_zopt:
+        log("[bench] latent fit, 4 views 256x256, 200 Adam iterations")
+        res["latent_fit"] = zopt_run()
+        log("[bench] latent fit", res["latent_fit"])
 
     if not a.no_serve:
         log("[bench] serving stream")

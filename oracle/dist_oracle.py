@@ -605,3 +605,14 @@ def k_min(eps, d, alpha, theta):
     """App. A.1: smallest k with |d (1 - alpha sin theta)^k| < eps is the first
     integer above (log eps - log d) / log|1 - alpha sin theta|."""
     return (math.log(eps) - math.log(d)) / math.log(abs(1.0 - alpha * math.sin(theta)))
+
+
+def adam_step(z, g, m, v, t, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba 2015, Alg. 1), the optimiser the paper uses
+    for latent-code fitting (App. B.4: learning rate 1e-2).  t counts from 1.
+    Returns the new (z, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return z - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -638,15 +638,19 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
     const long long rays = (long long)n_img * (hw >> (2 * lv));
     ma.list = w->list[n & 1];
     ma.count = w->counters + n;
+    // every image splits after the same steps: then the children replace the
+    // rays, otherwise the march step appends its survivors to the next list
+    const bool split = n % 3 == 2 && lv > 0;
+    int* nxt = w->list[(n + 1) & 1];
+    int* ncnt = w->counters + n + 1;
+    ma.next_list = split ? nullptr : nxt;
+    ma.next_count = split ? nullptr : ncnt;
     {
       TimedLaunch tl(ctx, 0, st, ma.count, 1);
       launch_march(prec, ma, mlp_grid(ctx, rays, prec), st);
     }
-    int* nxt = w->list[(n + 1) & 1];
-    int* ncnt = w->counters + n + 1;
-    if (n % 3 == 2 && lv > 0)
+    if (split)
       launch_split(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * (lv - 1)), lv - 1, n + 1, nxt, ncnt, st);
-    launch_compact(w->pool, w->imgs, w->list[n & 1], w->counters + n, (int)rays, nxt, ncnt, nullptr, st);
   }
   HIPCHK(hipGetLastError());
   return DIST_OK;

@@ -75,6 +75,10 @@ struct MarchArgs {
   const int* list;                 // active ray slots
   const int* count;                // number of entries in list
   unsigned long long* qcount;      // per-image decoder queries (or null)
+  // rays still ACTIVE after the step are appended here (null: the caller
+  // builds the next list itself, e.g. at a coarse-to-fine split)
+  int* next_list;
+  int* next_count;
 };
 
 struct EvalArgs {

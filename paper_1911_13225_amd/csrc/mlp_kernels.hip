@@ -763,6 +763,27 @@ __device__ __forceinline__ float sdf_from_m(float4 p, float m) {
   return 0.5f * (r - 0.5f) + 0.05f * tanhf(m);
 }
 
+// Append `value` for every thread with flag set; one atomic per workgroup.
+// Called by all threads of the workgroup.
+__device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* counter) {
+  __shared__ int wcnt[kThreads / 64];
+  __shared__ int base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(flag);
+  const int within = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wcnt[w] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < kThreads / 64; ++i) tot += wcnt[i];
+    base = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
+  int off = base;
+  for (int i = 0; i < w; ++i) off += wcnt[i];
+  if (flag) list[off + within] = value;
+}
+
 // ---------------------------------------------------------------------------
 // March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
 // ---------------------------------------------------------------------------
@@ -790,6 +811,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     }
     __syncthreads();
     const int wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+    bool still = false;
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -833,7 +855,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       }
       pl.st[r] = st;
       pl.n[r] = (uint8_t)(n + 1);
+      still = st == ST_ACTIVE;
     }
+    // compaction fused into the step: survivors form the next active list
+    if (a.next_list) wg_append(still, still ? s.rid[tid] : 0, a.next_list, a.next_count);
     if (a.qcount && tid < M) {
       // queries of this step per image, one atomic per distinct image in a wave
       const int r = s.rid[tid];

@@ -48,8 +48,6 @@ void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, i
                        int* counter, hipStream_t s);
 void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_children,
                   int child_lvl, int child_step, int* list, int* counter, hipStream_t s);
-void launch_compact(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count,
-                    int max_items, int* out_list, int* out_count, unsigned long long* qcount, hipStream_t s);
 void launch_finalize(const RayPool& pl, const ImgDesc* imgs, const int* imgs_list, int n_img, int hw,
                      const FinalizeOut& o, hipStream_t s);
 void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, const int* hit_count, int max_hits,

@@ -1,5 +1,5 @@
 // Ray bookkeeping kernels: generation and unit-sphere initialisation, the
-// coarse-to-fine split, active-ray compaction, finalisation of the rendered
+// coarse-to-fine split, finalisation of the rendered
 // maps, normals, and the gradient-sample list of the backward pass.  All of
 // them are memory-bound (a few tens of bytes per ray) and use wave64 ballots
 // with one atomic per workgroup for list appends.
@@ -136,42 +136,6 @@ __global__ __launch_bounds__(256) void k_split(RayPool pl, ImgDesc* imgs, const 
 __global__ void k_set_level(ImgDesc* imgs, const int* imgs_list, int n, int lvl) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) imgs[imgs_list[i]].cur_level = lvl;
-}
-
-// ---------------------------------------------------------------------------
-// Compaction (dynamic synchronized inference, Sec. 3.2 / App. B.2): keep the
-// rays that are still ACTIVE at their image's current level, and count the
-// queries each image spent in the step just marched.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_compact(RayPool pl, const ImgDesc* imgs, const int* in_list,
-                                                 const int* in_count, int* out_list, int* out_count,
-                                                 unsigned long long* qcount) {
-  const int count = *in_count;
-  const int lane = threadIdx.x & 63;
-  for (int base = blockIdx.x * 256; base < count; base += gridDim.x * 256) {
-    const int i = base + threadIdx.x;
-    bool keep = false, valid = i < count;
-    int r = 0, img = -1;
-    if (valid) {
-      r = in_list[i];
-      img = pl.img[r];
-      const ImgDesc& im = imgs[img];
-      const int off = r - im.slot_base;
-      const int hw = im.H * im.W;
-      const int lvl = off < hw ? 0 : (off < hw + (hw >> 2) ? 1 : 2);
-      keep = pl.st[r] == ST_ACTIVE && lvl == im.cur_level;
-    }
-    // per-image query counts, one atomic per distinct image in the wave
-    unsigned long long todo = qcount ? __ballot(valid) : 0ull;
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int li = __shfl(img, leader);
-      const unsigned long long same = __ballot(valid && img == li);
-      if (lane == leader) atomicAdd(&qcount[li], (unsigned long long)__popcll(same));
-      todo &= ~same;
-    }
-    block_append(keep, r, out_list, out_count);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -654,13 +618,6 @@ void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_
   hipLaunchKernelGGL(k_split, dim3(nblk(max_children, 256), n_img), dim3(256), 0, s, pl, imgs, imgs_list,
                      child_lvl, child_step, list, counter);
   hipLaunchKernelGGL(k_set_level, dim3(nblk(n_img, 256)), dim3(256), 0, s, imgs, imgs_list, n_img, child_lvl);
-}
-void launch_compact(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count,
-                    int max_items, int* out_list, int* out_count, unsigned long long* qcount, hipStream_t s) {
-  if (max_items <= 0) return;
-  unsigned g = nblk(max_items, 256);
-  if (g > 2048) g = 2048;
-  hipLaunchKernelGGL(k_compact, dim3(g), dim3(256), 0, s, pl, imgs, in_list, in_count, out_list, out_count, qcount);
 }
 void launch_finalize(const RayPool& pl, const ImgDesc* imgs, const int* imgs_list, int n_img, int hw,
                      const FinalizeOut& o, hipStream_t s) {

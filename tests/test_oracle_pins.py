@@ -431,3 +431,21 @@ def test_subset_render_equals_full_render():
                                    rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(sub.rec_t[:, pix], full.rec_t[:, pix], rtol=1e-12, atol=1e-14)
     np.testing.assert_allclose(sub.normal.reshape(-1, 3)[pix], full.normal.reshape(-1, 3)[pix], rtol=0, atol=1e-9)
+
+
+def test_adam_step_matches_torch_adam():
+    """The oracle's Adam (paper's optimiser) against torch.optim.Adam, float64."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(21))
+    z = rng.standard_normal(7)
+    zt = torch.tensor(z.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([zt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(7)
+    v = np.zeros(7)
+    for t in range(1, 6):
+        g = rng.standard_normal(7) * (10.0 ** -t)
+        z, m, v = O.adam_step(z, g, m, v, t)
+        opt.zero_grad()
+        zt.grad = torch.tensor(g)
+        opt.step()
+        assert np.allclose(z, zt.detach().numpy(), rtol=0, atol=1e-14)
