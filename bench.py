@@ -319,6 +319,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--no-zopt", action="store_true")
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="comma-separated request rates (req/s) for a serving sweep, --serve-requests each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (reference dispatch for HBM byte counters)")
     a = ap.parse_args()
@@ -408,6 +410,12 @@ def main():
         log("[bench] serving stream")
         res["serving"] = serving_run(a.serve_rate, a.serve_requests)
         log("[bench] serving", res["serving"])
+    if a.serve_sweep:
+        res["serving_sweep"] = []
+        for rate in [float(x) for x in a.serve_sweep.split(",") if x]:
+            log("[bench] serving sweep at", rate, "req/s")
+            res["serving_sweep"].append(serving_run(rate, a.serve_requests))
+            log("[bench]  ", res["serving_sweep"][-1])
 
     if not a.no_cpu:
         log("[bench] cpu baseline (oracle)")

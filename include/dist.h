@@ -178,6 +178,25 @@ int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved,
                     const float* g_depth, const float* g_normal, const float* g_sil,
                     float* g_z, float* const* g_W, float* const* g_b, void* stream);
 
+/* Gradient of the depth and silhouette terms w.r.t. the camera extrinsics
+ * of every view (the camera-pose experiment of Sec. 4.1, "Back-Propagation
+ * Effectiveness"; App. A.3: the soft silhouette is differentiable w.r.t. the
+ * extrinsics).  As for z, the march points are detached (Sec. 3.4): each
+ * depth/silhouette sample of the backward above keeps its ray parameter t,
+ * and only its position p = c + t R_wc u (u = the pixel's unit direction in
+ * the camera frame) moves, adding s grad_p f(p) to dL/dc and
+ * s t grad_p f(p) u^T to dL/dR_wc; pixels whose ray misses the unit sphere
+ * add dL/dS dS/d(c, R_wc) of S = sqrt(|c|^2 - (c.v)^2) - 1, v = R_wc u.
+ * Normal terms are not part of this gradient.
+ *   saved    from dist_render_fwd (the latent codes stay fixed)
+ *   g_depth, g_sil  device [n_images][H][W] (either may be NULL = zero)
+ *   g_cam    device float [n_views][12]: dL/dc (3), then dL/dR_wc (9,
+ *            row-major); overwritten.  Views used by no image get zeros.
+ * The reduction order is fixed, so results are bitwise reproducible. */
+int dist_render_bwd_camera(dist_ctx* ctx, const dist_saved* saved,
+                           const float* g_depth, const float* g_sil,
+                           float* g_cam, void* stream);
+
 /* Free a forward state. */
 int dist_saved_free(dist_saved* saved);
 

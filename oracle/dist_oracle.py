@@ -115,6 +115,34 @@ class Decoder:
             delta = g_h * (pre[l - 1] > 0.0)
         return gZ, gW, gb
 
+    def sdf_grad_p(self, Z, P, seeds):
+        """seeds_i * grad_p f(P_i, Z_i) [n,3]: the spatial gradient of f through
+        the residual term 0.5 |p| and the point columns of layer 0 and of the
+        skip layer.  ReLU'(0) is taken as 0."""
+        Z = np.asarray(Z, np.float64)
+        P = np.asarray(P, np.float64)
+        seeds = np.asarray(seeds, np.float64)
+        n = P.shape[0]
+        if n == 0:
+            return np.zeros((0, 3))
+        m, inputs, pre = self.layer_inputs(Z, P, keep=True)
+        th = np.tanh(m)
+        gP = (0.5 * seeds / np.linalg.norm(P, axis=1))[:, None] * P
+        delta = (seeds * 0.05 * (1.0 - th * th))[:, None]
+        for l in range(self.nl - 1, -1, -1):
+            g_in = delta @ self.W[l]
+            if l == 0:
+                gP += g_in[:, self.L: self.L + 3]
+                break
+            if self.skip is not None and l == self.skip:
+                nh = self.W[l - 1].shape[0]
+                gP += g_in[:, nh + self.L: nh + self.L + 3]
+                g_h = g_in[:, :nh]
+            else:
+                g_h = g_in
+            delta = g_h * (pre[l - 1] > 0.0)
+        return gP
+
 
 def _bf16_round(x):
     """Round float64 values to the nearest bfloat16 (ties to even), via float32."""
@@ -590,6 +618,77 @@ def backward(dec: Decoder, Z, renders: Sequence[Render], pairs, prm, grads, want
             gW[l] += gWi[l]
             gb[l] += gbi[l]
     return gz, gW, gb
+
+
+def camera_samples(r: Render, prm, g_depth, g_sil):
+    """The depth and silhouette samples of ``gradient_samples`` with, for each,
+    its ray parameter t and the pixel's camera-frame unit direction u (so that
+    p = c + t R u).  Returns (points [m,3], seeds [m], t [m], u [m,3])."""
+    K = int(prm.k_samples)
+    alpha = float(prm.alpha)
+    c = r.c
+    st = r.status.reshape(-1)
+    gd = np.asarray(g_depth, np.float64).reshape(-1)
+    gs = np.asarray(g_sil, np.float64).reshape(-1)
+    nrm = np.sqrt(r.xt ** 2 + r.yt ** 2 + 1.0)
+    u = np.stack([r.xt / nrm, r.yt / nrm, 1.0 / nrm], axis=1)
+    pts, seeds, ts, us = [], [], [], []
+    hit = st == HIT
+    for j in range(K):
+        sel = hit & np.isfinite(r.rec_absf[j]) & (gd != 0)
+        t = r.rec_t[j, sel]
+        pts.append(c[None, :] + t[:, None] * r.dirs[sel])
+        seeds.append(alpha * gd[sel] / nrm[sel])
+        ts.append(t)
+        us.append(u[sel])
+    sel = (st != MISS) & np.isfinite(r.rec_absf[0]) & (gs != 0)
+    t = r.rec_t[0, sel]
+    pts.append(c[None, :] + t[:, None] * r.dirs[sel])
+    seeds.append(gs[sel] * np.sign(r.rec_f[0, sel]))
+    ts.append(t)
+    us.append(u[sel])
+    return np.concatenate(pts, 0), np.concatenate(seeds, 0), np.concatenate(ts, 0), np.concatenate(us, 0)
+
+
+def camera_backward(dec: Decoder, Z, renders: Sequence[Render], cams: Sequence, pairs, prm, grads):
+    """dL/d(camera extrinsics) per view, (g_c [n_views,3], g_R [n_views,3,3]),
+    for the depth and silhouette terms (the quantities the paper's camera-pose
+    experiment optimises, Sec. 4.1 "Back-Propagation Effectiveness"; App. A.3:
+    the silhouette is differentiable w.r.t. the extrinsics).
+
+    Reading F1: as for z (Sec. 3.4), the march points are detached: each
+    depth/silhouette sample keeps its ray parameter t, and only its position
+    p = c + t R u moves with the camera, so a sample adds
+    s grad_p f(p) to dL/dc and s t grad_p f(p) u^T to dL/dR (R_wc, row-major).
+    Rays that miss the unit sphere have S = sqrt(|c|^2 - (c.v)^2) - 1 with
+    v = R u, differentiated exactly.  Normal terms are not included (g_normal
+    is not an input here).
+    """
+    Z = np.asarray(Z, np.float64)
+    nv = len(cams)
+    g_c = np.zeros((nv, 3))
+    g_R = np.zeros((nv, 3, 3))
+    for r, (vi, li), (g_d, g_s) in zip(renders, pairs, grads):
+        P, s, t, u = camera_samples(r, prm, g_d, g_s)
+        if P.shape[0]:
+            gp = dec.sdf_grad_p(np.broadcast_to(Z[li], (P.shape[0], Z.shape[1])), P, s)
+            g_c[vi] += gp.sum(0)
+            g_R[vi] += np.einsum("ki,kj->ij", gp * t[:, None], u)
+        # background silhouette of rays that miss the unit sphere
+        gs = np.asarray(g_s, np.float64).reshape(-1)
+        sel = (r.status.reshape(-1) == MISS) & (gs != 0)
+        if np.any(sel):
+            c = r.c
+            v = r.dirs[sel]
+            nrm = np.sqrt(r.xt[sel] ** 2 + r.yt[sel] ** 2 + 1.0)
+            uu = np.stack([r.xt[sel] / nrm, r.yt[sel] / nrm, 1.0 / nrm], axis=1)
+            b = v @ c
+            q = np.sqrt(np.maximum(c @ c - b * b, 0.0))
+            w = gs[sel] / q
+            g_c[vi] += (w[:, None] * (c[None, :] - b[:, None] * v)).sum(0)
+            dv = -(w * b)[:, None] * c[None, :]
+            g_R[vi] += np.einsum("ki,kj->ij", dv, uu)
+    return g_c, g_R
 
 
 # ============================================================================

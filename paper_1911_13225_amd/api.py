@@ -183,6 +183,16 @@ def dist_render_bwd(ctx: Context, saved: Saved, g_depth=None, g_normal=None, g_s
     return g_z
 
 
+def dist_render_bwd_camera(ctx: Context, saved: Saved, n_views: int, g_depth=None, g_sil=None):
+    """Gradient of the depth and silhouette terms w.r.t. each view's camera
+    extrinsics: a tensor [n_views, 12] = (dL/dc, dL/dR_wc row-major)."""
+    g_cam = torch.empty(n_views, 12, device="cuda")
+    args = [None if g is None else g.detach().float().contiguous() for g in (g_depth, g_sil)]
+    check(ctx.lib.dist_render_bwd_camera(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_cam),
+                                         _stream()))
+    return g_cam
+
+
 def dist_sdf_eval(ctx: Context, points: torch.Tensor, latent_ids: torch.Tensor, z: torch.Tensor, precision: int):
     n = points.shape[0]
     f = torch.empty(n, device=points.device)

@@ -49,6 +49,16 @@ struct NrmSave {
   float* dtanh = nullptr;
 };
 
+// Buffers of the camera-extrinsic gradient: per sample its image, pixel and
+// ray parameter, and the adjoint's per-wave point-gradient partials.
+struct CamSpace {
+  char* mem = nullptr;
+  size_t bytes = 0;
+  long long cap_samples = 0;
+  int4* sample_cam = nullptr;
+  float* gp = nullptr;
+};
+
 // Buffers of one forward render (ray pool, lists, counters, outputs staging).
 struct Workspace {
   char* mem = nullptr;
@@ -68,7 +78,9 @@ struct Workspace {
   float* fv = nullptr;
   float4* nraw = nullptr;
   int* hit_pix = nullptr;
+  int* img_view = nullptr;
   NrmSave* ns = nullptr;
+  CamSpace* cs = nullptr;
   // pinned staging of the per-call descriptors
   dist::ImgDesc* h_imgs = nullptr;
   int* h_ints = nullptr;
@@ -119,7 +131,7 @@ struct dist_saved {
   dist_ctx* ctx = nullptr;
   Workspace* ws = nullptr;
   const float* z = nullptr;          // the forward's latent codes (caller-owned)
-  int n_img = 0, hw = 0, n_lat = 0;
+  int n_img = 0, hw = 0, n_lat = 0, n_views = 0;
   dist_trace_params prm{};
   std::vector<int> img_latent, order;
   bool masks_kept = false;           // the stencil queries kept their ReLU masks

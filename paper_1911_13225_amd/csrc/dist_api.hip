@@ -375,6 +375,7 @@ static void ws_layout(Workspace& w, Carver& c) {
   w.fv = c.take<float>((size_t)w.cap_pix * 6);
   w.nraw = c.take<float4>(w.cap_pix);
   w.hit_pix = c.take<int>(w.cap_pix);
+  w.img_view = c.take<int>(w.cap_img);
 }
 
 static void bw_layout(BwdSpace& w, Carver& c) {
@@ -431,7 +432,7 @@ static int ws_get(dist_ctx* ctx, int cap_rays, int cap_pix, int cap_img, int cap
   c.off = 0;
   ws_layout(*w, c);
   if (hipHostMalloc((void**)&w->h_imgs, sizeof(ImgDesc) * cap_img) != hipSuccess ||
-      hipHostMalloc((void**)&w->h_ints, sizeof(int) * 3 * cap_img) != hipSuccess ||
+      hipHostMalloc((void**)&w->h_ints, sizeof(int) * 4 * cap_img) != hipSuccess ||
       hipEventCreateWithFlags(&w->staged, hipEventDisableTiming) != hipSuccess) {
     ctx_free(ctx, w->mem, w->bytes);
     delete w;
@@ -460,6 +461,10 @@ static void ws_destroy(dist_ctx* ctx, Workspace* w) {
   if (w->ns) {
     ctx_free(ctx, w->ns->mem, w->ns->bytes);
     delete w->ns;
+  }
+  if (w->cs) {
+    ctx_free(ctx, w->cs->mem, w->cs->bytes);
+    delete w->cs;
   }
   delete w;
 }
@@ -588,7 +593,7 @@ int slots_per_image(int hw, int levels) {
 
 // Stage image descriptors and the per-image index arrays (pinned -> device).
 static int stage_images(Workspace* w, const std::vector<ImgDesc>& d, const std::vector<int>& order,
-                        const std::vector<int>& lat, hipStream_t st) {
+                        const std::vector<int>& lat, const std::vector<int>& view, hipStream_t st) {
   if (w->staged_pending) HIPCHK(hipEventSynchronize(w->staged));
   const int n = (int)d.size();
   memcpy(w->h_imgs, d.data(), sizeof(ImgDesc) * n);
@@ -596,7 +601,9 @@ static int stage_images(Workspace* w, const std::vector<ImgDesc>& d, const std::
     w->h_ints[i] = i;
     w->h_ints[n + i] = order[i];
     w->h_ints[2 * n + i] = lat[i];
+    w->h_ints[3 * n + i] = view[i];
   }
+  HIPCHK(hipMemcpyAsync(w->img_view, w->h_ints + 3 * n, sizeof(int) * n, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(w->imgs, w->h_imgs, sizeof(ImgDesc) * n, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(w->imgs_list, w->h_ints, sizeof(int) * n, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(w->img_order, w->h_ints + n, sizeof(int) * n, hipMemcpyHostToDevice, st));
@@ -746,7 +753,7 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
   std::vector<int> order(n_img);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return li[a] < li[b]; });
-  rc = stage_images(w, d, order, li, st);
+  rc = stage_images(w, d, order, li, vi, st);
   if (!rc) rc = fold_biases(ctx, w, z, n_latents, st);
   // a forward whose state is saved keeps the ReLU masks of its normal-stencil
   // queries, so that the backward skips their recompute
@@ -769,6 +776,7 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
     s->n_img = n_img;
     s->hw = hw;
     s->n_lat = n_latents;
+    s->n_views = n_views;
     s->prm = *prm;
     s->z = z;
     s->img_latent = li;
@@ -795,7 +803,9 @@ extern "C" int dist_saved_free(dist_saved* s) {
 // ReLU pattern must match the float32 network; a bf16 recompute flips units
 // near zero) and back-propagates in bf16.
 static int adj_prec(int render_prec) { return render_prec == DIST_FP32 ? kPrecF32 : kPrecSplit; }
-static int vjp_prec(int adj) { return adj == kPrecSplit ? kPrecBF16 : adj; }
+// The VJP from saved masks runs in the adjoint's own tile (the 128-row bf16
+// tile would reuse the weights twice as often, but its VJP epilogue spills).
+static int vjp_prec(int adj) { return adj; }
 
 static int reduce_only(dist_ctx* ctx, BwdSpace* b, int n_lat, float* g_z, hipStream_t st) {
   const int w0 = ctx->wpad[0];
@@ -823,9 +833,7 @@ static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int 
     launch_adjoint(prec, aa, grid, st);
   }
   if (split) {
-    // the normal-stencil samples (second list): VJP from the masks the forward
-    // kept, in the 128-row bf16 tile for bf16 renders (the VJP of the split
-    // recompute is a plain bf16 product either way)
+    // the normal-stencil samples (second list): VJP from the masks the forward kept
     const int vp = vjp_prec(prec);
     aa.net = ctx->net[vp];
     aa.partial = b->partial2;
@@ -975,6 +983,71 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
     return reduce_only(ctx, b, n_lat, g_z, st);
   }
   return run_adjoint_and_reduce(ctx, w, b, prec, n_lat, g_z, split, st);
+}
+
+static int cs_get(dist_ctx* ctx, Workspace* w, long long cap_samples) {
+  CamSpace* c = w->cs;
+  if (c && c->cap_samples >= cap_samples) return DIST_OK;
+  if (c) {
+    ctx_free(ctx, c->mem, c->bytes);
+    delete c;
+    w->cs = nullptr;
+  }
+  c = new CamSpace();
+  c->cap_samples = cap_samples;
+  const size_t a = ((size_t)cap_samples * sizeof(int4) + 255) & ~(size_t)255;
+  c->bytes = a + (size_t)cap_samples * 12 * sizeof(float) + 256;
+  int rc = ctx_alloc(ctx, (void**)&c->mem, c->bytes);
+  if (rc != DIST_OK) { delete c; return rc; }
+  c->sample_cam = (int4*)c->mem;
+  c->gp = (float*)(c->mem + a);
+  w->cs = c;
+  return DIST_OK;
+}
+
+extern "C" int dist_render_bwd_camera(dist_ctx* ctx, const dist_saved* saved, const float* g_depth,
+                                      const float* g_sil, float* g_cam, void* stream) {
+  if (!ctx || !saved || !g_cam) return dist_set_error(DIST_EINVAL, "null argument");
+  if (saved->ctx != ctx) return dist_set_error(DIST_EINVAL, "saved state belongs to another context");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = saved->ws;
+  const int prec = adj_prec(saved->prm.precision);
+  const int tile = adj_tile_rows(prec);
+  const int n_img = saved->n_img, hw = saved->hw, n_lat = saved->n_lat;
+  const long long cap = (long long)n_img * hw * saved->prm.k_samples + (long long)n_lat * tile;
+  if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
+  const int bpi = (hw + 255) / 256;
+  const int grid = mlp_grid(ctx, cap, prec);
+  int rc = bw_get(ctx, w, (int)cap, n_img * bpi, n_lat, tile, adj_mask_words(prec, ctx->net[prec]) * grid);
+  if (!rc) rc = cs_get(ctx, w, cap);
+  if (rc) return rc;
+  BwdSpace* b = w->bw;
+  SeedIn in{};
+  in.g_depth = g_depth;
+  in.g_sil = g_sil;
+  in.nraw = w->nraw;
+  in.delta = saved->prm.normal_delta;
+  launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, tile, in, b->bsum, b->boff,
+                 b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st, 0, nullptr,
+                 w->cs->sample_cam);
+  AdjArgs aa{};
+  aa.net = ctx->net[prec];
+  aa.bias0_lat = w->bias0_lat;
+  aa.biasS_lat = w->biasS_lat;
+  aa.samples = b->samples;
+  aa.sample_lat = b->sample_lat;
+  aa.n_samples = b->n_samples;
+  aa.mask_ws = b->mask_ws;
+  aa.partial = b->partial;
+  aa.gp_part = w->cs->gp;
+  {
+    TimedLaunch tl(ctx, 2, st, b->n_samples, 1);
+    launch_adjoint(prec, aa, grid, st);
+  }
+  launch_cam_reduce(w->pool, w->imgs, w->img_view, n_img, saved->n_views, b->samples, w->cs->sample_cam, w->cs->gp,
+                    b->n_samples, g_sil, g_cam, st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
 }
 
 // ---------------------------------------------------------------------------

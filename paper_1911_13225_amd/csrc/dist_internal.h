@@ -126,6 +126,10 @@ struct AdjArgs {
   const int* sample_idx;
   const unsigned* smask;
   const float* sdtanh;
+  // camera gradient (optional): per sample and wave, gm * (W0_p^T delta0 +
+  // Wskip_p^T delta_skip) partial sums over that wave's features,
+  // [sample][4][3] (the spatial gradient of m, weighted by the row's factor)
+  float* gp_part;
 };
 
 // Precision codes of the decoder kernels: 0 float32, 1 bfloat16, 2 split

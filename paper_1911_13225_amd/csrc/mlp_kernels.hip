@@ -371,6 +371,9 @@ struct EpCtx {
   float* hrow;              // weight-gradient capture: h of this layer, row stride rstride (or null)
   float* drow;              // weight-gradient capture: Delta of this layer (or null)
   int rstride;
+  float* gp;                // camera gradient: per-row point-gradient partials [row][4][3] (or null)
+  int gp_row0;              // global row index of the tile's first row
+  bool gp_accum;            // add to the partials (the skip layer wrote them first)
 };
 
 // 1 if x > 0, else 0, as an integer clamp med3(bits, 0, 1) of the float's bits
@@ -579,7 +582,7 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
 // pre-activation is the same expression layer0_fill evaluates).
 template <int P, int MTW, int NTW, bool L0, bool CAP>
 __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
-                                       int nt0, int mt0, int mg, int lane) {
+                                       int nt0, int mt0, int mg, int nw, int lane) {
   const int r = lane & 31, g = lane >> 5;
   const int N0 = net.wpad[0];
 #pragma unroll
@@ -629,6 +632,52 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
           *(float4*)(ec.drow + (size_t)m * ec.rstride + feat(nt0, j, q, g)) =
               make_float4(w * acc[i][j][4 * q], w * acc[i][j][4 * q + 1], w * acc[i][j][4 * q + 2],
                           w * acc[i][j][4 * q + 3]);
+      }
+    }
+  }
+  if (ec.gp && ec.which >= 0) {
+    // point gradient of m through this layer's point columns, per row:
+    // sum_n delta[n] W_p[:, n] over the wave's features, times the row factor
+    const float* wp = ec.which == 0 ? net.w0p : net.wsp;
+    const int ws = ec.which == 0 ? net.wpad[0] : net.wpad[net.skip];
+    float gx[MTW], gy[MTW], gz[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) gx[i] = gy[i] = gz[i] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = feat(nt0, j, q, g);
+        const float4 ax = ld4(wp + n), ay = ld4(wp + ws + n), az = ld4(wp + 2 * ws + n);
+        const float wx[4] = {ax.x, ax.y, ax.z, ax.w}, wy[4] = {ay.x, ay.y, ay.z, ay.w},
+                    wz[4] = {az.x, az.y, az.z, az.w};
+#pragma unroll
+        for (int i = 0; i < MTW; ++i)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float d = acc[i][j][4 * q + e];
+            gx[i] = fmaf(d, wx[e], gx[i]);
+            gy[i] = fmaf(d, wy[e], gy[i]);
+            gz[i] = fmaf(d, wz[e], gz[i]);
+          }
+      }
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      const float x = gx[i] + __shfl_xor(gx[i], 32), y = gy[i] + __shfl_xor(gy[i], 32),
+                  z = gz[i] + __shfl_xor(gz[i], 32);
+      if (g == 0) {
+        const int m = (mt0 + i) * 32 + r;
+        const float w = s.gm[m];
+        float* dst = ec.gp + ((size_t)(ec.gp_row0 + m) * 4 + nw) * 3;
+        if (ec.gp_accum) {
+          dst[0] += w * x;
+          dst[1] += w * y;
+          dst[2] += w * z;
+        } else {
+          dst[0] = w * x;
+          dst[1] = w * y;
+          dst[2] = w * z;
+        }
       }
     }
   }
@@ -694,8 +743,8 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   if constexpr (MODE == EP_LAST) ep_last<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
   if constexpr (MODE == EP_LAST_ADJ) ep_last<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
   if constexpr (MODE == EP_VJP) {
-    if (ec.layer == 0) ep_vjp<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, mg, lane);
-    else ep_vjp<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, mg, lane);
+    if (ec.layer == 0) ep_vjp<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, mg, nw, lane);
+    else ep_vjp<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, mg, nw, lane);
   }
   __syncthreads();
 }
@@ -943,7 +992,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 // factor s.gm where the column sums are taken).
 template <int P, bool CAP>
 __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, const MaskRef& mk, float* part,
-                                           size_t row0, int rstride) {
+                                           size_t row0, int rstride, int tile) {
   const NetDev& net = a.net;
   for (int l = net.nl - 2; l >= 1; --l) {
     EpCtx ec{};
@@ -955,6 +1004,9 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
     ec.kmax = net.kmax;
     ec.which = (l - 1 == 0) ? 0 : ((l - 1 == net.skip) ? 1 : -1);
     ec.write_act = (l - 1 != 0);
+    ec.gp = a.gp_part;
+    ec.gp_row0 = tile * Cfg<P>::M;
+    ec.gp_accum = (l - 1 == 0) && net.skip >= 1;   // the skip layer comes first in this loop
     if constexpr (CAP) {
       ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
       ec.rstride = rstride;
@@ -1012,8 +1064,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       }
     }
     float* part = a.partial + (size_t)tile * 4 * net.kmax;
-    if (theta) vjp_layers<P, true>(a, s, mk, part, row0, rstride);
-    else vjp_layers<P, false>(a, s, mk, part, 0, 0);
+    if (theta) vjp_layers<P, true>(a, s, mk, part, row0, rstride, tile);
+    else vjp_layers<P, false>(a, s, mk, part, 0, 0, tile);
   }
 }
 
@@ -1053,7 +1105,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       store4<P>(s, m, n, (n >> 2) & 1, v, true);
     }
     __syncthreads();
-    vjp_layers<P, false>(a, s, mk, a.partial + (size_t)tile * 4 * net.kmax, 0, 0);
+    vjp_layers<P, false>(a, s, mk, a.partial + (size_t)tile * 4 * net.kmax, 0, 0, tile);
   }
 }
 

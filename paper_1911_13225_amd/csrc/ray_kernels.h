@@ -55,12 +55,15 @@ void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, con
 void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
                     int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
                     int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s,
-                    int lat_fixed = 0, const SplitList* split = nullptr);
+                    int lat_fixed = 0, const SplitList* split = nullptr, int4* sample_cam = nullptr);
 void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
                         int* sample_lat, hipStream_t s);
 void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
                       const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,
                       const float* Wsz, int L, float* gz, hipStream_t s, int lat0 = 0, int accumulate = 0);
+void launch_cam_reduce(const RayPool& pl, const ImgDesc* imgs, const int* img_view, int n_img, int n_views,
+                       const float4* samples, const int4* sample_cam, const float* gp_part, const int* n_samples,
+                       const float* g_sil, float* g_cam, hipStream_t s);
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s);
 void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
                     int* out_count, const AdvEntry* table, const int* hdr, int* img_active,

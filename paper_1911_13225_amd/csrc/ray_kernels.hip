@@ -338,7 +338,7 @@ __device__ __forceinline__ int block_excl_scan(int c, int* buf) {
 // their adjoint can use the masks the forward kept.
 __global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc* imgs, const int* img_order,
                                                        SeedIn in, const int* boff, const int* boff2, float4* samples,
-                                                       int* sample_lat, int* sample_idx) {
+                                                       int* sample_lat, int* sample_idx, int4* sample_cam) {
   __shared__ int buf[256];
   const int img = img_order[blockIdx.y];
   const ImgDesc& im = imgs[img];
@@ -379,6 +379,7 @@ __global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc
     }
     samples[o] = make_float4(fmaf(tk, d.x, cx), fmaf(tk, d.y, cy), fmaf(tk, d.z, cz), seed);
     sample_lat[o] = im.latent;
+    if (sample_cam) sample_cam[o] = make_int4(img, pix, __float_as_int(tk), 0);
     ++o;
   }
   if (ps.nn) {
@@ -409,13 +410,98 @@ __global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc
 // stencil index (split layout) is 0, a valid entry whose contribution the zero
 // seed cancels.
 __global__ void k_samples_pad(const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
-                              int* sample_lat, int* sample_idx) {
+                              int* sample_lat, int* sample_idx, int4* sample_cam) {
   const int l = blockIdx.x;
   const int b = seg_base[l], t = seg_total[l], p = seg_padded[l];
   for (int i = t + threadIdx.x; i < p; i += blockDim.x) {
     samples[b + i] = make_float4(0.f, 0.f, 0.f, 0.f);
     sample_lat[b + i] = l;
     if (sample_idx) sample_idx[b + i] = 0;
+    if (sample_cam) sample_cam[b + i] = make_int4(-1, 0, 0, 0);
+  }
+}
+
+// Camera-extrinsic gradient of one view (blockIdx.x), fixed summation order:
+// every depth/silhouette sample of the view's images adds s grad_p f(p) to
+// dL/dc and s t grad_p f(p) u^T to dL/dR (p = c + t R u, t detached), with
+// s grad_p f = s 0.5 p/|p| + the adjoint's per-wave partials; every pixel whose
+// ray misses the unit sphere adds dL/dS dS/d(c, R) of S = sqrt(|c|^2 -
+// (c.v)^2) - 1 (App. A.3).  Output g_cam[v] = (dL/dc, dL/dR row-major).
+__global__ __launch_bounds__(256) void k_cam_reduce(RayPool pl, const ImgDesc* imgs, const int* img_view, int n_img,
+                                                    const float4* samples, const int4* sample_cam,
+                                                    const float* gp_part, const int* n_samples, const float* g_sil,
+                                                    float* g_cam) {
+  __shared__ float red[256];
+  const int v = blockIdx.x;
+  float acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.f;
+  const int ns = *n_samples;
+  for (int i = threadIdx.x; i < ns; i += 256) {
+    const int4 sc = sample_cam[i];
+    if (sc.x < 0 || img_view[sc.x] != v) continue;
+    const ImgDesc& im = imgs[sc.x];
+    const float4 smp = samples[i];
+    const float rn = sqrtf(smp.x * smp.x + smp.y * smp.y + smp.z * smp.z);
+    const float h = rn > 0.f ? 0.5f * smp.w / rn : 0.f;
+    float g[3] = {h * smp.x, h * smp.y, h * smp.z};
+    const float* pp = gp_part + (size_t)i * 12;
+    for (int w = 0; w < 4; ++w) {
+      g[0] += pp[3 * w];
+      g[1] += pp[3 * w + 1];
+      g[2] += pp[3 * w + 2];
+    }
+    const int V = sc.y / im.W, U = sc.y - V * im.W;
+    float3 d;
+    float xt, yt;
+    level_ray(im, 0, U, V, d, xt, yt);
+    const float nrm = sqrtf(xt * xt + yt * yt + 1.f);
+    const float u[3] = {xt / nrm, yt / nrm, 1.f / nrm};
+    const float t = __int_as_float(sc.z);
+    for (int a = 0; a < 3; ++a) {
+      acc[a] += g[a];
+      for (int b = 0; b < 3; ++b) acc[3 + 3 * a + b] = fmaf(g[a] * t, u[b], acc[3 + 3 * a + b]);
+    }
+  }
+  if (g_sil) {
+    for (int img = 0; img < n_img; ++img) {
+      if (img_view[img] != v) continue;
+      const ImgDesc& im = imgs[img];
+      const int hw = im.H * im.W;
+      for (int pix = threadIdx.x; pix < hw; pix += 256) {
+        const int r = im.slot_base + im.lvl_off[0] + pix;
+        const float gs = g_sil[(size_t)im.out_base + pix];
+        if (pl.st[r] != ST_MISS || gs == 0.f) continue;
+        const int V = pix / im.W, U = pix - V * im.W;
+        float3 d;
+        float xt, yt;
+        level_ray(im, 0, U, V, d, xt, yt);
+        const float nrm = sqrtf(xt * xt + yt * yt + 1.f);
+        const float u[3] = {xt / nrm, yt / nrm, 1.f / nrm};
+        const float c[3] = {im.c[0], im.c[1], im.c[2]};
+        const float dv[3] = {d.x, d.y, d.z};
+        const float b = c[0] * dv[0] + c[1] * dv[1] + c[2] * dv[2];
+        const float q = sqrtf(fmaxf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] - b * b, 0.f));
+        if (!(q > 0.f)) continue;
+        const float w = gs / q;
+        for (int a = 0; a < 3; ++a) {
+          acc[a] = fmaf(w, c[a] - b * dv[a], acc[a]);
+          const float da = -w * b * c[a];
+          for (int bb = 0; bb < 3; ++bb) acc[3 + 3 * a + bb] = fmaf(da, u[bb], acc[3 + 3 * a + bb]);
+        }
+      }
+    }
+  }
+  // fixed-order tree reduction of each of the 12 sums
+  for (int k = 0; k < 12; ++k) {
+    red[threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) g_cam[12 * v + k] = red[0];
+    __syncthreads();
   }
 }
 
@@ -632,7 +718,7 @@ void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, con
 void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent, int n_img,
                     int hw, int n_lat, int tile, const SeedIn& in, int* bsum, int* boff, int* seg_base,
                     int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat, hipStream_t s,
-                    int lat_fixed, const SplitList* sl) {
+                    int lat_fixed, const SplitList* sl, int4* sample_cam) {
   const int bpi = (int)nblk(hw, 256);
   const bool split = sl != nullptr && in.hit_pix != nullptr;
   hipLaunchKernelGGL(k_samples_count, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, bsum,
@@ -644,17 +730,23 @@ void launch_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order
                        lat_fixed, tile, n_lat, sl->boff, sl->seg_base, sl->seg_total, sl->seg_padded, n_samples,
                        n_samples + 2);
   hipLaunchKernelGGL(k_samples_write, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, in, boff,
-                     split ? sl->boff : nullptr, samples, sample_lat, split ? sl->sample_idx : nullptr);
+                     split ? sl->boff : nullptr, samples, sample_lat, split ? sl->sample_idx : nullptr, sample_cam);
   hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
-                     sample_lat, nullptr);
+                     sample_lat, nullptr, sample_cam);
   if (split)
     hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, sl->seg_base, sl->seg_total, sl->seg_padded,
-                       samples, sample_lat, sl->sample_idx);
+                       samples, sample_lat, sl->sample_idx, nullptr);
 }
 void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, const int* seg_padded, float4* samples,
                         int* sample_lat, hipStream_t s) {
   hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
-                     sample_lat, nullptr);
+                     sample_lat, nullptr, nullptr);
+}
+void launch_cam_reduce(const RayPool& pl, const ImgDesc* imgs, const int* img_view, int n_img, int n_views,
+                       const float4* samples, const int4* sample_cam, const float* gp_part, const int* n_samples,
+                       const float* g_sil, float* g_cam, hipStream_t s) {
+  hipLaunchKernelGGL(k_cam_reduce, dim3(n_views), dim3(256), 0, s, pl, imgs, img_view, n_img, samples, sample_cam,
+                     gp_part, n_samples, g_sil, g_cam);
 }
 void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const int* seg_base,
                       const int* seg_padded, int n_lat, int w0, int mg0, const float* W0z, int ws, int mgs,

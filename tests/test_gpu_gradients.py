@@ -42,22 +42,36 @@ def ctx():
 
 
 def test_adjoint_matches_central_differences(ctx):
+    """Central differences of a ReLU network cross kinks (a step of 1e-3 on z
+    moves ~1e-4 of pre-activation, so a few units per point change side),
+    which gives the difference quotient an error of its own.  The HIP adjoint
+    must match the HIP forward's differences as well as the exact FP64
+    function matches its own differences at the same points and steps, up to
+    the float32 rounding of the forward: sqrt(n) * 1e-8 / (2h) per coordinate,
+    about 1e-3 (h = 1e-3) and 1e-2 (h = 1e-4) of the gradient."""
     from paper_1911_13225_amd import api
     spec = di.DEEPSDF_SPEC
+    dec = oracle_decoder(spec)
     n = 4096
     rng = np.random.Generator(np.random.PCG64(31))
     d = rng.standard_normal((n, 3))
     P = (d / np.linalg.norm(d, axis=1, keepdims=True) * rng.uniform(0.35, 0.7, (n, 1))).astype(np.float32)
     seeds = rng.standard_normal(n).astype(np.float32)
-    z = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=1000), device="cuda")
+    z32 = di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=1000)
+    z = torch.tensor(z32, device="cuda")
     Pt = torch.tensor(P, device="cuda")
     lat = torch.zeros(n, dtype=torch.int32, device="cuda")
     st = torch.tensor(seeds, device="cuda")
     g = api.dist_sdf_vjp(ctx, Pt, lat, st, z, 0)[0].double().cpu().numpy()
+    P64, s64 = P.astype(np.float64), seeds.astype(np.float64)
+    go = dec.sdf_vjp(np.broadcast_to(z32[0].astype(np.float64), (n, spec.latent_dim)), P64, s64,
+                     want_theta=False)[0].sum(0)
+    rel_adj = np.linalg.norm(g - go) / np.linalg.norm(go)
+    _log("adjoint vs oracle rel", rel_adj)
+    assert rel_adj <= 1e-3          # the float32 dL/dz tolerance (ReLU units within ~1e-7 of zero flip)
     coords = rng.choice(spec.latent_dim, 16, replace=False)
-    s64 = seeds.astype(np.float64)
-    for h, tol in ((1e-3, 2e-3), (1e-4, 2e-2)):
-        fd = np.zeros(16)
+    for h, noise in ((1e-3, 2e-3), (1e-4, 2e-2)):
+        fd, fdo = np.zeros(16), np.zeros(16)
         for a, i in enumerate(coords):
             zp = z.clone()
             zm = z.clone()
@@ -65,12 +79,16 @@ def test_adjoint_matches_central_differences(ctx):
             zm[0, i] -= h
             fp = api.dist_sdf_eval(ctx, Pt, lat, zp, 0).double().cpu().numpy()
             fm = api.dist_sdf_eval(ctx, Pt, lat, zm, 0).double().cpu().numpy()
-            # the step actually taken in float32
-            hh = (float(zp[0, i]) - float(zm[0, i])) / 2.0
+            hh = (float(zp[0, i]) - float(zm[0, i])) / 2.0          # the step taken in float32
             fd[a] = np.dot(s64, fp - fm) / (2.0 * hh)
+            Zp = np.broadcast_to(zp[0].double().cpu().numpy(), (n, spec.latent_dim))
+            Zm = np.broadcast_to(zm[0].double().cpu().numpy(), (n, spec.latent_dim))
+            fdo[a] = np.dot(s64, dec.sdf(Zp, P64) - dec.sdf(Zm, P64)) / (2.0 * hh)
         rel = np.linalg.norm(fd - g[coords]) / np.linalg.norm(g[coords])
-        _log("central differences h", h, "rel", rel, "|g|", np.linalg.norm(g[coords]))
-        assert rel <= tol
+        rel_o = np.linalg.norm(fdo - go[coords]) / np.linalg.norm(go[coords])
+        _log("central differences h", h, "hip rel", rel, "fp64 function rel", rel_o)
+        assert rel_o <= 0.1
+        assert rel <= rel_o + noise
 
 
 def _fit_targets(spec, cams, prm):
@@ -107,7 +125,7 @@ def test_latent_fit_matches_oracle(ctx):
         L.backward()
         if it == 0:
             g0_gpu = z.grad.detach().double().cpu().numpy()[0]
-        loss_g[it] = float(L)
+        loss_g[it] = float(L.detach())
         opt.step()
     zg = z.detach().double().cpu().numpy()
 
@@ -137,6 +155,45 @@ def test_latent_fit_matches_oracle(ctx):
         _log("  it", it, "loss hip", loss_g[it], "oracle", loss_o[it])
     _log("  |z - z*| / |z0 - z*|: hip", dz_g, "oracle", dz_o)
     assert rel0 <= 1e-3
-    for it in checks:
-        assert abs(loss_g[it] - loss_o[it]) <= 2e-2 * loss_o[0]
-    assert loss_g[iters - 1] < loss_g[0] and loss_o[iters - 1] < loss_o[0]
+    # the same start and first step; Adam's per-coordinate normalisation then
+    # lets float32 and float64 runs drift apart (coordinates with near-zero
+    # gradient move by +-lr either way), so later the curves are only required
+    # to fit equally well
+    assert abs(loss_g[0] - loss_o[0]) <= 1e-4 * loss_o[0]
+    assert abs(loss_g[1] - loss_o[1]) <= 1e-3 * loss_o[0]
+    assert abs(loss_g[10] - loss_o[10]) <= 2e-2 * loss_o[0]
+    assert loss_g[iters - 1] <= 0.1 * loss_g[0] and loss_o[iters - 1] <= 0.1 * loss_o[0]
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-3), (1, 1e-2)], ids=["fp32", "bf16"])
+def test_camera_gradient_matches_oracle(ctx, precision, tol):
+    """dL/d(c, R_wc) per view of a depth + silhouette loss, free running
+    against the oracle's camera_backward (same seeds from the oracle's maps)."""
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=2, k_samples=2 if precision == 0 else 1,
+                         precision=precision, want_normals=0)
+    H = 40
+    cams = di.random_sphere_cameras(2, H, H)
+    Z = di.make_latents(2, spec.latent_dim, sigma=0.05)
+    pairs = [(i // 2, i % 2) for i in range(4)]
+    dec = oracle_decoder(spec)
+    rs = O.render(dec, Z, cams, pairs, prm)
+    grads, gd, gs = [], [], []
+    for r, (v, l) in zip(rs, pairs):
+        dt, nt, st = di.sphere_target_maps(cams[v], 0.45)
+        _, g_d, _, g_s = O.loss_and_grads(r, dt, nt, st, w_d=10.0, w_s=1.0)
+        grads.append((g_d, g_s))
+        gd.append(g_d)
+        gs.append(g_s)
+    g_c, g_R = O.camera_backward(dec, Z, rs, cams, pairs, prm, grads)
+    ref = np.concatenate([g_c, g_R.reshape(2, 9)], axis=1)
+    out = api.dist_render_fwd(ctx, cams, torch.tensor(Z, device="cuda"), prm, save=True)
+    T = lambda a: torch.tensor(np.stack(a).astype(np.float32), device="cuda")
+    g = api.dist_render_bwd_camera(ctx, out["saved"], 2, T(gd), T(gs)).double().cpu().numpy()
+    g2 = api.dist_render_bwd_camera(ctx, out["saved"], 2, T(gd), T(gs)).double().cpu().numpy()
+    out["saved"].free()
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    _log("camera gradient precision", precision, "rel", rel, "|g|", np.linalg.norm(ref))
+    assert np.array_equal(g, g2)
+    assert rel <= tol
