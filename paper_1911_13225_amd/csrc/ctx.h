@@ -104,7 +104,7 @@ struct dist_ctx {
   float* wsp = nullptr;                  // [3][wpad_skip]
   float* wsz = nullptr;                  // [wpad_skip][L]
   float* wlast = nullptr;                // [wpad[nl-2]]
-  std::vector<void*> wpack[2], wpackT[2], wpacklo;
+  std::vector<void*> wpack[2], wpackT[2], wpacklo, bfrag[2];
   dist::NetDev net[3];          // float32, bfloat16, split bfloat16
   std::mutex ws_mu;
   std::vector<Workspace*> ws_free;

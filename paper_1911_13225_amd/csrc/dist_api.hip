@@ -135,6 +135,7 @@ static int pack_weights(dist_ctx* ctx, const float* const* W, const float* const
       launch_pack_w(p, true, ctx->Wf[l], out, in, ncols, ctx->wpad[l], ctx->kpad[l], ctx->wpackT[p][l], st);
     }
     launch_pack_w(kPrecSplit, false, ctx->Wf[l], out, in, ncols, ctx->wpad[l], ctx->kpad[l], ctx->wpacklo[l], st);
+    for (int q = 0; q < 2; ++q) launch_pack_bias(q, ctx->bias_pad[l], ctx->wpad[l], ctx->bfrag[q][l], st);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
@@ -215,6 +216,10 @@ extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const 
   }
   ctx->wpacklo.assign(nl, nullptr);
   for (int l = 1; l <= nl - 2; ++l) A(&ctx->wpacklo[l], 2 * ctx->wpad[l] * ctx->kpad[l]);
+  for (int q = 0; q < 2; ++q) {
+    ctx->bfrag[q].assign(nl, nullptr);
+    for (int l = 1; l <= nl - 2; ++l) A(&ctx->bfrag[q][l], (size_t)(ctx->wpad[l] / 32) * 64 * (q ? 16 : 4));
+  }
   if (rc != DIST_OK) { dist_destroy(ctx); return rc; }
   for (int p = 0; p < 3; ++p) {
     const int q = p == 0 ? 0 : 1;      // split precision shares the bf16 packs (hi parts)
@@ -231,6 +236,7 @@ extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const 
       nd.wpT[l] = ctx->wpackT[q][l];
       nd.wplo[l] = p == 2 ? ctx->wpacklo[l] : nullptr;
       nd.bias[l] = ctx->bias_pad[l];
+      nd.bfrag[l] = ctx->bfrag[q][l];
     }
     nd.w0p = ctx->w0p;
     nd.wsp = ctx->wsp;

@@ -59,6 +59,10 @@ struct NetDev {
   const void* wpT[kMaxLayers];     // W_l^T packed as A fragments (rows = inputs)
   const void* wplo[kMaxLayers];    // split precision: bf16(W_l - bf16(W_l)) fragments
   const float* bias[kMaxLayers];   // padded biases (float32)
+  // the biases as MFMA A fragments (column 0 holds b: float32, or b split in
+  // three bf16 parts hi + mid + lo in columns 0-2), so that one MFMA against a
+  // ones fragment broadcasts b into the accumulators of a tile
+  const void* bfrag[kMaxLayers];
   const float* w0p;                // [3][wpad0]: point columns of layer 0
   const float* wsp;                // [3][wpad_skip]: point columns of the skip layer
   const float* wlast;              // [wpad[nl-2]] output-layer weights
@@ -161,6 +165,7 @@ void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t s);
 
 // packing / folding
+void launch_pack_bias(int precision, const float* bias, int wpad, void* dst, hipStream_t st);
 void launch_pack_w(int precision, bool transpose, const float* W, int out, int in_stride, int ncols,
                    int npad, int kpad, void* dst, hipStream_t s);
 void launch_fold_bias(const float* b, const float* Wz, const float* z, int n_lat, int L, int nout,

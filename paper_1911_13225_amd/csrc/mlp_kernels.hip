@@ -439,6 +439,34 @@ __device__ __forceinline__ void acc_zero(f32x16 (&acc)[MTW][NTW]) {
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 }
 
+// Accumulator start by MFMA: D = A B with A = the bias fragment of the layer
+// (column 0: b in float32, or columns 0-2: b = hi + mid + lo in bf16) and B
+// a ones fragment (rows 0-2 of every column), C = 0; one MFMA per 32x32 tile
+// instead of 16 accumulator writes per lane (the VJP starts from A = 0).
+template <int P, int MTW, int NTW>
+__device__ __forceinline__ void acc_mfma_start(f32x16 (&acc)[MTW][NTW], const void* bfrag, int nt0, int lane) {
+  const int g = lane >> 5;
+  const f32x16 zero = {};
+  if constexpr (P == 0) {
+    const float ones = g == 0 ? 1.f : 0.f;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+      const float a = bfrag ? ((const float*)bfrag)[(size_t)(nt0 + j) * 64 + lane] : 0.f;
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, ones, zero, 0, 0, 0);
+    }
+  } else {
+    const bf16 one = (bf16)(g == 0 ? 1.f : 0.f), z0 = (bf16)0.f;
+    const bf16x8 ones = {one, one, one, z0, z0, z0, z0, z0};
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+      const bf16x8 a = bfrag ? ((const bf16x8*)bfrag)[(size_t)(nt0 + j) * 64 + lane] : bf16x8{};
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, ones, zero, 0, 0, 0);
+    }
+  }
+}
+
 // Forward layers start the accumulation from the bias, so the epilogue only
 // applies the ReLU.  The skip layer's bias is the per-latent folded bias plus
 // the float32 point columns W_p p of the row.
@@ -728,8 +756,9 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   const int nw = wave % WN, mg = wave / WN;
   const int nt0 = nw * NTW, mt0 = mg * MTW;
   f32x16 acc[MTW][NTW];
-  if constexpr (MODE == EP_VJP) acc_zero<MTW, NTW>(acc);
-  else acc_bias<P, MTW, NTW, SKIP>(acc, ec, s, nt0, mt0, lane);
+  if constexpr (MODE == EP_VJP) acc_mfma_start<P, MTW, NTW>(acc, nullptr, nt0, lane);
+  else if constexpr (SKIP) acc_bias<P, MTW, NTW, true>(acc, ec, s, nt0, mt0, lane);
+  else acc_mfma_start<P, MTW, NTW>(acc, net.bfrag[ec.layer], nt0, lane);
   if constexpr (P == 1) {
     gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane);
   } else if constexpr (P == 2) {
@@ -1251,6 +1280,30 @@ void launch_pack_w(int precision, bool transpose, const float* W, int out, int i
   const int grid = (int)((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
   hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, st, precision, transpose ? 1 : 0, W, out, in_stride, ncols,
                      rows_pad, cols_pad, dst);
+}
+
+// Bias fragments (see acc_mfma_start): per 32-row tile, 64 lanes; lane l of
+// tile t holds row t*32 + l%32 in its first column(s) if l < 32, zeros else.
+__global__ void k_pack_bias(int precision, const float* __restrict__ bias, int n_tiles, void* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_tiles * 64) return;
+  const int tile = i >> 6, lane = i & 63;
+  const float b = lane < 32 ? bias[tile * 32 + lane] : 0.f;
+  if (precision == 0) {
+    ((float*)dst)[i] = b;
+  } else {
+    const bf16 hi = (bf16)b;
+    const float r1 = b - (float)hi;
+    const bf16 mid = (bf16)r1;
+    const bf16 lo = (bf16)(r1 - (float)mid);
+    const bf16 z0 = (bf16)0.f;
+    ((bf16x8*)dst)[i] = bf16x8{hi, mid, lo, z0, z0, z0, z0, z0};
+  }
+}
+
+void launch_pack_bias(int precision, const float* bias, int wpad, void* dst, hipStream_t st) {
+  const int n_tiles = wpad / 32;
+  hipLaunchKernelGGL(k_pack_bias, dim3((n_tiles * 64 + 255) / 256), dim3(256), 0, st, precision, bias, n_tiles, dst);
 }
 
 // dst[l][n] = b[n] + sum_j Wz[n][j] z[l][j]  (rows n >= nout are zero)
