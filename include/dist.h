@@ -178,6 +178,18 @@ int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved,
                     const float* g_depth, const float* g_normal, const float* g_sil,
                     float* g_z, float* const* g_W, float* const* g_b, void* stream);
 
+/* dL/dz as dist_render_bwd, except that the depth term is the exact
+ * derivative instead of the paper's approximation (the second term of Eq. 2
+ * that Sec. 3.4 drops): a hit's surface point p = c + d v solves f(p, z) = 0,
+ * so dd/dz = -(df/dz) / (grad_p f . v) at the Eq. 1 point (one sample per
+ * hit, seed -dL/dz_c / |(xt, yt, 1)| / (grad_p f . v)); silhouette and normal
+ * terms are the paper's.  Rays that graze the surface (|grad f . v| <= 1e-2
+ * |grad f|) get no depth term.  Two passes: grad f . v at the hits, then the
+ * backward.  Arguments and errors as dist_render_bwd (no weight gradient). */
+int dist_render_bwd_implicit(dist_ctx* ctx, const dist_saved* saved,
+                             const float* g_depth, const float* g_normal, const float* g_sil,
+                             float* g_z, void* stream);
+
 /* Gradient of the depth and silhouette terms w.r.t. the camera extrinsics
  * of every view (the camera-pose experiment of Sec. 4.1, "Back-Propagation
  * Effectiveness"; App. A.3: the soft silhouette is differentiable w.r.t. the

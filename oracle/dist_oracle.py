@@ -620,6 +620,44 @@ def backward(dec: Decoder, Z, renders: Sequence[Render], pairs, prm, grads, want
     return gz, gW, gb
 
 
+GRAZING = 1e-2     # |grad f . v| <= GRAZING |grad f|: no implicit depth term (Reading X1)
+
+
+def implicit_backward(dec: Decoder, Z, renders: Sequence[Render], pairs, prm, grads):
+    """dL/dz with the exact derivative of the depth instead of the paper's
+    approximation (the gap that Sec. 3.4 accepts by dropping the second term of
+    Eq. 2): at a hit the surface point p = c + d v satisfies f(p, z) = 0, so by
+    the implicit function theorem dd/dz = -(df/dz) / (grad_p f . v), evaluated
+    at the Eq. 1 point.  Silhouette and normal terms are the paper's.
+
+    Reading X1: pixels whose ray grazes the surface (|grad f . v| <= 1e-2
+    |grad f|) get no depth term (the derivative is singular there).
+    Returns g_z [n_lat, L].
+    """
+    Z = np.asarray(Z, np.float64)
+    gz = np.zeros_like(Z)
+    for r, (vi, li), (g_d, g_n, g_s) in zip(renders, pairs, grads):
+        # the paper's silhouette and normal terms
+        P, s = gradient_samples(r, prm, np.zeros_like(np.asarray(g_d, np.float64)), g_n, g_s)
+        if P.shape[0]:
+            gz[li] += dec.sdf_vjp(np.broadcast_to(Z[li], (P.shape[0], Z.shape[1])), P, s,
+                                  want_theta=False)[0].sum(0)
+        gd = np.asarray(g_d, np.float64).reshape(-1)
+        sel = (r.status.reshape(-1) == HIT) & (gd != 0)
+        if not np.any(sel):
+            continue
+        v = r.dirs[sel]
+        p = r.c[None, :] + r.dist.reshape(-1)[sel, None] * v
+        Zr = np.broadcast_to(Z[li], (p.shape[0], Z.shape[1]))
+        gp = dec.sdf_grad_p(Zr, p, np.ones(p.shape[0]))
+        gv = (gp * v).sum(1)
+        ok = np.abs(gv) > GRAZING * np.linalg.norm(gp, axis=1)
+        nrm = np.sqrt(r.xt[sel] ** 2 + r.yt[sel] ** 2 + 1.0)
+        seed = np.where(ok, -gd[sel] / nrm / np.where(ok, gv, 1.0), 0.0)
+        gz[li] += dec.sdf_vjp(Zr, p, seed, want_theta=False)[0].sum(0)
+    return gz
+
+
 def camera_samples(r: Render, prm, g_depth, g_sil):
     """The depth and silhouette samples of ``gradient_samples`` with, for each,
     its ray parameter t and the pixel's camera-frame unit direction u (so that

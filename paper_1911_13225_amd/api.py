@@ -183,6 +183,15 @@ def dist_render_bwd(ctx: Context, saved: Saved, g_depth=None, g_normal=None, g_s
     return g_z
 
 
+def dist_render_bwd_implicit(ctx: Context, saved: Saved, g_depth=None, g_normal=None, g_sil=None, n_latents=None):
+    """dL/dz with the exact (implicit-function) depth derivative at each hit;
+    silhouette and normal terms as dist_render_bwd."""
+    g_z = torch.empty(n_latents, ctx.latent_dim, device="cuda")
+    args = [None if g is None else g.detach().float().contiguous() for g in (g_depth, g_normal, g_sil)]
+    check(ctx.lib.dist_render_bwd_implicit(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_z), _stream()))
+    return g_z
+
+
 def dist_render_bwd_camera(ctx: Context, saved: Saved, n_views: int, g_depth=None, g_sil=None):
     """Gradient of the depth and silhouette terms w.r.t. each view's camera
     extrinsics: a tensor [n_views, 12] = (dL/dc, dL/dR_wc row-major)."""

@@ -54,9 +54,10 @@ struct NrmSave {
 struct CamSpace {
   char* mem = nullptr;
   size_t bytes = 0;
-  long long cap_samples = 0;
+  long long cap_samples = 0, cap_pix = 0;
   int4* sample_cam = nullptr;
   float* gp = nullptr;
+  float* gv = nullptr;             // per output pixel: grad f . v at the hit (implicit depth gradient)
 };
 
 // Buffers of one forward render (ray pool, lists, counters, outputs staging).

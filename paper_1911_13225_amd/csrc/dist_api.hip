@@ -949,12 +949,36 @@ static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const f
   return DIST_OK;
 }
 
-extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const float* g_depth, const float* g_normal,
-                               const float* g_sil, float* g_z, float* const* g_W, float* const* g_b, void* stream) {
-  if (!ctx || !saved || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
-  if (saved->ctx != ctx) return dist_set_error(DIST_EINVAL, "saved state belongs to another context");
-  if ((g_W == nullptr) != (g_b == nullptr)) return dist_set_error(DIST_EINVAL, "pass both g_W and g_b, or neither");
-  hipStream_t st = (hipStream_t)stream;
+static int cs_get(dist_ctx* ctx, Workspace* w, long long cap_samples, long long cap_pix = 0) {
+  CamSpace* c = w->cs;
+  if (c && c->cap_samples >= cap_samples && c->cap_pix >= cap_pix) return DIST_OK;
+  cap_samples = std::max(cap_samples, c ? c->cap_samples : 0);
+  cap_pix = std::max(cap_pix, c ? c->cap_pix : 0);
+  if (c) {
+    ctx_free(ctx, c->mem, c->bytes);
+    delete c;
+    w->cs = nullptr;
+  }
+  c = new CamSpace();
+  c->cap_samples = cap_samples;
+  c->cap_pix = cap_pix;
+  const size_t a = ((size_t)cap_samples * sizeof(int4) + 255) & ~(size_t)255;
+  const size_t g = ((size_t)cap_samples * 12 * sizeof(float) + 255) & ~(size_t)255;
+  c->bytes = a + g + (size_t)cap_pix * sizeof(float) + 256;
+  int rc = ctx_alloc(ctx, (void**)&c->mem, c->bytes);
+  if (rc != DIST_OK) { delete c; return rc; }
+  c->sample_cam = (int4*)c->mem;
+  c->gp = (float*)(c->mem + a);
+  c->gv = (float*)(c->mem + a + g);
+  w->cs = c;
+  return DIST_OK;
+}
+
+// The backward of dist_render_bwd; with imp_gv the depth term of each hit is
+// the exact (implicit-function) one, using grad f . v measured per pixel.
+static int render_bwd(dist_ctx* ctx, const dist_saved* saved, const float* g_depth, const float* g_normal,
+                      const float* g_sil, float* g_z, float* const* g_W, float* const* g_b, const float* imp_gv,
+                      hipStream_t st) {
   Workspace* w = saved->ws;
   const int prec = adj_prec(saved->prm.precision);
   const int tile = adj_tile_rows(prec);
@@ -964,7 +988,7 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   const bool split = saved->masks_kept && !g_W && g_normal != nullptr;
   // sample lists are padded per latent to a multiple of both kernels' tiles
   const int pad = split ? std::max(tile, adj_tile_rows(vjp_prec(prec))) : tile;
-  const long long cap = (long long)n_img * hw * (saved->prm.k_samples + 6) + 2LL * n_lat * pad;
+  const long long cap = (long long)n_img * hw * (std::max(saved->prm.k_samples, 2) + 6) + 2LL * n_lat * pad;
   if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
   const int bpi = (hw + 255) / 256;
   const int grid = mlp_grid(ctx, cap, prec);
@@ -978,6 +1002,7 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   in.nraw = w->nraw;
   in.delta = saved->prm.normal_delta;
   in.hit_pix = split ? w->hit_pix : nullptr;
+  in.imp_gv = imp_gv;
   const SplitList sl{b->bsum2, b->boff2, b->seg2_base, b->seg2_total, b->seg2_padded, b->sample_idx};
   launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, pad, in, b->bsum, b->boff,
                  b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st, 0,
@@ -991,24 +1016,67 @@ extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const flo
   return run_adjoint_and_reduce(ctx, w, b, prec, n_lat, g_z, split, st);
 }
 
-static int cs_get(dist_ctx* ctx, Workspace* w, long long cap_samples) {
-  CamSpace* c = w->cs;
-  if (c && c->cap_samples >= cap_samples) return DIST_OK;
-  if (c) {
-    ctx_free(ctx, c->mem, c->bytes);
-    delete c;
-    w->cs = nullptr;
+extern "C" int dist_render_bwd(dist_ctx* ctx, const dist_saved* saved, const float* g_depth, const float* g_normal,
+                               const float* g_sil, float* g_z, float* const* g_W, float* const* g_b, void* stream) {
+  if (!ctx || !saved || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (saved->ctx != ctx) return dist_set_error(DIST_EINVAL, "saved state belongs to another context");
+  if ((g_W == nullptr) != (g_b == nullptr)) return dist_set_error(DIST_EINVAL, "pass both g_W and g_b, or neither");
+  return render_bwd(ctx, saved, g_depth, g_normal, g_sil, g_z, g_W, g_b, nullptr, (hipStream_t)stream);
+}
+
+__global__ void k_fill_f32(float* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+extern "C" int dist_render_bwd_implicit(dist_ctx* ctx, const dist_saved* saved, const float* g_depth,
+                                        const float* g_normal, const float* g_sil, float* g_z, void* stream) {
+  if (!ctx || !saved || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (saved->ctx != ctx) return dist_set_error(DIST_EINVAL, "saved state belongs to another context");
+  hipStream_t st = (hipStream_t)stream;
+  if (!g_depth) return render_bwd(ctx, saved, g_depth, g_normal, g_sil, g_z, nullptr, nullptr, nullptr, st);
+  Workspace* w = saved->ws;
+  const int prec = adj_prec(saved->prm.precision);
+  const int tile = adj_tile_rows(prec);
+  const int n_img = saved->n_img, hw = saved->hw, n_lat = saved->n_lat;
+  const long long npix = (long long)n_img * hw;
+  // pass 1: grad f . v at the Eq. 1 point of every hit with a depth gradient.
+  // The buffers are sized for pass 2 up front (no reallocation between passes).
+  const int pad = std::max(tile, adj_tile_rows(vjp_prec(prec)));
+  const long long cap2 = npix * (std::max(saved->prm.k_samples, 2) + 6) + 2LL * n_lat * pad;
+  const long long cap = npix + (long long)n_lat * tile;
+  if (cap2 > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
+  const int bpi = (hw + 255) / 256;
+  const int grid = mlp_grid(ctx, cap2, prec);
+  int rc = bw_get(ctx, w, (int)cap2, n_img * bpi, n_lat, tile, adj_mask_words(prec, ctx->net[prec]) * grid);
+  if (!rc) rc = cs_get(ctx, w, cap, npix);
+  if (rc) return rc;
+  BwdSpace* b = w->bw;
+  SeedIn in{};
+  in.g_depth = g_depth;
+  in.hit_mode = 1;
+  launch_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_lat, tile, in, b->bsum, b->boff,
+                 b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat, st, 0, nullptr,
+                 w->cs->sample_cam);
+  AdjArgs aa{};
+  aa.net = ctx->net[prec];
+  aa.bias0_lat = w->bias0_lat;
+  aa.biasS_lat = w->biasS_lat;
+  aa.samples = b->samples;
+  aa.sample_lat = b->sample_lat;
+  aa.n_samples = b->n_samples;
+  aa.mask_ws = b->mask_ws;
+  aa.partial = b->partial;
+  aa.gp_part = w->cs->gp;
+  {
+    TimedLaunch tl(ctx, 2, st, b->n_samples, 1);
+    launch_adjoint(prec, aa, grid, st);
   }
-  c = new CamSpace();
-  c->cap_samples = cap_samples;
-  const size_t a = ((size_t)cap_samples * sizeof(int4) + 255) & ~(size_t)255;
-  c->bytes = a + (size_t)cap_samples * 12 * sizeof(float) + 256;
-  int rc = ctx_alloc(ctx, (void**)&c->mem, c->bytes);
-  if (rc != DIST_OK) { delete c; return rc; }
-  c->sample_cam = (int4*)c->mem;
-  c->gp = (float*)(c->mem + a);
-  w->cs = c;
-  return DIST_OK;
+  hipLaunchKernelGGL(k_fill_f32, dim3(512), dim3(256), 0, st, w->cs->gv, npix);
+  launch_hit_gv(w->pool, w->imgs, b->samples, w->cs->sample_cam, w->cs->gp, b->n_samples, (int)cap, w->cs->gv, st);
+  HIPCHK(hipGetLastError());
+  // pass 2: the backward with implicit depth seeds
+  return render_bwd(ctx, saved, g_depth, g_normal, g_sil, g_z, nullptr, nullptr, w->cs->gv, st);
 }
 
 extern "C" int dist_render_bwd_camera(dist_ctx* ctx, const dist_saved* saved, const float* g_depth,

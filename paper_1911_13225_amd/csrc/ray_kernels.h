@@ -32,6 +32,12 @@ struct SeedIn {
   const float4* nraw;
   float delta;
   const int* hit_pix;  // split layout: per output pixel, its index in the forward's hit list
+  // exact depth gradient: 1 = only one unit-seed sample per hit with a depth
+  // gradient, at its Eq. 1 point (to measure grad f . v there); with imp_gv
+  // the depth term of a hit is one sample at that point with seed
+  // -dL/dz_c / |(xt, yt, 1)| / (grad f . v) (imp_gv[q] = 0: no depth term)
+  int hit_mode;
+  const float* imp_gv;
 };
 
 // Second sample list of the split layout (normal-stencil samples).
@@ -64,6 +70,8 @@ void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const i
 void launch_cam_reduce(const RayPool& pl, const ImgDesc* imgs, const int* img_view, int n_img, int n_views,
                        const float4* samples, const int4* sample_cam, const float* gp_part, const int* n_samples,
                        const float* g_sil, float* g_cam, hipStream_t s);
+void launch_hit_gv(const RayPool& pl, const ImgDesc* imgs, const float4* samples, const int4* sample_cam,
+                   const float* gp_part, const int* n_samples, int max_samples, float* gv, hipStream_t s);
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s);
 void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
                     int* out_count, const AdvEntry* table, const int* hdr, int* img_active,

@@ -220,11 +220,20 @@ __device__ __forceinline__ PixSamples pixel_samples(const RayPool& pl, const Img
   if (st == ST_MISS) return ps;
   const float gd = in.g_depth ? in.g_depth[q] : 0.f;
   const float gs = in.g_sil ? in.g_sil[q] : 0.f;
-  if (st == ST_HIT && gd != 0.f) {
+  if (in.hit_mode) {
+    ps.base = (st == ST_HIT && gd != 0.f) ? 1 : 0;
+    return ps;
+  }
+  if (in.imp_gv) {
+    // silhouette sample at the minimum-|f| query, depth sample at the Eq. 1 point
+    ps.base = ((gs != 0.f && pl.rec_f[r] != INFINITY) ? 1 : 0) + ((st == ST_HIT && gd != 0.f && in.imp_gv[q] != 0.f) ? 1 : 0);
+  } else if (st == ST_HIT && gd != 0.f) {
     for (int k = 0; k < im.K; ++k) ps.nd += (pl.rec_f[(size_t)k * pl.cap + r] != INFINITY) ? 1 : 0;
   }
-  const int ns = (gs != 0.f && pl.rec_f[r] != INFINITY) ? 1 : 0;
-  ps.base = ps.nd > ns ? ps.nd : ns;
+  if (!in.imp_gv) {
+    const int ns = (gs != 0.f && pl.rec_f[r] != INFINITY) ? 1 : 0;
+    ps.base = ps.nd > ns ? ps.nd : ns;
+  }
   if (st == ST_HIT && in.g_normal && in.nraw) {
     const float* g = in.g_normal + 3 * q;
     if ((g[0] != 0.f || g[1] != 0.f || g[2] != 0.f) && in.nraw[q].w > 0.f) ps.nn = 6;
@@ -370,7 +379,27 @@ __global__ __launch_bounds__(256) void k_samples_write(RayPool pl, const ImgDesc
   const float gd = in.g_depth ? in.g_depth[q] : 0.f;
   const float gs = in.g_sil ? in.g_sil[q] : 0.f;
   const float dseed = im.alpha * gd / sqrtf(xt * xt + yt * yt + 1.f);
-  for (int k = 0; k < ps.base; ++k) {
+  const float dist_eq1 = d.w + pl.flast[r];
+  if (in.hit_mode || in.imp_gv) {
+    const float f0 = pl.rec_f[r];
+    if (in.imp_gv && gs != 0.f && f0 != INFINITY) {
+      const float t0 = pl.rec_t[r];
+      samples[o] = make_float4(fmaf(t0, d.x, cx), fmaf(t0, d.y, cy), fmaf(t0, d.z, cz),
+                               gs * (f0 > 0.f ? 1.f : (f0 < 0.f ? -1.f : 0.f)));
+      sample_lat[o] = im.latent;
+      if (sample_cam) sample_cam[o] = make_int4(img, pix, __float_as_int(t0), 0);
+      ++o;
+    }
+    const bool dep = pl.st[r] == ST_HIT && gd != 0.f && (in.hit_mode || in.imp_gv[q] != 0.f);
+    if (dep) {
+      const float seed = in.hit_mode ? 1.f : -gd / sqrtf(xt * xt + yt * yt + 1.f) / in.imp_gv[q];
+      samples[o] = make_float4(fmaf(dist_eq1, d.x, cx), fmaf(dist_eq1, d.y, cy), fmaf(dist_eq1, d.z, cz), seed);
+      sample_lat[o] = im.latent;
+      if (sample_cam) sample_cam[o] = make_int4(img, pix, __float_as_int(dist_eq1), 0);
+      ++o;
+    }
+  }
+  for (int k = 0; k < ((in.hit_mode || in.imp_gv) ? 0 : ps.base); ++k) {
     const float tk = pl.rec_t[(size_t)k * pl.cap + r];
     float seed = k < ps.nd ? dseed : 0.f;
     if (k == 0 && gs != 0.f) {
@@ -742,6 +771,39 @@ void launch_samples_pad(int n_lat, const int* seg_base, const int* seg_total, co
   hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
                      sample_lat, nullptr, nullptr);
 }
+// grad_p f . v at each hit's Eq. 1 point (unit seeds): the adjoint's per-wave
+// partials plus the residual term 0.5 p / |p|; 0 where the ray grazes the
+// surface (|grad f . v| <= 1e-2 |grad f|), which then gets no implicit depth term.
+__global__ void k_hit_gv(RayPool pl, const ImgDesc* imgs, const float4* samples, const int4* sample_cam,
+                         const float* gp_part, const int* n_samples, float* gv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_samples) return;
+  const int4 sc = sample_cam[i];
+  if (sc.x < 0) return;
+  const ImgDesc& im = imgs[sc.x];
+  const float4 smp = samples[i];
+  const float rn = sqrtf(smp.x * smp.x + smp.y * smp.y + smp.z * smp.z);
+  const float h = rn > 0.f ? 0.5f * smp.w / rn : 0.f;
+  float g[3] = {h * smp.x, h * smp.y, h * smp.z};
+  const float* pp = gp_part + (size_t)i * 12;
+  for (int w = 0; w < 4; ++w) {
+    g[0] += pp[3 * w];
+    g[1] += pp[3 * w + 1];
+    g[2] += pp[3 * w + 2];
+  }
+  const float4 d = pl.d[im.slot_base + im.lvl_off[0] + sc.y];
+  const float dv = g[0] * d.x + g[1] * d.y + g[2] * d.z;
+  const float gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  gv[(size_t)im.out_base + sc.y] = fabsf(dv) > 1e-2f * gn ? dv : 0.f;
+}
+
+void launch_hit_gv(const RayPool& pl, const ImgDesc* imgs, const float4* samples, const int4* sample_cam,
+                   const float* gp_part, const int* n_samples, int max_samples, float* gv, hipStream_t s) {
+  if (max_samples <= 0) return;
+  hipLaunchKernelGGL(k_hit_gv, dim3(nblk(max_samples, 256)), dim3(256), 0, s, pl, imgs, samples, sample_cam, gp_part,
+                     n_samples, gv);
+}
+
 void launch_cam_reduce(const RayPool& pl, const ImgDesc* imgs, const int* img_view, int n_img, int n_views,
                        const float4* samples, const int4* sample_cam, const float* gp_part, const int* n_samples,
                        const float* g_sil, float* g_cam, hipStream_t s) {

@@ -197,3 +197,41 @@ def test_camera_gradient_matches_oracle(ctx, precision, tol):
     _log("camera gradient precision", precision, "rel", rel, "|g|", np.linalg.norm(ref))
     assert np.array_equal(g, g2)
     assert rel <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 2e-3), (1, 2e-2)], ids=["fp32", "bf16"])
+def test_implicit_depth_gradient_matches_oracle(ctx, precision, tol):
+    """dL/dz with the exact depth derivative at the hits (silhouette and normal
+    terms as the paper), free running against the oracle's implicit_backward;
+    the paper's approximation is reported beside it."""
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=2, k_samples=1, precision=precision,
+                         want_normals=1)
+    H = 40
+    cams = di.random_sphere_cameras(2, H, H)
+    Z = di.make_latents(2, spec.latent_dim, sigma=0.05)
+    pairs = [(i // 2, i % 2) for i in range(4)]
+    dec = oracle_decoder(spec)
+    rs = O.render(dec, Z, cams, pairs, prm)
+    grads, gd, gn, gs = [], [], [], []
+    for r, (v, l) in zip(rs, pairs):
+        dt, nt, st = di.sphere_target_maps(cams[v], 0.45)
+        _, g_d, g_n, g_s = O.loss_and_grads(r, dt, nt, st, w_d=10.0, w_s=1.0, w_n=1.0)
+        grads.append((g_d, g_n, g_s))
+        gd.append(g_d)
+        gn.append(g_n)
+        gs.append(g_s)
+    ref = O.implicit_backward(dec, Z, rs, pairs, prm, grads)
+    paper = O.backward(dec, Z, rs, pairs, prm, grads, want_theta=False)[0]
+    out = api.dist_render_fwd(ctx, cams, torch.tensor(Z, device="cuda"), prm, save=True)
+    T = lambda a: torch.tensor(np.stack(a).astype(np.float32), device="cuda")
+    g = api.dist_render_bwd_implicit(ctx, out["saved"], T(gd), T(gn), T(gs), n_latents=2).double().cpu().numpy()
+    g2 = api.dist_render_bwd_implicit(ctx, out["saved"], T(gd), T(gn), T(gs), n_latents=2).double().cpu().numpy()
+    out["saved"].free()
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    gap = np.linalg.norm(paper - ref) / np.linalg.norm(ref)
+    cos = float(np.sum(paper * ref) / (np.linalg.norm(paper) * np.linalg.norm(ref)))
+    _log("implicit gradient precision", precision, "rel", rel, "| paper vs exact: rel", gap, "cos", cos)
+    assert np.array_equal(g, g2)
+    assert rel <= tol

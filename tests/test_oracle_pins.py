@@ -537,3 +537,55 @@ def test_camera_gradient_against_frozen_sample_differences():
                 Rm[i, j] -= e
                 fd = (surrogate(c0, Rp) - surrogate(c0, Rm)) / (2 * e)
                 assert abs(fd - g_R[vi, i, j]) <= 1e-6 * max(1.0, abs(g_R[vi, i, j])) + 1e-9
+
+
+# ----------------------------------------------------------------------------
+# exact (implicit-function) depth gradient
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("spec", [di.C1_SPEC, di.DEEPSDF_SPEC], ids=["c1", "deepsdf"])
+def test_implicit_depth_gradient_closed_form(spec):
+    """On the linear-regime decoder the surface is the sphere |p| = R(z),
+    R = 0.5 - 0.1 tanh(a + u.z): the hit distance t* solves |c + t v| = R, so
+    dt*/dz = -0.1 sech^2(m) u / (p_hat . v).  The oracle's implicit gradient
+    equals that formula at its Eq. 1 points and the true derivative at the
+    exact roots to within the convergence tolerance."""
+    dec = _linear_decoder(spec)
+    L = spec.latent_dim
+    z = di.make_latents(1, L, sigma=0.01)
+    z64 = z[0].astype(np.float64)
+    P0 = np.zeros((L + 1, 3))
+    Zs = np.vstack([np.zeros(L), np.eye(L)])
+    m_all, _, _ = dec.layer_inputs(Zs, P0, keep=False)
+    a, u = m_all[0], m_all[1:] - m_all[0]
+    mz = a + u @ z64
+    Rz = 0.5 - 0.1 * math.tanh(mz)
+    H = 24
+    cam = di.front_camera(H, H)
+    prm = _prm(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=1, want_normals=0, k_samples=1)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    depth_t, _, sil_t = di.sphere_target_maps(cam, Rz)
+    dt = np.where(sil_t > 0.5, depth_t + 0.01, np.inf).astype(np.float32)
+    _, g_d, g_n, g_s = O.loss_and_grads(r, dt, np.zeros((H, H, 3)), sil_t, w_d=10.0, w_s=0.0)
+    gz = O.implicit_backward(dec, z, [r], [(0, 0)], prm, [(g_d, g_n, g_s)])[0]
+    hit = (r.status == O.HIT).reshape(-1) & (g_d.reshape(-1) != 0)
+    nrm = np.sqrt(r.xt[hit] ** 2 + r.yt[hit] ** 2 + 1)
+    v = r.dirs[hit]
+    sech2 = 1 - math.tanh(mz) ** 2
+    # formula at the Eq. 1 points (what the oracle evaluates)
+    p = cam.c.astype(np.float64) + r.dist.reshape(-1)[hit, None] * v
+    pv = np.sum(p / np.linalg.norm(p, axis=1, keepdims=True) * v, axis=1)
+    w = g_d.reshape(-1)[hit] / nrm
+    expect = -0.1 * sech2 * u * np.sum(w / pv)
+    np.testing.assert_allclose(gz, expect, rtol=1e-9, atol=1e-14)
+    # the true derivative at the exact roots
+    c = cam.c.astype(np.float64)
+    b = v @ c
+    t_star = -b - np.sqrt(b * b - (c @ c - Rz * Rz))
+    ps = c[None, :] + t_star[:, None] * v
+    true = -0.1 * sech2 * u * np.sum(w / np.sum(ps / Rz * v, axis=1))
+    # the Eq. 1 point lies within eps / s of the root (s = -p_hat . v), which
+    # moves 1 / (p_hat . v) by O(eps / (R s^2)) per pixel: 0.7% here
+    assert np.linalg.norm(gz - true) <= 2e-2 * np.linalg.norm(true)
+    # the paper's approximation differs (it omits the 1 / (grad f . v) factor)
+    gp_, _, _ = O.backward(dec, z, [r], [(0, 0)], prm, [(g_d, g_n, g_s)], want_theta=False)
+    assert np.linalg.norm(gp_[0] - gz) > 1e-2 * np.linalg.norm(gz)
