@@ -152,6 +152,19 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
 // multiple of kDepth (the padded widths are multiples of 128).
 constexpr int kDepth = 4;
 
+// Weight fragments are read with raw buffer loads: a scalar resource for the
+// layer's packed array (its byte size bounds every load), the lane's 16-byte
+// slot as the vector offset and the fragment's position as a scalar offset,
+// so stepping k costs no vector address arithmetic.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frag_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+template <class T>
+__device__ __forceinline__ T ld_frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 template <class Frag, int MTW, int NTW>
 struct Pipe {
   Frag a[kDepth][NTW];
@@ -160,11 +173,13 @@ struct Pipe {
 
 template <int MTW, int NTW>
 __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& s, const bf16x8* __restrict__ wp,
-                                          int ksteps, int nt0, int mt0, int lane) {
+                                          int ksteps, int nt0, int mt0, int lane, int nbytes) {
   const int r = lane & 31, g = lane >> 5;
-  const bf16x8* wrow[NTW];
+  const __amdgpu_buffer_rsrc_t rs = frag_rsrc(wp, nbytes);
+  const int voff = lane * 16;
+  int wrow[NTW];                 // byte offset of fragment (n-tile nt0 + j, k-step 0)
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
+  for (int j = 0; j < NTW; ++j) wrow[j] = (nt0 + j) * ksteps * 1024;
   const char* arow[MTW];
   int sw[MTW];
 #pragma unroll
@@ -177,7 +192,7 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
 #pragma unroll
   for (int d = 0; d < kDepth; ++d) {
 #pragma unroll
-    for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)d * 64];
+    for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + d * 1024);
     __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
   }
 #pragma unroll
@@ -201,7 +216,7 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
       {
         const int kn = min(ks + kDepth, ksteps - 1);
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)kn * 64];
+        for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
@@ -212,15 +227,15 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
 // B = activations); without X3 only the hi planes are used (bf16 product).
 template <int MTW, int NTW, bool X3>
 __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>& s, const bf16x8* __restrict__ wp,
-                                           const bf16x8* __restrict__ wlo, int ksteps, int nt0, int mt0, int lane) {
+                                           const bf16x8* __restrict__ wlo, int ksteps, int nt0, int mt0, int lane,
+                                           int nbytes) {
   const int r = lane & 31, g = lane >> 5;
-  const bf16x8* wrow[NTW];
-  const bf16x8* lrow[NTW];
+  const __amdgpu_buffer_rsrc_t rs = frag_rsrc(wp, nbytes);
+  const __amdgpu_buffer_rsrc_t rl = frag_rsrc(X3 ? wlo : wp, nbytes);
+  const int voff = lane * 16;
+  int wrow[NTW];
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) {
-    wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
-    lrow[j] = X3 ? wlo + (size_t)(nt0 + j) * ksteps * 64 + lane : nullptr;
-  }
+  for (int j = 0; j < NTW; ++j) wrow[j] = (nt0 + j) * ksteps * 1024;
   const char* arow[MTW];
   int sw[MTW];
 #pragma unroll
@@ -234,8 +249,8 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
   for (int d = 0; d < kDepth; ++d) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
-      ph.a[d][j] = wrow[j][(size_t)d * 64];
-      if constexpr (X3) pl.a[d][j] = lrow[j][(size_t)d * 64];
+      ph.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + d * 1024);
+      if constexpr (X3) pl.a[d][j] = ld_frag<bf16x8>(rl, voff, wrow[j] + d * 1024);
     }
     __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
   }
@@ -271,8 +286,8 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
         const int kn = min(ks + kDepth, ksteps - 1);
 #pragma unroll
         for (int j = 0; j < NTW; ++j) {
-          ph.a[d][j] = wrow[j][(size_t)kn * 64];
-          if constexpr (X3) pl.a[d][j] = lrow[j][(size_t)kn * 64];
+          ph.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
+          if constexpr (X3) pl.a[d][j] = ld_frag<bf16x8>(rl, voff, wrow[j] + kn * 1024);
         }
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
@@ -282,11 +297,13 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
 
 template <int MTW, int NTW>
 __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s, const f32x4* __restrict__ wp,
-                                         int ksteps, int nt0, int mt0, int lane) {
+                                         int ksteps, int nt0, int mt0, int lane, int nbytes) {
   const int r = lane & 31, g = lane >> 5;
-  const f32x4* wrow[NTW];
+  const __amdgpu_buffer_rsrc_t rs = frag_rsrc(wp, nbytes);
+  const int voff = lane * 16;
+  int wrow[NTW];
 #pragma unroll
-  for (int j = 0; j < NTW; ++j) wrow[j] = wp + (size_t)(nt0 + j) * ksteps * 64 + lane;
+  for (int j = 0; j < NTW; ++j) wrow[j] = (nt0 + j) * ksteps * 1024;
   const char* arow[MTW];
   int sw[MTW];
 #pragma unroll
@@ -299,7 +316,7 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
 #pragma unroll
   for (int d = 0; d < kDepth; ++d) {
 #pragma unroll
-    for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)d * 64];
+    for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<f32x4>(rs, voff, wrow[j] + d * 1024);
     __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
   }
 #pragma unroll
@@ -325,7 +342,7 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
       {
         const int kn = min(ks + kDepth, ksteps - 1);
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) p.a[d][j] = wrow[j][(size_t)kn * 64];
+        for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<f32x4>(rs, voff, wrow[j] + kn * 1024);
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
@@ -748,11 +765,12 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
 // groups of N/4 outputs and each covers all rows of the tile.
 template <int P, int MTW, int NTW, int MODE, bool CAP, bool SKIP>
 __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
-                                          const void* wlo, int ksteps) {
+                                          const void* wlo, int ksteps, int nbytes) {
   constexpr int WN = 4;
-  // lane-dependent addressing is recomputed per layer (see opaque())
+  // lane-dependent addressing is recomputed per layer (see opaque()); the wave
+  // index is uniform, so weight addresses are a scalar base plus a lane offset
   const int t = opaque((int)threadIdx.x);
-  const int wave = t >> 6, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   const int nw = wave % WN, mg = wave / WN;
   const int nt0 = nw * NTW, mt0 = mg * MTW;
   f32x16 acc[MTW][NTW];
@@ -760,11 +778,12 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   else if constexpr (SKIP) acc_bias<P, MTW, NTW, true>(acc, ec, s, nt0, mt0, lane);
   else acc_mfma_start<P, MTW, NTW>(acc, net.bfrag[ec.layer], nt0, lane);
   if constexpr (P == 1) {
-    gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane);
+    gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane, nbytes);
   } else if constexpr (P == 2) {
-    gemm_split<MTW, NTW, MODE != EP_VJP>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane);
+    gemm_split<MTW, NTW, MODE != EP_VJP>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane,
+                                         nbytes);
   } else {
-    gemm_f32<MTW, NTW>(acc, s, (const f32x4*)wp, ksteps, nt0, mt0, lane);
+    gemm_f32<MTW, NTW>(acc, s, (const f32x4*)wp, ksteps, nt0, mt0, lane, nbytes);
   }
   __syncthreads();
   if constexpr (MODE == EP_ACT) ep_act<P, MTW, NTW, false, CAP>(ec, acc, s, nt0, mt0, lane);
@@ -786,9 +805,10 @@ __device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const S
                                      const void* wlo, int N, int K) {
   constexpr int MT = Cfg<P>::MT;
   const int ksteps = K / (P ? 16 : 8);
-  if (N == 512) layer_run<P, MT, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps);
-  else if (N == 256) layer_run<P, MT, 2, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps);
-  else layer_run<P, MT, 1, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps);
+  const int nbytes = N * K * (P ? 2 : 4);       // the layer's packed fragment array
+  if (N == 512) layer_run<P, MT, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+  else if (N == 256) layer_run<P, MT, 2, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+  else layer_run<P, MT, 1, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
   return 4;
 }
 
