@@ -215,7 +215,8 @@ int dist_saved_free(dist_saved* saved);
 /* Decoder query (one network feed-forward per point, paper Sec. 3.2):
  * f[i] = f(points[i], z[latent_ids[i]]).  points device [n, 3], latent_ids
  * device int32 [n] in [0, n_latents), z device [n_latents, latent_dim],
- * f device [n].  precision DIST_FP32, DIST_BF16 or DIST_BF16X3. */
+ * f device [n].  precision DIST_FP32, DIST_BF16 or DIST_BF16X3.  n = 0 is a
+ * no-op (the arrays may then be NULL). */
 int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
                   const float* z, int32_t n_latents, int64_t n, int32_t precision,
                   float* f, void* stream);
@@ -225,7 +226,8 @@ int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
  * z_l)/dz_l, and optionally the weight gradient.  precision DIST_FP32
  * (float32 throughout) or DIST_BF16 / DIST_BF16X3 (split-bf16 recompute,
  * bf16 back-propagation).  Synchronises the host (it stages the grouping of
- * samples by latent). */
+ * samples by latent).  With n = 0, g_z (and g_W, g_b) are zeroed and points,
+ * latent_ids and seeds may be NULL. */
 int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
                  const float* seeds, const float* z, int32_t n_latents, int64_t n,
                  int32_t precision, float* g_z, float* const* g_W, float* const* g_b,

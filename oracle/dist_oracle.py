@@ -233,12 +233,22 @@ def unit_sphere_init(c, D, near, far):
     b = D @ c
     cc = float(c @ c)
     disc = b * b - (cc - 1.0)
-    inside = disc > 0.0
+    # Reading R16: the camera is outside the sphere, so the two roots of the
+    # line share a sign; the ray meets the sphere only if they lie ahead (b < 0)
+    inside = (disc > 0.0) & (b < 0.0)
     sq = np.sqrt(np.maximum(disc, 0.0))
     t_lo = np.maximum(-b - sq, near)
     t_hi = np.minimum(-b + sq, far)
-    dist = np.sqrt(np.maximum(cc - b * b, 0.0))
+    dist = ray_origin_distance(c, b)
     return inside, t_lo, t_hi, dist, np.abs(disc)
+
+
+def ray_origin_distance(c, b):
+    """Distance from the origin to the ray c + t v, t >= 0, with b = c . v:
+    the foot of the perpendicular if it lies ahead (b < 0), else the camera
+    centre (App. A.3 uses it for the soft silhouette of rays that miss)."""
+    cc = float(c @ c)
+    return np.where(b < 0.0, np.sqrt(np.maximum(cc - b * b, 0.0)), math.sqrt(cc))
 
 
 # ============================================================================
@@ -459,7 +469,7 @@ def render_image(sdf_fn: Callable, cam: Cam, prm, pixels: Optional[np.ndarray] =
     # sphere; (distance of the ray from the origin) - 1 for rays that miss it.
     miss = st.status == MISS
     b = D @ c
-    sil[keys[miss]] = np.sqrt(np.maximum(c @ c - b[miss] ** 2, 0.0)) - 1.0
+    sil[keys[miss]] = ray_origin_distance(c, b[miss]) - 1.0
     sil[keys[~miss]] = st.rec_absf[0, ~miss] - float(prm.eps)
 
     normal = np.zeros((n, 3))
@@ -698,8 +708,9 @@ def camera_backward(dec: Decoder, Z, renders: Sequence[Render], cams: Sequence, 
     depth/silhouette sample keeps its ray parameter t, and only its position
     p = c + t R u moves with the camera, so a sample adds
     s grad_p f(p) to dL/dc and s t grad_p f(p) u^T to dL/dR (R_wc, row-major).
-    Rays that miss the unit sphere have S = sqrt(|c|^2 - (c.v)^2) - 1 with
-    v = R u, differentiated exactly.  Normal terms are not included (g_normal
+    Rays that miss the unit sphere have S = (distance from the origin to the
+    ray) - 1, i.e. sqrt(|c|^2 - (c.v)^2) - 1 with v = R u when the foot of the
+    perpendicular lies ahead (c.v < 0), else |c| - 1; differentiated exactly.  Normal terms are not included (g_normal
     is not an input here).
     """
     Z = np.asarray(Z, np.float64)
@@ -721,10 +732,13 @@ def camera_backward(dec: Decoder, Z, renders: Sequence[Render], cams: Sequence, 
             nrm = np.sqrt(r.xt[sel] ** 2 + r.yt[sel] ** 2 + 1.0)
             uu = np.stack([r.xt[sel] / nrm, r.yt[sel] / nrm, 1.0 / nrm], axis=1)
             b = v @ c
-            q = np.sqrt(np.maximum(c @ c - b * b, 0.0))
+            ahead = b < 0.0
+            # foot ahead: S = sqrt(|c|^2 - b^2) - 1; else S = |c| - 1
+            q = np.where(ahead, np.sqrt(np.maximum(c @ c - b * b, 0.0)), math.sqrt(c @ c))
             w = gs[sel] / q
-            g_c[vi] += (w[:, None] * (c[None, :] - b[:, None] * v)).sum(0)
-            dv = -(w * b)[:, None] * c[None, :]
+            bb = np.where(ahead, b, 0.0)
+            g_c[vi] += (w[:, None] * (c[None, :] - bb[:, None] * v)).sum(0)
+            dv = -(w * bb)[:, None] * c[None, :]
             g_R[vi] += np.einsum("ki,kj->ij", dv, uu)
     return g_c, g_R
 

@@ -1129,7 +1129,9 @@ extern "C" int dist_render_bwd_camera(dist_ctx* ctx, const dist_saved* saved, co
 // ---------------------------------------------------------------------------
 extern "C" int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* latent_ids, const float* z,
                              int32_t n_latents, int64_t n, int32_t precision, float* f, void* stream) {
-  if (!ctx || !points || !latent_ids || !z || !f) return dist_set_error(DIST_EINVAL, "null argument");
+  if (!ctx) return dist_set_error(DIST_EINVAL, "null argument");
+  if (n == 0) return DIST_OK;                       // nothing is read or written
+  if (!points || !latent_ids || !z || !f) return dist_set_error(DIST_EINVAL, "null argument");
   if (n < 0 || n > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "n out of range");
   if (n_latents < 1) return dist_set_error(DIST_EINVAL, "n_latents must be positive");
   if (precision < 0 || precision > 2) return dist_set_error(DIST_EINVAL, "bad precision");
@@ -1164,7 +1166,8 @@ extern "C" int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* 
 extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* latent_ids, const float* seeds,
                             const float* z, int32_t n_latents, int64_t n, int32_t precision, float* g_z,
                             float* const* g_W, float* const* g_b, void* stream) {
-  if (!ctx || !points || !latent_ids || !seeds || !z || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (!ctx || !z || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (n > 0 && (!points || !latent_ids || !seeds)) return dist_set_error(DIST_EINVAL, "null argument");
   if (n < 0 || n > (1LL << 28)) return dist_set_error(DIST_EINVAL, "n out of range");
   if (n_latents < 1) return dist_set_error(DIST_EINVAL, "n_latents must be positive");
   if (precision < 0 || precision > 2) return dist_set_error(DIST_EINVAL, "bad precision");

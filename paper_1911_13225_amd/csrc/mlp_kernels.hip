@@ -551,7 +551,7 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
         const float x[4] = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
         if constexpr (MASK) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) bits |= pos_bit(x[e]) << (8 * q + 4 * g + e);
+          for (int e = 0; e < 4; ++e) bits |= pos_bit(x[e]) << (8 * q + e);   // the lane's half: << 4g below
         }
         store4_relu<P>(s, m, n, g, x);
         if constexpr (CAP)
@@ -559,6 +559,7 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
               make_float4(fmaxf(x[0], 0.f), fmaxf(x[1], 0.f), fmaxf(x[2], 0.f), fmaxf(x[3], 0.f));
       }
       if constexpr (MASK) {
+        bits <<= 4 * g;
         bits |= __shfl_xor(bits, 32);
         if (g == 0 && row >= 0) ec.mk.p[mask_at(ec.mk, row, ec.layer, nt0 + j)] = bits;
       }
@@ -600,7 +601,7 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
           sum[i] = fmaf(wl[e], h[e], sum[i]);
           const unsigned b = pos_bit(x);
           v[e] = __uint_as_float(__float_as_uint(wl[e]) & (0u - b));
-          if constexpr (ADJ) bits[i][j] |= b << (8 * q + 4 * g + e);
+          if constexpr (ADJ) bits[i][j] |= b << (8 * q + e);
         }
         if constexpr (ADJ) store4<P>(s, m, n, g, v, true);
         if constexpr (CAP) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(h[0], h[1], h[2], h[3]);
@@ -615,7 +616,8 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
       const int row = mask_row(ec.mk, s, m);
 #pragma unroll
       for (int j = 0; j < NTW; ++j) {
-        const unsigned b = bits[i][j] | __shfl_xor(bits[i][j], 32);
+        const unsigned bl = bits[i][j] << (4 * g);
+        const unsigned b = bl | __shfl_xor(bl, 32);
         if (g == 0 && row >= 0) ec.mk.p[mask_at(ec.mk, row, ec.layer, nt0 + j)] = b;
       }
     }
@@ -654,15 +656,16 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
                                 fmaf(wx.z, p.x, fmaf(wy.z, p.y, fmaf(wz.z, p.z, b.z))),
                                 fmaf(wx.w, p.x, fmaf(wy.w, p.y, fmaf(wz.w, p.z, b.w)))};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) bits |= pos_bit(pre[e]) << (8 * q + 4 * g + e);
+          for (int e = 0; e < 4; ++e) bits |= pos_bit(pre[e]) << (8 * q + e);
         }
       } else {
-        bits = ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, m), 0), ec.layer, nt0 + j)];
+        // the lane's features are bits 8q + 4g + e of the stored word
+        bits = ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, m), 0), ec.layer, nt0 + j)] >> (4 * g);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[i][j][4 * q + e] = keep_if(acc[i][j][4 * q + e], bits, 8 * q + 4 * g + e);
+        for (int e = 0; e < 4; ++e) acc[i][j][4 * q + e] = keep_if(acc[i][j][4 * q + e], bits, 8 * q + e);
       if (ec.write_act) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {

@@ -57,7 +57,15 @@ __device__ __forceinline__ bool sphere_interval(const ImgDesc& im, float3 d, flo
   const float sq = sqrtf(fmaxf(disc, 0.f));
   t_lo = fmaxf(-b - sq, im.near_);
   t_hi = fminf(-b + sq, im.far_);
-  return disc > 0.f;
+  // the camera is outside the sphere, so both roots share a sign: the ray
+  // meets the sphere only if they lie ahead of it (b < 0)
+  return disc > 0.f && b < 0.f;
+}
+
+// Distance from the origin to the ray c + t v, t >= 0 (b = c . v): the foot of
+// the perpendicular if it lies ahead, else the camera centre (App. A.3).
+__device__ __forceinline__ float ray_origin_distance(float cc, float b) {
+  return b < 0.f ? sqrtf(fmaxf(cc - b * b, 0.f)) : sqrtf(cc);
 }
 
 __device__ __forceinline__ void init_ray(const RayPool& pl, const ImgDesc& im, int img, int r, float3 d, float t,
@@ -168,7 +176,7 @@ __global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* img
     if (st == ST_MISS) {
       const float b = im.c[0] * d.x + im.c[1] * d.y + im.c[2] * d.z;
       const float cc = im.c[0] * im.c[0] + im.c[1] * im.c[1] + im.c[2] * im.c[2];
-      sil = sqrtf(fmaxf(cc - b * b, 0.f)) - 1.f;
+      sil = ray_origin_distance(cc, b) - 1.f;
     } else {
       sil = fabsf(pl.rec_f[r]) - im.eps;
     }
@@ -509,8 +517,11 @@ __global__ __launch_bounds__(256) void k_cam_reduce(RayPool pl, const ImgDesc* i
         const float u[3] = {xt / nrm, yt / nrm, 1.f / nrm};
         const float c[3] = {im.c[0], im.c[1], im.c[2]};
         const float dv[3] = {d.x, d.y, d.z};
-        const float b = c[0] * dv[0] + c[1] * dv[1] + c[2] * dv[2];
-        const float q = sqrtf(fmaxf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] - b * b, 0.f));
+        const float b0 = c[0] * dv[0] + c[1] * dv[1] + c[2] * dv[2];
+        // S = (distance from the origin to the ray) - 1: with the foot of the
+        // perpendicular behind the camera it is |c| - 1 (b enters as 0)
+        const float b = b0 < 0.f ? b0 : 0.f;
+        const float q = ray_origin_distance(c[0] * c[0] + c[1] * c[1] + c[2] * c[2], b0);
         if (!(q > 0.f)) continue;
         const float w = gs / q;
         for (int a = 0; a < 3; ++a) {

@@ -519,7 +519,8 @@ def test_camera_gradient_against_frozen_sample_differences():
             val = np.dot(s, dec.sdf(np.broadcast_to(Z[0], (p.shape[0], Z.shape[1])), p)) if p.shape[0] else 0.0
             v = um @ R.T
             b = v @ c
-            return val + np.dot(gsf[miss], np.sqrt(c @ c - b * b) - 1.0)
+            dist = np.where(b < 0, np.sqrt(c @ c - b * b), np.sqrt(c @ c))
+            return val + np.dot(gsf[miss], dist - 1.0)
 
         # a step of 1e-7 keeps every ReLU unit on its side (1e-6 already
         # crosses a kink for one of these samples); rounding stays ~1e-9
@@ -589,3 +590,29 @@ def test_implicit_depth_gradient_closed_form(spec):
     # the paper's approximation differs (it omits the 1 / (grad f . v) factor)
     gp_, _, _ = O.backward(dec, z, [r], [(0, 0)], prm, [(g_d, g_n, g_s)], want_theta=False)
     assert np.linalg.norm(gp_[0] - gz) > 1e-2 * np.linalg.norm(gz)
+
+
+def test_view_facing_away_is_background():
+    """A camera outside the sphere looking away from it: the ray lines of some
+    pixels cross the sphere behind the camera, but no ray meets it; every pixel
+    is background with S = |c| - 1 - the distance from the origin to the ray
+    (App. A.3) - and the camera gradient of S is c / |c| per pixel."""
+    spec = di.C1_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    cam = di.front_camera(8, 8)
+    R = cam.R_wc.astype(np.float64) @ np.diag([-1.0, 1.0, -1.0])
+    away = di.Camera(cam.fx, cam.fy, cam.cx, cam.cy, R.astype(np.float32), cam.c, 8, 8)
+    prm = _prm(alpha=1.0, eps=1e-3, max_steps=20, c2f_levels=0, want_normals=0, k_samples=1)
+    Z = di.make_latents(1, spec.latent_dim)
+    r = O.render(dec, Z, [away], [(0, 0)], prm)[0]
+    c = away.c.astype(np.float64)
+    assert np.all(r.status == O.MISS) and r.queries == 0
+    # some pixel lines do cross the sphere (behind the camera)
+    b = r.dirs @ c
+    assert np.any(b * b - (c @ c - 1.0) > 0)
+    np.testing.assert_allclose(r.sil, np.linalg.norm(c) - 1.0, rtol=0, atol=1e-15)
+    gs = np.full((8, 8), 0.5)
+    g_c, g_R = O.camera_backward(dec, Z, [r], [away], [(0, 0)], prm, [(np.zeros((8, 8)), gs)])
+    np.testing.assert_allclose(g_c[0], 64 * 0.5 * c / np.linalg.norm(c), rtol=1e-12)
+    assert np.all(g_R == 0)
