@@ -154,6 +154,7 @@ struct DwArgs {
 void launch_dw(const DwArgs& a, hipStream_t s);
 
 int mlp_tile_rows(int precision);                 // rays per MLP tile
+int mlp_wg_per_cu(int precision);                 // MLP workgroups resident per CU
 int adj_tile_rows(int precision);                 // samples per adjoint tile
 size_t mlp_smem_bytes(int precision, const NetDev& net);
 size_t adj_mask_words(int precision, const NetDev& net);   // per workgroup

@@ -25,18 +25,25 @@ typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// WG = workgroups resident per CU.  A 64-row bf16 tile needs 68 KB of LDS for
+// the 512-wide DeepSDF decoder, so two workgroups share a CU (one wave per SIMD
+// each, at most 256 registers per lane): while one waits on LDS or its
+// epilogue, the other keeps the matrix cores busy.  The 4-byte formats need
+// 128 KB per 64-row tile and run one workgroup per CU with the full 512
+// registers (accumulators in AGPRs).  The backward kernels always run one
+// workgroup per CU: their adjoint state does not fit in 256 registers.
 template <int P> struct Cfg;
 template <> struct Cfg<1> {           // bf16 x bf16 -> f32, v_mfma_f32_32x32x16_bf16
-  static constexpr int M = 128, MT = 4, ES = 2, EPC = 8;
+  static constexpr int M = 64, MT = 2, ES = 2, EPC = 8, WG = 2;
 };
 template <> struct Cfg<0> {           // f32 x f32 -> f32, v_mfma_f32_32x32x2_f32
-  static constexpr int M = 64, MT = 2, ES = 4, EPC = 4;
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 4, WG = 1;
 };
 template <> struct Cfg<2> {           // split bf16: x = hi + lo; hi*hi + lo*hi + hi*lo, f32 accumulation
-  static constexpr int M = 64, MT = 2, ES = 4, EPC = 8;   // a row holds interleaved hi/lo 16-byte chunks
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 8, WG = 1;   // a row holds interleaved hi/lo 16-byte chunks
 };
 
-__host__ __device__ inline int rows_for(int P) { return P == 1 ? 128 : 64; }
+__host__ __device__ inline int rows_for(int) { return 64; }
 __host__ __device__ inline size_t smem_bytes_for(int P, int kmax) {
   const int M = rows_for(P);
   const int ES = P == 1 ? 2 : 4;
@@ -889,7 +896,7 @@ __device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* 
 // March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_march(MarchArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WG, Cfg<P>::WG))) void k_march(MarchArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -982,7 +989,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 // Plain decoder queries (explicit points, or the 6-point normal stencil)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_eval(EvalArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WG, Cfg<P>::WG))) void k_eval(EvalArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x;
@@ -1222,6 +1229,7 @@ void launch_dw(const DwArgs& a, hipStream_t st) {
 // Host-side helpers
 // ---------------------------------------------------------------------------
 int mlp_tile_rows(int precision) { return rows_for(precision); }
+int mlp_wg_per_cu(int precision) { return precision == 1 ? Cfg<1>::WG : 1; }
 int adj_tile_rows(int precision) { return mlp_tile_rows(precision); }
 size_t mlp_smem_bytes(int precision, const NetDev& net) { return smem_bytes_for(precision, net.kmax); }
 size_t adj_mask_words(int precision, const NetDev& net) {
