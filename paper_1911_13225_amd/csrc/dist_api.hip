@@ -630,7 +630,7 @@ int fold_biases(dist_ctx* ctx, Workspace* w, const float* z, int n_lat, hipStrea
 
 static int mlp_grid(dist_ctx* ctx, long long rows, int prec) {
   const long long tiles = (rows + mlp_tile_rows(prec) - 1) / mlp_tile_rows(prec);
-  return (int)std::max(1LL, std::min<long long>(tiles, (long long)ctx->n_cu * mlp_wg_per_cu(prec)));
+  return (int)std::max(1LL, std::min<long long>(tiles, ctx->n_cu));
 }
 
 // March all images of a workspace from their coarsest level to completion.

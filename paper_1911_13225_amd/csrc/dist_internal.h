@@ -20,7 +20,6 @@ namespace dist {
 constexpr int kMaxLayers = 12;
 constexpr int kMaxK = 4;
 constexpr int kMaxWidth = 512;
-constexpr int kThreads = 256;          // 4 waves of 64 per MLP workgroup (one per SIMD)
 
 enum : uint8_t { ST_ACTIVE = 0, ST_HIT = 1, ST_MISS = 2, ST_ESCAPED = 3, ST_UNCONVERGED = 4 };
 
@@ -154,7 +153,6 @@ struct DwArgs {
 void launch_dw(const DwArgs& a, hipStream_t s);
 
 int mlp_tile_rows(int precision);                 // rays per MLP tile
-int mlp_wg_per_cu(int precision);                 // MLP workgroups resident per CU
 int adj_tile_rows(int precision);                 // samples per adjoint tile
 size_t mlp_smem_bytes(int precision, const NetDev& net);
 size_t adj_mask_words(int precision, const NetDev& net);   // per workgroup
@@ -162,6 +160,8 @@ hipError_t mlp_setup(int precision, const NetDev& net);    // raise LDS limits
 
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t s);
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t s);
+// backward kernels: precision kPrecSplit or kPrecF32 (no bf16 variant; other
+// values launch nothing)
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t s);
 

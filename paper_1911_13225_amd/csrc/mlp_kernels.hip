@@ -25,25 +25,28 @@ typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// WG = workgroups resident per CU.  A 64-row bf16 tile needs 68 KB of LDS for
-// the 512-wide DeepSDF decoder, so two workgroups share a CU (one wave per SIMD
-// each, at most 256 registers per lane): while one waits on LDS or its
-// epilogue, the other keeps the matrix cores busy.  The 4-byte formats need
-// 128 KB per 64-row tile and run one workgroup per CU with the full 512
-// registers (accumulators in AGPRs).  The backward kernels always run one
-// workgroup per CU: their adjoint state does not fit in 256 registers.
+// M rows per tile, MT = M / 32 row tiles, NW waves per workgroup (one
+// workgroup per CU), WPE waves per SIMD.  Each wave streams the weight
+// fragments of its own output columns from L2 through the vector memory path,
+// which is the first unit to saturate: bf16 therefore takes 128-row tiles and
+// 8 waves (two per SIMD, 256 registers each), every wave covering all 128 rows
+// for 1/8 of the outputs, so one weight fragment feeds 4 MFMAs and the second
+// wave of a SIMD issues while the first waits.  The 4-byte formats keep 64-row
+// tiles (128 KB of LDS) and one wave per SIMD with the full 512 registers
+// (accumulators in AGPRs).
 template <int P> struct Cfg;
 template <> struct Cfg<1> {           // bf16 x bf16 -> f32, v_mfma_f32_32x32x16_bf16
-  static constexpr int M = 64, MT = 2, ES = 2, EPC = 8, WG = 2;
+  static constexpr int M = 128, MT = 4, ES = 2, EPC = 8, NW = 8, WPE = 2, NT = NW * 64;
 };
 template <> struct Cfg<0> {           // f32 x f32 -> f32, v_mfma_f32_32x32x2_f32
-  static constexpr int M = 64, MT = 2, ES = 4, EPC = 4, WG = 1;
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 4, NW = 4, WPE = 1, NT = NW * 64;
 };
 template <> struct Cfg<2> {           // split bf16: x = hi + lo; hi*hi + lo*hi + hi*lo, f32 accumulation
-  static constexpr int M = 64, MT = 2, ES = 4, EPC = 8, WG = 1;   // a row holds interleaved hi/lo 16-byte chunks
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 8, NW = 4, WPE = 1, NT = NW * 64;   // a row holds interleaved hi/lo 16-byte chunks
 };
 
-__host__ __device__ inline int rows_for(int) { return 64; }
+__host__ __device__ inline int rows_for(int P) { return P == 1 ? Cfg<1>::M : 64; }
+__host__ __device__ inline int threads_for(int P) { return P == 1 ? Cfg<1>::NT : Cfg<0>::NT; }
 __host__ __device__ inline size_t smem_bytes_for(int P, int kmax) {
   const int M = rows_for(P);
   const int ES = P == 1 ? 2 : 4;
@@ -93,7 +96,7 @@ __device__ __forceinline__ int opaque(int x) {
 __device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
 
 // Each thread owns one chunk of EPC output features (its W0_p columns stay in
-// registers) and walks the rows of the tile; N0 / EPC divides kThreads.
+// registers) and walks the rows of the tile; N0 / EPC divides the thread count.
 template <int P, bool CAP>
 __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_,
                                             float* hcap, int rstride) {
@@ -101,7 +104,7 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
   constexpr int M = Cfg<P>::M, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
   const int cpr = N0 / EPC;
-  const int rpp = kThreads / cpr;
+  const int rpp = Cfg<P>::NT / cpr;
   const int ch = tid % cpr;
   const int n = ch * EPC;
   float wx[EPC], wy[EPC], wz[EPC];
@@ -771,12 +774,11 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
 }
 
 // Run one layer (accumulator init + GEMM + barrier + epilogue + barrier) for an
-// output width N (128, 256 or 512 after padding): the 4 waves split N into 4
-// groups of N/4 outputs and each covers all rows of the tile.
-template <int P, int MTW, int NTW, int MODE, bool CAP, bool SKIP>
+// output width N (128, 256 or 512 after padding): WN waves split N into groups
+// of NTW 32-wide tiles; the NW / WN wave groups split the rows into MTW tiles.
+template <int P, int MTW, int NTW, int WN, int MODE, bool CAP, bool SKIP>
 __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                           const void* wlo, int ksteps, int nbytes) {
-  constexpr int WN = 4;
   // lane-dependent addressing is recomputed per layer (see opaque()); the wave
   // index is uniform, so weight addresses are a scalar base plus a lane offset
   const int t = opaque((int)threadIdx.x);
@@ -816,10 +818,20 @@ __device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const S
   constexpr int MT = Cfg<P>::MT;
   const int ksteps = K / (P ? 16 : 8);
   const int nbytes = N * K * (P ? 2 : 4);       // the layer's packed fragment array
-  if (N == 512) layer_run<P, MT, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-  else if (N == 256) layer_run<P, MT, 2, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-  else layer_run<P, MT, 1, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-  return 4;
+  if constexpr (Cfg<P>::NW == 8) {
+    if (N == 512) layer_run<P, MT, 2, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else if (N == 256) layer_run<P, MT, 1, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else {
+      layer_run<P, MT / 2, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+      return 4;
+    }
+    return 8;
+  } else {
+    if (N == 512) layer_run<P, MT, 4, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else if (N == 256) layer_run<P, MT, 2, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else layer_run<P, MT, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    return 4;
+  }
 }
 
 __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_lat, int l) {
@@ -873,8 +885,9 @@ __device__ __forceinline__ float sdf_from_m(float4 p, float m) {
 
 // Append `value` for every thread with flag set; one atomic per workgroup.
 // Called by all threads of the workgroup.
+template <int NT>
 __device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* counter) {
-  __shared__ int wcnt[kThreads / 64];
+  __shared__ int wcnt[NT / 64];
   __shared__ int base;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const unsigned long long bal = __ballot(flag);
@@ -883,7 +896,7 @@ __device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* 
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
-    for (int i = 0; i < kThreads / 64; ++i) tot += wcnt[i];
+    for (int i = 0; i < NT / 64; ++i) tot += wcnt[i];
     base = tot ? atomicAdd(counter, tot) : 0;
   }
   __syncthreads();
@@ -896,7 +909,7 @@ __device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* 
 // March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WG, Cfg<P>::WG))) void k_march(MarchArgs a) {
+__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WPE, Cfg<P>::WPE))) void k_march(MarchArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -966,7 +979,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Cfg<P>
       still = st == ST_ACTIVE;
     }
     // compaction fused into the step: survivors form the next active list
-    if (a.next_list) wg_append(still, still ? s.rid[tid] : 0, a.next_list, a.next_count);
+    if (a.next_list) wg_append<Cfg<P>::NT>(still, still ? s.rid[tid] : 0, a.next_list, a.next_count);
     if (a.qcount && tid < M) {
       // queries of this step per image, one atomic per distinct image in a wave
       const int r = s.rid[tid];
@@ -989,7 +1002,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Cfg<P>
 // Plain decoder queries (explicit points, or the 6-point normal stencil)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WG, Cfg<P>::WG))) void k_eval(EvalArgs a) {
+__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WPE, Cfg<P>::WPE))) void k_eval(EvalArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x;
@@ -1081,7 +1094,7 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
 // and at the skip layer (Sskip); dL/dz = W0_z^T S0 + Wskip_z^T Sskip.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint(AdjArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
@@ -1116,7 +1129,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (theta) {
       // Delta of the last hidden layer: gm * w_last * [h > 0]
       const int ll = net.nl - 2, W = net.wpad[ll];
-      for (int i = tid; i < M * W; i += kThreads) {
+      for (int i = tid; i < M * W; i += Cfg<P>::NT) {
         const int m = i / W, n = i - m * W;
         const size_t o = (row0 + m) * rstride + (size_t)ll * net.kmax + n;
         a.dbuf[o] = a.hbuf[o] > 0.f ? s.gm[m] * net.wlast[n] : 0.f;
@@ -1135,7 +1148,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
 // hidden layer, and the forward's 1 - tanh(m)^2 gives the row factor.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_vjp_saved(AdjArgs a) {
+__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_vjp_saved(AdjArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
@@ -1155,7 +1168,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))
       s.gm[tid] = smp.w * 0.05f * a.sdtanh[si];
     }
     __syncthreads();
-    for (int i = tid; i < M * q4; i += kThreads) {
+    for (int i = tid; i < M * q4; i += Cfg<P>::NT) {
       const int m = i / q4, n = 4 * (i - m * q4);
       const unsigned word = a.smask[mask_at(mk, s.rid[m], ll, n >> 5)] >> (n & 31);
       const float4 w4 = ld4(net.wlast + n);
@@ -1229,7 +1242,7 @@ void launch_dw(const DwArgs& a, hipStream_t st) {
 // Host-side helpers
 // ---------------------------------------------------------------------------
 int mlp_tile_rows(int precision) { return rows_for(precision); }
-int mlp_wg_per_cu(int precision) { return precision == 1 ? Cfg<1>::WG : 1; }
+
 int adj_tile_rows(int precision) { return mlp_tile_rows(precision); }
 size_t mlp_smem_bytes(int precision, const NetDev& net) { return smem_bytes_for(precision, net.kmax); }
 size_t adj_mask_words(int precision, const NetDev& net) {
@@ -1242,9 +1255,12 @@ static hipError_t setup_p(int bytes) {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_eval<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_vjp_saved<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess || P == kPrecBF16) return e;          // the backward has no bf16 kernels
+  e = hipFuncSetAttribute((const void*)k_vjp_saved<P == kPrecBF16 ? kPrecSplit : P>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_adjoint<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return hipFuncSetAttribute((const void*)k_adjoint<P == kPrecBF16 ? kPrecSplit : P>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t mlp_setup(int precision, const NetDev& net) {
@@ -1257,15 +1273,27 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
 #define DIST_DISPATCH(KERNEL, ARGS)                                                                    \
   do {                                                                                                 \
     const size_t sm = mlp_smem_bytes(precision, ARGS.net);                                             \
-    if (precision == 1) hipLaunchKernelGGL(KERNEL<1>, dim3(grid), dim3(kThreads), sm, st, ARGS);       \
-    else if (precision == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(grid), dim3(kThreads), sm, st, ARGS);  \
-    else hipLaunchKernelGGL(KERNEL<0>, dim3(grid), dim3(kThreads), sm, st, ARGS);                      \
+    const dim3 blk(threads_for(precision));                                                            \
+    if (precision == 1) hipLaunchKernelGGL(KERNEL<1>, dim3(grid), blk, sm, st, ARGS);                  \
+    else if (precision == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(grid), blk, sm, st, ARGS);             \
+    else hipLaunchKernelGGL(KERNEL<0>, dim3(grid), blk, sm, st, ARGS);                                 \
+  } while (0)
+
+// the backward kernels exist in split and float32 precision only
+#define DIST_DISPATCH_BWD(KERNEL, ARGS)                                                                \
+  do {                                                                                                 \
+    const size_t sm = mlp_smem_bytes(precision, ARGS.net);                                             \
+    const dim3 blk(threads_for(precision));                                                            \
+    if (precision == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(grid), blk, sm, st, ARGS);                  \
+    else if (precision == 0) hipLaunchKernelGGL(KERNEL<0>, dim3(grid), blk, sm, st, ARGS);             \
   } while (0)
 
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_march, a); }
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_eval, a); }
-void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_adjoint, a); }
-void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_vjp_saved, a); }
+void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH_BWD(k_adjoint, a); }
+void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t st) {
+  DIST_DISPATCH_BWD(k_vjp_saved, a);
+}
 
 // ---------------------------------------------------------------------------
 // Weight packing into MFMA A-operand fragments.

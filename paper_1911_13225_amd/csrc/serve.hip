@@ -238,7 +238,7 @@ static int capture_tick(Server* s, int par) {
   ma.list = s->lists[nxt];
   ma.count = s->counters + nxt;
   ma.qcount = s->qcount;          // queries counted where they are made
-  launch_march(kPrecBF16, ma, ctx->n_cu * mlp_wg_per_cu(kPrecBF16), s->st);
+  launch_march(kPrecBF16, ma, ctx->n_cu, s->st);
   hipGraph_t g = nullptr;
   HIPCHK_S(hipStreamEndCapture(s->st, &g));
   HIPCHK_S(hipGraphInstantiate(&s->exec[par], g, nullptr, nullptr, 0));
