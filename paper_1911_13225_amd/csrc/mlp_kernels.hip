@@ -25,28 +25,33 @@ typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// M rows per tile, MT = M / 32 row tiles, NW waves per workgroup (one
-// workgroup per CU), WPE waves per SIMD.  Each wave streams the weight
-// fragments of its own output columns from L2 through the vector memory path,
-// which is the first unit to saturate: bf16 therefore takes 128-row tiles and
-// 8 waves (two per SIMD, 256 registers each), every wave covering all 128 rows
-// for 1/8 of the outputs, so one weight fragment feeds 4 MFMAs and the second
-// wave of a SIMD issues while the first waits.  The 4-byte formats keep 64-row
-// tiles (128 KB of LDS) and one wave per SIMD with the full 512 registers
-// (accumulators in AGPRs).
+// M rows per tile (MT = M / 32 row tiles), one workgroup per CU.  Each wave
+// streams the weight fragments of its own output columns from L2 through the
+// vector memory path, the first unit to saturate, so bf16 takes 128-row tiles
+// (one weight fragment feeds 4 MFMAs).  The 4-byte formats need 128 KB of LDS
+// for 64 rows.
 template <int P> struct Cfg;
 template <> struct Cfg<1> {           // bf16 x bf16 -> f32, v_mfma_f32_32x32x16_bf16
-  static constexpr int M = 128, MT = 4, ES = 2, EPC = 8, NW = 8, WPE = 2, NT = NW * 64;
+  static constexpr int M = 128, MT = 4, ES = 2, EPC = 8;
 };
 template <> struct Cfg<0> {           // f32 x f32 -> f32, v_mfma_f32_32x32x2_f32
-  static constexpr int M = 64, MT = 2, ES = 4, EPC = 4, NW = 4, WPE = 1, NT = NW * 64;
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 4;
 };
 template <> struct Cfg<2> {           // split bf16: x = hi + lo; hi*hi + lo*hi + hi*lo, f32 accumulation
-  static constexpr int M = 64, MT = 2, ES = 4, EPC = 8, NW = 4, WPE = 1, NT = NW * 64;   // a row holds interleaved hi/lo 16-byte chunks
+  static constexpr int M = 64, MT = 2, ES = 4, EPC = 8;   // a row holds interleaved hi/lo 16-byte chunks
 };
 
+// Waves per workgroup.  The forward kernels of the bf16 formats run 8 waves
+// (two per SIMD, at most 256 registers each): every wave covers all rows for
+// 1/8 of the outputs and the second wave of a SIMD issues while the first
+// waits on memory, a barrier or its epilogue.  The float32 forward and the
+// backward kernels (whose adjoint state needs more registers) run 4 waves,
+// one per SIMD with 512 registers (accumulators in AGPRs).
+template <int P> constexpr int kFwdWaves = P == 0 ? 4 : 8;
+constexpr int kBwdWaves = 4;
+
 __host__ __device__ inline int rows_for(int P) { return P == 1 ? Cfg<1>::M : 64; }
-__host__ __device__ inline int threads_for(int P) { return P == 1 ? Cfg<1>::NT : Cfg<0>::NT; }
+__host__ __device__ inline int fwd_threads(int P) { return (P == 0 ? 4 : 8) * 64; }
 __host__ __device__ inline size_t smem_bytes_for(int P, int kmax) {
   const int M = rows_for(P);
   const int ES = P == 1 ? 2 : 4;
@@ -96,15 +101,15 @@ __device__ __forceinline__ int opaque(int x) {
 __device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
 
 // Each thread owns one chunk of EPC output features (its W0_p columns stay in
-// registers) and walks the rows of the tile; N0 / EPC divides the thread count.
-template <int P, bool CAP>
+// registers) and walks the rows of the tile; N0 / EPC divides NT.
+template <int P, int NT, bool CAP>
 __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_,
                                             float* hcap, int rstride) {
   const int tid = opaque(tid_);
   constexpr int M = Cfg<P>::M, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
   const int cpr = N0 / EPC;
-  const int rpp = Cfg<P>::NT / cpr;
+  const int rpp = NT / cpr;
   const int ch = tid % cpr;
   const int n = ch * EPC;
   float wx[EPC], wy[EPC], wz[EPC];
@@ -812,13 +817,14 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
 // One layer of output width N and contracted width K; returns the number of
 // wave groups that wrote output-layer partial sums.
 // SKIP: the layer reads [h, z, p] (its bias is per latent plus W_p p).
-template <int P, int MODE, bool CAP, bool SKIP = false>
+template <int P, int NW, int MODE, bool CAP, bool SKIP = false>
 __device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                      const void* wlo, int N, int K) {
   constexpr int MT = Cfg<P>::MT;
   const int ksteps = K / (P ? 16 : 8);
   const int nbytes = N * K * (P ? 2 : 4);       // the layer's packed fragment array
-  if constexpr (Cfg<P>::NW == 8) {
+  static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+  if constexpr (NW == 8) {
     if (N == 512) layer_run<P, MT, 2, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
     else if (N == 256) layer_run<P, MT, 1, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
     else {
@@ -852,11 +858,11 @@ __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_l
 // s.part and returns the number of partial groups.  ADJ records the ReLU masks
 // and the output-layer seed for the adjoint; CAP keeps float32 copies of every
 // hidden activation in hcap for the weight gradient.
-template <int P, bool ADJ, bool CAP>
+template <int P, int NW, bool ADJ, bool CAP>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
                                            const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr) {
   const int rstride = (net.nl - 1) * net.kmax;
-  layer0_fill<P, CAP>(net, bias0_lat, s, tid, hcap, rstride);
+  layer0_fill<P, NW * 64, CAP>(net, bias0_lat, s, tid, hcap, rstride);
   __syncthreads();
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
@@ -868,12 +874,12 @@ __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0
     }
     // the skip layer is never the last hidden layer (skip <= nl - 3)
     if (l == net.nl - 2)
-      wn = layer<P, ADJ ? EP_LAST_ADJ : EP_LAST, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
+      wn = layer<P, NW, ADJ ? EP_LAST_ADJ : EP_LAST, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
     else if (l == net.skip)
-      wn = layer<P, ADJ ? EP_ACT_MASK : EP_ACT, CAP, true>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l],
+      wn = layer<P, NW, ADJ ? EP_ACT_MASK : EP_ACT, CAP, true>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l],
                                                            net.kpad[l]);
     else
-      wn = layer<P, ADJ ? EP_ACT_MASK : EP_ACT, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
+      wn = layer<P, NW, ADJ ? EP_ACT_MASK : EP_ACT, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
   }
   return wn;
 }
@@ -909,7 +915,7 @@ __device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* 
 // March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WPE, Cfg<P>::WPE))) void k_march(MarchArgs a) {
+__global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_eu(kFwdWaves<P> / 4, kFwdWaves<P> / 4))) void k_march(MarchArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x, lane = tid & 63;
@@ -931,7 +937,7 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<
       s.rid[tid] = r;
     }
     __syncthreads();
-    const int wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+    const int wn = mlp_forward<P, kFwdWaves<P>, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     bool still = false;
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
@@ -979,7 +985,7 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<
       still = st == ST_ACTIVE;
     }
     // compaction fused into the step: survivors form the next active list
-    if (a.next_list) wg_append<Cfg<P>::NT>(still, still ? s.rid[tid] : 0, a.next_list, a.next_count);
+    if (a.next_list) wg_append<kFwdWaves<P> * 64>(still, still ? s.rid[tid] : 0, a.next_list, a.next_count);
     if (a.qcount && tid < M) {
       // queries of this step per image, one atomic per distinct image in a wave
       const int r = s.rid[tid];
@@ -1002,7 +1008,7 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<
 // Plain decoder queries (explicit points, or the 6-point normal stencil)
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<P>::WPE, Cfg<P>::WPE))) void k_eval(EvalArgs a) {
+__global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_eu(kFwdWaves<P> / 4, kFwdWaves<P> / 4))) void k_eval(EvalArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x;
@@ -1042,10 +1048,10 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<
     __syncthreads();
     int wn;
     if constexpr (P != kPrecBF16)
-      wn = keep ? mlp_forward<P, true, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, mk)
-                : mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+      wn = keep ? mlp_forward<P, kFwdWaves<P>, true, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, mk)
+                : mlp_forward<P, kFwdWaves<P>, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     else
-      wn = mlp_forward<P, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+      wn = mlp_forward<P, kFwdWaves<P>, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -1083,7 +1089,7 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
       ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
       ec.rstride = rstride;
     }
-    layer<P, EP_VJP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
+    layer<P, kBwdWaves, EP_VJP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
   }
 }
 
@@ -1094,7 +1100,7 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
 // and at the skip layer (Sskip); dL/dz = W0_z^T S0 + Wskip_z^T Sskip.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint(AdjArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
@@ -1116,8 +1122,8 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1
       s.lat[tid] = a.sample_lat[idx];
     }
     __syncthreads();
-    const int wn = theta ? mlp_forward<P, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
-                         : mlp_forward<P, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
+    const int wn = theta ? mlp_forward<P, kBwdWaves, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
+                         : mlp_forward<P, kBwdWaves, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
     if (tid < M) {
       float m = net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -1129,7 +1135,7 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1
     if (theta) {
       // Delta of the last hidden layer: gm * w_last * [h > 0]
       const int ll = net.nl - 2, W = net.wpad[ll];
-      for (int i = tid; i < M * W; i += Cfg<P>::NT) {
+      for (int i = tid; i < M * W; i += kBwdWaves * 64) {
         const int m = i / W, n = i - m * W;
         const size_t o = (row0 + m) * rstride + (size_t)ll * net.kmax + n;
         a.dbuf[o] = a.hbuf[o] > 0.f ? s.gm[m] * net.wlast[n] : 0.f;
@@ -1148,7 +1154,7 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1
 // hidden layer, and the forward's 1 - tanh(m)^2 gives the row factor.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_vjp_saved(AdjArgs a) {
+__global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_vjp_saved(AdjArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
@@ -1168,7 +1174,7 @@ __global__ __launch_bounds__(Cfg<P>::NT) __attribute__((amdgpu_waves_per_eu(1, 1
       s.gm[tid] = smp.w * 0.05f * a.sdtanh[si];
     }
     __syncthreads();
-    for (int i = tid; i < M * q4; i += Cfg<P>::NT) {
+    for (int i = tid; i < M * q4; i += kBwdWaves * 64) {
       const int m = i / q4, n = 4 * (i - m * q4);
       const unsigned word = a.smask[mask_at(mk, s.rid[m], ll, n >> 5)] >> (n & 31);
       const float4 w4 = ld4(net.wlast + n);
@@ -1273,7 +1279,7 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
 #define DIST_DISPATCH(KERNEL, ARGS)                                                                    \
   do {                                                                                                 \
     const size_t sm = mlp_smem_bytes(precision, ARGS.net);                                             \
-    const dim3 blk(threads_for(precision));                                                            \
+    const dim3 blk(fwd_threads(precision));                                                            \
     if (precision == 1) hipLaunchKernelGGL(KERNEL<1>, dim3(grid), blk, sm, st, ARGS);                  \
     else if (precision == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(grid), blk, sm, st, ARGS);             \
     else hipLaunchKernelGGL(KERNEL<0>, dim3(grid), blk, sm, st, ARGS);                                 \
@@ -1283,7 +1289,7 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
 #define DIST_DISPATCH_BWD(KERNEL, ARGS)                                                                \
   do {                                                                                                 \
     const size_t sm = mlp_smem_bytes(precision, ARGS.net);                                             \
-    const dim3 blk(threads_for(precision));                                                            \
+    const dim3 blk(kBwdWaves * 64);                                                                    \
     if (precision == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(grid), blk, sm, st, ARGS);                  \
     else if (precision == 0) hipLaunchKernelGGL(KERNEL<0>, dim3(grid), blk, sm, st, ARGS);             \
   } while (0)
