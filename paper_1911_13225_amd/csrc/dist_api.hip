@@ -660,7 +660,8 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
     ma.next_count = split ? nullptr : ncnt;
     {
       TimedLaunch tl(ctx, 0, st, ma.count, 1);
-      launch_march(prec, ma, mlp_grid(ctx, rays, prec), st);
+      // the bf16 march may choose 64-row tiles, so size its grid by those
+      launch_march(prec, ma, mlp_grid(ctx, rays, prec == kPrecBF16 ? kPrecSplit : prec), st);
     }
     if (split)
       launch_split(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * (lv - 1)), lv - 1, n + 1, nxt, ncnt, st);

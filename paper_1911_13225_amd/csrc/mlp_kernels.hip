@@ -102,11 +102,11 @@ __device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p
 
 // Each thread owns one chunk of EPC output features (its W0_p columns stay in
 // registers) and walks the rows of the tile; N0 / EPC divides NT.
-template <int P, int NT, bool CAP>
+template <int P, int NT, int MR, bool CAP>
 __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_,
                                             float* hcap, int rstride) {
   const int tid = opaque(tid_);
-  constexpr int M = Cfg<P>::M, EPC = Cfg<P>::EPC;
+  constexpr int M = MR, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
   const int cpr = N0 / EPC;
   const int rpp = NT / cpr;
@@ -585,10 +585,10 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
 // Last hidden layer: m-partial = sum_n w_last[n] relu(x[n]) per row (reduced
 // across the waves in a fixed order by the caller); with ADJ the seed
 // d m / d(pre-activation) = w_last [x > 0] is written to LDS.
-template <int P, int MTW, int NTW, bool ADJ, bool CAP>
+template <int P, int MR, int MTW, int NTW, bool ADJ, bool CAP>
 __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
                                         int nt0, int mt0, int nw, int lane) {
-  constexpr int M = Cfg<P>::M;
+  constexpr int M = MR;
   const int r = lane & 31, g = lane >> 5;
   float sum[MTW];
   unsigned bits[MTW][NTW];
@@ -781,7 +781,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
 // Run one layer (accumulator init + GEMM + barrier + epilogue + barrier) for an
 // output width N (128, 256 or 512 after padding): WN waves split N into groups
 // of NTW 32-wide tiles; the NW / WN wave groups split the rows into MTW tiles.
-template <int P, int MTW, int NTW, int WN, int MODE, bool CAP, bool SKIP>
+template <int P, int MR, int MTW, int NTW, int WN, int MODE, bool CAP, bool SKIP>
 __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                           const void* wlo, int ksteps, int nbytes) {
   // lane-dependent addressing is recomputed per layer (see opaque()); the wave
@@ -805,8 +805,8 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   __syncthreads();
   if constexpr (MODE == EP_ACT) ep_act<P, MTW, NTW, false, CAP>(ec, acc, s, nt0, mt0, lane);
   if constexpr (MODE == EP_ACT_MASK) ep_act<P, MTW, NTW, true, CAP>(ec, acc, s, nt0, mt0, lane);
-  if constexpr (MODE == EP_LAST) ep_last<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
-  if constexpr (MODE == EP_LAST_ADJ) ep_last<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
+  if constexpr (MODE == EP_LAST) ep_last<P, MR, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
+  if constexpr (MODE == EP_LAST_ADJ) ep_last<P, MR, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
   if constexpr (MODE == EP_VJP) {
     if (ec.layer == 0) ep_vjp<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, mg, nw, lane);
     else ep_vjp<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, mg, nw, lane);
@@ -817,25 +817,25 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
 // One layer of output width N and contracted width K; returns the number of
 // wave groups that wrote output-layer partial sums.
 // SKIP: the layer reads [h, z, p] (its bias is per latent plus W_p p).
-template <int P, int NW, int MODE, bool CAP, bool SKIP = false>
+template <int P, int NW, int MR, int MODE, bool CAP, bool SKIP = false>
 __device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                      const void* wlo, int N, int K) {
-  constexpr int MT = Cfg<P>::MT;
+  constexpr int MT = MR / 32;
   const int ksteps = K / (P ? 16 : 8);
   const int nbytes = N * K * (P ? 2 : 4);       // the layer's packed fragment array
   static_assert(NW == 4 || NW == 8, "4 or 8 waves");
   if constexpr (NW == 8) {
-    if (N == 512) layer_run<P, MT, 2, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-    else if (N == 256) layer_run<P, MT, 1, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    if (N == 512) layer_run<P, MR, MT, 2, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else if (N == 256) layer_run<P, MR, MT, 1, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
     else {
-      layer_run<P, MT / 2, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+      layer_run<P, MR, MT / 2, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
       return 4;
     }
     return 8;
   } else {
-    if (N == 512) layer_run<P, MT, 4, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-    else if (N == 256) layer_run<P, MT, 2, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-    else layer_run<P, MT, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    if (N == 512) layer_run<P, MR, MT, 4, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else if (N == 256) layer_run<P, MR, MT, 2, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else layer_run<P, MR, MT, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
     return 4;
   }
 }
@@ -858,11 +858,11 @@ __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_l
 // s.part and returns the number of partial groups.  ADJ records the ReLU masks
 // and the output-layer seed for the adjoint; CAP keeps float32 copies of every
 // hidden activation in hcap for the weight gradient.
-template <int P, int NW, bool ADJ, bool CAP>
+template <int P, int NW, int MR, bool ADJ, bool CAP>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
                                            const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr) {
   const int rstride = (net.nl - 1) * net.kmax;
-  layer0_fill<P, NW * 64, CAP>(net, bias0_lat, s, tid, hcap, rstride);
+  layer0_fill<P, NW * 64, MR, CAP>(net, bias0_lat, s, tid, hcap, rstride);
   __syncthreads();
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
@@ -874,12 +874,12 @@ __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0
     }
     // the skip layer is never the last hidden layer (skip <= nl - 3)
     if (l == net.nl - 2)
-      wn = layer<P, NW, ADJ ? EP_LAST_ADJ : EP_LAST, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
+      wn = layer<P, NW, MR, ADJ ? EP_LAST_ADJ : EP_LAST, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
     else if (l == net.skip)
-      wn = layer<P, NW, ADJ ? EP_ACT_MASK : EP_ACT, CAP, true>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l],
+      wn = layer<P, NW, MR, ADJ ? EP_ACT_MASK : EP_ACT, CAP, true>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l],
                                                            net.kpad[l]);
     else
-      wn = layer<P, NW, ADJ ? EP_ACT_MASK : EP_ACT, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
+      wn = layer<P, NW, MR, ADJ ? EP_ACT_MASK : EP_ACT, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
   }
   return wn;
 }
@@ -914,12 +914,9 @@ __device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* 
 // ---------------------------------------------------------------------------
 // March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_eu(kFwdWaves<P> / 4, kFwdWaves<P> / 4))) void k_march(MarchArgs a) {
-  constexpr int M = Cfg<P>::M;
-  Sm<P> s(dyn_smem, a.net.kmax);
+template <int P, int M>
+__device__ __forceinline__ void march_tiles(const MarchArgs& a, const Sm<P>& s, int count) {
   const int tid = threadIdx.x, lane = tid & 63;
-  const int count = *a.count;
   for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
     if (tid < M) {
       const int idx = tile * M + tid;
@@ -937,7 +934,7 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
       s.rid[tid] = r;
     }
     __syncthreads();
-    const int wn = mlp_forward<P, kFwdWaves<P>, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+    const int wn = mlp_forward<P, kFwdWaves<P>, M, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     bool still = false;
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
@@ -1004,6 +1001,24 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
   }
 }
 
+
+// The bf16 step takes 64-row tiles when they finish sooner.  A 64-row tile
+// streams the same weights for half the rows, so it is bound by the vector
+// memory path and costs about 0.77x a 128-row tile: it wins only when every
+// workgroup has at most one tile (the converging tail of the march).
+template <int P>
+__global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_eu(kFwdWaves<P> / 4, kFwdWaves<P> / 4))) void k_march(MarchArgs a) {
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const int count = *a.count;
+  if constexpr (P == kPrecBF16) {
+    const int g = gridDim.x;
+    const int r128 = (count + 128 * g - 1) / (128 * g), r64 = (count + 64 * g - 1) / (64 * g);
+    if (r64 * 77 < r128 * 100) march_tiles<P, 64>(a, s, count);
+    else march_tiles<P, 128>(a, s, count);
+  } else {
+    march_tiles<P, Cfg<P>::M>(a, s, count);
+  }
+}
 // ---------------------------------------------------------------------------
 // Plain decoder queries (explicit points, or the 6-point normal stencil)
 // ---------------------------------------------------------------------------
@@ -1048,10 +1063,10 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
     __syncthreads();
     int wn;
     if constexpr (P != kPrecBF16)
-      wn = keep ? mlp_forward<P, kFwdWaves<P>, true, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, mk)
-                : mlp_forward<P, kFwdWaves<P>, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+      wn = keep ? mlp_forward<P, kFwdWaves<P>, Cfg<P>::M, true, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, mk)
+                : mlp_forward<P, kFwdWaves<P>, Cfg<P>::M, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     else
-      wn = mlp_forward<P, kFwdWaves<P>, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+      wn = mlp_forward<P, kFwdWaves<P>, Cfg<P>::M, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
     if (tid < M && s.rid[tid] >= 0) {
       float m = a.net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -1089,7 +1104,7 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
       ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
       ec.rstride = rstride;
     }
-    layer<P, kBwdWaves, EP_VJP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
+    layer<P, kBwdWaves, Cfg<P>::M, EP_VJP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
   }
 }
 
@@ -1122,8 +1137,8 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
       s.lat[tid] = a.sample_lat[idx];
     }
     __syncthreads();
-    const int wn = theta ? mlp_forward<P, kBwdWaves, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
-                         : mlp_forward<P, kBwdWaves, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
+    const int wn = theta ? mlp_forward<P, kBwdWaves, Cfg<P>::M, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
+                         : mlp_forward<P, kBwdWaves, Cfg<P>::M, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
     if (tid < M) {
       float m = net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
