@@ -668,6 +668,110 @@ def implicit_backward(dec: Decoder, Z, renders: Sequence[Render], pairs, prm, gr
     return gz
 
 
+def unrolled_backward(dec: Decoder, Z, cams: Sequence, pairs, prm, grads):
+    """dL/dz of the depth and silhouette terms differentiated exactly through
+    the unrolled march: Eq. 2 with both of its terms (Sec. 3.4).
+
+    Eq. 2 splits the derivative of a query f(p^(i)(z), z) into the part at the
+    detached point, df/dz, and the part through the point, grad_p f . dp/dz
+    with dp^(i)/dz = v dt^(i)/dz.  The ray parameter accumulates the steps,
+    t^(i+1) = t^(i) + alpha f^(i) (Sec. 3.2), so dt/dz is carried along the
+    march in forward mode:
+        df^(i)/dz   = df/dz(p^(i)) + (grad_p f(p^(i)) . v) dt^(i)/dz
+        dt^(i+1)/dz = dt^(i)/dz + alpha df^(i)/dz.
+
+    Reading U1: the result is the exact derivative of the rendered outputs
+    along the forward's discrete trajectory (its step counts, statuses, record
+    steps and coarse-to-fine decisions held fixed): the depth through Eq. 1
+    with its residual term, d = t^(N-1) + f^(N-1), and the silhouette through
+    the minimum-|f| query, S = |f^(k)| - eps, dS/dz = sign f^(k) df^(k)/dz.  A
+    child ray of the coarse-to-fine split starts from its parent's t and
+    inherits dt/dz unless the clamp into its own interval binds or the parent
+    missed the sphere (then 0).  Rays that miss the unit sphere add nothing.
+
+    ``grads[i] = (g_depth, g_sil)``.  Returns g_z [n_lat, L].
+    """
+    Z = np.asarray(Z, np.float64)
+    gz = np.zeros_like(Z)
+    for (vi, li), (g_d, g_s) in zip(pairs, grads):
+        cam = cam_from(cams[vi])
+        dd, ds, st, _ = unrolled_image(dec, Z[li], cam, prm)
+        gd = np.asarray(g_d, np.float64).reshape(-1)
+        gs = np.asarray(g_s, np.float64).reshape(-1)
+        xt, yt, _ = level_rays(cam, 0, *np.divmod(np.arange(cam.H * cam.W), cam.W)[::-1])
+        nrm = np.sqrt(xt * xt + yt * yt + 1.0)
+        hit = st == HIT
+        gz[li] += ((gd * hit / nrm)[:, None] * np.nan_to_num(dd)).sum(0)
+        gz[li] += (gs[:, None] * np.nan_to_num(ds)).sum(0)
+    return gz
+
+
+def unrolled_image(dec: Decoder, z, cam: Cam, prm):
+    """The march of ``render_image`` carrying dt/dz per ray (see
+    ``unrolled_backward``).  Returns, per full-resolution pixel, dd/dz [n, L]
+    (hits; NaN elsewhere), dS/dz [n, L] (rays inside the unit sphere; 0 for
+    misses), the status and the final t."""
+    z = np.asarray(z, np.float64)
+    L = z.size
+    H, W, Lv = cam.H, cam.W, int(prm.c2f_levels)
+    alpha, eps, max_steps = float(prm.alpha), float(prm.eps), int(prm.max_steps)
+    c = cam.c
+    parent = None
+    for seg in range(Lv + 1):
+        level = Lv - seg
+        Hl, Wl = H >> level, W >> level
+        V, U = np.divmod(np.arange(Hl * Wl), Wl)
+        _, _, D = level_rays(cam, level, U, V)
+        inside, t_lo, t_hi, _, _ = unit_sphere_init(c, D, prm.near, prm.far)
+        n = D.shape[0]
+        t = t_lo.copy()
+        J = np.zeros((n, L))
+        if parent is not None:
+            pt, pst, pJ, pWl = parent
+            pi = (V >> 1) * pWl + (U >> 1)
+            tp = np.where(pst[pi] == MISS, -np.inf, pt[pi])
+            t = np.minimum(np.maximum(tp, t_lo), t_hi)
+            free = (pst[pi] != MISS) & (tp > t_lo) & (tp < t_hi)
+            J = np.where(free[:, None], pJ[pi], 0.0)
+        status = np.where(inside, ACTIVE, MISS).astype(np.int8)
+        rec_absf = np.full(n, np.inf)
+        rec_f = np.zeros(n)
+        rec_df = np.zeros((n, L))
+        dd = np.full((n, L), np.nan)
+        n_begin = 3 * seg
+        n_end = 3 * (seg + 1) if level > 0 else max_steps
+        for step in range(n_begin, min(n_end, max_steps)):
+            idx = np.nonzero(status == ACTIVE)[0]
+            if idx.size == 0:
+                continue
+            P = c[None, :] + t[idx, None] * D[idx]
+            Zr = np.broadcast_to(z, (idx.size, L))
+            f = dec.sdf(Zr, P)
+            fz = dec.sdf_vjp(Zr, P, np.ones(idx.size), want_theta=False)[0]
+            fp = dec.sdf_grad_p(Zr, P, np.ones(idx.size))
+            df = fz + (fp * D[idx]).sum(1)[:, None] * J[idx]          # Eq. 2, both terms
+            af = np.abs(f)
+            better = af < rec_absf[idx]                               # ties keep the earlier step
+            b = idx[better]
+            rec_absf[b], rec_f[b], rec_df[b] = af[better], f[better], df[better]
+            hit = af < eps
+            status[idx[hit]] = HIT
+            dd[idx[hit]] = J[idx[hit]] + df[hit]                      # d = t + f (Eq. 1)
+            rest, fr, dfr = idx[~hit], f[~hit], df[~hit]
+            if step == max_steps - 1:
+                status[rest] = UNCONVERGED
+                continue
+            t[rest] = t[rest] + alpha * fr
+            J[rest] = J[rest] + alpha * dfr
+            esc = (t[rest] > t_hi[rest]) | (t[rest] < t_lo[rest])
+            status[rest[esc]] = ESCAPED
+        if level > 0:
+            parent = (t, status, J, Wl)
+    sgn = np.sign(rec_f)
+    ds = np.where((status != MISS)[:, None] & np.isfinite(rec_absf)[:, None], sgn[:, None] * rec_df, 0.0)
+    return dd, ds, status, t
+
+
 def camera_samples(r: Render, prm, g_depth, g_sil):
     """The depth and silhouette samples of ``gradient_samples`` with, for each,
     its ray parameter t and the pixel's camera-frame unit direction u (so that

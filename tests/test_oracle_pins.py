@@ -616,3 +616,79 @@ def test_view_facing_away_is_background():
     g_c, g_R = O.camera_backward(dec, Z, [r], [away], [(0, 0)], prm, [(np.zeros((8, 8)), gs)])
     np.testing.assert_allclose(g_c[0], 64 * 0.5 * c / np.linalg.norm(c), rtol=1e-12)
     assert np.all(g_R == 0)
+
+
+# ----------------------------------------------------------------------------
+# exact gradient through the unrolled march (Eq. 2 with both terms)
+# ----------------------------------------------------------------------------
+def _render_loss(r, g_d, g_s):
+    hit = r.status == O.HIT
+    return float(np.sum(np.where(hit, g_d * np.where(hit, r.depth, 0.0), 0.0))
+                 + np.sum(np.where(r.status != O.MISS, g_s * np.where(r.status != O.MISS, r.sil, 0.0), 0.0)))
+
+
+@pytest.mark.parametrize("spec,c2f", [(di.C1_SPEC, 0), (di.C1_SPEC, 1), (di.DEEPSDF_SPEC, 1)],
+                         ids=["c1", "c1-c2f", "deepsdf-c2f"])
+def test_unrolled_gradient_against_render_differences(spec, c2f):
+    """The unrolled derivative (Eq. 2, both terms, carried through every step
+    and the coarse-to-fine splits) equals central differences of the oracle's
+    own render along a random direction in z, on the pixels whose discrete
+    trajectory (status, step count, minimum-|f| step) is the same at z +- h u
+    and whose decisions are not within 1e-5 of a threshold.  The difference
+    shrinks in proportion to h (a ReLU unit of some query changing side within
+    the step), so h is small: 1e-8, where rounding of the loss adds ~5e-8."""
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    z = di.make_latents(1, spec.latent_dim, sigma=0.05).astype(np.float64)
+    H = 16
+    cam = di.look_at_camera((0.4, -0.3, 1.9), H, H, fov_deg=45.0)
+    prm = _prm(alpha=1.5, eps=1e-3, max_steps=30, c2f_levels=c2f, want_normals=0, k_samples=1)
+    rng = np.random.Generator(np.random.PCG64(11))
+    u = rng.standard_normal(spec.latent_dim)
+    u /= np.linalg.norm(u)
+    h = 1e-8
+    r0, rp, rm = (O.render(dec, zz, [cam], [(0, 0)], prm)[0] for zz in (z, z + h * u, z - h * u))
+    same = ((r0.status == rp.status) & (r0.status == rm.status) & (r0.nsteps == rp.nsteps)
+            & (r0.nsteps == rm.nsteps) & (r0.margin > 1e-5))
+    same &= (r0.rec_n[0] == rp.rec_n[0]).reshape(H, H) & (r0.rec_n[0] == rm.rec_n[0]).reshape(H, H)
+    g_d = rng.standard_normal((H, H)) * same
+    g_s = rng.standard_normal((H, H)) * same
+    fd = (_render_loss(rp, g_d, g_s) - _render_loss(rm, g_d, g_s)) / (2 * h)
+    gz = O.unrolled_backward(dec, z, [cam], [(0, 0)], prm, [(g_d, g_s)])[0]
+    assert int(same.sum()) > H * H // 4 and int((r0.status == O.HIT)[same].sum()) > 10
+    assert abs(gz @ u - fd) <= 2e-6 * abs(fd) + 2e-7
+    # the paper's first-term gradient is a different number here
+    gp_ = O.backward(dec, z, [r0], [(0, 0)], prm, [(g_d, np.zeros((H, H, 3)), g_s)], want_theta=False)[0][0]
+    assert abs(gp_ @ u - fd) > 1e-3 * abs(fd)
+
+
+def test_unrolled_gradient_converges_to_the_implicit_one():
+    """Marched to a tight threshold, the unrolled derivative of a hit's depth
+    tends to the derivative of the exact root: on the linear-regime decoder
+    (surface |p| = R(z)) dt*/dz = -0.1 sech^2(m) u / (p_hat . v)."""
+    spec = di.C1_SPEC
+    dec = _linear_decoder(spec)
+    L = spec.latent_dim
+    z = di.make_latents(1, L, sigma=0.01).astype(np.float64)
+    P0 = np.zeros((L + 1, 3))
+    m_all, _, _ = dec.layer_inputs(np.vstack([np.zeros(L), np.eye(L)]), P0, keep=False)
+    a, uz = m_all[0], m_all[1:] - m_all[0]
+    mz = a + uz @ z[0]
+    Rz = 0.5 - 0.1 * math.tanh(mz)
+    H = 12
+    cam = di.front_camera(H, H)
+    prm = _prm(alpha=1.0, eps=1e-10, max_steps=200, c2f_levels=0, want_normals=0, k_samples=1)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    hit = r.status == O.HIT
+    assert int(hit.sum()) > 20
+    g_d = np.where(hit, 1.0, 0.0)
+    gz = O.unrolled_backward(dec, z, [cam], [(0, 0)], prm, [(g_d, np.zeros((H, H)))])[0]
+    h = hit.reshape(-1)
+    v = r.dirs[h]
+    c = cam.c.astype(np.float64)
+    b = v @ c
+    t_star = -b - np.sqrt(b * b - (c @ c - Rz * Rz))
+    ps = c[None, :] + t_star[:, None] * v
+    nrm = np.sqrt(r.xt[h] ** 2 + r.yt[h] ** 2 + 1)
+    true = -0.1 * (1 - math.tanh(mz) ** 2) * uz * np.sum(1.0 / nrm / np.sum(ps / Rz * v, axis=1))
+    assert np.linalg.norm(gz - true) <= 1e-6 * np.linalg.norm(true)
