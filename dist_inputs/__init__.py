@@ -198,6 +198,7 @@ class TraceParams:
     k_samples: int = 1
     precision: int = 0          # 0 = FP32 plain, 1 = BF16 MFMA
     want_normals: int = 1
+    keep_history: int = 0       # 1: the saved forward keeps t per step (unrolled backward)
 
 
 CONFIGS = {

@@ -96,10 +96,14 @@ typedef struct {
  *   k_samples    K (1..4): number of minimum-|f| queries per ray that carry
  *                the depth gradient (Sec. 3.4, App. B.4)
  *   precision    DIST_FP32, DIST_BF16 or DIST_BF16X3
- *   want_normals 1 to compute normals (6 float32 queries per hit) */
+ *   want_normals 1 to compute normals (6 float32 queries per hit)
+ *   keep_history 1 to keep, in the saved state of dist_render_fwd, the ray
+ *                parameter t of every ray at every marching step, which
+ *                dist_render_bwd_unrolled needs (4 bytes x max_steps per ray
+ *                slot of device memory); 0 otherwise.  dist_submit ignores it. */
 typedef struct {
   float alpha, eps, normal_delta, near_, far_;
-  int32_t max_steps, c2f_levels, k_samples, precision, want_normals;
+  int32_t max_steps, c2f_levels, k_samples, precision, want_normals, keep_history;
 } dist_trace_params;
 
 /* DeepSDF-style decoder (paper App. B.1): n_layers fully connected layers;
@@ -208,6 +212,30 @@ int dist_render_bwd_implicit(dist_ctx* ctx, const dist_saved* saved,
 int dist_render_bwd_camera(dist_ctx* ctx, const dist_saved* saved,
                            const float* g_depth, const float* g_sil,
                            float* g_cam, void* stream);
+
+/* Exact dL/dz of the depth and silhouette terms through the unrolled march:
+ * Eq. 2 of Sec. 3.4 with both of its terms.  Each query's derivative is its
+ * direct part df/dz at the point plus the part through the point,
+ * (grad_p f . v) dt/dz, where t accumulates the steps t += alpha f; the
+ * result is the derivative of the rendered outputs along the forward's
+ * discrete trajectory (its step counts, statuses, minimum-|f| steps and
+ * coarse-to-fine decisions held fixed): the depth through Eq. 1 with its
+ * residual term (d = t + f at the last query), the silhouette through the
+ * minimum-|f| query (dS/dz = sign f df/dz).  A child ray of the coarse-to-fine
+ * split passes its dt to its parent unless the clamp into its own unit-sphere
+ * interval bound.  Computed in reverse over the marching steps: at each step
+ * the decoder is re-evaluated at every ray's point of that step (the
+ * recompute of App. B.2) and back-propagated, costing about two decoder
+ * passes per march query.
+ *   saved    from dist_render_fwd with keep_history = 1 (DIST_EINVAL
+ *            otherwise)
+ *   g_depth, g_sil  device [n_images][H][W] (either may be NULL = zero)
+ *   g_z      device [n_latents, latent_dim]; overwritten
+ * Normal terms are not part of this gradient.  The reduction order is fixed,
+ * so results are bitwise reproducible. */
+int dist_render_bwd_unrolled(dist_ctx* ctx, const dist_saved* saved,
+                             const float* g_depth, const float* g_sil,
+                             float* g_z, void* stream);
 
 /* Free a forward state. */
 int dist_saved_free(dist_saved* saved);

@@ -36,7 +36,7 @@ class dist_trace_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("eps", ctypes.c_float), ("normal_delta", ctypes.c_float),
                 ("near_", ctypes.c_float), ("far_", ctypes.c_float), ("max_steps", ctypes.c_int32),
                 ("c2f_levels", ctypes.c_int32), ("k_samples", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("want_normals", ctypes.c_int32)]
+                ("want_normals", ctypes.c_int32), ("keep_history", ctypes.c_int32)]
 
 
 class dist_decoder_desc(ctypes.Structure):
@@ -76,6 +76,7 @@ _SIGS = [
     ("dist_render_bwd", ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
     ("dist_render_bwd_camera", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("dist_render_bwd_implicit", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("dist_render_bwd_unrolled", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("dist_saved_free", ctypes.c_int, [_P]),
     ("dist_sdf_eval", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P]),
     ("dist_sdf_vjp", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P,

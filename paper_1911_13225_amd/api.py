@@ -48,6 +48,7 @@ def make_params(p) -> N.dist_trace_params:
     q.near_, q.far_ = float(p.near), float(p.far)
     q.max_steps, q.c2f_levels, q.k_samples = int(p.max_steps), int(p.c2f_levels), int(p.k_samples)
     q.precision, q.want_normals = int(p.precision), int(p.want_normals)
+    q.keep_history = int(getattr(p, "keep_history", 0))
     return q
 
 
@@ -189,6 +190,16 @@ def dist_render_bwd_implicit(ctx: Context, saved: Saved, g_depth=None, g_normal=
     g_z = torch.empty(n_latents, ctx.latent_dim, device="cuda")
     args = [None if g is None else g.detach().float().contiguous() for g in (g_depth, g_normal, g_sil)]
     check(ctx.lib.dist_render_bwd_implicit(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_z), _stream()))
+    return g_z
+
+
+def dist_render_bwd_unrolled(ctx: Context, saved: Saved, g_depth=None, g_sil=None, n_latents=None):
+    """Exact dL/dz of the depth and silhouette terms through the unrolled march
+    (the forward must have run with keep_history = 1)."""
+    g_z = torch.empty(n_latents, ctx.latent_dim, device="cuda")
+    args = [None if g is None else g.detach().float().contiguous() for g in (g_depth, g_sil)]
+    check(ctx.lib.dist_render_bwd_unrolled(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_z),
+                                           _stream()))
     return g_z
 
 

@@ -60,6 +60,17 @@ struct CamSpace {
   float* gv = nullptr;             // per output pixel: grad f . v at the hit (implicit depth gradient)
 };
 
+// Buffers of the gradient through the unrolled march: the ray parameter of
+// every ray slot at every step (kept by the forward) and the per-slot adjoint
+// of t.
+struct UnrollSpace {
+  char* mem = nullptr;
+  size_t bytes = 0;
+  long long cap_hist = 0, cap_lam = 0;
+  float* t_hist = nullptr;         // [max_steps][pool capacity]
+  float* lam = nullptr;            // [pool capacity]
+};
+
 // Buffers of one forward render (ray pool, lists, counters, outputs staging).
 struct Workspace {
   char* mem = nullptr;
@@ -82,6 +93,7 @@ struct Workspace {
   int* img_view = nullptr;
   NrmSave* ns = nullptr;
   CamSpace* cs = nullptr;
+  UnrollSpace* us = nullptr;
   // pinned staging of the per-call descriptors
   dist::ImgDesc* h_imgs = nullptr;
   int* h_ints = nullptr;
@@ -136,6 +148,7 @@ struct dist_saved {
   dist_trace_params prm{};
   std::vector<int> img_latent, order;
   bool masks_kept = false;           // the stencil queries kept their ReLU masks
+  bool hist_kept = false;            // t of every ray at every step is in ws->us
 };
 
 int dist_set_error(int code, const char* fmt, ...);
@@ -150,7 +163,8 @@ int ctx_alloc(dist_ctx* ctx, void** p, size_t bytes);
 void ctx_free(dist_ctx* ctx, void* p, size_t bytes);
 int slots_per_image(int hw, int levels);
 int fold_biases(dist_ctx* ctx, Workspace* w, const float* z, int n_lat, hipStream_t st);
-int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, hipStream_t st);
+int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, hipStream_t st,
+              float* t_hist = nullptr);
 int run_finalize(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, float* depth,
                  float* dist, float* normal, float* sil, uint8_t* status, uint8_t* nsteps, hipStream_t st,
                  bool keep_masks = false);

@@ -472,6 +472,10 @@ static void ws_destroy(dist_ctx* ctx, Workspace* w) {
     ctx_free(ctx, w->cs->mem, w->cs->bytes);
     delete w->cs;
   }
+  if (w->us) {
+    ctx_free(ctx, w->us->mem, w->us->bytes);
+    delete w->us;
+  }
   delete w;
 }
 
@@ -536,6 +540,30 @@ static int ns_get(dist_ctx* ctx, Workspace* w, long long cap_samples, size_t wor
   return DIST_OK;
 }
 
+// Buffers of the gradient through the unrolled march: t of cap_lam ray slots
+// at each of steps steps, and one adjoint per slot.
+static int us_get(dist_ctx* ctx, Workspace* w, long long cap_lam, int steps) {
+  UnrollSpace* u = w->us;
+  const long long cap_hist = cap_lam * steps;
+  if (u && u->cap_hist >= cap_hist && u->cap_lam >= cap_lam) return DIST_OK;
+  if (u) {
+    ctx_free(ctx, u->mem, u->bytes);
+    delete u;
+    w->us = nullptr;
+  }
+  u = new UnrollSpace();
+  u->cap_hist = cap_hist;
+  u->cap_lam = cap_lam;
+  const size_t hb = ((size_t)cap_hist * 4 + 255) & ~(size_t)255;
+  u->bytes = hb + (size_t)cap_lam * 4 + 256;
+  int rc = ctx_alloc(ctx, (void**)&u->mem, u->bytes);
+  if (rc != DIST_OK) { delete u; return rc; }
+  u->t_hist = (float*)u->mem;
+  u->lam = (float*)(u->mem + hb);
+  w->us = u;
+  return DIST_OK;
+}
+
 // ---------------------------------------------------------------------------
 // forward render
 // ---------------------------------------------------------------------------
@@ -549,6 +577,7 @@ static int validate_params(const dist_trace_params* p, int H, int W) {
   if (p->k_samples < 1 || p->k_samples > kMaxK) return dist_set_error(DIST_EINVAL, "k_samples must be in [1, 4]");
   if (p->precision != DIST_FP32 && p->precision != DIST_BF16 && p->precision != DIST_BF16X3)
     return dist_set_error(DIST_EINVAL, "precision must be DIST_FP32, DIST_BF16 or DIST_BF16X3");
+  if (p->keep_history != 0 && p->keep_history != 1) return dist_set_error(DIST_EINVAL, "keep_history must be 0 or 1");
   const int m = 1 << p->c2f_levels;
   if (H < 1 || W < 1 || H % m || W % m || (long long)H * W > (1 << 22))
     return dist_set_error(DIST_EINVAL, "H and W must be positive multiples of 2^c2f_levels (at most 4M pixels)");
@@ -634,7 +663,8 @@ static int mlp_grid(dist_ctx* ctx, long long rows, int prec) {
 }
 
 // March all images of a workspace from their coarsest level to completion.
-int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, hipStream_t st) {
+int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_params* prm, hipStream_t st,
+              float* t_hist) {
   const int L = prm->c2f_levels, prec = prm->precision;
   launch_fill_i32(w->counters, 0, prm->max_steps + 8, st);
   launch_fill_u64(w->qcount, n_img, st);
@@ -651,6 +681,7 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
     const long long rays = (long long)n_img * (hw >> (2 * lv));
     ma.list = w->list[n & 1];
     ma.count = w->counters + n;
+    ma.t_hist = t_hist ? t_hist + (size_t)n * w->pool.cap : nullptr;
     // every image splits after the same steps: then the children replace the
     // rays, otherwise the march step appends its survivors to the next list
     const bool split = n % 3 == 2 && lv > 0;
@@ -769,7 +800,10 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
   const size_t mwords = (size_t)(ctx->nl - 1) * (ctx->net[np].kmax / 32);
   bool keep = saved && prm->want_normals && n_stencil <= INT_MAX && n_stencil * (long long)mwords <= (1LL << 40);
   if (!rc && keep && ns_get(ctx, w, n_stencil, mwords) != DIST_OK) keep = false;  // fall back to the recompute
-  if (!rc) rc = run_trace(ctx, w, n_img, hw, prm, st);
+  // a saved forward asked to keep its march history records t per step
+  const bool hist = saved && prm->keep_history;
+  if (!rc && hist) rc = us_get(ctx, w, w->pool.cap, prm->max_steps);
+  if (!rc) rc = run_trace(ctx, w, n_img, hw, prm, st, hist ? w->us->t_hist : nullptr);
   if (!rc) rc = run_finalize(ctx, w, n_img, hw, prm, depth, dist, normal, sil, status, nsteps, st, keep);
   if (!rc && queries) hipLaunchKernelGGL(k_u64_to_i64, dim3((n_img + 255) / 256), dim3(256), 0, st, w->qcount, queries, n_img);
   if (rc) {
@@ -789,6 +823,7 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
     s->img_latent = li;
     s->order = order;
     s->masks_kept = keep;
+    s->hist_kept = hist;
     *saved = s;
   } else {
     ws_put(ctx, w);
@@ -1121,6 +1156,63 @@ extern "C" int dist_render_bwd_camera(dist_ctx* ctx, const dist_saved* saved, co
   }
   launch_cam_reduce(w->pool, w->imgs, w->img_view, n_img, saved->n_views, b->samples, w->cs->sample_cam, w->cs->gp,
                     b->n_samples, g_sil, g_cam, st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+extern "C" int dist_render_bwd_unrolled(dist_ctx* ctx, const dist_saved* saved, const float* g_depth,
+                                        const float* g_sil, float* g_z, void* stream) {
+  if (!ctx || !saved || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (saved->ctx != ctx) return dist_set_error(DIST_EINVAL, "saved state belongs to another context");
+  if (!saved->hist_kept) return dist_set_error(DIST_EINVAL, "the forward did not keep its march history (keep_history)");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = saved->ws;
+  const int prec = adj_prec(saved->prm.precision);
+  const int tile = adj_tile_rows(prec);
+  const int n_img = saved->n_img, hw = saved->hw, n_lat = saved->n_lat;
+  const int Lv = saved->prm.c2f_levels, steps = saved->prm.max_steps;
+  // one sample per ray of the step's level at most, padded per latent
+  const long long cap = (long long)n_img * hw + (long long)n_lat * tile;
+  if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
+  const int bpi = (hw + 255) / 256;
+  const int grid = mlp_grid(ctx, cap, prec);
+  int rc = bw_get(ctx, w, (int)cap, n_img * bpi, n_lat, tile, adj_mask_words(prec, ctx->net[prec]) * grid);
+  if (!rc) rc = cs_get(ctx, w, cap);
+  if (rc) return rc;
+  BwdSpace* b = w->bw;
+  UnrollSpace* u = w->us;
+  const int spi = slots_per_image(hw, Lv);
+  hipLaunchKernelGGL(k_fill_f32, dim3(64), dim3(256), 0, st, g_z, (long long)n_lat * ctx->L);
+  launch_ul_init(w->pool, w->imgs, n_img, spi, g_depth, u->lam, st);
+  AdjArgs aa{};
+  aa.net = ctx->net[prec];
+  aa.bias0_lat = w->bias0_lat;
+  aa.biasS_lat = w->biasS_lat;
+  aa.samples = b->samples;
+  aa.sample_lat = b->sample_lat;
+  aa.n_samples = b->n_samples;
+  aa.mask_ws = b->mask_ws;
+  aa.partial = b->partial;
+  aa.gp_part = w->cs->gp;
+  const int w0 = ctx->wpad[0];
+  const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
+  for (int n = steps - 1; n >= 0; --n) {
+    const int lv = std::max(Lv - n / 3, 0);
+    // the rays of level lv + ... have all been processed: after the split
+    // that follows step n, the children's adjoints flow to their parents
+    if (n % 3 == 2 && lv > 0) launch_ul_split(w->pool, w->imgs, w->img_order, n_img, hw >> (2 * lv), lv, u->lam, st);
+    UlIn in{n, lv, g_depth, g_sil, u->t_hist + (size_t)n * w->pool.cap, u->lam};
+    launch_ul_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw >> (2 * lv), n_lat, tile, in, b->bsum,
+                      b->boff, b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, b->sample_lat,
+                      w->cs->sample_cam, st);
+    {
+      TimedLaunch tl(ctx, 2, st, b->n_samples, 1);
+      launch_adjoint(prec, aa, grid, st);
+    }
+    launch_gz_reduce(b->partial, ctx->kmax, tile, (int)(cap / tile) + 1, b->seg_base, b->seg_padded, n_lat, w0, 1,
+                     ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st, 0, 1);
+    launch_ul_lambda(w->pool, b->samples, w->cs->sample_cam, w->cs->gp, b->n_samples, (int)cap, u->lam, st);
+  }
   HIPCHK(hipGetLastError());
   return DIST_OK;
 }

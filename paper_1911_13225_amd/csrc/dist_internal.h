@@ -82,6 +82,7 @@ struct MarchArgs {
   // builds the next list itself, e.g. at a coarse-to-fine split)
   int* next_list;
   int* next_count;
+  float* t_hist;                   // per ray slot: t of this step (or null)
 };
 
 struct EvalArgs {

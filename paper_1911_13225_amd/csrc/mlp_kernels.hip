@@ -928,6 +928,7 @@ __device__ __forceinline__ void march_tiles(const MarchArgs& a, const Sm<P>& s, 
         const float4 d = a.pool.d[r];
         p = make_float4(fmaf(d.w, d.x, im.c[0]), fmaf(d.w, d.y, im.c[1]), fmaf(d.w, d.z, im.c[2]), 0.f);
         lt = im.latent;
+        if (a.t_hist) a.t_hist[r] = d.w;
       }
       s.pts[tid] = p;
       s.lat[tid] = lt;

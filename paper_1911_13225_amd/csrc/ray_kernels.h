@@ -40,6 +40,17 @@ struct SeedIn {
   const float* imp_gv;
 };
 
+// One step of the gradient through the unrolled march: the rays of level lvl
+// that took global step `step`, their t at that step (t_hist, indexed by ray
+// slot) and the current adjoints of t (lam, by ray slot).
+struct UlIn {
+  int step, lvl;
+  const float* g_depth;
+  const float* g_sil;
+  const float* t_hist;
+  const float* lam;
+};
+
 // Second sample list of the split layout (normal-stencil samples).
 struct SplitList {
   int* bsum;
@@ -72,6 +83,16 @@ void launch_cam_reduce(const RayPool& pl, const ImgDesc* imgs, const int* img_vi
                        const float* g_sil, float* g_cam, hipStream_t s);
 void launch_hit_gv(const RayPool& pl, const ImgDesc* imgs, const float4* samples, const int4* sample_cam,
                    const float* gp_part, const int* n_samples, int max_samples, float* gv, hipStream_t s);
+void launch_ul_init(const RayPool& pl, const ImgDesc* imgs, int n_img, int spi, const float* g_depth, float* lam,
+                    hipStream_t s);
+void launch_ul_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent,
+                       int n_img, int nr, int n_lat, int tile, const UlIn& in, int* bsum, int* boff, int* seg_base,
+                       int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat,
+                       int4* sample_cam, hipStream_t s);
+void launch_ul_lambda(const RayPool& pl, const float4* samples, const int4* sample_cam, const float* gp_part,
+                      const int* n_samples, int max_samples, float* lam, hipStream_t s);
+void launch_ul_split(const RayPool& pl, const ImgDesc* imgs, const int* img_order, int n_img, int max_parents,
+                     int plvl, float* lam, hipStream_t s);
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s);
 void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
                     int* out_count, const AdvEntry* table, const int* hdr, int* img_active,

@@ -730,6 +730,150 @@ __global__ void k_fill_u64(unsigned long long* p, int n) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Exact gradient through the unrolled march (Eq. 2 with both terms), in
+// reverse over the marching steps.  lam[r] is the adjoint of ray r's current
+// t: dL/dt after the step being processed.  A ray's query at step n gets the
+// seed
+//   a = alpha lam[r]            if the step moved t (t += alpha f)
+//     + dL/dd / |(xt, yt, 1)|   at a level-0 hit's last step (d = t + f)
+//     + dL/dS sign f            at a level-0 ray's minimum-|f| step,
+// the decoder's VJP at that point adds a df/dz to dL/dz, and lam[r] gains
+// a grad_p f . v (the same query's dependence on t through p = c + t v).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ul_seed(const RayPool& pl, const ImgDesc& im, int r, int pix, const UlIn& in) {
+  const uint8_t st = pl.st[r];
+  if (st == ST_MISS) return 0.f;
+  const int last = (int)pl.n[r] - 1;
+  if (in.step > last) return 0.f;
+  const bool term = in.step == last;
+  const bool moved = !(term && (st == ST_HIT || st == ST_UNCONVERGED));
+  float a = moved ? im.alpha * in.lam[r] : 0.f;
+  if (in.lvl == 0) {
+    const size_t q = (size_t)im.out_base + pix;
+    if (term && st == ST_HIT && in.g_depth) {
+      const int V = pix / im.W, U = pix - V * im.W;
+      float3 dd;
+      float xt, yt;
+      level_ray(im, 0, U, V, dd, xt, yt);
+      a += in.g_depth[q] / sqrtf(xt * xt + yt * yt + 1.f);
+    }
+    if (in.g_sil && (int)pl.rec_n[r] == in.step && pl.rec_f[r] != INFINITY) {
+      const float f0 = pl.rec_f[r];
+      a += in.g_sil[q] * (f0 > 0.f ? 1.f : (f0 < 0.f ? -1.f : 0.f));
+    }
+  }
+  return a;
+}
+
+// Per block of 256 rays of level in.lvl: the number of rays with a nonzero seed.
+__global__ __launch_bounds__(256) void k_ul_count(RayPool pl, const ImgDesc* imgs, const int* img_order, UlIn in,
+                                                  int* bsum) {
+  __shared__ int red[256];
+  const ImgDesc& im = imgs[img_order[blockIdx.y]];
+  const int nr = (im.H >> in.lvl) * (im.W >> in.lvl);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  int c = 0;
+  if (i < nr) c = ul_seed(pl, im, im.slot_base + im.lvl_off[in.lvl] + i, i, in) != 0.f ? 1 : 0;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// Writes one sample per counted ray: its point of step in.step and its seed;
+// sample_cam = (image, ray slot).
+__global__ __launch_bounds__(256) void k_ul_write(RayPool pl, const ImgDesc* imgs, const int* img_order, UlIn in,
+                                                  const int* boff, float4* samples, int* sample_lat,
+                                                  int4* sample_cam) {
+  __shared__ int buf[256];
+  const int img = img_order[blockIdx.y];
+  const ImgDesc& im = imgs[img];
+  const int nr = (im.H >> in.lvl) * (im.W >> in.lvl);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int r = im.slot_base + im.lvl_off[in.lvl] + i;
+  const float a = i < nr ? ul_seed(pl, im, r, i, in) : 0.f;
+  const int o = boff[blockIdx.y * gridDim.x + blockIdx.x] + block_excl_scan(a != 0.f ? 1 : 0, buf);
+  if (a == 0.f) return;
+  const float4 d = pl.d[r];
+  const float t = in.t_hist[r];
+  samples[o] = make_float4(fmaf(t, d.x, im.c[0]), fmaf(t, d.y, im.c[1]), fmaf(t, d.z, im.c[2]), a);
+  sample_lat[o] = im.latent;
+  sample_cam[o] = make_int4(img, r, 0, 0);
+}
+
+// lam[r] += a grad_p f . v for every sample of the step (grad_p f = the
+// residual term's p / (2 |p|) plus the adjoint's per-wave partials).
+__global__ void k_ul_lambda(RayPool pl, const float4* samples, const int4* sample_cam, const float* gp_part,
+                            const int* n_samples, float* lam) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *n_samples) return;
+  const int4 sc = sample_cam[i];
+  if (sc.x < 0) return;
+  const float4 smp = samples[i];
+  const float rn = sqrtf(smp.x * smp.x + smp.y * smp.y + smp.z * smp.z);
+  const float h = rn > 0.f ? 0.5f * smp.w / rn : 0.f;
+  float g[3] = {h * smp.x, h * smp.y, h * smp.z};
+  const float* pp = gp_part + (size_t)i * 12;
+  for (int w = 0; w < 4; ++w) {
+    g[0] += pp[3 * w];
+    g[1] += pp[3 * w + 1];
+    g[2] += pp[3 * w + 2];
+  }
+  const float4 d = pl.d[sc.y];
+  lam[sc.y] += g[0] * d.x + g[1] * d.y + g[2] * d.z;
+}
+
+// Coarse-to-fine split in reverse: every ray of level plvl collects the
+// adjoints of its four children (fixed order) whose start was its t, i.e. it
+// did not miss the sphere and the clamp into the child's interval (computed
+// exactly as the forward's split) did not bind.
+__global__ __launch_bounds__(256) void k_ul_split(RayPool pl, const ImgDesc* imgs, const int* img_order, int plvl,
+                                                  float* lam) {
+  const ImgDesc& im = imgs[img_order[blockIdx.y]];
+  const int Wp = im.W >> plvl, Hp = im.H >> plvl, Wc = im.W >> (plvl - 1);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= Wp * Hp) return;
+  const int pr = im.slot_base + im.lvl_off[plvl] + i;
+  if (pl.st[pr] == ST_MISS) return;
+  const float tp = pl.d[pr].w;
+  const int Vp = i / Wp, Up = i - Vp * Wp;
+  float acc = 0.f;
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const int U = 2 * Up + dx, V = 2 * Vp + dy;
+      float3 d;
+      float xt, yt, t_lo, t_hi;
+      level_ray(im, plvl - 1, U, V, d, xt, yt);
+      const bool inside = sphere_interval(im, d, t_lo, t_hi);
+      if (inside && tp > t_lo && tp < t_hi) acc += lam[im.slot_base + im.lvl_off[plvl - 1] + V * Wc + U];
+    }
+  lam[pr] += acc;
+}
+
+// Initial adjoints: dL/dd / |(xt, yt, 1)| for level-0 hits (d = t + f, so the
+// last t carries the depth gradient directly), 0 for every other ray slot.
+__global__ __launch_bounds__(256) void k_ul_init(RayPool pl, const ImgDesc* imgs, const float* g_depth, int spi,
+                                                 float* lam) {
+  const ImgDesc& im = imgs[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= spi) return;
+  const int r = im.slot_base + i;
+  float v = 0.f;
+  const int pix = i - im.lvl_off[0];
+  if (g_depth && pix >= 0 && pix < im.H * im.W && pl.st[r] == ST_HIT) {
+    const int V = pix / im.W, U = pix - V * im.W;
+    float3 dd;
+    float xt, yt;
+    level_ray(im, 0, U, V, dd, xt, yt);
+    v = g_depth[(size_t)im.out_base + pix] / sqrtf(xt * xt + yt * yt + 1.f);
+  }
+  lam[r] = v;
+}
+
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_rays, int* list,
@@ -850,6 +994,34 @@ void launch_adam(float* z, float* m, float* v, const float* g, int L, float lr, 
   hipLaunchKernelGGL(k_adam, dim3(nblk(L, 256)), dim3(256), 0, s, z, m, v, g, L, lr, 0.9f, 0.999f, 1e-8f, t);
 }
 
+void launch_ul_init(const RayPool& pl, const ImgDesc* imgs, int n_img, int spi, const float* g_depth, float* lam,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_ul_init, dim3(nblk(spi, 256), n_img), dim3(256), 0, s, pl, imgs, g_depth, spi, lam);
+}
+void launch_ul_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent,
+                       int n_img, int nr, int n_lat, int tile, const UlIn& in, int* bsum, int* boff, int* seg_base,
+                       int* seg_total, int* seg_padded, int* n_samples, float4* samples, int* sample_lat,
+                       int4* sample_cam, hipStream_t s) {
+  const int bpl = (int)nblk(nr, 256);
+  hipLaunchKernelGGL(k_ul_count, dim3(bpl, n_img), dim3(256), 0, s, pl, imgs, img_order, in, bsum);
+  hipLaunchKernelGGL(k_samples_scan, dim3(1), dim3(1024), 0, s, bsum, n_img, bpl, img_order, img_latent, 0, tile,
+                     n_lat, boff, seg_base, seg_total, seg_padded, nullptr, n_samples);
+  hipLaunchKernelGGL(k_ul_write, dim3(bpl, n_img), dim3(256), 0, s, pl, imgs, img_order, in, boff, samples,
+                     sample_lat, sample_cam);
+  hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
+                     sample_lat, nullptr, sample_cam);
+}
+void launch_ul_lambda(const RayPool& pl, const float4* samples, const int4* sample_cam, const float* gp_part,
+                      const int* n_samples, int max_samples, float* lam, hipStream_t s) {
+  if (max_samples <= 0) return;
+  hipLaunchKernelGGL(k_ul_lambda, dim3(nblk(max_samples, 256)), dim3(256), 0, s, pl, samples, sample_cam, gp_part,
+                     n_samples, lam);
+}
+void launch_ul_split(const RayPool& pl, const ImgDesc* imgs, const int* img_order, int n_img, int max_parents,
+                     int plvl, float* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_ul_split, dim3(nblk(max_parents, 256), n_img), dim3(256), 0, s, pl, imgs, img_order, plvl,
+                     lam);
+}
 void launch_fill_i32(int* p, int v, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);
 }

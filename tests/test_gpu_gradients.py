@@ -41,6 +41,19 @@ def ctx():
     return gpu_ctx(di.DEEPSDF_SPEC)
 
 
+@pytest.fixture(scope="module")
+def ctx_by_spec(ctx):
+    made = {}
+
+    def get(spec):
+        if spec is di.DEEPSDF_SPEC:
+            return ctx
+        if spec.latent_dim not in made:
+            made[spec.latent_dim] = gpu_ctx(spec)
+        return made[spec.latent_dim]
+    return get
+
+
 def test_adjoint_matches_central_differences(ctx):
     """Central differences of a ReLU network cross kinks (a step of 1e-3 on z
     moves ~1e-4 of pre-activation, so a few units per point change side),
@@ -235,3 +248,55 @@ def test_implicit_depth_gradient_matches_oracle(ctx, precision, tol):
     _log("implicit gradient precision", precision, "rel", rel, "| paper vs exact: rel", gap, "cos", cos)
     assert np.array_equal(g, g2)
     assert rel <= tol
+
+
+@pytest.mark.parametrize("spec,H,levels,precision,tol", [
+    (di.C1_SPEC, 24, 0, 0, 1e-3),
+    (di.C1_SPEC, 24, 1, 0, 1e-3),
+    (di.DEEPSDF_SPEC, 32, 2, 0, 1e-3),
+    (di.DEEPSDF_SPEC, 32, 2, 1, 1e-2),
+], ids=["c1-fp32", "c1-c2f1-fp32", "deepsdf-c2f2-fp32", "deepsdf-c2f2-bf16"])
+def test_unrolled_gradient_matches_oracle(ctx_by_spec, spec, H, levels, precision, tol):
+    """dL/dz of the depth and silhouette terms through the unrolled march (Eq. 2
+    with both terms) against the oracle's forward-mode unrolled_backward, on
+    the pixels whose discrete trajectory (status, step count) agrees with the
+    oracle's; the paper's first-term gradient is reported beside it."""
+    from paper_1911_13225_amd import api, _native as N
+    c = ctx_by_spec(spec)
+    prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=40, c2f_levels=levels, k_samples=1, precision=precision,
+                         want_normals=0, keep_history=1)
+    cams = di.random_sphere_cameras(2, H, H)
+    Z = di.make_latents(2, spec.latent_dim, sigma=0.05)
+    pairs = [(i // 2, i % 2) for i in range(4)]
+    dec = oracle_decoder(spec)
+    rs = O.render(dec, Z, cams, pairs, prm)
+    _log("case: latent", spec.latent_dim, "H", H, "levels", levels, "precision", precision)
+    out = api.dist_render_fwd(c, cams, torch.tensor(Z, device="cuda"), prm, save=True)
+    gd, gs, grads = [], [], []
+    for i, (r, (v, l)) in enumerate(zip(rs, pairs)):
+        same = ((out["status"][i].cpu().numpy() == r.status) & (out["nsteps"][i].cpu().numpy() == r.nsteps))
+        dt, nt, st = di.sphere_target_maps(cams[v], 0.45)
+        _, g_d, _, g_s = O.loss_and_grads(r, dt, nt, st, w_d=10.0, w_s=1.0)
+        g_d, g_s = g_d * same, g_s * same
+        grads.append((g_d, g_s))
+        gd.append(g_d)
+        gs.append(g_s)
+    ref = O.unrolled_backward(dec, Z, cams, pairs, prm, grads)
+    paper = O.backward(dec, Z, rs, pairs, prm, [(a, np.zeros(a.shape + (3,)), b) for a, b in grads],
+                       want_theta=False)[0]
+    T = lambda a: torch.tensor(np.stack(a).astype(np.float32), device="cuda")
+    g = api.dist_render_bwd_unrolled(c, out["saved"], T(gd), T(gs), n_latents=2).double().cpu().numpy()
+    g2 = api.dist_render_bwd_unrolled(c, out["saved"], T(gd), T(gs), n_latents=2).double().cpu().numpy()
+    out["saved"].free()
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    gap = np.linalg.norm(paper - ref) / np.linalg.norm(ref)
+    _log("unrolled gradient rel", rel, "| paper vs exact: rel", gap)
+    assert np.array_equal(g, g2)
+    assert rel <= tol
+    # a forward without the history cannot run the unrolled backward
+    prm.keep_history = 0
+    out = api.dist_render_fwd(c, cams, torch.tensor(Z, device="cuda"), prm, save=True)
+    with pytest.raises(N.DistError) as e:
+        api.dist_render_bwd_unrolled(c, out["saved"], T(gd), T(gs), n_latents=2)
+    out["saved"].free()
+    assert e.value.code == -1
