@@ -143,6 +143,46 @@ def measured_traffic(kernel):
     return float(vals["bytes_per_launch"])
 
 
+def gradient_variants(w, reps=2):
+    """dL/dz of the depth and silhouette terms of the benchmark workload by the
+    paper's approximation, the implicit-function depth derivative and the exact
+    gradient through the unrolled march: time per call and the relative gap of
+    each to the unrolled one."""
+    import copy
+    import torch
+    from paper_1911_13225_amd import api
+    prm = copy.copy(w["prm"])
+    prm.keep_history = 1
+    Z = w["Z"]
+    out = api.dist_render_fwd(w["ctx"], w["cams"], Z, prm, save=True)
+    depth = out["depth"].requires_grad_(True)
+    sil = out["sil"].requires_grad_(True)
+    dt, nt, st = w["targets"]
+    L = api.render_loss(depth, out["normal"], sil, dt, nt, st, w_d=10.0, w_s=1.0, w_n=0.0)
+    gd, gs = torch.autograd.grad(L, (depth, sil))
+    n = Z.shape[0]
+    calls = {
+        "paper": lambda: api.dist_render_bwd(w["ctx"], out["saved"], gd, None, gs, n_latents=n),
+        "implicit": lambda: api.dist_render_bwd_implicit(w["ctx"], out["saved"], gd, None, gs, n_latents=n),
+        "unrolled": lambda: api.dist_render_bwd_unrolled(w["ctx"], out["saved"], gd, gs, n_latents=n),
+    }
+    res, g = {}, {}
+    for name, fn in calls.items():
+        g[name] = fn().double()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 2)
+    ref = g["unrolled"]
+    for name in ("paper", "implicit"):
+        res[name + "_rel_gap_to_unrolled"] = round(float((g[name] - ref).norm() / ref.norm()), 4)
+    res["loss_terms"] = "10 L1 depth + silhouette (normal terms are not part of the unrolled gradient)"
+    out["saved"].free()
+    return res
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle on a bounded sample of the benchmark workload."""
     import dist_inputs as di
@@ -321,6 +361,7 @@ def main():
     ap.add_argument("--no-zopt", action="store_true")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated request rates (req/s) for a serving sweep, --serve-requests each")
+    ap.add_argument("--no-grad-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (reference dispatch for HBM byte counters)")
     a = ap.parse_args()
@@ -375,6 +416,10 @@ def main():
     res["roofline"] = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"] / 1e12,
                        "unit": "TFLOP/s", "frac": round(achieved / (PEAK["bf16"] / 1e12), 4),
                        "traffic": measured_traffic(name)}
+    if not a.no_grad_variants:
+        log("[bench] gradient variants on the same workload")
+        res["gradient_variants"] = gradient_variants(w)
+        log("[bench] gradient variants", res["gradient_variants"])
     del w
     torch.cuda.empty_cache()
 
