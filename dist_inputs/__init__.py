@@ -183,6 +183,56 @@ def sphere_target_maps(cam: Camera, radius: float = 0.5):
     return (depth.astype(np.float32), normal.astype(np.float32), hit.astype(np.float32))
 
 
+def ring_cameras(n: int, H: int, W: int, radius: float = 2.0, elevation_deg: float = 20.0) -> List[Camera]:
+    """``n`` cameras evenly spaced over 360 degrees of azimuth around the
+    vertical axis, at ``radius`` and a fixed elevation, looking at the origin
+    (the multi-view setting's views "uniformly distributed around the object")."""
+    cams = []
+    el = math.radians(elevation_deg)
+    for i in range(n):
+        az = 2.0 * math.pi * i / n
+        cams.append(look_at_camera((radius * math.cos(el) * math.sin(az), -radius * math.sin(el),
+                                    radius * math.cos(el) * math.cos(az)), H, W))
+    return cams
+
+
+def texture_params(seed: int = 5000, freq: float = 8.0):
+    """A procedural colour field on R^3: channel k is 0.5 + 0.5 sin(w_k . X + phi_k)
+    with w_k ~ N(0, freq^2 I3) and phi_k ~ U[0, 2 pi) (PCG64 ``seed``)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.standard_normal((3, 3)) * freq
+    phi = rng.random(3) * 2.0 * math.pi
+    return w, phi
+
+
+def textured_sphere_images(cams: Sequence[Camera], radius: float = 0.45, seed: int = 5000,
+                           background: float = 0.0, freq: float = 8.0) -> np.ndarray:
+    """Colour images [n, H, W, 3] (float32) of a sphere of ``radius`` at the
+    origin painted with the procedural colour field of ``texture_params``:
+    every view sees the same colour at the same surface point, as photometric
+    consistency across views assumes.  Pixels off the sphere get
+    ``background``."""
+    w, phi = texture_params(seed, freq)
+    out = []
+    for cam in cams:
+        H, W = cam.H, cam.W
+        u = np.arange(W, dtype=np.float64) + 0.5
+        v = np.arange(H, dtype=np.float64) + 0.5
+        xt = np.broadcast_to((u[None, :] - cam.cx) / cam.fx, (H, W))
+        yt = np.broadcast_to((v[:, None] - cam.cy) / cam.fy, (H, W))
+        dc = np.stack([xt, yt, np.ones_like(xt)], axis=-1)
+        dw = (dc / np.linalg.norm(dc, axis=-1, keepdims=True)) @ cam.R_wc.astype(np.float64).T
+        c = cam.c.astype(np.float64)
+        b = dw @ c
+        disc = b * b - (c @ c - radius * radius)
+        hit = disc > 0
+        t = np.where(hit, -b - np.sqrt(np.maximum(disc, 0.0)), 0.0)
+        X = c[None, None, :] + t[..., None] * dw
+        col = 0.5 + 0.5 * np.sin(X @ w.T + phi[None, None, :])
+        out.append(np.where(hit[..., None], col, background))
+    return np.stack(out).astype(np.float32)
+
+
 # ----------------------------------------------------------------------------
 # Trace parameters per workload
 # ----------------------------------------------------------------------------

@@ -848,6 +848,86 @@ def camera_backward(dec: Decoder, Z, renders: Sequence[Render], cams: Sequence, 
 
 
 # ============================================================================
+# Multi-view photometric loss (Sec. 4, multi-view reconstruction; App. C loss)
+# ============================================================================
+PHOTO_VIS = 1e-3       # Delta_d^2 below this: the point is visible in both views
+
+
+def photometric_loss(cams: Sequence, depth, images, pairs, weight=5.0):
+    """Cross-view photometric loss and its gradient w.r.t. the rendered depth.
+
+    For every ordered pair (i, j) and every pixel x of view i with a rendered
+    depth, the surface point X = c_i + d v_i(x) (d = z_c |(xt, yt, 1)|, Sec. 3.3)
+    is projected into view j; the colour of view j there, by bilinear
+    interpolation, is the warped image I_{j->i}(x), and the loss adds
+    weight / (H W) * sum_channels |I_i(x) - I_{j->i}(x)| (the L1 photometric
+    error of the multi-view objective, weight 5.0).
+
+    Reading P1 (visibility, "Delta_d^2 < 0.001"): Delta_d is the depth of X
+    in view j's frame minus view j's rendered depth at the pixel nearest to the
+    projection; the pixel counts only if that depth is finite and
+    Delta_d^2 < 1e-3, X lies in front of view j and the 2x2 interpolation
+    footprint lies inside the image.  Reading P2: the visibility decision and
+    view j's depth are constants; the gradient flows only through X (the depth
+    of view i) and the interpolation weights.
+
+    ``depth``: [n][H,W] z_c (inf = background); ``images``: [n][H,W,3].
+    Returns (L, g_depth [n][H,W]).
+    """
+    cs = [cam_from(c) for c in cams]
+    n = len(cs)
+    H, W = cs[0].H, cs[0].W
+    scale = float(weight) / (H * W)
+    g = [np.zeros(H * W) for _ in range(n)]
+    L = 0.0
+    V, U = np.divmod(np.arange(H * W), W)
+    for i, j in pairs:
+        ci, cj = cs[i], cs[j]
+        zi = np.asarray(depth[i], np.float64).reshape(-1)
+        Ii = np.asarray(images[i], np.float64).reshape(-1, 3)
+        Ij = np.asarray(images[j], np.float64)
+        Dj = np.asarray(depth[j], np.float64)
+        xt, yt, Dir = level_rays(ci, 0, U, V)
+        nrm = np.sqrt(xt * xt + yt * yt + 1.0)
+        fg = np.isfinite(zi)
+        X = ci.c[None, :] + np.where(fg, zi * nrm, 0.0)[:, None] * Dir
+        Xc = (X - cj.c[None, :]) @ cj.R                 # R^T (X - c) per row
+        front = Xc[:, 2] > 0.0
+        zc = np.where(front, Xc[:, 2], 1.0)
+        a = cj.fx * Xc[:, 0] / zc + cj.cx - 0.5           # pixel-index coordinates in view j
+        b = cj.fy * Xc[:, 1] / zc + cj.cy - 0.5
+        an = np.floor(a + 0.5).astype(np.int64)
+        bn = np.floor(b + 0.5).astype(np.int64)
+        a0 = np.floor(a).astype(np.int64)
+        b0 = np.floor(b).astype(np.int64)
+        ok = fg & front & (an >= 0) & (an < W) & (bn >= 0) & (bn < H)
+        ok &= (a0 >= 0) & (a0 + 1 < W) & (b0 >= 0) & (b0 + 1 < H)
+        dj = np.where(ok, Dj[np.clip(bn, 0, H - 1), np.clip(an, 0, W - 1)], np.inf)
+        ok &= np.isfinite(dj)
+        ok &= (Xc[:, 2] - np.where(ok, dj, 0.0)) ** 2 < PHOTO_VIS
+        idx = np.nonzero(ok)[0]
+        if idx.size == 0:
+            continue
+        al, be = (a - a0)[idx], (b - b0)[idx]
+        A0, B0 = a0[idx], b0[idx]
+        I00, I01 = Ij[B0, A0], Ij[B0, A0 + 1]
+        I10, I11 = Ij[B0 + 1, A0], Ij[B0 + 1, A0 + 1]
+        Iw = ((1 - be)[:, None] * ((1 - al)[:, None] * I00 + al[:, None] * I01)
+              + be[:, None] * ((1 - al)[:, None] * I10 + al[:, None] * I11))
+        r = Ii[idx] - Iw
+        L += scale * float(np.abs(r).sum())
+        dIa = (1 - be)[:, None] * (I01 - I00) + be[:, None] * (I11 - I10)
+        dIb = (1 - al)[:, None] * (I10 - I00) + al[:, None] * (I11 - I01)
+        q = Xc[idx]
+        dX = (Dir[idx] * nrm[idx, None]) @ cj.R            # d Xc / d z_c of view i
+        da = cj.fx * (dX[:, 0] / q[:, 2] - q[:, 0] * dX[:, 2] / q[:, 2] ** 2)
+        db = cj.fy * (dX[:, 1] / q[:, 2] - q[:, 1] * dX[:, 2] / q[:, 2] ** 2)
+        dIw = dIa * da[:, None] + dIb * db[:, None]
+        g[i][idx] += scale * (-np.sign(r) * dIw).sum(1)
+    return L, [gi.reshape(H, W) for gi in g]
+
+
+# ============================================================================
 # Closed forms from the appendix
 # ============================================================================
 def eps_for_camera(d_min, sensor, focal, resolution, theta=0.0):

@@ -692,3 +692,53 @@ def test_unrolled_gradient_converges_to_the_implicit_one():
     nrm = np.sqrt(r.xt[h] ** 2 + r.yt[h] ** 2 + 1)
     true = -0.1 * (1 - math.tanh(mz) ** 2) * uz * np.sum(1.0 / nrm / np.sum(ps / Rz * v, axis=1))
     assert np.linalg.norm(gz - true) <= 1e-6 * np.linalg.norm(true)
+
+
+# ----------------------------------------------------------------------------
+# multi-view photometric loss
+# ----------------------------------------------------------------------------
+def test_photometric_warp_of_an_identical_view_is_the_identity():
+    """Warping a view into an identical camera lands every surface point on its
+    own pixel centre: the warped image is the source image, every foreground
+    pixel whose 2x2 footprint lies inside the image is visible, and with a zero
+    target image the loss is weight / (H W) times the source's colour sum."""
+    H = 40
+    cam = di.ring_cameras(8, H, H)[3]
+    im = di.textured_sphere_images([cam], 0.45)[0]
+    D = di.sphere_target_maps(cam, 0.45)[0]
+    L, g = O.photometric_loss([cam, cam], [D, D], [np.zeros_like(im), im], [(0, 1)], weight=5.0)
+    fg = np.isfinite(D)
+    fg[:, -1] = False
+    fg[-1, :] = False
+    expect = 5.0 / (H * H) * float(im[fg].astype(np.float64).sum())
+    assert abs(L - expect) <= 1e-5 * expect
+    L2, g2 = O.photometric_loss([cam, cam], [D, D], [im, im], [(0, 1)])
+    assert L2 <= 1e-5 * expect
+
+
+def test_photometric_gradient_against_central_differences():
+    """dL/d(depth) of the photometric loss against central differences of the
+    loss in single depth values (step 1e-6), on random visible pixels."""
+    H = 48
+    cams = di.ring_cameras(8, H, H)
+    im = di.textured_sphere_images(cams, 0.45, freq=4.0)
+    D = [di.sphere_target_maps(c, 0.45)[0].astype(np.float64) * 1.003 for c in cams]
+    pairs = [(i, (i + 1) % 8) for i in range(8)] + [(i, (i + 7) % 8) for i in range(8)]
+    L, g = O.photometric_loss(cams, D, im, pairs)
+    rng = np.random.Generator(np.random.PCG64(3))
+    checked = 0
+    for _ in range(60):
+        v = int(rng.integers(8))
+        nz = np.argwhere(np.abs(g[v]) > 1e-4)
+        if nz.size == 0:
+            continue
+        y, x = nz[int(rng.integers(len(nz)))]
+        h = 1e-6
+        Dp = [d.copy() for d in D]
+        Dm = [d.copy() for d in D]
+        Dp[v][y, x] += h
+        Dm[v][y, x] -= h
+        fd = (O.photometric_loss(cams, Dp, im, pairs)[0] - O.photometric_loss(cams, Dm, im, pairs)[0]) / (2 * h)
+        assert abs(fd - g[v][y, x]) <= 1e-5 * abs(g[v][y, x]) + 1e-9
+        checked += 1
+    assert checked >= 30
