@@ -237,6 +237,33 @@ int dist_render_bwd_unrolled(dist_ctx* ctx, const dist_saved* saved,
                              const float* g_depth, const float* g_sil,
                              float* g_z, void* stream);
 
+/* Cross-view photometric loss of multi-view reconstruction (Sec. 4, the
+ * multi-view objective sum_i sum_{j in N_i} |I_i - I_{j->i}|; App. C: L1,
+ * visibility by Delta_d^2 < 0.001, weight 5.0 in the paper).  For every
+ * ordered pair (i, j) and every pixel x of view i with a finite depth, the
+ * surface point X = c_i + z_c |(xt, yt, 1)| v_i(x) is projected into view j;
+ * the pixel counts if X is in front of view j, the pixel of view j nearest to
+ * the projection has a finite depth D_j with (depth of X in view j - D_j)^2
+ * < 1e-3, and the 2x2 bilinear footprint lies inside the image; it then adds
+ * weight / (H W) * sum over the 3 channels of |I_i(x) - I_j(projection)|.
+ * The gradient flows to the depth of view i only (the visibility decision
+ * and view j's depth are constants).
+ *   cams     host array of n_views cameras (1..16 views, shared H and W)
+ *   depth    device float [n_views][H][W]: rendered z_c (+inf = background)
+ *   images   device float [n_views][H][W][3]: colour images
+ *   pairs    host int32 [n_pairs][2] (1..64 pairs): (i, j) warps view j into
+ *            view i; a view may have several neighbours
+ *   weight   loss weight
+ *   loss_map device float [n_views][H][W]: each pixel's loss (overwritten)
+ *   loss     device float scalar: the total, summed in a fixed order
+ *   g_depth  device float [n_views][H][W]: dL/d(depth) (overwritten), or NULL
+ * Stream-ordered, no allocation; bitwise reproducible.  DIST_EINVAL for bad
+ * arguments. */
+int dist_photometric_loss(const dist_camera* cams, int32_t n_views,
+                          const float* depth, const float* images,
+                          const int32_t* pairs, int32_t n_pairs, float weight,
+                          float* loss_map, float* loss, float* g_depth, void* stream);
+
 /* Free a forward state. */
 int dist_saved_free(dist_saved* saved);
 

@@ -203,6 +203,25 @@ def dist_render_bwd_unrolled(ctx: Context, saved: Saved, g_depth=None, g_sil=Non
     return g_z
 
 
+def dist_photometric_loss(cams, depth: torch.Tensor, images: torch.Tensor, pairs, weight=5.0, want_grad=True):
+    """Cross-view photometric loss of rendered depth maps [n, H, W] and colour
+    images [n, H, W, 3]; pairs (i, j) warp view j into view i.  Returns
+    (loss tensor [1], dL/d(depth) [n, H, W] or None)."""
+    lib = N.load()
+    n = len(cams)
+    cams_c = (N.dist_camera * n)(*[make_camera(c) for c in cams])
+    flat = [int(v) for p in pairs for v in p]
+    pairs_c = (ctypes.c_int32 * len(flat))(*flat)
+    d = depth.detach().float().contiguous()
+    im = images.detach().float().contiguous()
+    loss_map = torch.empty_like(d)
+    loss = torch.empty(1, device=d.device)
+    g = torch.empty_like(d) if want_grad else None
+    check(lib.dist_photometric_loss(cams_c, n, _ptr(d), _ptr(im), pairs_c, len(pairs), float(weight), _ptr(loss_map),
+                                    _ptr(loss), _ptr(g), _stream()))
+    return loss, g
+
+
 def dist_render_bwd_camera(ctx: Context, saved: Saved, n_views: int, g_depth=None, g_sil=None):
     """Gradient of the depth and silhouette terms w.r.t. each view's camera
     extrinsics: a tensor [n_views, 12] = (dL/dc, dL/dR_wc row-major)."""
