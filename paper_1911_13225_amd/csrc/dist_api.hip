@@ -845,9 +845,10 @@ extern "C" int dist_saved_free(dist_saved* s) {
 // ReLU pattern must match the float32 network; a bf16 recompute flips units
 // near zero) and back-propagates in bf16.
 static int adj_prec(int render_prec) { return render_prec == DIST_FP32 ? kPrecF32 : kPrecSplit; }
-// The VJP from saved masks runs in the adjoint's own tile (the 128-row bf16
-// tile would reuse the weights twice as often, but its VJP epilogue spills).
-static int vjp_prec(int adj) { return adj; }
+// The VJP from saved masks needs no recompute, so on the bf16 paths it runs
+// the bf16 kernel (128-row tiles, the same bf16 products as the split
+// kernel's VJP, which uses only the hi parts).
+static int vjp_prec(int adj) { return adj == kPrecSplit ? kPrecBF16 : adj; }
 
 static int reduce_only(dist_ctx* ctx, BwdSpace* b, int n_lat, float* g_z, hipStream_t st) {
   const int w0 = ctx->wpad[0];

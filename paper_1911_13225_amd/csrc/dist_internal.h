@@ -161,8 +161,8 @@ hipError_t mlp_setup(int precision, const NetDev& net);    // raise LDS limits
 
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t s);
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t s);
-// backward kernels: precision kPrecSplit or kPrecF32 (no bf16 variant; other
-// values launch nothing)
+// recompute-and-VJP: precision kPrecSplit or kPrecF32 (no bf16 variant; other
+// values launch nothing); VJP from saved masks: any precision
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t s);
 

@@ -49,6 +49,9 @@ template <> struct Cfg<2> {           // split bf16: x = hi + lo; hi*hi + lo*hi 
 // one per SIMD with 512 registers (accumulators in AGPRs).
 template <int P> constexpr int kFwdWaves = P == 0 ? 4 : 8;
 constexpr int kBwdWaves = 4;
+// The VJP from saved masks needs no recompute: its bf16 variant takes the
+// forward's 128-row, 8-wave layout (the split and float32 ones keep 4 waves).
+template <int P> constexpr int kVjpWaves = P == 1 ? 8 : 4;
 
 __host__ __device__ inline int rows_for(int P) { return P == 1 ? Cfg<1>::M : 64; }
 __host__ __device__ inline int fwd_threads(int P) { return (P == 0 ? 4 : 8) * 64; }
@@ -367,7 +370,8 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
 // ---------------------------------------------------------------------------
 // Epilogues
 // ---------------------------------------------------------------------------
-enum { EP_ACT = 0, EP_LAST = 1, EP_ACT_MASK = 2, EP_LAST_ADJ = 3, EP_VJP = 4 };
+// EP_VJP_NOGP: the VJP without the point-gradient partials (compiled out)
+enum { EP_ACT = 0, EP_LAST = 1, EP_ACT_MASK = 2, EP_LAST_ADJ = 3, EP_VJP = 4, EP_VJP_NOGP = 5 };
 
 // ReLU mask bits of a tile row: word w of layer l of row m is at
 // p[row * rs + l * ls + w], with row = m (per-workgroup scratch) or, with rid,
@@ -642,9 +646,9 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
 // VJP through one layer: acc = W^T delta for the output of layer ec.layer;
 // apply that layer's ReLU mask (recomputed in float32 for layer 0, whose
 // pre-activation is the same expression layer0_fill evaluates).
-template <int P, int MTW, int NTW, bool L0, bool CAP>
+template <int P, int MTW, int NTW, bool L0, bool CAP, bool GP>
 __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
-                                       int nt0, int mt0, int mg, int nw, int lane) {
+                                       int nt0, int mt0, int mg, int nw, int lane, const unsigned (&mb)[MTW][NTW]) {
   const int r = lane & 31, g = lane >> 5;
   const int N0 = net.wpad[0];
 #pragma unroll
@@ -675,7 +679,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
         }
       } else {
         // the lane's features are bits 8q + 4g + e of the stored word
-        bits = ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, m), 0), ec.layer, nt0 + j)] >> (4 * g);
+        bits = mb[i][j] >> (4 * g);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -698,7 +702,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
       }
     }
   }
-  if (ec.gp && ec.which >= 0) {
+  if (GP && ec.gp && ec.which >= 0) {
     // point gradient of m through this layer's point columns, per row:
     // sum_n delta[n] W_p[:, n] over the wave's features, times the row factor
     const float* wp = ec.which == 0 ? net.w0p : net.wsp;
@@ -791,13 +795,30 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   const int nw = wave % WN, mg = wave / WN;
   const int nt0 = nw * NTW, mt0 = mg * MTW;
   f32x16 acc[MTW][NTW];
-  if constexpr (MODE == EP_VJP) acc_mfma_start<P, MTW, NTW>(acc, nullptr, nt0, lane);
+  // the VJP's ReLU mask words are requested before the GEMM, so their latency
+  // (HBM for saved masks) hides behind it (the bf16 layout has no registers to
+  // spare: it reads them in the epilogue)
+  unsigned mb[MTW][NTW];
+  constexpr bool VJP = MODE == EP_VJP || MODE == EP_VJP_NOGP;
+  constexpr bool EARLY = P != kPrecBF16;
+  auto load_masks = [&]() {
+    const int r = lane & 31;
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+      for (int j = 0; j < NTW; ++j)
+        mb[i][j] = ec.layer != 0
+                       ? ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, (mt0 + i) * 32 + r), 0), ec.layer, nt0 + j)]
+                       : 0u;
+  };
+  if constexpr (VJP && EARLY) load_masks();
+  if constexpr (VJP) acc_mfma_start<P, MTW, NTW>(acc, nullptr, nt0, lane);
   else if constexpr (SKIP) acc_bias<P, MTW, NTW, true>(acc, ec, s, nt0, mt0, lane);
   else acc_mfma_start<P, MTW, NTW>(acc, net.bfrag[ec.layer], nt0, lane);
   if constexpr (P == 1) {
     gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane, nbytes);
   } else if constexpr (P == 2) {
-    gemm_split<MTW, NTW, MODE != EP_VJP>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane,
+    gemm_split<MTW, NTW, !VJP>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane,
                                          nbytes);
   } else {
     gemm_f32<MTW, NTW>(acc, s, (const f32x4*)wp, ksteps, nt0, mt0, lane, nbytes);
@@ -807,9 +828,11 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   if constexpr (MODE == EP_ACT_MASK) ep_act<P, MTW, NTW, true, CAP>(ec, acc, s, nt0, mt0, lane);
   if constexpr (MODE == EP_LAST) ep_last<P, MR, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
   if constexpr (MODE == EP_LAST_ADJ) ep_last<P, MR, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
-  if constexpr (MODE == EP_VJP) {
-    if (ec.layer == 0) ep_vjp<P, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, mg, nw, lane);
-    else ep_vjp<P, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, mg, nw, lane);
+  if constexpr (VJP) {
+    constexpr bool GP = MODE == EP_VJP;
+    if constexpr (!EARLY) load_masks();
+    if (ec.layer == 0) ep_vjp<P, MTW, NTW, true, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
+    else ep_vjp<P, MTW, NTW, false, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
   }
   __syncthreads();
 }
@@ -1084,7 +1107,7 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
 // VJP through the hidden layers l = nl-2 .. 1 for the rows of a tile whose
 // output-layer seed is in LDS (unit-delta chain; every row is weighted by its
 // factor s.gm where the column sums are taken).
-template <int P, bool CAP>
+template <int P, int NW, bool CAP, bool GP = true>
 __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, const MaskRef& mk, float* part,
                                            size_t row0, int rstride, int tile) {
   const NetDev& net = a.net;
@@ -1105,7 +1128,7 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
       ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
       ec.rstride = rstride;
     }
-    layer<P, kBwdWaves, Cfg<P>::M, EP_VJP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
+    layer<P, NW, Cfg<P>::M, GP ? EP_VJP : EP_VJP_NOGP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
   }
 }
 
@@ -1158,8 +1181,8 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
       }
     }
     float* part = a.partial + (size_t)tile * 4 * net.kmax;
-    if (theta) vjp_layers<P, true>(a, s, mk, part, row0, rstride, tile);
-    else vjp_layers<P, false>(a, s, mk, part, 0, 0, tile);
+    if (theta) vjp_layers<P, kBwdWaves, true>(a, s, mk, part, row0, rstride, tile);
+    else vjp_layers<P, kBwdWaves, false>(a, s, mk, part, 0, 0, tile);
   }
 }
 
@@ -1170,7 +1193,7 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
 // hidden layer, and the forward's 1 - tanh(m)^2 gives the row factor.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_vjp_saved(AdjArgs a) {
+__global__ __launch_bounds__(kVjpWaves<P> * 64) __attribute__((amdgpu_waves_per_eu(kVjpWaves<P> / 4, kVjpWaves<P> / 4))) void k_vjp_saved(AdjArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
@@ -1190,7 +1213,7 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
       s.gm[tid] = smp.w * 0.05f * a.sdtanh[si];
     }
     __syncthreads();
-    for (int i = tid; i < M * q4; i += kBwdWaves * 64) {
+    for (int i = tid; i < M * q4; i += kVjpWaves<P> * 64) {
       const int m = i / q4, n = 4 * (i - m * q4);
       const unsigned word = a.smask[mask_at(mk, s.rid[m], ll, n >> 5)] >> (n & 31);
       const float4 w4 = ld4(net.wlast + n);
@@ -1199,7 +1222,8 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
       store4<P>(s, m, n, (n >> 2) & 1, v, true);
     }
     __syncthreads();
-    vjp_layers<P, false>(a, s, mk, a.partial + (size_t)tile * 4 * net.kmax, 0, 0, tile);
+    // no point gradients here (the camera and unrolled passes use k_adjoint)
+    vjp_layers<P, kVjpWaves<P>, false, false>(a, s, mk, a.partial + (size_t)tile * 4 * net.kmax, 0, 0, tile);
   }
 }
 
@@ -1277,10 +1301,8 @@ static hipError_t setup_p(int bytes) {
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_eval<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  if (e != hipSuccess || P == kPrecBF16) return e;          // the backward has no bf16 kernels
-  e = hipFuncSetAttribute((const void*)k_vjp_saved<P == kPrecBF16 ? kPrecSplit : P>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_vjp_saved<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess || P == kPrecBF16) return e;          // the recompute has no bf16 kernel
   return hipFuncSetAttribute((const void*)k_adjoint<P == kPrecBF16 ? kPrecSplit : P>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
@@ -1301,7 +1323,7 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
     else hipLaunchKernelGGL(KERNEL<0>, dim3(grid), blk, sm, st, ARGS);                                 \
   } while (0)
 
-// the backward kernels exist in split and float32 precision only
+// the recompute-and-VJP kernel exists in split and float32 precision only
 #define DIST_DISPATCH_BWD(KERNEL, ARGS)                                                                \
   do {                                                                                                 \
     const size_t sm = mlp_smem_bytes(precision, ARGS.net);                                             \
@@ -1314,7 +1336,10 @@ void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t st) {
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_eval, a); }
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH_BWD(k_adjoint, a); }
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t st) {
-  DIST_DISPATCH_BWD(k_vjp_saved, a);
+  const size_t sm = mlp_smem_bytes(precision, a.net);
+  if (precision == 1) hipLaunchKernelGGL(k_vjp_saved<1>, dim3(grid), dim3(kVjpWaves<1> * 64), sm, st, a);
+  else if (precision == 2) hipLaunchKernelGGL(k_vjp_saved<2>, dim3(grid), dim3(kVjpWaves<2> * 64), sm, st, a);
+  else if (precision == 0) hipLaunchKernelGGL(k_vjp_saved<0>, dim3(grid), dim3(kVjpWaves<0> * 64), sm, st, a);
 }
 
 // ---------------------------------------------------------------------------
