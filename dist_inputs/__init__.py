@@ -43,7 +43,7 @@ class DecoderSpec:
     """Layer sizes of a DeepSDF-style decoder.
 
     ``out_dims[l]`` is the output width of linear layer ``l``; the last entry
-    is 1.  Layer 0 reads ``[z, p]`` (latent_dim + 3 values).  If
+    is 1 for a signed distance network, 3 for a colour network.  Layer 0 reads ``[z, p]`` (latent_dim + 3 values).  If
     ``skip_layer`` is set, that layer reads ``[h, z, p]`` where ``h`` is the
     previous layer's output.
     """
@@ -74,6 +74,15 @@ C1_SPEC = DecoderSpec(latent_dim=64, out_dims=(128, 128, 128, 128, 1), skip_laye
 DEEPSDF_SPEC = DecoderSpec(latent_dim=256,
                            out_dims=(512, 512, 512, 253, 512, 512, 512, 512, 1),
                            skip_layer=4)
+
+
+# Colour network of texture rendering: the geometry network's layout reading
+# the concatenated shape and texture codes (256 + 256) and emitting 3 channels.
+COLOR_SPEC = DecoderSpec(latent_dim=512,
+                         out_dims=(512, 512, 512, 253, 512, 512, 512, 512, 3),
+                         skip_layer=4)
+# A small colour network for quick tests: codes 32 + 32, 128 x4, 3 channels.
+C1_COLOR_SPEC = DecoderSpec(latent_dim=64, out_dims=(128, 128, 128, 128, 3), skip_layer=None)
 
 
 def make_decoder(spec: DecoderSpec, seed: int = 0):

@@ -848,6 +848,95 @@ def camera_backward(dec: Decoder, Z, renders: Sequence[Render], cams: Sequence, 
 
 
 # ============================================================================
+# Colour rendering at the hit points (Sec. 3.3 "Color and Semantics"; App. C)
+# ============================================================================
+class ColorDecoder(Decoder):
+    """The colour network of texture rendering: the geometry network's layout
+    (App. C) reading the concatenated shape and texture codes, three outputs.
+
+    Reading C1: each channel is c = 0.5 (1 + tanh(m)) (the DeepSDF-style tanh
+    output mapped to [0, 1]); the code z is [z_shape, z_tex]; the colour is
+    evaluated at the Eq. 1 point of every hit, which the backward treats as
+    detached (the principle of Sec. 3.4).
+    """
+
+    def color(self, Z, P):
+        Z = np.asarray(Z, np.float64)
+        P = np.asarray(P, np.float64)
+        if P.shape[0] == 0:
+            return np.zeros((0, 3))
+        h = self._hidden(Z, P)
+        m = h @ self.W[-1].T + self.b[-1]
+        return 0.5 * (1.0 + np.tanh(m))
+
+    def _hidden(self, Z, P, keep=None):
+        x0 = np.concatenate([Z, P], axis=1)
+        h = x0
+        for l in range(self.nl - 1):
+            x = np.concatenate([h, Z, P], axis=1) if (self.skip is not None and l == self.skip) else h
+            a = x @ self.W[l].T + self.b[l]
+            if keep is not None:
+                keep.append((x, a))
+            h = np.maximum(a, 0.0)
+        return h
+
+    def color_vjp(self, Z, P, seeds):
+        """sum_i seeds_i . d c(P_i, Z_i) / dZ_i per row: gZ [n, L]."""
+        Z = np.asarray(Z, np.float64)
+        P = np.asarray(P, np.float64)
+        seeds = np.asarray(seeds, np.float64)
+        n = P.shape[0]
+        gZ = np.zeros((n, self.L))
+        if n == 0:
+            return gZ
+        keep = []
+        h = self._hidden(Z, P, keep)
+        m = h @ self.W[-1].T + self.b[-1]
+        th = np.tanh(m)
+        delta = seeds * 0.5 * (1.0 - th * th)                   # d/dm of the output channels
+        g_h = delta @ self.W[-1]
+        for l in range(self.nl - 2, -1, -1):
+            x, a = keep[l]
+            d = g_h * (a > 0.0)
+            g_in = d @ self.W[l]
+            if l == 0:
+                gZ += g_in[:, : self.L]
+                break
+            if self.skip is not None and l == self.skip:
+                nh = self.W[l - 1].shape[0]
+                gZ += g_in[:, nh: nh + self.L]
+                g_h = g_in[:, :nh]
+            else:
+                g_h = g_in
+        return gZ
+
+
+def render_color(dec: ColorDecoder, Zc, renders: Sequence[Render], pairs):
+    """Colour images [n][H, W, 3] of the hits of geometry renders (image i uses
+    code Zc[pairs[i][1]]); 0 off the hits."""
+    out = []
+    for r, (vi, li) in zip(renders, pairs):
+        hit = (r.status == HIT).reshape(-1)
+        P = r.c[None, :] + r.dist.reshape(-1)[hit, None] * r.dirs[hit]
+        rgb = np.zeros((r.H * r.W, 3))
+        rgb[hit] = dec.color(np.broadcast_to(np.asarray(Zc[li], np.float64), (P.shape[0], dec.L)), P)
+        out.append(rgb.reshape(r.H, r.W, 3))
+    return out
+
+
+def color_backward(dec: ColorDecoder, Zc, renders: Sequence[Render], pairs, g_rgb):
+    """dL/dZc [n_lat, L] from per-image dL/d(colour) [H, W, 3] (hit points detached)."""
+    Zc = np.asarray(Zc, np.float64)
+    gz = np.zeros_like(Zc)
+    for r, (vi, li), g in zip(renders, pairs, g_rgb):
+        hit = (r.status == HIT).reshape(-1)
+        P = r.c[None, :] + r.dist.reshape(-1)[hit, None] * r.dirs[hit]
+        s = np.asarray(g, np.float64).reshape(-1, 3)[hit]
+        gz[li] += dec.color_vjp(np.broadcast_to(Zc[li], (P.shape[0], dec.L)), P, s).sum(0)
+    return gz
+
+
+# ============================================================================
 # Multi-view photometric loss (Sec. 4, multi-view reconstruction; App. C loss)
 # ============================================================================
 PHOTO_VIS = 1e-3       # Delta_d^2 below this: the point is visible in both views

@@ -742,3 +742,40 @@ def test_photometric_gradient_against_central_differences():
         assert abs(fd - g[v][y, x]) <= 1e-5 * abs(g[v][y, x]) + 1e-9
         checked += 1
     assert checked >= 30
+
+
+# ----------------------------------------------------------------------------
+# colour network at the hit points
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("spec", [di.C1_COLOR_SPEC, di.COLOR_SPEC], ids=["c1", "deepsdf"])
+def test_color_vjp_against_torch_autograd_and_differences(spec):
+    """The colour network's VJP w.r.t. the code against torch float64 autograd
+    of an independent torch forward, and against central differences."""
+    torch = pytest.importorskip("torch")
+    Ws, bs = di.make_decoder(spec, seed=3)
+    dec = O.ColorDecoder(spec, Ws, bs)
+    rng = np.random.Generator(np.random.PCG64(9))
+    n = 40
+    Z = np.repeat(rng.standard_normal((1, spec.latent_dim)) * 0.3, n, 0)
+    P = rng.uniform(-0.6, 0.6, (n, 3))
+    seeds = rng.standard_normal((n, 3))
+    g = dec.color_vjp(Z, P, seeds).sum(0)
+    Wt = [torch.tensor(np.asarray(W, np.float64)) for W in Ws]
+    bt = [torch.tensor(np.asarray(b, np.float64)) for b in bs]
+    z = torch.tensor(Z[0], requires_grad=True)
+    Pt = torch.tensor(P)
+    Zt = z[None, :].expand(n, -1)
+    h = torch.cat([Zt, Pt], 1)
+    for l in range(len(Wt)):
+        x = torch.cat([h, Zt, Pt], 1) if (spec.skip_layer is not None and l == spec.skip_layer) else h
+        a = x @ Wt[l].T + bt[l]
+        h = torch.relu(a) if l < len(Wt) - 1 else a
+    c = 0.5 * (1 + torch.tanh(h))
+    (c * torch.tensor(seeds)).sum().backward()
+    np.testing.assert_allclose(g, z.grad.numpy(), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(dec.color(Z, P), c.detach().numpy(), rtol=1e-12, atol=1e-14)
+    k = int(np.argmax(np.abs(g)))
+    e = np.zeros(spec.latent_dim)
+    e[k] = 1e-6
+    fd = ((dec.color(Z + e, P) - dec.color(Z - e, P)) * seeds).sum() / 2e-6
+    assert abs(fd - g[k]) <= 1e-6 * abs(g[k]) + 1e-9
