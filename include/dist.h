@@ -109,7 +109,8 @@ typedef struct {
 /* DeepSDF-style decoder (paper App. B.1): n_layers fully connected layers;
  * layer 0 reads [z, p] (latent_dim + 3 values), layer `skip_layer` (or -1)
  * reads [h, z, p], hidden layers use ReLU and the last layer has width 1.
- * The signed distance is f(p) = 0.5 (|p| - 0.5) + 0.05 tanh(m(z, p)).
+ * The signed distance is f(p) = 0.5 (|p| - 0.5) + 0.05 tanh(m(z, p)).  A last
+ * layer of width 3 makes a colour network (dist_render_color).
  * out_dims: host array of n_layers output widths (last = 1).  Hidden widths
  * up to 512, latent_dim up to 512, n_layers up to 12. */
 typedef struct {
@@ -236,6 +237,32 @@ int dist_render_bwd_camera(dist_ctx* ctx, const dist_saved* saved,
 int dist_render_bwd_unrolled(dist_ctx* ctx, const dist_saved* saved,
                              const float* g_depth, const float* g_sil,
                              float* g_z, void* stream);
+
+/* Colour rendered jointly with the geometry (Sec. 3.3, "Color and
+ * Semantics"; App. C: the texture network has the geometry network's
+ * architecture and reads the concatenated shape and texture codes).  A
+ * context created with a last layer of width 3 is a colour network; each
+ * channel is 0.5 (1 + tanh(m_c)).  It is evaluated at the Eq. 1 point of every
+ * hit of a saved geometry render (the points are detached for the backward,
+ * as Sec. 3.4 treats the march points).
+ *   cctx       colour context (dist_create with out_dims[n_layers-1] = 3); a
+ *              geometry entry point given a colour context returns DIST_EINVAL
+ *   geom       saved state of dist_render_fwd (another context's)
+ *   zc         device [n_latents][latent_dim of cctx]: one code per latent of
+ *              the render (e.g. [z_shape, z_tex])
+ *   precision  DIST_FP32, or DIST_BF16 (bf16 forward; the backward recomputes
+ *              in split bf16 as the geometry's backward does)
+ *   rgb        device float [n_images][H][W][3], overwritten; 0 off the hits
+ * Calls on one colour context share its buffers: issue them on one stream. */
+int dist_render_color(dist_ctx* cctx, const dist_saved* geom, const float* zc,
+                      int32_t n_latents, int32_t precision, float* rgb, void* stream);
+
+/* dL/dzc of the colour at the hits: g_rgb device [n_images][H][W][3]
+ * (dL/d(colour)); g_zc device [n_latents][latent_dim], overwritten.  Fixed
+ * reduction order, bitwise reproducible.  Arguments as dist_render_color. */
+int dist_render_color_bwd(dist_ctx* cctx, const dist_saved* geom, const float* zc,
+                          int32_t n_latents, int32_t precision, const float* g_rgb,
+                          float* g_zc, void* stream);
 
 /* Cross-view photometric loss of multi-view reconstruction (Sec. 4, the
  * multi-view objective sum_i sum_{j in N_i} |I_i - I_{j->i}|; App. C: L1,

@@ -77,6 +77,8 @@ _SIGS = [
     ("dist_render_bwd_camera", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     ("dist_render_bwd_implicit", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("dist_render_bwd_unrolled", ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    ("dist_render_color", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+    ("dist_render_color_bwd", ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     ("dist_photometric_loss", ctypes.c_int, [ctypes.POINTER(dist_camera), ctypes.c_int32, _P, _P,
                                              ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_float, _P, _P,
                                              _P, _P]),

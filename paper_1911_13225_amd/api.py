@@ -110,8 +110,9 @@ def dist_timing_read(ctx: Context, kernel: int):
 class Saved:
     """Owner of a dist_saved handle."""
 
-    def __init__(self, lib, handle):
+    def __init__(self, lib, handle, shape=None):
         self.lib, self.handle = lib, handle
+        self.shape = shape          # (n_img, H, W) of the render
 
     def free(self):
         if self.handle:
@@ -155,7 +156,7 @@ def dist_render_fwd(ctx: Context, cams, z: torch.Tensor, params, pairs=None, sav
                                   _ptr(out["sil"]), _ptr(out["status"]), _ptr(out["nsteps"]), _ptr(out["queries"]),
                                   ctypes.byref(sv) if save else None, _stream()))
     if save:
-        out["saved"] = Saved(ctx.lib, sv)
+        out["saved"] = Saved(ctx.lib, sv, (n_img, H, W))
         out["_z"] = zc          # keep the latent buffer alive for the backward
     return out
 
@@ -201,6 +202,26 @@ def dist_render_bwd_unrolled(ctx: Context, saved: Saved, g_depth=None, g_sil=Non
     check(ctx.lib.dist_render_bwd_unrolled(ctx.handle, saved.handle, *[_ptr(a) for a in args], _ptr(g_z),
                                            _stream()))
     return g_z
+
+
+def dist_render_color(cctx: Context, saved: Saved, zc: torch.Tensor, precision: int = 1):
+    """Colour [n_img, H, W, 3] of the hits of a saved geometry render, by the
+    colour network ``cctx`` with one code per latent of the render."""
+    zc_ = zc.detach().float().contiguous()
+    rgb = torch.empty(saved.shape + (3,), device=zc.device)
+    check(cctx.lib.dist_render_color(cctx.handle, saved.handle, _ptr(zc_), zc.shape[0], int(precision), _ptr(rgb),
+                                     _stream()))
+    return rgb
+
+
+def dist_render_color_bwd(cctx: Context, saved: Saved, zc: torch.Tensor, g_rgb: torch.Tensor, precision: int = 1):
+    """dL/d(code) [n_lat, code width] of the colour at the hits (hit points detached)."""
+    zc_ = zc.detach().float().contiguous()
+    g = g_rgb.detach().float().contiguous()
+    g_zc = torch.empty_like(zc_)
+    check(cctx.lib.dist_render_color_bwd(cctx.handle, saved.handle, _ptr(zc_), zc.shape[0], int(precision), _ptr(g),
+                                         _ptr(g_zc), _stream()))
+    return g_zc
 
 
 def dist_photometric_loss(cams, depth: torch.Tensor, images: torch.Tensor, pairs, weight=5.0, want_grad=True):

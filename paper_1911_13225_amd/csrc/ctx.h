@@ -102,8 +102,26 @@ struct Workspace {
   BwdSpace* bw = nullptr;
 };
 
+// Buffers of a colour network's calls (folded biases, hit list, backward).
+struct ColorSpace {
+  char* mem = nullptr;
+  size_t bytes = 0;
+  int cap_lat = 0;
+  long long cap_pix = 0;
+  float* bias0 = nullptr;          // [n_lat][wpad0]
+  float* biasS = nullptr;          // [n_lat][wpad_skip]
+  int* list = nullptr;             // hit ray slots
+  int* count = nullptr;
+  float4* cseed = nullptr;         // backward: per sample dL/d(colour)
+  long long cap_seed = 0;
+  BwdSpace* bw = nullptr;
+};
+
 struct dist_ctx {
   int device = 0;
+  int n_out = 1;                    // 1: signed distance network, 3: colour network
+  ColorSpace* col = nullptr;
+  std::mutex col_mu;
   int n_cu = 256;
   int nl = 0, L = 0, skip = -1, kmax = 0;
   std::vector<int> out_dims, in_dims, wpad, kpad;

@@ -116,15 +116,19 @@ static int pack_weights(dist_ctx* ctx, const float* const* W, const float* const
     HIPCHK(hipMemcpy(bb.data(), b[l], ctx->out_dims[l] * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(ctx->bias_pad[l], bb.data(), bb.size() * 4, hipMemcpyHostToDevice));
   }
-  // output layer
+  // output layer: n_out rows, each padded to the last hidden width
   {
-    const int lo = nl - 1;
-    std::vector<float> wl(ctx->wpad[nl - 2], 0.f);
-    HIPCHK(hipMemcpy(wl.data(), W[lo], ctx->in_dims[lo] * 4, hipMemcpyDeviceToHost));
+    const int lo = nl - 1, no = ctx->n_out, wp = ctx->wpad[nl - 2], in = ctx->in_dims[lo];
+    std::vector<float> Wl((size_t)no * in), wl((size_t)no * wp, 0.f), bl(no, 0.f);
+    HIPCHK(hipMemcpy(Wl.data(), W[lo], Wl.size() * 4, hipMemcpyDeviceToHost));
+    for (int c = 0; c < no; ++c)
+      for (int k = 0; k < in; ++k) wl[(size_t)c * wp + k] = Wl[(size_t)c * in + k];
     HIPCHK(hipMemcpy(ctx->wlast, wl.data(), wl.size() * 4, hipMemcpyHostToDevice));
-    float bl = 0.f;
-    HIPCHK(hipMemcpy(&bl, b[lo], 4, hipMemcpyDeviceToHost));
-    ctx->net[0].blast = ctx->net[1].blast = ctx->net[2].blast = bl;
+    HIPCHK(hipMemcpy(bl.data(), b[lo], no * 4, hipMemcpyDeviceToHost));
+    for (int p = 0; p < 3; ++p) {
+      ctx->net[p].blast = bl[0];
+      for (int c = 0; c < 3; ++c) ctx->net[p].blast_c[c] = c < no ? bl[c] : 0.f;
+    }
   }
   // MFMA fragments
   for (int l = 1; l <= nl - 2; ++l) {
@@ -150,7 +154,8 @@ extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const 
   if (L < 1 || L > 512) return dist_set_error(DIST_EINVAL, "latent_dim must be in [1, 512]");
   if (skip != -1 && (skip < 1 || skip >= nl - 2))
     return dist_set_error(DIST_EINVAL, "skip_layer must be -1 or in [1, n_layers-3]");
-  if (desc->out_dims[nl - 1] != 1) return dist_set_error(DIST_EINVAL, "the last layer must have width 1");
+  if (desc->out_dims[nl - 1] != 1 && desc->out_dims[nl - 1] != 3)
+    return dist_set_error(DIST_EINVAL, "the last layer must have width 1 (signed distance) or 3 (colour)");
   for (int l = 0; l < nl - 1; ++l)
     if (desc->out_dims[l] < 1 || desc->out_dims[l] > kMaxWidth)
       return dist_set_error(DIST_EINVAL, "hidden widths must be in [1, %d]", kMaxWidth);
@@ -159,6 +164,7 @@ extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const 
   hipStream_t st = (hipStream_t)stream;
 
   dist_ctx* ctx = new dist_ctx();
+  ctx->n_out = desc->out_dims[nl - 1];
   ctx->nl = nl;
   ctx->L = L;
   ctx->skip = skip;
@@ -204,7 +210,7 @@ extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const 
   }
   ctx->bias_pad.assign(nl, nullptr);
   for (int l = 0; l < nl - 1; ++l) A((void**)&ctx->bias_pad[l], sizeof(float) * ctx->wpad[l]);
-  A((void**)&ctx->wlast, sizeof(float) * ctx->wpad[nl - 2]);
+  A((void**)&ctx->wlast, sizeof(float) * ctx->wpad[nl - 2] * ctx->n_out);
   for (int p = 0; p < 2; ++p) {
     ctx->wpack[p].assign(nl, nullptr);
     ctx->wpackT[p].assign(nl, nullptr);
@@ -241,6 +247,7 @@ extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const 
     nd.w0p = ctx->w0p;
     nd.wsp = ctx->wsp;
     nd.wlast = ctx->wlast;
+    nd.nout = ctx->n_out;
   }
   rc = pack_weights(ctx, W, b, st);
   if (rc == DIST_OK) {
@@ -276,6 +283,14 @@ extern "C" int dist_destroy(dist_ctx* ctx) {
       (void)hipEventDestroy(pr.first);
       (void)hipEventDestroy(pr.second);
     }
+  if (ctx->col) {
+    if (ctx->col->bw) {
+      ctx_free(ctx, ctx->col->bw->mem, ctx->col->bw->bytes);
+      delete ctx->col->bw;
+    }
+    ctx_free(ctx, ctx->col->mem, ctx->col->bytes);
+    delete ctx->col;
+  }
   for (auto& o : ctx->owned) ctx_free(ctx, o.first, o.second);
   delete ctx;
   return DIST_OK;
@@ -489,16 +504,16 @@ static void ws_release_all(dist_ctx* ctx) {
   for (Workspace* w : v) ws_destroy(ctx, w);
 }
 
-static int bw_get(dist_ctx* ctx, Workspace* w, int cap_samples, int cap_blocks, int cap_lat, int tile,
-                  size_t mask_words) {
-  BwdSpace* b = w->bw;
+static int bw_get_into(dist_ctx* ctx, BwdSpace*& slot, int cap_samples, int cap_blocks, int cap_lat, int tile,
+                       size_t mask_words) {
+  BwdSpace* b = slot;
   if (b && b->cap_samples >= cap_samples && b->cap_blocks >= cap_blocks && b->cap_lat >= cap_lat && b->tile == tile &&
       b->mask_words >= mask_words)
     return DIST_OK;
   if (b) {
     ctx_free(ctx, b->mem, b->bytes);
     delete b;
-    w->bw = nullptr;
+    slot = nullptr;
   }
   b = new BwdSpace();
   b->cap_samples = cap_samples;
@@ -514,8 +529,13 @@ static int bw_get(dist_ctx* ctx, Workspace* w, int cap_samples, int cap_blocks, 
   c.base = b->mem;
   c.off = 0;
   bw_layout(*b, c);
-  w->bw = b;
+  slot = b;
   return DIST_OK;
+}
+
+static int bw_get(dist_ctx* ctx, Workspace* w, int cap_samples, int cap_blocks, int cap_lat, int tile,
+                  size_t mask_words) {
+  return bw_get_into(ctx, w->bw, cap_samples, cap_blocks, cap_lat, tile, mask_words);
 }
 
 // Buffers for the ReLU masks of up to cap_samples stencil queries.
@@ -759,6 +779,7 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
                                uint8_t* status, uint8_t* nsteps, int64_t* queries, dist_saved** saved,
                                void* stream) {
   if (!ctx || !cams || !z || !prm) return dist_set_error(DIST_EINVAL, "null argument");
+  if (ctx->n_out != 1) return dist_set_error(DIST_EINVAL, "a colour network does not render geometry");
   if (n_views < 1 || n_latents < 1) return dist_set_error(DIST_EINVAL, "n_views and n_latents must be positive");
   const int n_img = pairs ? n_images : n_views * n_latents;
   if (n_img < 1 || n_img > 65536) return dist_set_error(DIST_EINVAL, "n_images must be in [1, 65536]");
@@ -1219,11 +1240,153 @@ extern "C" int dist_render_bwd_unrolled(dist_ctx* ctx, const dist_saved* saved, 
 }
 
 // ---------------------------------------------------------------------------
+// colour at the hits of a geometry render
+// ---------------------------------------------------------------------------
+// Buffers of a colour network's calls, grown on demand (held by the context).
+static int col_get(dist_ctx* cctx, int n_lat, long long n_pix) {
+  ColorSpace* c = cctx->col;
+  if (c && c->cap_lat >= n_lat && c->cap_pix >= n_pix) return DIST_OK;
+  const int cap_lat = std::max(n_lat, c ? c->cap_lat : 0);
+  const long long cap_pix = std::max(n_pix, c ? c->cap_pix : 0LL);
+  BwdSpace* keep_bw = c ? c->bw : nullptr;
+  if (c) {
+    ctx_free(cctx, c->mem, c->bytes);
+    delete c;
+    cctx->col = nullptr;
+  }
+  c = new ColorSpace();
+  c->bw = keep_bw;
+  c->cap_lat = cap_lat;
+  c->cap_pix = cap_pix;
+  const int ws = cctx->skip >= 0 ? cctx->wpad[cctx->skip] : 0;
+  const size_t b0 = (((size_t)cap_lat * cctx->wpad[0] * 4) + 255) & ~(size_t)255;
+  const size_t bs = (((size_t)cap_lat * ws * 4) + 255) & ~(size_t)255;
+  const size_t li = (((size_t)cap_pix * 4) + 255) & ~(size_t)255;
+  c->cap_seed = cap_pix + (long long)cap_lat * 64;
+  const size_t cs = (size_t)c->cap_seed * sizeof(float4);
+  c->bytes = b0 + bs + li + 256 + cs;
+  int rc = ctx_alloc(cctx, (void**)&c->mem, c->bytes);
+  if (rc != DIST_OK) {
+    if (keep_bw) {
+      ctx_free(cctx, keep_bw->mem, keep_bw->bytes);
+      delete keep_bw;
+    }
+    delete c;
+    return rc;
+  }
+  c->bias0 = (float*)c->mem;
+  c->biasS = (float*)(c->mem + b0);
+  c->list = (int*)(c->mem + b0 + bs);
+  c->count = (int*)(c->mem + b0 + bs + li);
+  c->cseed = (float4*)(c->mem + b0 + bs + li + 256);
+  cctx->col = c;
+  return DIST_OK;
+}
+
+static int color_check(dist_ctx* cctx, const dist_saved* geom, const float* zc, int32_t n_latents, int32_t precision) {
+  if (!cctx || !geom || !zc) return dist_set_error(DIST_EINVAL, "null argument");
+  if (cctx->n_out != 3) return dist_set_error(DIST_EINVAL, "not a colour network (last layer width 3)");
+  if (geom->ctx->device != cctx->device) return dist_set_error(DIST_EINVAL, "the two networks live on different devices");
+  if (n_latents != geom->n_lat) return dist_set_error(DIST_EINVAL, "one colour code per latent of the render");
+  if (precision != DIST_FP32 && precision != DIST_BF16)
+    return dist_set_error(DIST_EINVAL, "precision must be DIST_FP32 or DIST_BF16");
+  return DIST_OK;
+}
+
+static void color_fold(dist_ctx* cctx, const float* zc, int n_lat, hipStream_t st) {
+  ColorSpace* c = cctx->col;
+  launch_fold_bias(cctx->bf[0], cctx->w0z, zc, n_lat, cctx->L, cctx->out_dims[0], cctx->wpad[0], c->bias0, st);
+  if (cctx->skip >= 0)
+    launch_fold_bias(cctx->bf[cctx->skip], cctx->wsz, zc, n_lat, cctx->L, cctx->out_dims[cctx->skip],
+                     cctx->wpad[cctx->skip], c->biasS, st);
+}
+
+extern "C" int dist_render_color(dist_ctx* cctx, const dist_saved* geom, const float* zc, int32_t n_latents,
+                                 int32_t precision, float* rgb, void* stream) {
+  int rc = color_check(cctx, geom, zc, n_latents, precision);
+  if (rc) return rc;
+  if (!rgb) return dist_set_error(DIST_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(cctx->col_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = geom->ws;
+  const int n_img = geom->n_img, hw = geom->hw;
+  const long long npix = (long long)n_img * hw;
+  rc = col_get(cctx, n_latents, npix);
+  if (rc) return rc;
+  ColorSpace* c = cctx->col;
+  const int prec = precision == DIST_FP32 ? kPrecF32 : kPrecBF16;
+  color_fold(cctx, zc, n_latents, st);
+  hipLaunchKernelGGL(k_fill_f32, dim3(512), dim3(256), 0, st, rgb, 3 * npix);
+  launch_fill_i32(c->count, 0, 1, st);
+  launch_color_hits(w->pool, w->imgs, n_img, hw, c->list, c->count, st);
+  ColorArgs ca{};
+  ca.net = cctx->net[prec];
+  ca.pool = w->pool;
+  ca.imgs = w->imgs;
+  ca.bias0_lat = c->bias0;
+  ca.biasS_lat = c->biasS;
+  ca.list = c->list;
+  ca.count = c->count;
+  ca.rgb = rgb;
+  launch_color(prec, ca, mlp_grid(cctx, npix, prec), st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+extern "C" int dist_render_color_bwd(dist_ctx* cctx, const dist_saved* geom, const float* zc, int32_t n_latents,
+                                     int32_t precision, const float* g_rgb, float* g_zc, void* stream) {
+  int rc = color_check(cctx, geom, zc, n_latents, precision);
+  if (rc) return rc;
+  if (!g_rgb || !g_zc) return dist_set_error(DIST_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(cctx->col_mu);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace* w = geom->ws;
+  const int n_img = geom->n_img, hw = geom->hw;
+  const long long npix = (long long)n_img * hw;
+  // recompute in split bf16 on the bf16 path (as the signed distance's adjoint)
+  const int prec = precision == DIST_FP32 ? kPrecF32 : kPrecSplit;
+  const int tile = adj_tile_rows(prec);
+  const long long cap = npix + (long long)n_latents * tile;
+  if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many gradient samples");
+  rc = col_get(cctx, n_latents, npix);
+  if (rc) return rc;
+  ColorSpace* c = cctx->col;
+  const int grid = mlp_grid(cctx, cap, prec);
+  const int bpi = (hw + 255) / 256;
+  rc = bw_get_into(cctx, c->bw, (int)cap, n_img * bpi, n_latents, tile,
+                   adj_mask_words(prec, cctx->net[prec]) * grid);
+  if (rc) return rc;
+  BwdSpace* b = c->bw;
+  color_fold(cctx, zc, n_latents, st);
+  launch_color_samples(w->pool, w->imgs, w->img_order, w->img_latent, n_img, hw, n_latents, tile, g_rgb, b->bsum,
+                       b->boff, b->seg_base, b->seg_total, b->seg_padded, b->n_samples, b->samples, c->cseed,
+                       b->sample_lat, std::min<long long>(cap, c->cap_seed), st);
+  AdjArgs aa{};
+  aa.net = cctx->net[prec];
+  aa.bias0_lat = c->bias0;
+  aa.biasS_lat = c->biasS;
+  aa.samples = b->samples;
+  aa.sample_lat = b->sample_lat;
+  aa.n_samples = b->n_samples;
+  aa.mask_ws = b->mask_ws;
+  aa.partial = b->partial;
+  aa.cseed = c->cseed;
+  launch_color_adjoint(prec, aa, grid, st);
+  const int w0 = cctx->wpad[0];
+  const int ws = cctx->skip >= 0 ? cctx->wpad[cctx->skip] : 0;
+  launch_gz_reduce(b->partial, cctx->kmax, tile, (int)(cap / tile) + 1, b->seg_base, b->seg_padded, n_latents, w0, 1,
+                   cctx->w0z, ws, 1, cctx->skip >= 0 ? cctx->wsz : nullptr, cctx->L, g_zc, st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+// ---------------------------------------------------------------------------
 // decoder queries at explicit points
 // ---------------------------------------------------------------------------
 extern "C" int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* latent_ids, const float* z,
                              int32_t n_latents, int64_t n, int32_t precision, float* f, void* stream) {
   if (!ctx) return dist_set_error(DIST_EINVAL, "null argument");
+  if (ctx->n_out != 1) return dist_set_error(DIST_EINVAL, "a colour network has no signed distance");
   if (n == 0) return DIST_OK;                       // nothing is read or written
   if (!points || !latent_ids || !z || !f) return dist_set_error(DIST_EINVAL, "null argument");
   if (n < 0 || n > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "n out of range");
@@ -1261,6 +1424,7 @@ extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* l
                             const float* z, int32_t n_latents, int64_t n, int32_t precision, float* g_z,
                             float* const* g_W, float* const* g_b, void* stream) {
   if (!ctx || !z || !g_z) return dist_set_error(DIST_EINVAL, "null argument");
+  if (ctx->n_out != 1) return dist_set_error(DIST_EINVAL, "a colour network has no signed distance");
   if (n > 0 && (!points || !latent_ids || !seeds)) return dist_set_error(DIST_EINVAL, "null argument");
   if (n < 0 || n > (1LL << 28)) return dist_set_error(DIST_EINVAL, "n out of range");
   if (n_latents < 1) return dist_set_error(DIST_EINVAL, "n_latents must be positive");

@@ -64,8 +64,22 @@ struct NetDev {
   const void* bfrag[kMaxLayers];
   const float* w0p;                // [3][wpad0]: point columns of layer 0
   const float* wsp;                // [3][wpad_skip]: point columns of the skip layer
-  const float* wlast;              // [wpad[nl-2]] output-layer weights
-  float blast;                     // output-layer bias
+  const float* wlast;              // [nout][wpad[nl-2]] output-layer weights
+  float blast;                     // output-layer bias (output 0)
+  int nout;                        // outputs: 1 (signed distance) or 3 (colour)
+  float blast_c[3];                // output-layer biases of a colour network
+};
+
+// Colour of the hits of a geometry render (k_color): one row per hit ray.
+struct ColorArgs {
+  NetDev net;                      // the colour network (nout = 3)
+  RayPool pool;                    // the geometry render's rays
+  const ImgDesc* imgs;
+  const float* bias0_lat;          // folded with the colour codes
+  const float* biasS_lat;
+  const int* list;                 // hit ray slots
+  const int* count;
+  float* rgb;                      // [pixels][3]
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -134,6 +148,8 @@ struct AdjArgs {
   // Wskip_p^T delta_skip) partial sums over that wave's features,
   // [sample][4][3] (the spatial gradient of m, weighted by the row's factor)
   float* gp_part;
+  // colour network (k_color_adjoint): per sample dL/d(colour), (r, g, b, 0)
+  const float4* cseed;
 };
 
 // Precision codes of the decoder kernels: 0 float32, 1 bfloat16, 2 split
@@ -165,6 +181,10 @@ void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t s);
 // values launch nothing); VJP from saved masks: any precision
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t s);
+// colour network: forward at hits (precision kPrecF32 or kPrecBF16) and
+// recompute + VJP with per-sample colour seeds (kPrecF32 or kPrecSplit)
+void launch_color(int precision, const ColorArgs& a, int grid, hipStream_t s);
+void launch_color_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
 
 // packing / folding
 void launch_pack_bias(int precision, const float* bias, int wpad, void* dst, hipStream_t st);

@@ -55,10 +55,10 @@ template <int P> constexpr int kVjpWaves = P == 1 ? 8 : 4;
 
 __host__ __device__ inline int rows_for(int P) { return P == 1 ? Cfg<1>::M : 64; }
 __host__ __device__ inline int fwd_threads(int P) { return (P == 0 ? 4 : 8) * 64; }
-__host__ __device__ inline size_t smem_bytes_for(int P, int kmax) {
+__host__ __device__ inline size_t smem_bytes_for(int P, int kmax, int nout = 1) {
   const int M = rows_for(P);
   const int ES = P == 1 ? 2 : 4;
-  return (size_t)M * kmax * ES + (size_t)M * (16 + 4 + 4 + 4 + 4) + (size_t)8 * M * 4;
+  return (size_t)M * kmax * ES + (size_t)M * (16 + 4 + 4 + 4 + 4) + (size_t)8 * M * 4 * nout;
 }
 
 template <int P> struct Sm {
@@ -589,16 +589,18 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
 // Last hidden layer: m-partial = sum_n w_last[n] relu(x[n]) per row (reduced
 // across the waves in a fixed order by the caller); with ADJ the seed
 // d m / d(pre-activation) = w_last [x > 0] is written to LDS.
-template <int P, int MR, int MTW, int NTW, bool ADJ, bool CAP>
+template <int P, int MR, int MTW, int NTW, bool ADJ, bool CAP, int NOUT>
 __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
                                         int nt0, int mt0, int nw, int lane) {
   constexpr int M = MR;
   const int r = lane & 31, g = lane >> 5;
-  float sum[MTW];
+  const int wstride = net.wpad[net.nl - 2];
+  float sum[NOUT][MTW];
   unsigned bits[MTW][NTW];
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
-    sum[i] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) sum[c][i] = 0.f;
 #pragma unroll
     for (int j = 0; j < NTW; ++j) bits[i][j] = 0u;
   }
@@ -607,8 +609,15 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int n = feat(nt0, j, q, g);
-      const float4 w4 = ld4(net.wlast + n);
-      const float wl[4] = {w4.x, w4.y, w4.z, w4.w};
+      float wl[NOUT][4];
+#pragma unroll
+      for (int c = 0; c < NOUT; ++c) {
+        const float4 w4 = ld4(net.wlast + c * wstride + n);
+        wl[c][0] = w4.x;
+        wl[c][1] = w4.y;
+        wl[c][2] = w4.z;
+        wl[c][3] = w4.w;
+      }
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
         const int m = (mt0 + i) * 32 + r;
@@ -617,20 +626,26 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
         for (int e = 0; e < 4; ++e) {
           const float x = acc[i][j][4 * q + e];
           h[e] = fmaxf(x, 0.f);
-          sum[i] = fmaf(wl[e], h[e], sum[i]);
+#pragma unroll
+          for (int c = 0; c < NOUT; ++c) sum[c][i] = fmaf(wl[c][e], h[e], sum[c][i]);
           const unsigned b = pos_bit(x);
-          v[e] = __uint_as_float(__float_as_uint(wl[e]) & (0u - b));
+          v[e] = __uint_as_float(__float_as_uint(wl[0][e]) & (0u - b));
           if constexpr (ADJ) bits[i][j] |= b << (8 * q + e);
         }
-        if constexpr (ADJ) store4<P>(s, m, n, g, v, true);
+        // the seed of the output layer (a single output; a colour network
+        // builds its seed from the three channels after the forward)
+        if constexpr (ADJ && NOUT == 1) store4<P>(s, m, n, g, v, true);
         if constexpr (CAP) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(h[0], h[1], h[2], h[3]);
       }
     }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
     const int m = (mt0 + i) * 32 + r;
-    const float t = sum[i] + __shfl_xor(sum[i], 32);
-    if (g == 0) s.part[nw * M + m] = t;
+#pragma unroll
+    for (int c = 0; c < NOUT; ++c) {
+      const float t = sum[c][i] + __shfl_xor(sum[c][i], 32);
+      if (g == 0) s.part[(c * 8 + nw) * M + m] = t;
+    }
     if constexpr (ADJ) {
       const int row = mask_row(ec.mk, s, m);
 #pragma unroll
@@ -785,7 +800,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
 // Run one layer (accumulator init + GEMM + barrier + epilogue + barrier) for an
 // output width N (128, 256 or 512 after padding): WN waves split N into groups
 // of NTW 32-wide tiles; the NW / WN wave groups split the rows into MTW tiles.
-template <int P, int MR, int MTW, int NTW, int WN, int MODE, bool CAP, bool SKIP>
+template <int P, int MR, int MTW, int NTW, int WN, int MODE, bool CAP, bool SKIP, int NOUT = 1>
 __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                           const void* wlo, int ksteps, int nbytes) {
   // lane-dependent addressing is recomputed per layer (see opaque()); the wave
@@ -826,8 +841,8 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   __syncthreads();
   if constexpr (MODE == EP_ACT) ep_act<P, MTW, NTW, false, CAP>(ec, acc, s, nt0, mt0, lane);
   if constexpr (MODE == EP_ACT_MASK) ep_act<P, MTW, NTW, true, CAP>(ec, acc, s, nt0, mt0, lane);
-  if constexpr (MODE == EP_LAST) ep_last<P, MR, MTW, NTW, false, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
-  if constexpr (MODE == EP_LAST_ADJ) ep_last<P, MR, MTW, NTW, true, CAP>(net, ec, acc, s, nt0, mt0, nw, lane);
+  if constexpr (MODE == EP_LAST) ep_last<P, MR, MTW, NTW, false, CAP, NOUT>(net, ec, acc, s, nt0, mt0, nw, lane);
+  if constexpr (MODE == EP_LAST_ADJ) ep_last<P, MR, MTW, NTW, true, CAP, NOUT>(net, ec, acc, s, nt0, mt0, nw, lane);
   if constexpr (VJP) {
     constexpr bool GP = MODE == EP_VJP;
     if constexpr (!EARLY) load_masks();
@@ -840,7 +855,7 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
 // One layer of output width N and contracted width K; returns the number of
 // wave groups that wrote output-layer partial sums.
 // SKIP: the layer reads [h, z, p] (its bias is per latent plus W_p p).
-template <int P, int NW, int MR, int MODE, bool CAP, bool SKIP = false>
+template <int P, int NW, int MR, int MODE, bool CAP, bool SKIP = false, int NOUT = 1>
 __device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const Sm<P>& s, const void* wp,
                                      const void* wlo, int N, int K) {
   constexpr int MT = MR / 32;
@@ -848,17 +863,17 @@ __device__ __forceinline__ int layer(const NetDev& net, const EpCtx& ec, const S
   const int nbytes = N * K * (P ? 2 : 4);       // the layer's packed fragment array
   static_assert(NW == 4 || NW == 8, "4 or 8 waves");
   if constexpr (NW == 8) {
-    if (N == 512) layer_run<P, MR, MT, 2, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-    else if (N == 256) layer_run<P, MR, MT, 1, 8, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    if (N == 512) layer_run<P, MR, MT, 2, 8, MODE, CAP, SKIP, NOUT>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else if (N == 256) layer_run<P, MR, MT, 1, 8, MODE, CAP, SKIP, NOUT>(net, ec, s, wp, wlo, ksteps, nbytes);
     else {
-      layer_run<P, MR, MT / 2, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+      layer_run<P, MR, MT / 2, 1, 4, MODE, CAP, SKIP, NOUT>(net, ec, s, wp, wlo, ksteps, nbytes);
       return 4;
     }
     return 8;
   } else {
-    if (N == 512) layer_run<P, MR, MT, 4, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-    else if (N == 256) layer_run<P, MR, MT, 2, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
-    else layer_run<P, MR, MT, 1, 4, MODE, CAP, SKIP>(net, ec, s, wp, wlo, ksteps, nbytes);
+    if (N == 512) layer_run<P, MR, MT, 4, 4, MODE, CAP, SKIP, NOUT>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else if (N == 256) layer_run<P, MR, MT, 2, 4, MODE, CAP, SKIP, NOUT>(net, ec, s, wp, wlo, ksteps, nbytes);
+    else layer_run<P, MR, MT, 1, 4, MODE, CAP, SKIP, NOUT>(net, ec, s, wp, wlo, ksteps, nbytes);
     return 4;
   }
 }
@@ -881,7 +896,7 @@ __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_l
 // s.part and returns the number of partial groups.  ADJ records the ReLU masks
 // and the output-layer seed for the adjoint; CAP keeps float32 copies of every
 // hidden activation in hcap for the weight gradient.
-template <int P, int NW, int MR, bool ADJ, bool CAP>
+template <int P, int NW, int MR, bool ADJ, bool CAP, int NOUT = 1>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
                                            const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr) {
   const int rstride = (net.nl - 1) * net.kmax;
@@ -897,7 +912,7 @@ __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0
     }
     // the skip layer is never the last hidden layer (skip <= nl - 3)
     if (l == net.nl - 2)
-      wn = layer<P, NW, MR, ADJ ? EP_LAST_ADJ : EP_LAST, CAP>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
+      wn = layer<P, NW, MR, ADJ ? EP_LAST_ADJ : EP_LAST, CAP, false, NOUT>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l], net.kpad[l]);
     else if (l == net.skip)
       wn = layer<P, NW, MR, ADJ ? EP_ACT_MASK : EP_ACT, CAP, true>(net, ec, s, net.wp[l], net.wplo[l], net.wpad[l],
                                                            net.kpad[l]);
@@ -1228,6 +1243,110 @@ __global__ __launch_bounds__(kVjpWaves<P> * 64) __attribute__((amdgpu_waves_per_
 }
 
 // ---------------------------------------------------------------------------
+// Colour network at the hits of a geometry render (Sec. 3.3, colour rendered
+// jointly with the SDF; App. C, the texture network): three outputs, each
+// channel 0.5 (1 + tanh(m_c)), at the Eq. 1 point of every hit ray.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_eu(kFwdWaves<P> / 4, kFwdWaves<P> / 4))) void k_color(ColorArgs a) {
+  constexpr int M = Cfg<P>::M;
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const int tid = threadIdx.x;
+  const int count = *a.count;
+  for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
+    if (tid < M) {
+      const int idx = tile * M + tid;
+      float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+      int lt = 0, r = -1;
+      if (idx < count) {
+        r = a.list[idx];
+        const ImgDesc& im = a.imgs[a.pool.img[r]];
+        const float4 d = a.pool.d[r];
+        const float dd = d.w + a.pool.flast[r];          // Eq. 1 ray distance
+        p = make_float4(fmaf(dd, d.x, im.c[0]), fmaf(dd, d.y, im.c[1]), fmaf(dd, d.z, im.c[2]), 0.f);
+        lt = im.latent;
+      }
+      s.pts[tid] = p;
+      s.lat[tid] = lt;
+      s.rid[tid] = r;
+    }
+    __syncthreads();
+    const int wn = mlp_forward<P, kFwdWaves<P>, M, false, false, 3>(a.net, a.bias0_lat, a.biasS_lat, s, tid,
+                                                                      MaskRef{});
+    if (tid < M && s.rid[tid] >= 0) {
+      const int r = s.rid[tid];
+      const ImgDesc& im = a.imgs[a.pool.img[r]];
+      const size_t q = (size_t)im.out_base + (size_t)(r - im.slot_base - im.lvl_off[0]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float m = a.net.blast_c[c];
+        for (int w = 0; w < wn; ++w) m += s.part[(c * 8 + w) * M + tid];
+        a.rgb[3 * q + c] = 0.5f * (1.f + tanhf(m));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Backward of the colour: recompute at the (detached) hit points with masks in
+// per-workgroup scratch, seed the last hidden layer with
+// sum_c g_c 0.5 (1 - tanh^2 m_c) w_last[c] on its active units, and run the
+// VJP with unit row weights; the column sums at layer 0 and the skip layer
+// give dL/dz per latent as for the signed distance.
+template <int P>
+__global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_color_adjoint(AdjArgs a) {
+  constexpr int M = Cfg<P>::M;
+  constexpr int NT = kBwdWaves * 64;
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const NetDev& net = a.net;
+  const int tid = threadIdx.x;
+  const int count = *a.n_samples;
+  const int ntmax = net.kmax / 32;
+  const MaskRef mk{a.mask_ws + (size_t)blockIdx.x * (size_t)(net.nl) * M * ntmax, ntmax, M * ntmax, false};
+  const int ll = net.nl - 2, W = net.wpad[ll], q4 = W / 4;
+  for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
+    if (tid < M) {
+      const float4 smp = a.samples[tile * M + tid];
+      s.pts[tid] = make_float4(smp.x, smp.y, smp.z, 0.f);
+      s.lat[tid] = a.sample_lat[tile * M + tid];
+    }
+    __syncthreads();
+    const int wn = mlp_forward<P, kBwdWaves, M, true, false, 3>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
+    if (tid < M) {
+      const float4 g = a.cseed[tile * M + tid];
+      const float gc[3] = {g.x, g.y, g.z};
+      float ac[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float m = net.blast_c[c];
+        for (int w = 0; w < wn; ++w) m += s.part[(c * 8 + w) * M + tid];
+        const float th = tanhf(m);
+        ac[c] = gc[c] * 0.5f * (1.f - th * th);
+      }
+      // this row's partial-sum slots are read: they now keep its channel factors
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s.part[c * 8 * M + tid] = ac[c];
+      s.gm[tid] = 1.f;
+    }
+    __syncthreads();
+    for (int i = tid; i < M * q4; i += NT) {
+      const int m = i / q4, n = 4 * (i - m * q4);
+      const unsigned word = mk.p[mask_at(mk, m, ll, n >> 5)] >> (n & 31);
+      const float a0 = s.part[m], a1 = s.part[8 * M + m], a2 = s.part[16 * M + m];
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float d = fmaf(a0, net.wlast[n + e], fmaf(a1, net.wlast[W + n + e], a2 * net.wlast[2 * W + n + e]));
+        v[e] = ((word >> e) & 1u) ? d : 0.f;
+      }
+      store4<P>(s, m, n, (n >> 2) & 1, v, true);
+    }
+    __syncthreads();
+    vjp_layers<P, kBwdWaves, false, false>(a, s, mk, a.partial + (size_t)tile * 4 * net.kmax, 0, 0, tile);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient of one layer from captured rows (fixed summation order):
 //   gW[n][k] += sum_r Delta_l[r][n] * in_l(r, k),  gb[n] += sum_r Delta_l[r][n]
 // in_l is [z, p] for layer 0, [h, z, p] for the skip layer, h_{l-1} otherwise;
@@ -1290,7 +1409,7 @@ void launch_dw(const DwArgs& a, hipStream_t st) {
 int mlp_tile_rows(int precision) { return rows_for(precision); }
 
 int adj_tile_rows(int precision) { return mlp_tile_rows(precision); }
-size_t mlp_smem_bytes(int precision, const NetDev& net) { return smem_bytes_for(precision, net.kmax); }
+size_t mlp_smem_bytes(int precision, const NetDev& net) { return smem_bytes_for(precision, net.kmax, net.nout); }
 size_t adj_mask_words(int precision, const NetDev& net) {
   return (size_t)net.nl * mlp_tile_rows(precision) * (net.kmax / 32);
 }
@@ -1309,6 +1428,15 @@ static hipError_t setup_p(int bytes) {
 
 hipError_t mlp_setup(int precision, const NetDev& net) {
   const int bytes = (int)mlp_smem_bytes(precision, net);
+  if (net.nout == 3) {                     // a colour network: its own kernels only
+    if (precision == 1)
+      return hipFuncSetAttribute((const void*)k_color<1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (precision == 2)
+      return hipFuncSetAttribute((const void*)k_color_adjoint<2>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_color<0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_color_adjoint<0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  }
   if (precision == 1) return setup_p<1>(bytes);
   if (precision == 2) return setup_p<2>(bytes);
   return setup_p<0>(bytes);
@@ -1333,6 +1461,16 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
   } while (0)
 
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_march, a); }
+void launch_color(int precision, const ColorArgs& a, int grid, hipStream_t st) {
+  const size_t sm = mlp_smem_bytes(precision, a.net);
+  if (precision == 1) hipLaunchKernelGGL(k_color<1>, dim3(grid), dim3(kFwdWaves<1> * 64), sm, st, a);
+  else if (precision == 0) hipLaunchKernelGGL(k_color<0>, dim3(grid), dim3(kFwdWaves<0> * 64), sm, st, a);
+}
+void launch_color_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) {
+  const size_t sm = mlp_smem_bytes(precision, a.net);
+  if (precision == 2) hipLaunchKernelGGL(k_color_adjoint<2>, dim3(grid), dim3(kBwdWaves * 64), sm, st, a);
+  else if (precision == 0) hipLaunchKernelGGL(k_color_adjoint<0>, dim3(grid), dim3(kBwdWaves * 64), sm, st, a);
+}
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_eval, a); }
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH_BWD(k_adjoint, a); }
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t st) {

@@ -93,6 +93,12 @@ void launch_ul_lambda(const RayPool& pl, const float4* samples, const int4* samp
                       const int* n_samples, int max_samples, float* lam, hipStream_t s);
 void launch_ul_split(const RayPool& pl, const ImgDesc* imgs, const int* img_order, int n_img, int max_parents,
                      int plvl, float* lam, hipStream_t s);
+void launch_color_hits(const RayPool& pl, const ImgDesc* imgs, int n_img, int hw, int* list, int* counter,
+                       hipStream_t s);
+void launch_color_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent,
+                          int n_img, int hw, int n_lat, int tile, const float* g_rgb, int* bsum, int* boff,
+                          int* seg_base, int* seg_total, int* seg_padded, int* n_samples, float4* samples,
+                          float4* cseed, int* sample_lat, long long cap, hipStream_t s);
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s);
 void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
                     int* out_count, const AdvEntry* table, const int* hdr, int* img_active,

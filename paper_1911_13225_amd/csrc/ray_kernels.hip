@@ -874,6 +874,61 @@ __global__ __launch_bounds__(256) void k_ul_init(RayPool pl, const ImgDesc* imgs
   lam[r] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Colour at the hits: the list of hit rays, and the backward's samples (one
+// per hit with a nonzero colour gradient: its Eq. 1 point and the gradient).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_color_hits(RayPool pl, const ImgDesc* imgs, int* list, int* counter) {
+  const ImgDesc& im = imgs[blockIdx.y];
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  const int r = im.slot_base + im.lvl_off[0] + pix;
+  const bool hit = pix < im.H * im.W && pl.st[r] == ST_HIT;
+  block_append(hit, r, list, counter);
+}
+
+__device__ __forceinline__ bool color_sample(const RayPool& pl, const ImgDesc& im, int pix, const float* g) {
+  if (pix >= im.H * im.W || pl.st[im.slot_base + im.lvl_off[0] + pix] != ST_HIT) return false;
+  const float* gq = g + 3 * ((size_t)im.out_base + pix);
+  return gq[0] != 0.f || gq[1] != 0.f || gq[2] != 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_color_count(RayPool pl, const ImgDesc* imgs, const int* img_order,
+                                                     const float* g_rgb, int* bsum) {
+  __shared__ int red[256];
+  const ImgDesc& im = imgs[img_order[blockIdx.y]];
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  red[threadIdx.x] = color_sample(pl, im, pix, g_rgb) ? 1 : 0;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_color_write(RayPool pl, const ImgDesc* imgs, const int* img_order,
+                                                     const float* g_rgb, const int* boff, float4* samples,
+                                                     float4* cseed, int* sample_lat) {
+  __shared__ int buf[256];
+  const ImgDesc& im = imgs[img_order[blockIdx.y]];
+  const int pix = blockIdx.x * 256 + threadIdx.x;
+  const bool take = color_sample(pl, im, pix, g_rgb);
+  const int o = boff[blockIdx.y * gridDim.x + blockIdx.x] + block_excl_scan(take ? 1 : 0, buf);
+  if (!take) return;
+  const int r = im.slot_base + im.lvl_off[0] + pix;
+  const float4 d = pl.d[r];
+  const float dd = d.w + pl.flast[r];                   // Eq. 1 ray distance
+  const float* gq = g_rgb + 3 * ((size_t)im.out_base + pix);
+  samples[o] = make_float4(fmaf(dd, d.x, im.c[0]), fmaf(dd, d.y, im.c[1]), fmaf(dd, d.z, im.c[2]), 0.f);
+  cseed[o] = make_float4(gq[0], gq[1], gq[2], 0.f);
+  sample_lat[o] = im.latent;
+}
+
+__global__ void k_fill_f4(float4* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_rays, int* list,
@@ -1021,6 +1076,24 @@ void launch_ul_split(const RayPool& pl, const ImgDesc* imgs, const int* img_orde
                      int plvl, float* lam, hipStream_t s) {
   hipLaunchKernelGGL(k_ul_split, dim3(nblk(max_parents, 256), n_img), dim3(256), 0, s, pl, imgs, img_order, plvl,
                      lam);
+}
+void launch_color_hits(const RayPool& pl, const ImgDesc* imgs, int n_img, int hw, int* list, int* counter,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_color_hits, dim3(nblk(hw, 256), n_img), dim3(256), 0, s, pl, imgs, list, counter);
+}
+void launch_color_samples(const RayPool& pl, const ImgDesc* imgs, const int* img_order, const int* img_latent,
+                          int n_img, int hw, int n_lat, int tile, const float* g_rgb, int* bsum, int* boff,
+                          int* seg_base, int* seg_total, int* seg_padded, int* n_samples, float4* samples,
+                          float4* cseed, int* sample_lat, long long cap, hipStream_t s) {
+  const int bpi = (int)nblk(hw, 256);
+  hipLaunchKernelGGL(k_fill_f4, dim3(256), dim3(256), 0, s, cseed, cap);
+  hipLaunchKernelGGL(k_color_count, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, g_rgb, bsum);
+  hipLaunchKernelGGL(k_samples_scan, dim3(1), dim3(1024), 0, s, bsum, n_img, bpi, img_order, img_latent, 0, tile,
+                     n_lat, boff, seg_base, seg_total, seg_padded, nullptr, n_samples);
+  hipLaunchKernelGGL(k_color_write, dim3(bpi, n_img), dim3(256), 0, s, pl, imgs, img_order, g_rgb, boff, samples,
+                     cseed, sample_lat);
+  hipLaunchKernelGGL(k_samples_pad, dim3(n_lat), dim3(256), 0, s, seg_base, seg_total, seg_padded, samples,
+                     sample_lat, nullptr, nullptr);
 }
 void launch_fill_i32(int* p, int v, int n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, s, p, v, n);

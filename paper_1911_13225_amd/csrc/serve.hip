@@ -640,6 +640,7 @@ static Server* get_server(dist_ctx* ctx, int* rc) {
 
 extern "C" int dist_submit(dist_ctx* ctx, const dist_request* req, uint64_t* ticket) {
   if (!ctx || !req || !ticket) return dist_set_error(DIST_EINVAL, "null argument");
+  if (ctx->n_out != 1) return dist_set_error(DIST_EINVAL, "a colour network does not render geometry");
   if (req->kind != DIST_REQ_RENDER && req->kind != DIST_REQ_ZOPT) return dist_set_error(DIST_EINVAL, "bad kind");
   if (req->n_views < 1 || req->n_views > 64 || !req->cams) return dist_set_error(DIST_EINVAL, "n_views in [1, 64]");
   if (!req->z) return dist_set_error(DIST_EINVAL, "null latent code");
