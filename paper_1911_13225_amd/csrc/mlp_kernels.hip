@@ -290,6 +290,9 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
           if constexpr (X3) pl.b[nb][i] = *(const bf16x8*)(arow[i] + (((c + 1) ^ sw[i]) << 4));
         }
       }
+      // the next step's LDS reads go out before this step's MFMAs (left to
+      // itself the scheduler sinks them below, exposing their latency)
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < MTW; ++i)
 #pragma unroll
