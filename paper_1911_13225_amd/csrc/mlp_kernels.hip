@@ -164,11 +164,14 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
 // Wave-level GEMM: acc[i][j] (m-tile mt0+i, n-tile nt0+j) += sum_k A[n][k] B[k][m]
 // ---------------------------------------------------------------------------
 // The k loop is software pipelined: weight fragments (from L2) are requested
-// kDepth k-steps before use in rotating register sets, and the activation
-// fragments of the next k-step (from LDS) are requested one step ahead, so the
-// MFMA pipe never waits on a single load round trip.  ksteps must be a
-// multiple of kDepth (the padded widths are multiples of 128).
-constexpr int kDepth = 4;
+// D k-steps before use in a ring of D register sets, and the activation
+// fragments of the next k-step (from LDS) are requested one step ahead (a
+// double buffer, so the loop is unrolled by U = max(D, 2) steps).  Measured
+// per use: four steps ahead for the bf16 forward (the march), two for the
+// bf16 VJP, split bf16 and float32 (1-2% either way: fewer loads in flight
+// queue less in the texture units that carry them, too few expose the round
+// trip).  ksteps must be a multiple of U (the padded widths are multiples of
+// 128).
 
 // Weight fragments are read with raw buffer loads: a scalar resource for the
 // layer's packed array (its byte size bounds every load), the lane's 16-byte
@@ -183,13 +186,13 @@ __device__ __forceinline__ T ld_frag(__amdgpu_buffer_rsrc_t r, int voff, int sof
   return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
-template <class Frag, int MTW, int NTW>
+template <class Frag, int MTW, int NTW, int D>
 struct Pipe {
-  Frag a[kDepth][NTW];
+  Frag a[D][NTW];
   Frag b[2][MTW];
 };
 
-template <int MTW, int NTW>
+template <int MTW, int NTW, int D = 2>
 __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& s, const bf16x8* __restrict__ wp,
                                           int ksteps, int nt0, int mt0, int lane, int nbytes) {
   const int r = lane & 31, g = lane >> 5;
@@ -206,19 +209,20 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
     arow[i] = s.act + (size_t)m * s.rowb;
     sw[i] = m & 15;
   }
-  Pipe<bf16x8, MTW, NTW> p;
+  Pipe<bf16x8, MTW, NTW, D> p;
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d) {
+  for (int d = 0; d < D; ++d) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + d * 1024);
     __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
   }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const bf16x8*)(arow[i] + (((g) ^ sw[i]) << 4));
-  for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
+  constexpr int U = D < 2 ? 2 : D;
+  for (int k0 = 0; k0 < ksteps; k0 += U) {
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
-      const int ks = k0 + d;
+    for (int d = 0; d < U; ++d) {
+      const int ks = k0 + d, sl = d % D;
       const int cb = d & 1, nb = cb ^ 1;
       {
         const int kn = min(ks + 1, ksteps - 1);     // unconditional (the last one is redundant)
@@ -230,11 +234,11 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
       for (int i = 0; i < MTW; ++i)
 #pragma unroll
         for (int j = 0; j < NTW; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p.a[d][j], p.b[cb][i], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p.a[sl][j], p.b[cb][i], acc[i][j], 0, 0, 0);
       {
-        const int kn = min(ks + kDepth, ksteps - 1);
+        const int kn = min(ks + D, ksteps - 1);
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
+        for (int j = 0; j < NTW; ++j) p.a[sl][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
@@ -243,7 +247,7 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
 
 // Split precision: with X3 the product is hi*hi + lo*hi + hi*lo (A = weights,
 // B = activations); without X3 only the hi planes are used (bf16 product).
-template <int MTW, int NTW, bool X3>
+template <int MTW, int NTW, bool X3, int D = 2>
 __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>& s, const bf16x8* __restrict__ wp,
                                            const bf16x8* __restrict__ wlo, int ksteps, int nt0, int mt0, int lane,
                                            int nbytes) {
@@ -262,9 +266,9 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
     arow[i] = s.act + (size_t)m * s.rowb;
     sw[i] = m & 15;
   }
-  Pipe<bf16x8, MTW, NTW> ph, pl;
+  Pipe<bf16x8, MTW, NTW, D> ph, pl;
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d) {
+  for (int d = 0; d < D; ++d) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
       ph.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + d * 1024);
@@ -277,10 +281,11 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
     ph.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g) ^ sw[i]) << 4));
     if constexpr (X3) pl.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g + 1) ^ sw[i]) << 4));
   }
-  for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
+  constexpr int U = D < 2 ? 2 : D;
+  for (int k0 = 0; k0 < ksteps; k0 += U) {
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
-      const int ks = k0 + d;
+    for (int d = 0; d < U; ++d) {
+      const int ks = k0 + d, sl = d % D;
       const int cb = d & 1, nb = cb ^ 1;
       {
         const int c = 2 * (2 * min(ks + 1, ksteps - 1) + g);
@@ -297,18 +302,18 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
       for (int i = 0; i < MTW; ++i)
 #pragma unroll
         for (int j = 0; j < NTW; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[d][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[sl][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
           if constexpr (X3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl.a[d][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[d][j], pl.b[cb][i], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl.a[sl][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[sl][j], pl.b[cb][i], acc[i][j], 0, 0, 0);
           }
         }
       {
-        const int kn = min(ks + kDepth, ksteps - 1);
+        const int kn = min(ks + D, ksteps - 1);
 #pragma unroll
         for (int j = 0; j < NTW; ++j) {
-          ph.a[d][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
-          if constexpr (X3) pl.a[d][j] = ld_frag<bf16x8>(rl, voff, wrow[j] + kn * 1024);
+          ph.a[sl][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
+          if constexpr (X3) pl.a[sl][j] = ld_frag<bf16x8>(rl, voff, wrow[j] + kn * 1024);
         }
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
@@ -316,7 +321,7 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
   }
 }
 
-template <int MTW, int NTW>
+template <int MTW, int NTW, int D = 2>
 __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s, const f32x4* __restrict__ wp,
                                          int ksteps, int nt0, int mt0, int lane, int nbytes) {
   const int r = lane & 31, g = lane >> 5;
@@ -333,19 +338,20 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
     arow[i] = s.act + (size_t)m * s.rowb;
     sw[i] = m & 15;
   }
-  Pipe<f32x4, MTW, NTW> p;
+  Pipe<f32x4, MTW, NTW, D> p;
 #pragma unroll
-  for (int d = 0; d < kDepth; ++d) {
+  for (int d = 0; d < D; ++d) {
 #pragma unroll
     for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<f32x4>(rs, voff, wrow[j] + d * 1024);
     __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
   }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const f32x4*)(arow[i] + (((g) ^ sw[i]) << 4));
-  for (int k0 = 0; k0 < ksteps; k0 += kDepth) {
+  constexpr int U = D < 2 ? 2 : D;
+  for (int k0 = 0; k0 < ksteps; k0 += U) {
 #pragma unroll
-    for (int d = 0; d < kDepth; ++d) {
-      const int ks = k0 + d;
+    for (int d = 0; d < U; ++d) {
+      const int ks = k0 + d, sl = d % D;
       const int cb = d & 1, nb = cb ^ 1;
       {
         const int kn = min(ks + 1, ksteps - 1);
@@ -359,11 +365,11 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
         for (int i = 0; i < MTW; ++i)
 #pragma unroll
           for (int j = 0; j < NTW; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(p.a[d][j][sidx], p.b[cb][i][sidx], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(p.a[sl][j][sidx], p.b[cb][i][sidx], acc[i][j], 0, 0, 0);
       {
-        const int kn = min(ks + kDepth, ksteps - 1);
+        const int kn = min(ks + D, ksteps - 1);
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) p.a[d][j] = ld_frag<f32x4>(rs, voff, wrow[j] + kn * 1024);
+        for (int j = 0; j < NTW; ++j) p.a[sl][j] = ld_frag<f32x4>(rs, voff, wrow[j] + kn * 1024);
       }
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
@@ -834,7 +840,7 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   else if constexpr (SKIP) acc_bias<P, MTW, NTW, true>(acc, ec, s, nt0, mt0, lane);
   else acc_mfma_start<P, MTW, NTW>(acc, net.bfrag[ec.layer], nt0, lane);
   if constexpr (P == 1) {
-    gemm_bf16<MTW, NTW>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane, nbytes);
+    gemm_bf16<MTW, NTW, VJP ? 2 : 4>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane, nbytes);
   } else if constexpr (P == 2) {
     gemm_split<MTW, NTW, !VJP>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane,
                                          nbytes);
