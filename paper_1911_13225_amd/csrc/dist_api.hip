@@ -871,11 +871,19 @@ static int adj_prec(int render_prec) { return render_prec == DIST_FP32 ? kPrecF3
 // kernel's VJP, which uses only the hi parts).
 static int vjp_prec(int adj) { return adj == kPrecSplit ? kPrecBF16 : adj; }
 
+// Row groups of the column sums S0 and Sskip written by a VJP kernel of `waves` waves.
+static int groups_s0(dist_ctx* ctx, int waves) { return mlp_row_groups(waves, ctx->wpad[0]); }
+static int groups_skip(dist_ctx* ctx, int waves) {
+  return ctx->skip >= 0 ? mlp_row_groups(waves, ctx->wpad[ctx->skip]) : 1;
+}
+
 static int reduce_only(dist_ctx* ctx, BwdSpace* b, int n_lat, float* g_z, hipStream_t st) {
   const int w0 = ctx->wpad[0];
   const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
+  const int aw = adjoint_waves();
   launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg_base, b->seg_padded, n_lat,
-                   w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
+                   w0, groups_s0(ctx, aw), ctx->w0z, ws, groups_skip(ctx, aw), ctx->skip >= 0 ? ctx->wsz : nullptr,
+                   ctx->L, g_z, st);
   HIPCHK(hipGetLastError());
   return DIST_OK;
 }
@@ -914,12 +922,16 @@ static int run_adjoint_and_reduce(dist_ctx* ctx, Workspace* w, BwdSpace* b, int 
   const int w0 = ctx->wpad[0];
   const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
   // every wave covers all rows of a tile, so each column sum has one row group
+  const int aw = adjoint_waves();
   launch_gz_reduce(b->partial, ctx->kmax, b->tile, b->cap_samples / b->tile + 1, b->seg_base, b->seg_padded, n_lat,
-                   w0, 1, ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st);
+                   w0, groups_s0(ctx, aw), ctx->w0z, ws, groups_skip(ctx, aw), ctx->skip >= 0 ? ctx->wsz : nullptr,
+                   ctx->L, g_z, st);
   if (split) {
     const int vt = adj_tile_rows(vjp_prec(prec));
-    launch_gz_reduce(b->partial2, ctx->kmax, vt, b->cap_samples / vt + 1, b->seg2_base, b->seg2_padded, n_lat, w0, 1,
-                     ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st, 0, 1);
+    const int vw = vjp_saved_waves(vjp_prec(prec));
+    launch_gz_reduce(b->partial2, ctx->kmax, vt, b->cap_samples / vt + 1, b->seg2_base, b->seg2_padded, n_lat, w0,
+                     groups_s0(ctx, vw), ctx->w0z, ws, groups_skip(ctx, vw), ctx->skip >= 0 ? ctx->wsz : nullptr,
+                     ctx->L, g_z, st, 0, 1);
   }
   HIPCHK(hipGetLastError());
   return DIST_OK;
@@ -1021,7 +1033,7 @@ static int cs_get(dist_ctx* ctx, Workspace* w, long long cap_samples, long long 
   c->cap_samples = cap_samples;
   c->cap_pix = cap_pix;
   const size_t a = ((size_t)cap_samples * sizeof(int4) + 255) & ~(size_t)255;
-  const size_t g = ((size_t)cap_samples * 12 * sizeof(float) + 255) & ~(size_t)255;
+  const size_t g = ((size_t)cap_samples * 3 * kGpSlots * sizeof(float) + 255) & ~(size_t)255;
   c->bytes = a + g + (size_t)cap_pix * sizeof(float) + 256;
   int rc = ctx_alloc(ctx, (void**)&c->mem, c->bytes);
   if (rc != DIST_OK) { delete c; return rc; }
@@ -1231,8 +1243,9 @@ extern "C" int dist_render_bwd_unrolled(dist_ctx* ctx, const dist_saved* saved, 
       TimedLaunch tl(ctx, 2, st, b->n_samples, 1);
       launch_adjoint(prec, aa, grid, st);
     }
-    launch_gz_reduce(b->partial, ctx->kmax, tile, (int)(cap / tile) + 1, b->seg_base, b->seg_padded, n_lat, w0, 1,
-                     ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st, 0, 1);
+    launch_gz_reduce(b->partial, ctx->kmax, tile, (int)(cap / tile) + 1, b->seg_base, b->seg_padded, n_lat, w0,
+                     groups_s0(ctx, adjoint_waves()), ctx->w0z, ws, groups_skip(ctx, adjoint_waves()),
+                     ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, g_z, st, 0, 1);
     launch_ul_lambda(w->pool, b->samples, w->cs->sample_cam, w->cs->gp, b->n_samples, (int)cap, u->lam, st);
   }
   HIPCHK(hipGetLastError());
@@ -1374,6 +1387,7 @@ extern "C" int dist_render_color_bwd(dist_ctx* cctx, const dist_saved* geom, con
   launch_color_adjoint(prec, aa, grid, st);
   const int w0 = cctx->wpad[0];
   const int ws = cctx->skip >= 0 ? cctx->wpad[cctx->skip] : 0;
+  // the colour adjoint runs 4 waves: one row group per column sum
   launch_gz_reduce(b->partial, cctx->kmax, tile, (int)(cap / tile) + 1, b->seg_base, b->seg_padded, n_latents, w0, 1,
                    cctx->w0z, ws, 1, cctx->skip >= 0 ? cctx->wsz : nullptr, cctx->L, g_zc, st);
   HIPCHK(hipGetLastError());

@@ -146,7 +146,8 @@ struct AdjArgs {
   const float* sdtanh;
   // camera gradient (optional): per sample and wave, gm * (W0_p^T delta0 +
   // Wskip_p^T delta_skip) partial sums over that wave's features,
-  // [sample][4][3] (the spatial gradient of m, weighted by the row's factor)
+  // [sample][kGpSlots][3] (the spatial gradient of m, weighted by the row's
+  // factor; slots beyond a layer's wave count hold zeros)
   float* gp_part;
   // colour network (k_color_adjoint): per sample dL/d(colour), (r, g, b, 0)
   const float4* cseed;
@@ -155,6 +156,7 @@ struct AdjArgs {
 // Precision codes of the decoder kernels: 0 float32, 1 bfloat16, 2 split
 // bfloat16 (x = hi + lo, products hi*hi + lo*hi + hi*lo, float32 accumulation).
 constexpr int kPrecF32 = 0, kPrecBF16 = 1, kPrecSplit = 2;
+constexpr int kGpSlots = 8;          // point-gradient partial slots per sample (one per wave)
 
 struct DwArgs {
   int layer, nl, skip, L, nh, kmax, rstride, rows, out, in;
@@ -180,6 +182,12 @@ void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t s);
 // recompute-and-VJP: precision kPrecSplit or kPrecF32 (no bf16 variant; other
 // values launch nothing); VJP from saved masks: any precision
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t s);
+// A layer of padded output width `width` run by `waves` waves splits its rows
+// into this many groups, each writing its own column sums (the count the
+// reduction of dL/dz must add): 2 for 8 waves on a 128-wide layer, else 1.
+int mlp_row_groups(int waves, int width);
+int adjoint_waves();                       // recompute-and-VJP kernel
+int vjp_saved_waves(int precision);        // VJP from saved masks
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t s);
 // colour network: forward at hits (precision kPrecF32 or kPrecBF16) and
 // recompute + VJP with per-sample colour seeds (kPrecF32 or kPrecSplit)

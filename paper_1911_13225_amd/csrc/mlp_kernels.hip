@@ -49,6 +49,9 @@ template <> struct Cfg<2> {           // split bf16: x = hi + lo; hi*hi + lo*hi 
 // one per SIMD with 512 registers (accumulators in AGPRs).
 template <int P> constexpr int kFwdWaves = P == 0 ? 4 : 8;
 constexpr int kBwdWaves = 4;
+// The recompute-and-VJP kernel fits two waves per SIMD (256 registers each):
+// 8 waves, as the forward.
+constexpr int kAdjWaves = 8;
 // The VJP from saved masks needs no recompute: its bf16 variant takes the
 // forward's 128-row, 8-wave layout (the split and float32 ones keep 4 waves).
 template <int P> constexpr int kVjpWaves = P == 1 ? 8 : 4;
@@ -416,7 +419,7 @@ struct EpCtx {
   float* hrow;              // weight-gradient capture: h of this layer, row stride rstride (or null)
   float* drow;              // weight-gradient capture: Delta of this layer (or null)
   int rstride;
-  float* gp;                // camera gradient: per-row point-gradient partials [row][4][3] (or null)
+  float* gp;                // camera gradient: per-row point-gradient partials [row][kGpSlots][3] (or null)
   int gp_row0;              // global row index of the tile's first row
   bool gp_accum;            // add to the partials (the skip layer wrote them first)
 };
@@ -670,7 +673,7 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
 // VJP through one layer: acc = W^T delta for the output of layer ec.layer;
 // apply that layer's ReLU mask (recomputed in float32 for layer 0, whose
 // pre-activation is the same expression layer0_fill evaluates).
-template <int P, int MTW, int NTW, bool L0, bool CAP, bool GP>
+template <int P, int MTW, int NTW, int WN, bool L0, bool CAP, bool GP>
 __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
                                        int nt0, int mt0, int mg, int nw, int lane, const unsigned (&mb)[MTW][NTW]) {
   const int r = lane & 31, g = lane >> 5;
@@ -759,7 +762,7 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
       if (g == 0) {
         const int m = (mt0 + i) * 32 + r;
         const float w = s.gm[m];
-        float* dst = ec.gp + ((size_t)(ec.gp_row0 + m) * 4 + nw) * 3;
+        float* dst = ec.gp + ((size_t)(ec.gp_row0 + m) * kGpSlots + nw) * 3;
         if (ec.gp_accum) {
           dst[0] += w * x;
           dst[1] += w * y;
@@ -768,6 +771,13 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
           dst[0] = w * x;
           dst[1] = w * y;
           dst[2] = w * z;
+          // slots of waves this layer does not have start at zero
+#pragma unroll
+          for (int k = WN; k < kGpSlots; k += WN) {
+            dst[3 * k] = 0.f;
+            dst[3 * k + 1] = 0.f;
+            dst[3 * k + 2] = 0.f;
+          }
         }
       }
     }
@@ -855,8 +865,8 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   if constexpr (VJP) {
     constexpr bool GP = MODE == EP_VJP;
     if constexpr (!EARLY) load_masks();
-    if (ec.layer == 0) ep_vjp<P, MTW, NTW, true, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
-    else ep_vjp<P, MTW, NTW, false, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
+    if (ec.layer == 0) ep_vjp<P, MTW, NTW, WN, true, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
+    else ep_vjp<P, MTW, NTW, WN, false, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
   }
   __syncthreads();
 }
@@ -1163,7 +1173,7 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
 // and at the skip layer (Sskip); dL/dz = W0_z^T S0 + Wskip_z^T Sskip.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adjoint(AdjArgs a) {
   constexpr int M = Cfg<P>::M;
   Sm<P> s(dyn_smem, a.net.kmax);
   const NetDev& net = a.net;
@@ -1185,8 +1195,8 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
       s.lat[tid] = a.sample_lat[idx];
     }
     __syncthreads();
-    const int wn = theta ? mlp_forward<P, kBwdWaves, Cfg<P>::M, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
-                         : mlp_forward<P, kBwdWaves, Cfg<P>::M, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
+    const int wn = theta ? mlp_forward<P, kAdjWaves, Cfg<P>::M, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
+                         : mlp_forward<P, kAdjWaves, Cfg<P>::M, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
     if (tid < M) {
       float m = net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
@@ -1198,15 +1208,15 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
     if (theta) {
       // Delta of the last hidden layer: gm * w_last * [h > 0]
       const int ll = net.nl - 2, W = net.wpad[ll];
-      for (int i = tid; i < M * W; i += kBwdWaves * 64) {
+      for (int i = tid; i < M * W; i += kAdjWaves * 64) {
         const int m = i / W, n = i - m * W;
         const size_t o = (row0 + m) * rstride + (size_t)ll * net.kmax + n;
         a.dbuf[o] = a.hbuf[o] > 0.f ? s.gm[m] * net.wlast[n] : 0.f;
       }
     }
     float* part = a.partial + (size_t)tile * 4 * net.kmax;
-    if (theta) vjp_layers<P, kBwdWaves, true>(a, s, mk, part, row0, rstride, tile);
-    else vjp_layers<P, kBwdWaves, false>(a, s, mk, part, 0, 0, tile);
+    if (theta) vjp_layers<P, kAdjWaves, true>(a, s, mk, part, row0, rstride, tile);
+    else vjp_layers<P, kAdjWaves, false>(a, s, mk, part, 0, 0, tile);
   }
 }
 
@@ -1464,7 +1474,7 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
 #define DIST_DISPATCH_BWD(KERNEL, ARGS)                                                                \
   do {                                                                                                 \
     const size_t sm = mlp_smem_bytes(precision, ARGS.net);                                             \
-    const dim3 blk(kBwdWaves * 64);                                                                    \
+    const dim3 blk(kAdjWaves * 64);                                                                    \
     if (precision == 2) hipLaunchKernelGGL(KERNEL<2>, dim3(grid), blk, sm, st, ARGS);                  \
     else if (precision == 0) hipLaunchKernelGGL(KERNEL<0>, dim3(grid), blk, sm, st, ARGS);             \
   } while (0)
@@ -1482,6 +1492,10 @@ void launch_color_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t
 }
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_eval, a); }
 void launch_adjoint(int precision, const AdjArgs& a, int grid, hipStream_t st) { DIST_DISPATCH_BWD(k_adjoint, a); }
+static_assert(kAdjWaves * 64 == 512, "the recompute-and-VJP dispatch assumes 8 waves");
+int mlp_row_groups(int waves, int width) { return (waves == 8 && width <= 128) ? 2 : 1; }
+int adjoint_waves() { return kAdjWaves; }
+int vjp_saved_waves(int precision) { return precision == 1 ? kVjpWaves<1> : kVjpWaves<0>; }
 void launch_vjp_saved(int precision, const AdjArgs& a, int grid, hipStream_t st) {
   const size_t sm = mlp_smem_bytes(precision, a.net);
   if (precision == 1) hipLaunchKernelGGL(k_vjp_saved<1>, dim3(grid), dim3(kVjpWaves<1> * 64), sm, st, a);

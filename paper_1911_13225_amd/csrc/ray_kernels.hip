@@ -482,8 +482,8 @@ __global__ __launch_bounds__(256) void k_cam_reduce(RayPool pl, const ImgDesc* i
     const float rn = sqrtf(smp.x * smp.x + smp.y * smp.y + smp.z * smp.z);
     const float h = rn > 0.f ? 0.5f * smp.w / rn : 0.f;
     float g[3] = {h * smp.x, h * smp.y, h * smp.z};
-    const float* pp = gp_part + (size_t)i * 12;
-    for (int w = 0; w < 4; ++w) {
+    const float* pp = gp_part + (size_t)i * 3 * kGpSlots;
+    for (int w = 0; w < kGpSlots; ++w) {
       g[0] += pp[3 * w];
       g[1] += pp[3 * w + 1];
       g[2] += pp[3 * w + 2];
@@ -817,8 +817,8 @@ __global__ void k_ul_lambda(RayPool pl, const float4* samples, const int4* sampl
   const float rn = sqrtf(smp.x * smp.x + smp.y * smp.y + smp.z * smp.z);
   const float h = rn > 0.f ? 0.5f * smp.w / rn : 0.f;
   float g[3] = {h * smp.x, h * smp.y, h * smp.z};
-  const float* pp = gp_part + (size_t)i * 12;
-  for (int w = 0; w < 4; ++w) {
+  const float* pp = gp_part + (size_t)i * 3 * kGpSlots;
+  for (int w = 0; w < kGpSlots; ++w) {
     g[0] += pp[3 * w];
     g[1] += pp[3 * w + 1];
     g[2] += pp[3 * w + 2];
@@ -995,8 +995,8 @@ __global__ void k_hit_gv(RayPool pl, const ImgDesc* imgs, const float4* samples,
   const float rn = sqrtf(smp.x * smp.x + smp.y * smp.y + smp.z * smp.z);
   const float h = rn > 0.f ? 0.5f * smp.w / rn : 0.f;
   float g[3] = {h * smp.x, h * smp.y, h * smp.z};
-  const float* pp = gp_part + (size_t)i * 12;
-  for (int w = 0; w < 4; ++w) {
+  const float* pp = gp_part + (size_t)i * 3 * kGpSlots;
+  for (int w = 0; w < kGpSlots; ++w) {
     g[0] += pp[3 * w];
     g[1] += pp[3 * w + 1];
     g[2] += pp[3 * w + 2];

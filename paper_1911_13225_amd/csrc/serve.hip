@@ -450,8 +450,10 @@ static void complete_render(Server* s, Request* r) {
   launch_adjoint(kPrecSplit, aa, grid, s->st);
   const int w0 = ctx->wpad[0];
   const int ws = ctx->skip >= 0 ? ctx->wpad[ctx->skip] : 0;
-  launch_gz_reduce(b.partial, ctx->kmax, b.tile, b.cap_samples / b.tile + 1, b.seg_base, b.seg_padded, 1, w0, 1,
-                   ctx->w0z, ws, 1, ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, r->d_gz, s->st, r->lat);
+  const int aw = adjoint_waves();
+  launch_gz_reduce(b.partial, ctx->kmax, b.tile, b.cap_samples / b.tile + 1, b.seg_base, b.seg_padded, 1, w0,
+                   mlp_row_groups(aw, w0), ctx->w0z, ws, ws ? mlp_row_groups(aw, ws) : 1,
+                   ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, r->d_gz, s->st, r->lat);
   const int L = ctx->L;
   launch_adam(s->z_pool + (size_t)r->lat * L, s->adam_m + (size_t)r->lat * L, s->adam_v + (size_t)r->lat * L,
               r->d_gz + (size_t)r->lat * L, L, q.lr, r->iter + 1, s->st);
