@@ -41,19 +41,17 @@ template <> struct Cfg<2> {           // split bf16: x = hi + lo; hi*hi + lo*hi 
   static constexpr int M = 64, MT = 2, ES = 4, EPC = 8;   // a row holds interleaved hi/lo 16-byte chunks
 };
 
-// Waves per workgroup.  The forward kernels of the bf16 formats run 8 waves
-// (two per SIMD, at most 256 registers each): every wave covers all rows for
-// 1/8 of the outputs and the second wave of a SIMD issues while the first
-// waits on memory, a barrier or its epilogue.  The float32 forward and the
-// backward kernels (whose adjoint state needs more registers) run 4 waves,
-// one per SIMD with 512 registers (accumulators in AGPRs).
+// Waves per workgroup.  8 waves run two per SIMD (at most 256 registers
+// each): every wave covers all rows for 1/8 of the outputs (1/4 of a 128-wide
+// layer, in two row groups) and the second wave of a SIMD issues while the
+// first waits on memory, a barrier or its epilogue.  4 waves run one per SIMD
+// with 512 registers (accumulators in AGPRs).  Measured per kernel: the bf16
+// and split forward, the recompute-and-VJP and the bf16 VJP from saved masks
+// (which takes the forward's 128-row layout) run 8; the float32 forward, the
+// split and float32 VJP from saved masks and the colour backward run 4.
 template <int P> constexpr int kFwdWaves = P == 0 ? 4 : 8;
 constexpr int kBwdWaves = 4;
-// The recompute-and-VJP kernel fits two waves per SIMD (256 registers each):
-// 8 waves, as the forward.
 constexpr int kAdjWaves = 8;
-// The VJP from saved masks needs no recompute: its bf16 variant takes the
-// forward's 128-row, 8-wave layout (the split and float32 ones keep 4 waves).
 template <int P> constexpr int kVjpWaves = P == 1 ? 8 : 4;
 
 __host__ __device__ inline int rows_for(int P) { return P == 1 ? Cfg<1>::M : 64; }
