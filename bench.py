@@ -183,6 +183,37 @@ def gradient_variants(w, reps=2):
     return res
 
 
+def color_run(w, reps=3):
+    """The colour network (the geometry layout on 512-wide shape + texture
+    codes, three outputs) at the hits of the benchmark workload's render:
+    time per colour render and per colour backward (bf16)."""
+    import torch
+    import dist_inputs as di
+    from paper_1911_13225_amd import api
+    spec = di.COLOR_SPEC
+    Wc, bc = di.make_decoder(spec, seed=7)
+    cctx = api.Context.from_spec(spec, Wc, bc)
+    zc = torch.tensor(di.make_latents(w["Z"].shape[0], spec.latent_dim, sigma=0.3, base_seed=6000), device="cuda")
+    out = api.dist_render_fwd(w["ctx"], w["cams"], w["Z"], w["prm"], save=True)
+    hits = int((out["status"] == 1).sum())
+    g = torch.randn(out["depth"].shape + (3,), device="cuda", generator=torch.Generator(device="cuda").manual_seed(0))
+    res = {"hits": hits}
+    for name, fn in (("render", lambda: api.dist_render_color(cctx, out["saved"], zc, 1)),
+                     ("backward", lambda: api.dist_render_color_bwd(cctx, out["saved"], zc, g, 1))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        res[name + "_ms"] = round(ms, 3)
+        res[name + "_hit_queries_per_s"] = round(hits / (ms * 1e-3), 1)
+    out["saved"].free()
+    cctx.close()
+    return res
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle on a bounded sample of the benchmark workload."""
     import dist_inputs as di
@@ -460,6 +491,9 @@ def main():
         log("[bench] gradient variants on the same workload")
         res["gradient_variants"] = gradient_variants(w)
         log("[bench] gradient variants", res["gradient_variants"])
+        log("[bench] colour network at the hits of the same workload")
+        res["color"] = color_run(w)
+        log("[bench] colour", res["color"])
     del w
     torch.cuda.empty_cache()
 
