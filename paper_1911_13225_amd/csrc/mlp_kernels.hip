@@ -171,8 +171,9 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
 // per use: four steps ahead for the bf16 forward (the march), two for the
 // bf16 VJP, split bf16 and float32 (1-2% either way: fewer loads in flight
 // queue less in the texture units that carry them, too few expose the round
-// trip).  ksteps must be a multiple of U (the padded widths are multiples of
-// 128).
+// trip).  The last U steps request no weights past the end of the layer.
+// ksteps must be a multiple of U and at least U (the padded widths are
+// multiples of 128).
 
 // Weight fragments are read with raw buffer loads: a scalar resource for the
 // layer's packed array (its byte size bounds every load), the lane's 16-byte
@@ -185,6 +186,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t frag_rsrc(const void* p, int b
 template <class T>
 __device__ __forceinline__ T ld_frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
+// The epilogue reads the accumulators of the last MFMAs right after the
+// GEMM, and a VALU read of a 16-pass MFMA result needs 19 wait states first
+// (the CDNA3/4 dependency table).  The compiler's hazard check was seen to
+// miss one such read (an integer med3 of the accumulator bits, four
+// instructions after the last MFMA), so every GEMM ends with the wait states
+// spelled out.
+__device__ __forceinline__ void mfma_drain() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 template <class Frag, int MTW, int NTW, int D>
@@ -220,30 +233,35 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
 #pragma unroll
   for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const bf16x8*)(arow[i] + (((g) ^ sw[i]) << 4));
   constexpr int U = D < 2 ? 2 : D;
-  for (int k0 = 0; k0 < ksteps; k0 += U) {
+  // one k-step: the next step's activation fragments, this step's MFMAs and,
+  // with pf, the weight fragments D steps ahead
+  auto step = [&](int ks, int d, bool pf) {
+    const int sl = d % D, cb = d & 1, nb = cb ^ 1;
+    {
+      const int kn = min(ks + 1, ksteps - 1);     // unconditional (the last one is redundant)
 #pragma unroll
-    for (int d = 0; d < U; ++d) {
-      const int ks = k0 + d, sl = d % D;
-      const int cb = d & 1, nb = cb ^ 1;
-      {
-        const int kn = min(ks + 1, ksteps - 1);     // unconditional (the last one is redundant)
-#pragma unroll
-        for (int i = 0; i < MTW; ++i)
-          p.b[nb][i] = *(const bf16x8*)(arow[i] + (((2 * kn + g) ^ sw[i]) << 4));
-      }
-#pragma unroll
-      for (int i = 0; i < MTW; ++i)
-#pragma unroll
-        for (int j = 0; j < NTW; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p.a[sl][j], p.b[cb][i], acc[i][j], 0, 0, 0);
-      {
-        const int kn = min(ks + D, ksteps - 1);
-#pragma unroll
-        for (int j = 0; j < NTW; ++j) p.a[sl][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
-      }
-      __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
+      for (int i = 0; i < MTW; ++i) p.b[nb][i] = *(const bf16x8*)(arow[i] + (((2 * kn + g) ^ sw[i]) << 4));
     }
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+      for (int j = 0; j < NTW; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p.a[sl][j], p.b[cb][i], acc[i][j], 0, 0, 0);
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) p.a[sl][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + (ks + D) * 1024);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
+  };
+  // every block but the last prefetches within the layer (ks + D < ksteps);
+  // the last block requests no weights past the end
+  for (int k0 = 0; k0 < ksteps - U; k0 += U) {
+#pragma unroll
+    for (int d = 0; d < U; ++d) step(k0 + d, d, true);
   }
+#pragma unroll
+  for (int d = 0; d < U; ++d) step(ksteps - U + d, d, d + D < U);
+  mfma_drain();
 }
 
 // Split precision: with X3 the product is hi*hi + lo*hi + hi*lo (A = weights,
@@ -283,43 +301,45 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
     if constexpr (X3) pl.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g + 1) ^ sw[i]) << 4));
   }
   constexpr int U = D < 2 ? 2 : D;
-  for (int k0 = 0; k0 < ksteps; k0 += U) {
+  auto step = [&](int ks, int d, bool pf) {
+    const int sl = d % D, cb = d & 1, nb = cb ^ 1;
+    {
+      const int c = 2 * (2 * min(ks + 1, ksteps - 1) + g);
 #pragma unroll
-    for (int d = 0; d < U; ++d) {
-      const int ks = k0 + d, sl = d % D;
-      const int cb = d & 1, nb = cb ^ 1;
-      {
-        const int c = 2 * (2 * min(ks + 1, ksteps - 1) + g);
-#pragma unroll
-        for (int i = 0; i < MTW; ++i) {
-          ph.b[nb][i] = *(const bf16x8*)(arow[i] + ((c ^ sw[i]) << 4));
-          if constexpr (X3) pl.b[nb][i] = *(const bf16x8*)(arow[i] + (((c + 1) ^ sw[i]) << 4));
-        }
+      for (int i = 0; i < MTW; ++i) {
+        ph.b[nb][i] = *(const bf16x8*)(arow[i] + ((c ^ sw[i]) << 4));
+        if constexpr (X3) pl.b[nb][i] = *(const bf16x8*)(arow[i] + (((c + 1) ^ sw[i]) << 4));
       }
-      // the next step's LDS reads go out before this step's MFMAs (left to
-      // itself the scheduler sinks them below, exposing their latency)
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int i = 0; i < MTW; ++i)
-#pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[sl][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
-          if constexpr (X3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl.a[sl][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[sl][j], pl.b[cb][i], acc[i][j], 0, 0, 0);
-          }
-        }
-      {
-        const int kn = min(ks + D, ksteps - 1);
-#pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-          ph.a[sl][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + kn * 1024);
-          if constexpr (X3) pl.a[sl][j] = ld_frag<bf16x8>(rl, voff, wrow[j] + kn * 1024);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
+    // the next step's LDS reads go out before this step's MFMAs (left to
+    // itself the scheduler sinks them below, exposing their latency)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[sl][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
+        if constexpr (X3) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pl.a[sl][j], ph.b[cb][i], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ph.a[sl][j], pl.b[cb][i], acc[i][j], 0, 0, 0);
+        }
+      }
+    if (pf) {
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        ph.a[sl][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + (ks + D) * 1024);
+        if constexpr (X3) pl.a[sl][j] = ld_frag<bf16x8>(rl, voff, wrow[j] + (ks + D) * 1024);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
+  };
+  for (int k0 = 0; k0 < ksteps - U; k0 += U) {
+#pragma unroll
+    for (int d = 0; d < U; ++d) step(k0 + d, d, true);
   }
+#pragma unroll
+  for (int d = 0; d < U; ++d) step(ksteps - U + d, d, d + D < U);
+  mfma_drain();
 }
 
 template <int MTW, int NTW, int D = 2>
@@ -375,6 +395,7 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
       __builtin_amdgcn_sched_barrier(0);   // keep the prefetch distance
     }
   }
+  mfma_drain();
 }
 
 // ---------------------------------------------------------------------------
