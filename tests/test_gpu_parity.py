@@ -229,6 +229,42 @@ def test_render_deepsdf_fp32(H, K, c2f):
     assert dn <= 2e-4
 
 
+def test_full_size_c3_bf16_sampled_pixels():
+    """The benchmark's launch: 8 views x 4 latents = 32 images of 256x256
+    through the bf16 path in one launch; four of the images checked on 240
+    random pixels each, traced one by one (with their coarse-to-fine
+    ancestors) by the oracle, to the bf16 render tolerances."""
+    spec = di.DEEPSDF_SPEC
+    prm = cfg_params("c3", precision=1)
+    H = 256
+    cams = di.random_sphere_cameras(8, H, H)
+    Z = di.make_latents(4, spec.latent_dim, sigma=0.01)
+    out = _gpu_render(spec, cams, Z, prm)
+    dec = oracle_decoder(spec)
+    rng = np.random.Generator(np.random.PCG64(12))
+    n_wc, mis, worst, worst_n = 0, 0, 0.0, 0.0
+    for i in (0, 9, 22, 31):                 # image i = (view i // 4, latent i % 4)
+        pix = rng.choice(H * H, 240, replace=False)
+        o = O.render(dec, Z, cams, [(i // 4, i % 4)], prm, pixels=[pix])[0]
+        g = _np(out, i)
+        st_o, st_g = o.status.reshape(-1)[pix], g["status"].reshape(-1)[pix]
+        both = (st_o == 1) & (st_g == 1)
+        n_o = o.normal.reshape(-1, 3)[pix]
+        cosv = np.abs(np.sum(o.dirs[pix] * n_o, axis=-1))
+        wc = both & (cosv >= 0.25)
+        err = np.abs(o.depth.reshape(-1)[pix][wc] - g["depth"].reshape(-1)[pix][wc])
+        ln = np.linalg.norm(o.nraw.reshape(-1, 3)[pix][wc], axis=-1)
+        dn = np.linalg.norm(n_o[wc] - g["normal"].reshape(-1, 3)[pix][wc], axis=-1) * ln
+        mis += int(((o.sil.reshape(-1)[pix] < 0) != (g["sil"].reshape(-1)[pix] < 0)).sum())
+        n_wc += int(wc.sum())
+        worst = max(worst, float(err.max()) if err.size else 0.0)
+        worst_n = max(worst_n, float(dn.max()) if dn.size else 0.0)
+        _log("  image", i, "hits", int(both.sum()), "wc", int(wc.sum()), "depth max", worst, "normal", worst_n)
+    assert n_wc >= 100
+    assert worst <= 2e-3 and worst_n <= 2e-3
+    assert mis <= 1
+
+
 def test_render_multi_image_pairs_fp32():
     """Several (view, latent) pairs in one launch give the same images as the oracle."""
     spec = di.C1_SPEC
