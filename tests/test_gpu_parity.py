@@ -271,8 +271,9 @@ def test_full_size_c3_bf16_sampled_gradient():
     sphere's maps) restricted to 600 sampled pixels of each of four images
     whose trajectory the oracle's agrees with, against the oracle's paper
     gradient of the same loss.  Measured 0.65% (depth term 0.44%, silhouette
-    0.47%; the normal term on its own is 15% off, a bf16 limit of the stencil
-    VJP, but it is 3% of the gradient here)."""
+    0.47%; the normal term on its own is 15% off: its central differences
+    sit at the bf16 hit point, up to 4e-4 from the FP64 one, and span
+    different ReLU kinks; it is 3% of the gradient here)."""
     from paper_1911_13225_amd import api
     spec = di.DEEPSDF_SPEC
     prm = cfg_params("c3", precision=1)
