@@ -12,10 +12,12 @@ in the docstring (tagged "Reading:"); the same readings are implemented by the
 GPU path from their own description.
 
 Parity pins (what checks this oracle against something other than itself) live
-in ``tests/test_oracle_pins.py``.  Parity unpinned: the coarse-to-fine split
-rule (Reading C2F), the alpha coefficient of the depth gradient (Reading G1)
-and the K-sample rule (Reading G2) are checked only for self-consistency; the
-paper gives no numbers for them.
+in ``tests/test_oracle_pins.py``.  The coarse-to-fine schedule (which steps
+run at which level, every child re-traced) is pinned by closed-form query
+counts on the analytic base field.  Parity unpinned: the start of a split
+child and its empty minimum-|f| records (Reading C2F), the alpha coefficient
+of the depth gradient (Reading G1) and the K-sample rule (Reading G2) are
+checked only for self-consistency; the paper gives no numbers for them.
 """
 from __future__ import annotations
 

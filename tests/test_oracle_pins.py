@@ -779,3 +779,146 @@ def test_color_vjp_against_torch_autograd_and_differences(spec):
     e[k] = 1e-6
     fd = ((dec.color(Z + e, P) - dec.color(Z - e, P)) * seeds).sum() / 2e-6
     assert abs(fd - g[k]) <= 1e-6 * abs(g[k]) + 1e-9
+
+
+# ----------------------------------------------------------------------------
+# silhouette seed, coarse-to-fine schedule, bf16-rounding decoder
+# ----------------------------------------------------------------------------
+def test_silhouette_seed_against_frozen_point_differences():
+    """Sec. 3.4 / App. A.3: S = min_n |f(p_n, z)| - eps, so with the minimising
+    query p* held fixed dS/dz = sign f(p*) df(p*, z)/dz.  The oracle's backward
+    given only dL/dS must equal central differences of the surrogate
+    sum_pix g_S (|f(p*, z)| - eps), and p* must be the query of smallest |f|
+    along the pixel's ray, found here by an independent scalar re-trace.  A
+    dropped sign, the sign of another record or the point of another record
+    fails this.  The step factor alpha = 2.5 makes many rays overshoot, so
+    that many argmin queries have f < 0 (with the workloads' alpha = 1.5 the
+    residual form never overshoots and every sign would be +1)."""
+    spec = di.C1_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    dec = O.Decoder(spec, Ws, bs)
+    H = 14
+    cam = di.front_camera(H, H)
+    z = di.make_latents(1, spec.latent_dim, sigma=0.05)
+    prm = _prm(alpha=2.5, eps=1e-3, max_steps=30, c2f_levels=0, k_samples=3, want_normals=0)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    z0 = z[0].astype(np.float64)
+    fn = lambda P, zv=z0: dec.sdf(np.broadcast_to(zv, (P.shape[0], zv.size)), P)
+    st = r.status.reshape(-1)
+    # independent re-trace: one ray at a time, every query kept
+    c = cam.c.astype(np.float64)
+    inside = np.nonzero(st != O.MISS)[0]
+    for q in inside:
+        v = r.dirs[q]
+        b = float(v @ c)
+        t = -b - math.sqrt(b * b - (c @ c - 1.0))
+        t_hi = -b + math.sqrt(b * b - (c @ c - 1.0))
+        seen = []
+        for n in range(prm.max_steps):
+            f = float(fn((c + t * v)[None])[0])
+            seen.append((abs(f), n, t))
+            if abs(f) < prm.eps or n == prm.max_steps - 1:
+                break
+            t += prm.alpha * f
+            if t > t_hi or t < -b - math.sqrt(b * b - (c @ c - 1.0)):
+                break
+        best = min(seen, key=lambda s: (s[0], s[1]))
+        assert abs(best[0] - r.rec_absf[0, q]) <= 1e-12
+        assert best[1] == r.rec_n[0, q]
+        assert abs(best[2] - r.rec_t[0, q]) <= 1e-12
+    rng = np.random.Generator(np.random.PCG64(31))
+    g_s = rng.standard_normal((H, H)) / (H * H)
+    gz, _, _ = O.backward(dec, z, [r], [(0, 0)], prm, [(np.zeros((H, H)), np.zeros((H, H, 3)), g_s)],
+                          want_theta=False)
+    sel = inside
+    p_star = c[None, :] + r.rec_t[0, sel, None] * r.dirs[sel]
+    neg = (r.rec_f[0, sel] < 0) & (st[sel] == O.HIT)
+    assert neg.sum() >= 5, "the pin needs hits whose minimum-|f| query is negative"
+    gsel = g_s.reshape(-1)[sel]
+
+    def surrogate(zv):
+        return float(np.dot(gsel, np.abs(fn(p_star, zv)) - prm.eps))
+
+    h = 1e-7
+    for j in range(0, spec.latent_dim, 5):
+        zp, zm = z0.copy(), z0.copy()
+        zp[j] += h
+        zm[j] -= h
+        fd = (surrogate(zp) - surrogate(zm)) / (2 * h)
+        assert abs(fd - gz[0, j]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-10, (j, fd, gz[0, j])
+
+
+@pytest.mark.parametrize("H,L", [(32, 2), (48, 2), (40, 1)])
+def test_coarse_to_fine_schedule_query_counts(H, L):
+    """Sec. 3.2 coarse-to-fine: tracing starts at 1/2^L of the resolution per
+    side and every ray splits into four after every three steps, every child
+    that meets the unit sphere being traced again.  So on the analytic base
+    field, where no ray converges within three steps of the sphere entry, the
+    queries of step 0 count the level-L rays that meet the unit sphere, those of
+    step 3 the level-(L-1) rays and those of step 6 the full-resolution rays.
+    The counts come from the closed form of a camera at distance |c| looking at
+    the origin: the ray through (xt, yt) meets the unit sphere iff
+    xt^2 + yt^2 < 1 / (|c|^2 - 1)."""
+    dec = _base_decoder()
+    z = di.make_latents(1, di.C1_SPEC.latent_dim)
+    cam = di.front_camera(H, H)
+    prm = _prm(alpha=1.5, eps=1e-3, max_steps=12, c2f_levels=L, want_normals=0)
+    r = O.render(dec, z, [cam], [(0, 0)], prm)[0]
+    cc = float(np.sum(cam.c.astype(np.float64) ** 2))
+
+    def meeting(level):
+        s = 2 ** level
+        ctr = s * np.arange(H // s, dtype=np.float64) + 0.5 * s
+        xt = (ctr[None, :] - cam.cx) / cam.fx
+        yt = (ctr[:, None] - cam.cy) / cam.fy
+        return int(np.sum(xt * xt + yt * yt < 1.0 / (cc - 1.0)))
+
+    for seg in range(L + 1):
+        assert r.queries_per_step[3 * seg] == meeting(L - seg), (seg, r.queries_per_step)
+    # between the splits the count only falls (rays stop, none start)
+    for n in range(1, prm.max_steps):
+        if n % 3 or n > 3 * L:
+            assert r.queries_per_step[n] <= r.queries_per_step[n - 1]
+
+
+@pytest.mark.parametrize("spec", [di.C1_SPEC, di.DEEPSDF_SPEC], ids=["c1", "deepsdf"])
+def test_bf16_emulated_decoder_matches_torch_bfloat16(spec):
+    """The bf16-rounding oracle decoder against an independent torch
+    evaluation: hidden-layer products take torch.bfloat16 casts of the input
+    activations and of the hidden part of the weights (exact float64
+    products and sums); layer 0, the skip layer's [z, p] columns, biases and the
+    output layer stay float64."""
+    torch = pytest.importorskip("torch")
+    Ws, bs = di.make_decoder(spec, seed=0)
+    rng = np.random.Generator(np.random.PCG64(41))
+    bs = [rng.standard_normal(b.shape).astype(np.float32) * 0.1 for b in bs]
+    emu = O.DecoderBF16Emulated(spec, Ws, bs)
+    n = 64
+    Z = rng.standard_normal((n, spec.latent_dim)) * 0.1
+    P = rng.uniform(-0.6, 0.6, (n, 3))
+    got = emu.sdf(Z, P)
+
+    def r16(x):
+        return x.to(torch.bfloat16).to(torch.float64)
+
+    Zt, Pt = torch.tensor(Z), torch.tensor(P)
+    zp = torch.cat([Zt, Pt], 1)
+    nl = len(Ws)
+    h = None
+    for l in range(nl):
+        W = torch.tensor(Ws[l].astype(np.float64))
+        b = torch.tensor(bs[l].astype(np.float64))
+        if l == 0:
+            a = zp @ W.T + b
+        elif l == nl - 1:
+            a = h @ W.T + b
+        elif spec.skip_layer is not None and l == spec.skip_layer:
+            nh = Ws[l - 1].shape[0]
+            a = r16(h) @ r16(W[:, :nh]).T + zp @ W[:, nh:].T + b
+        else:
+            a = r16(h) @ r16(W).T + b
+        h = torch.relu(a) if l < nl - 1 else a
+    want = (0.5 * (Pt.norm(dim=1) - 0.5) + 0.05 * torch.tanh(h[:, 0])).numpy()
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+    # and it is not the float64 decoder
+    assert np.abs(got - O.Decoder(spec, Ws, bs).sdf(Z, P)).max() > 1e-6
