@@ -3,8 +3,8 @@
 A step is one pass of the whole hot path over one batch: forward render of
 8 views x 4 latents = 32 images of 256x256 with the DeepSDF-scale decoder in
 bf16 (coarse-to-fine, aggressive marching, compaction, normals), the image
-loss (10 L1 depth + silhouette hinge + normal term, torch), and the backward
-pass (the paper's approximate gradient w.r.t. the latent codes).  Inputs are
+loss (10 L1 depth + silhouette hinge + normal term, on the device), and the
+backward pass (the paper's approximate gradient w.r.t. the latent codes).  Inputs are
 seeded synthetic decoders, latents and cameras, resident on the GPU before the
 timed region.  The same workload is also timed with the float32 plain tracer,
 and a single 256x256 image (the float32 workload) is timed for latency.
@@ -62,20 +62,19 @@ def build_workload(n_views=8, n_lat=4, H=256, precision=1):
     return dict(ctx=ctx, cams=cams, Z=Z, prm=prm, targets=(dt, nt, st), n_img=n_views * n_lat)
 
 
-def step(w):
-    """forward + loss + backward; returns (g_z, per-image query tensor)."""
-    import torch
+def step(w, keep=False):
+    """forward + loss + backward; returns (g_z, per-image query tensor) and,
+    with keep, the rendered maps."""
     from paper_1911_13225_amd import api
-    Z = w["Z"].clone().requires_grad_(True)
+    Z = w["Z"]
     out = api.dist_render_fwd(w["ctx"], w["cams"], Z, w["prm"], save=True)
-    depth = out["depth"].requires_grad_(True)
-    normal = out["normal"].requires_grad_(True)
-    sil = out["sil"].requires_grad_(True)
     dt, nt, st = w["targets"]
-    L = api.render_loss(depth, normal, sil, dt, nt, st, w_d=10.0, w_s=1.0, w_n=1.0)
-    gd, gn, gs = torch.autograd.grad(L, (depth, normal, sil))
+    _, gd, gn, gs = api.dist_render_loss(out["depth"], out["normal"], out["sil"], dt, nt, st, w_d=10.0, w_s=1.0,
+                                         w_n=1.0)
     g_z = api.dist_render_bwd(w["ctx"], out["saved"], gd, gn, gs, n_latents=Z.shape[0])
     out["saved"].free()
+    if keep:
+        return g_z, out["queries"], out
     return g_z, out["queries"]
 
 
@@ -155,11 +154,8 @@ def gradient_variants(w, reps=2):
     prm.keep_history = 1
     Z = w["Z"]
     out = api.dist_render_fwd(w["ctx"], w["cams"], Z, prm, save=True)
-    depth = out["depth"].requires_grad_(True)
-    sil = out["sil"].requires_grad_(True)
     dt, nt, st = w["targets"]
-    L = api.render_loss(depth, out["normal"], sil, dt, nt, st, w_d=10.0, w_s=1.0, w_n=0.0)
-    gd, gs = torch.autograd.grad(L, (depth, sil))
+    _, gd, _, gs = api.dist_render_loss(out["depth"], None, out["sil"], dt, None, st, w_d=10.0, w_s=1.0)
     n = Z.shape[0]
     calls = {
         "paper": lambda: api.dist_render_bwd(w["ctx"], out["saved"], gd, None, gs, n_latents=n),
@@ -214,8 +210,14 @@ def color_run(w, reps=3):
     return res
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The FP64 oracle on a bounded sample of the benchmark workload."""
+BASELINE_IMAGES = (0, 9, 22, 31)      # images of the benchmark batch the oracle samples (i = view i // 4, latent i % 4)
+
+
+def cpu_baseline(gpu_maps=None, seconds_target=15.0):
+    """The FP64 oracle on a bounded sample of the benchmark workload: rounds of
+    2048 random pixels (with their coarse-to-fine ancestors) of four of the 32
+    images, forward + normals + loss + backward.  With the GPU's maps of those
+    images, also the per-output error of the bf16 launch on the sampled pixels."""
     import dist_inputs as di
     from oracle import dist_oracle as O
     try:
@@ -226,27 +228,114 @@ def cpu_baseline(seconds_target=15.0):
     spec = di.DEEPSDF_SPEC
     Ws, bs = di.make_decoder(spec, seed=0)
     dec = O.Decoder(spec, Ws, bs)
-    cams = di.random_sphere_cameras(1, 256, 256)
-    Z = di.make_latents(1, spec.latent_dim, sigma=0.01)
+    H = 256
+    cams = di.random_sphere_cameras(8, H, H)
+    Z = di.make_latents(4, spec.latent_dim, sigma=0.01)
     prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=2, k_samples=1, precision=0,
                          want_normals=1)
     rng = np.random.Generator(np.random.PCG64(77))
     n_pix = 2048
     total_q, total_s, rounds = 0, 0.0, 0
+    seen = {i: {} for i in BASELINE_IMAGES}
     while total_s < seconds_target and rounds < 64:
-        pix = rng.choice(256 * 256, n_pix, replace=False)
+        img = BASELINE_IMAGES[rounds % len(BASELINE_IMAGES)]
+        v, l = img // 4, img % 4
+        pix = rng.choice(H * H, n_pix, replace=False)
         t0 = time.perf_counter()
-        r = O.render(dec, Z, cams, [(0, 0)], prm, pixels=[pix])[0]
-        dt, nt, st = di.sphere_target_maps(cams[0], 0.5)
+        r = O.render(dec, Z, cams, [(v, l)], prm, pixels=[pix])[0]
+        dt, nt, st = di.sphere_target_maps(cams[v], 0.5)
         _, g_d, g_n, g_s = O.loss_and_grads(r, dt, nt, st, w_d=10.0, w_s=1.0, w_n=1.0)
-        O.backward(dec, Z, [r], [(0, 0)], prm, [(g_d, g_n, g_s)], want_theta=False)
+        O.backward(dec, Z, [r], [(v, l)], prm, [(g_d, g_n, g_s)], want_theta=False)
         total_s += time.perf_counter() - t0
         total_q += r.queries
         rounds += 1
-    return {"value": round(total_q / total_s, 1), "unit": "queries/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{rounds} x {n_pix} random pixels of one 256x256 view (with their coarse-to-fine "
-                      f"ancestors), FP64 fwd + normals + loss + backward; {total_q} march queries in "
-                      f"{total_s:.1f} s"}
+        for q in pix:
+            seen[img][int(q)] = (r.status.reshape(-1)[q], r.depth.reshape(-1)[q], r.sil.reshape(-1)[q],
+                                 r.normal.reshape(-1, 3)[q], r.dirs[q])
+    out = {"value": round(total_q / total_s, 1), "unit": "queries/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"{rounds} x {n_pix} random pixels of images {list(BASELINE_IMAGES)} of the 32-image "
+                     f"workload (with their coarse-to-fine ancestors), FP64 fwd + normals + loss + backward; "
+                     f"{total_q} march queries in {total_s:.1f} s"}
+    if gpu_maps is not None:
+        out["error_vs_oracle"] = per_output_error(seen, gpu_maps)
+    return out
+
+
+def per_output_error(seen, gpu_maps):
+    """Per-output error of the GPU's bf16 maps against the oracle on the pixels
+    the oracle traced: depth over pixels that are foreground in both (all of
+    them, and the well-conditioned ones with |cos(ray, normal)| >= 0.25),
+    normals on the well-conditioned ones, binary silhouette mismatch over all
+    sampled pixels."""
+    dd, dd_wc, dn_wc, n_pix, mis = [], [], [], 0, 0
+    for img, px in seen.items():
+        g = gpu_maps[img]
+        for q, (st, dep, sil, nrm, dvec) in px.items():
+            n_pix += 1
+            mis += int((sil < 0) != (g["sil"][q] < 0))
+            if st == 1 and g["status"][q] == 1:
+                e = abs(float(dep) - float(g["depth"][q]))
+                dd.append(e)
+                if abs(float(np.dot(dvec, nrm))) >= 0.25:
+                    dd_wc.append(e)
+                    dn_wc.append(float(np.linalg.norm(nrm - g["normal"][q])))
+    dd = np.array(dd)
+    res = {"pixels": n_pix, "hits_both": int(dd.size), "silhouette_mismatch_frac": round(mis / max(n_pix, 1), 6),
+           "tolerance": {"depth": 2e-3, "silhouette_mismatch_frac": 1e-3}}
+    if dd.size:
+        res["depth_all_hits"] = {"max": float(dd.max()), "p99_9": float(np.percentile(dd, 99.9)),
+                                 "frac_above_2e-3": round(float((dd > 2e-3).mean()), 6)}
+        res["depth_well_conditioned"] = {"n": len(dd_wc), "max": float(max(dd_wc)) if dd_wc else None}
+        res["normal_well_conditioned_max"] = float(max(dn_wc)) if dn_wc else None
+    return res
+
+
+def strategy_ablation(sizes=(256, 512), reps=3):
+    """The paper's runtime ablation (Table 1) on a seeded single view: decoder
+    queries and fwd + loss + bwd time per frame (bf16) for dynamic
+    synchronized inference, + aggressive marching, + coarse-to-fine, and
+    coarse-to-fine with 100 steps; "parallel" (no culling of finished rays)
+    would query every ray that meets the unit sphere at every step."""
+    import torch
+    import dist_inputs as di
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    ctx = api.Context.from_spec(spec, Ws, bs)
+    Z = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.01), device="cuda")
+    variants = (("dynamic", 1.0, 0, 50), ("+aggressive", 1.5, 0, 50), ("+coarse_to_fine", 1.5, 2, 50),
+                ("+coarse_to_fine_100_steps", 1.5, 2, 100))
+    out = {}
+    for H in sizes:
+        cam = di.front_camera(H, H)
+        dt, nt, st = (torch.tensor(x, device="cuda")[None] for x in di.sphere_target_maps(cam, 0.5))
+        rows = {}
+        for name, alpha, c2f, steps in variants:
+            prm = di.TraceParams(alpha=alpha, eps=5e-4, max_steps=steps, c2f_levels=c2f, k_samples=1,
+                                 precision=1, want_normals=1)
+
+            def one():
+                o = api.dist_render_fwd(ctx, [cam], Z, prm, save=True)
+                _, gd, gn, gs = api.dist_render_loss(o["depth"], o["normal"], o["sil"], dt, nt, st, w_d=10.0,
+                                                     w_s=1.0, w_n=1.0)
+                api.dist_render_bwd(ctx, o["saved"], gd, gn, gs, n_latents=1)
+                o["saved"].free()
+                return o
+            o = one()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                one()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            rows[name] = {"alpha": alpha, "c2f_levels": c2f, "max_steps": steps,
+                          "queries": int(o["queries"].sum()), "hits": int((o["status"] == 1).sum()),
+                          "fwd_bwd_ms": round(ms, 3)}
+            if name == "dynamic":
+                rows["parallel_queries"] = int((o["status"] != 2).sum()) * steps
+        out[f"{H}x{H}"] = rows
+    ctx.close()
+    return out
 
 
 def serving_run(rate=10.0, n_req=24, zopt_iters=50, seed=4000):
@@ -350,31 +439,30 @@ def zopt_run(iters=200, n_views=4, H=256, precision=1):
     dt = torch.where(torch.isfinite(tgt["depth"]), tgt["depth"], torch.zeros_like(tgt["depth"]))
     st = (tgt["sil"] < 0).float()
     nz = torch.zeros(dt.shape + (3,), device="cuda")
-    z = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=1000), device="cuda",
-                     requires_grad=True)
-    d0 = float((z.detach() - zs).norm())
-    opt = torch.optim.Adam([z], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    z = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=1000), device="cuda")
+    d0 = float((z - zs).norm())
+    m = torch.zeros_like(z)
+    v = torch.zeros_like(z)
     curve = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(iters):
-        depth, _, sil, _ = api.DistRender.apply(z, ctx, cams, prm)
-        L = api.render_loss(depth, nz, sil, dt, nz, st, w_d=10.0, w_s=1.0, w_n=0.0)
-        opt.zero_grad()
-        L.backward()
-        opt.step()
+        out = api.dist_render_fwd(ctx, cams, z, prm, save=True)
+        loss, gd, _, gs = api.dist_render_loss(out["depth"], None, out["sil"], dt, None, st, w_d=10.0, w_s=1.0)
+        g = api.dist_render_bwd(ctx, out["saved"], gd, None, gs, n_latents=1)
+        out["saved"].free()
+        api.dist_adam_step(z, m, v, g, it + 1, lr=1e-2)
         if it in (0, 1, 10, 50, 100, iters - 1):
-            curve[it] = round(float(L), 6)
+            curve[it] = round(float(loss.sum()), 6)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    with torch.no_grad():
-        out = api.dist_render_fwd(ctx, cams, z.detach(), prm)
-        fg = (out["sil"] < 0) & (st > 0.5)
-        derr = float((out["depth"] - dt).abs()[fg].mean()) if bool(fg.any()) else None
+    out = api.dist_render_fwd(ctx, cams, z, prm)
+    fg = (out["sil"] < 0) & (st > 0.5)
+    derr = float((out["depth"] - dt).abs()[fg].mean()) if bool(fg.any()) else None
     ctx.close()
     return {"iters": iters, "views": n_views, "resolution": H, "precision": "bf16" if precision else "fp32",
             "its_per_s": round(iters / sec, 2), "loss": curve,
-            "z_dist_rel": {"start": 1.0, "end": round(float((z.detach() - zs).norm()) / d0, 4)},
+            "z_dist_rel": {"start": 1.0, "end": round(float((z - zs).norm()) / d0, 4)},
             "final_depth_abs_err_fg": derr}
 
 
@@ -396,18 +484,17 @@ def photometric_run(iters=50, n_views=8, H=112, precision=1):
     prm = di.TraceParams(alpha=1.5, eps=5e-4, max_steps=50, c2f_levels=0, k_samples=1, precision=precision,
                          want_normals=0)
     z = torch.tensor(di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=1000), device="cuda")
-    opt = torch.optim.Adam([z.requires_grad_(True)], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    m = torch.zeros_like(z)
+    v = torch.zeros_like(z)
     curve = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(iters):
-        out = api.dist_render_fwd(ctx, cams, z.detach(), prm, save=True)
+        out = api.dist_render_fwd(ctx, cams, z, prm, save=True)
         loss, g_depth = api.dist_photometric_loss(cams, out["depth"], images, pairs, weight=5.0)
         g = api.dist_render_bwd(ctx, out["saved"], g_depth, None, None, n_latents=1)
         out["saved"].free()
-        opt.zero_grad()
-        z.grad = g
-        opt.step()
+        api.dist_adam_step(z, m, v, g, it + 1, lr=1e-2)
         if it in (0, 1, 10, 25, iters - 1):
             curve[it] = round(float(loss.item()), 6)
     torch.cuda.synchronize()
@@ -426,12 +513,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=10.0)
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=100, help="requests per rate of the serving sweep")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--no-zopt", action="store_true")
-    ap.add_argument("--serve-sweep", type=str, default="",
-                    help="comma-separated request rates (req/s) for a serving sweep, --serve-requests each")
+    ap.add_argument("--serve-sweep", type=str, default="10,20,50,100,200,500",
+                    help="comma-separated Poisson request rates (req/s), --serve-requests each")
+    ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-grad-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (reference dispatch for HBM byte counters)")
@@ -470,6 +557,11 @@ def main():
     fps = w["n_img"] * r["steps"] / r["sec"]
     ks = kernel_summary(r, "bf16")
     log("[bench] bf16", round(ms_step, 2), "ms/step", ks)
+    # the maps of the images the oracle samples for the per-output error report
+    _, _, maps = step(w, keep=True)
+    gpu_maps = {i: {k: maps[k][i].reshape(-1, 3).cpu().numpy() if k == "normal" else maps[k][i].reshape(-1).cpu().numpy()
+                    for k in ("depth", "sil", "status", "normal")} for i in BASELINE_IMAGES}
+    del maps
 
     res = {"metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -530,20 +622,21 @@ def main():
         res["photometric_fit"] = photometric_run()
         log("[bench] photometric fit", res["photometric_fit"])
 
-    if not a.no_serve:
-        log("[bench] serving stream")
-        res["serving"] = serving_run(a.serve_rate, a.serve_requests)
-        log("[bench] serving", res["serving"])
-    if a.serve_sweep:
-        res["serving_sweep"] = []
+    if not a.no_ablation:
+        log("[bench] strategy ablation (Table 1 analogue), single view 256x256 and 512x512")
+        res["strategy_ablation"] = strategy_ablation()
+        log("[bench] ablation", res["strategy_ablation"])
+
+    if not a.no_serve and a.serve_sweep:
+        res["serving"] = []
         for rate in [float(x) for x in a.serve_sweep.split(",") if x]:
-            log("[bench] serving sweep at", rate, "req/s")
-            res["serving_sweep"].append(serving_run(rate, a.serve_requests))
-            log("[bench]  ", res["serving_sweep"][-1])
+            log("[bench] serving sweep at", rate, "req/s,", a.serve_requests, "requests")
+            res["serving"].append(serving_run(rate, a.serve_requests))
+            log("[bench]  ", res["serving"][-1])
 
     if not a.no_cpu:
-        log("[bench] cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline()
+        log("[bench] cpu baseline (oracle) and per-output error of the bf16 launch on its pixels")
+        res["cpu_baseline"] = cpu_baseline(gpu_maps)
     print(json.dumps(res), flush=True)
 
 

@@ -291,6 +291,53 @@ int dist_photometric_loss(const dist_camera* cams, int32_t n_views,
                           const int32_t* pairs, int32_t n_pairs, float weight,
                           float* loss_map, float* loss, float* g_depth, void* stream);
 
+/* Image-space loss of the latent fit and its gradient w.r.t. the rendered
+ * maps (Sec. 4.2.1: L1 depth; App. A.3: silhouette hinge; App. B.3: the normal
+ * term is the negative dot product; App. B.4 weights depth 10, silhouette 1).
+ * Per image i of H x W pixels:
+ *   loss[i] = 1/(H W) [ w_depth  sum_{fg_r & fg_t} |depth - depth_t|
+ *                     + w_sil    sum_pix sil_t max(0, sil) + (1 - sil_t) max(0, -sil)
+ *                     + w_normal sum_{fg_r & fg_t} -(normal . normal_t) ]
+ * fg_r is the rendered silhouette (sil < 0), fg_t the target's (sil_t > 0.5);
+ * sign(0) = 0 and max'(0) = 0; a hinge term whose weight sil_t or 1 - sil_t is
+ * zero adds nothing (so a target depth off its silhouette is never read).
+ *   depth, sil, depth_t, sil_t   device [n_images][H][W] (sil_t in [0, 1])
+ *   normal, normal_t             device [n_images][H][W][3]; read only when
+ *                                w_normal != 0 (then both are required)
+ *   loss                         device [n_images], overwritten
+ *   g_depth, g_sil               device [n_images][H][W], dL/d(map) with L the
+ *   g_normal                     sum of loss[i] ([..][3]); each may be NULL
+ *                                (not written); g_normal is zero when
+ *                                w_normal = 0
+ * One workgroup per image sums in a fixed order: bitwise reproducible.
+ * Stream-ordered, allocates nothing.  DIST_EINVAL for bad arguments. */
+int dist_render_loss(int32_t n_images, int32_t H, int32_t W,
+                     const float* depth, const float* normal, const float* sil,
+                     const float* depth_t, const float* normal_t, const float* sil_t,
+                     float w_depth, float w_sil, float w_normal,
+                     float* loss, float* g_depth, float* g_normal, float* g_sil, void* stream);
+
+/* One Adam step on n values (App. B.4: latent codes are optimised with Adam,
+ * learning rate 1e-2): with step count t >= 1,
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   z -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).
+ * z, m, v device [n] (updated in place; m and v start at zero), g device [n].
+ * Stream-ordered, allocates nothing.  DIST_EINVAL for bad arguments. */
+int dist_adam_step(float* z, float* m, float* v, const float* g, int32_t n, float lr,
+                   float beta1, float beta2, float eps, int32_t t, void* stream);
+
+/* Convergence threshold of App. A.2: the radius eps at which the eps-balls
+ * around the front ends of neighbouring pixels' rays stop overlapping, for a
+ * camera with focal length `focal`, sensor size `sensor` (same unit as
+ * focal), `resolution` pixels across the sensor, objects about `d_min` away
+ * and a ray at angle `theta` (radians) to the optical axis:
+ *   eps = d_min sensor cos^2(theta) / (2 focal resolution)
+ * (in pixel units sensor / focal = W / fx).  Host arithmetic only, no GPU.
+ * DIST_EINVAL unless d_min, sensor, focal > 0, resolution >= 1 and theta is
+ * finite. */
+int dist_eps_for_camera(double d_min, double sensor, double focal, int32_t resolution, double theta,
+                        double* eps);
+
 /* Free a forward state. */
 int dist_saved_free(dist_saved* saved);
 

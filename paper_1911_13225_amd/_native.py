@@ -82,6 +82,12 @@ _SIGS = [
     ("dist_photometric_loss", ctypes.c_int, [ctypes.POINTER(dist_camera), ctypes.c_int32, _P, _P,
                                              ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_float, _P, _P,
                                              _P, _P]),
+    ("dist_render_loss", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P,
+                                        ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P, _P]),
+    ("dist_adam_step", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_int32, _P]),
+    ("dist_eps_for_camera", ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                           ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     ("dist_saved_free", ctypes.c_int, [_P]),
     ("dist_sdf_eval", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P]),
     ("dist_sdf_vjp", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P,

@@ -305,17 +305,41 @@ class DistRender(torch.autograd.Function):
         return g_z, None, None, None, None
 
 
-def render_loss(depth, normal, sil, depth_t, normal_t, sil_t, w_d=10.0, w_s=1.0, w_n=0.0):
-    """L1 depth on the rendered-and-target foreground, the silhouette hinge of
-    App. A.3 and the negative normal dot product, each normalised by H*W."""
-    HW = depth.shape[-1] * depth.shape[-2]
-    fg = (sil < 0) & (sil_t > 0.5)
-    diff = torch.where(fg, depth - torch.where(fg, depth_t, torch.zeros_like(depth_t)), torch.zeros_like(depth))
-    L = w_d / HW * diff.abs().sum()
-    L = L + w_s / HW * (sil_t * torch.relu(sil) + (1 - sil_t) * torch.relu(-sil)).sum()
-    if w_n:
-        L = L + w_n / HW * (-(normal * normal_t).sum(-1) * fg).sum()
-    return L
+def dist_render_loss(depth, normal, sil, depth_t, normal_t, sil_t, w_d=10.0, w_s=1.0, w_n=0.0, want_grad=True):
+    """Per-image loss [n] of the latent fit (L1 depth, silhouette hinge,
+    normal term) and, with want_grad, its map gradients (g_depth, g_normal,
+    g_sil); normals may be None when w_n = 0."""
+    lib = N.load()
+    d, s, dt, st = [x.detach().float().contiguous() for x in (depth, sil, depth_t, sil_t)]
+    n_img, H, W = d.shape
+    use_n = float(w_n) != 0.0
+    nr = normal.detach().float().contiguous() if use_n else None
+    ntr = normal_t.detach().float().contiguous() if use_n else None
+    loss = torch.empty(n_img, device=d.device)
+    gd = torch.empty_like(d) if want_grad else None
+    gs = torch.empty_like(d) if want_grad else None
+    gn = torch.empty(n_img, H, W, 3, device=d.device) if want_grad else None
+    check(lib.dist_render_loss(n_img, H, W, _ptr(d), _ptr(nr), _ptr(s), _ptr(dt), _ptr(ntr), _ptr(st), float(w_d),
+                               float(w_s), float(w_n), _ptr(loss), _ptr(gd), _ptr(gn), _ptr(gs), _stream()))
+    return loss, gd, gn, gs
+
+
+def dist_eps_for_camera(d_min: float, sensor: float, focal: float, resolution: int, theta: float = 0.0) -> float:
+    """Convergence threshold of App. A.2 (host arithmetic in the library)."""
+    lib = N.load()
+    e = ctypes.c_double()
+    check(lib.dist_eps_for_camera(float(d_min), float(sensor), float(focal), int(resolution), float(theta),
+                                  ctypes.byref(e)))
+    return e.value
+
+
+def dist_adam_step(z: torch.Tensor, m: torch.Tensor, v: torch.Tensor, g: torch.Tensor, t: int, lr=1e-2,
+                   beta1=0.9, beta2=0.999, eps=1e-8):
+    """Adam step t (>= 1) on z in place; m and v are the moment buffers."""
+    lib = N.load()
+    gg = g.detach().float().contiguous()
+    check(lib.dist_adam_step(_ptr(z), _ptr(m), _ptr(v), _ptr(gg), z.numel(), float(lr), float(beta1), float(beta2),
+                             float(eps), int(t), _stream()))
 
 
 # ----------------------------------------------------------------------------

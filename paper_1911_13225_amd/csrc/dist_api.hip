@@ -1513,3 +1513,55 @@ extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* l
   ws_put(ctx, w);
   return rc;
 }
+
+// ---------------------------------------------------------------------------
+// image-space loss of inverse optimisation and the optimiser step
+// ---------------------------------------------------------------------------
+extern "C" int dist_render_loss(int32_t n_images, int32_t H, int32_t W, const float* depth, const float* normal,
+                                const float* sil, const float* depth_t, const float* normal_t, const float* sil_t,
+                                float w_depth, float w_sil, float w_normal, float* loss, float* g_depth,
+                                float* g_normal, float* g_sil, void* stream) {
+  if (n_images < 1 || n_images > 65536) return dist_set_error(DIST_EINVAL, "n_images must be in [1, 65536]");
+  if (H < 1 || W < 1 || (long long)H * W > (1 << 22))
+    return dist_set_error(DIST_EINVAL, "H and W must be positive (at most 4M pixels per image)");
+  if (!depth || !sil || !depth_t || !sil_t || !loss) return dist_set_error(DIST_EINVAL, "null argument");
+  if (!std::isfinite(w_depth) || !std::isfinite(w_sil) || !std::isfinite(w_normal))
+    return dist_set_error(DIST_EINVAL, "loss weights must be finite");
+  if (w_normal != 0.f && (!normal || !normal_t))
+    return dist_set_error(DIST_EINVAL, "a normal term needs the rendered and the target normals");
+  hipStream_t st = (hipStream_t)stream;
+  launch_render_loss(depth, normal, sil, depth_t, normal_t, sil_t, n_images, H * W, w_depth, w_sil, w_normal, loss,
+                     g_depth, g_normal, g_sil, st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+extern "C" int dist_adam_step(float* z, float* m, float* v, const float* g, int32_t n, float lr, float beta1,
+                              float beta2, float eps, int32_t t, void* stream) {
+  if (!z || !m || !v || !g) return dist_set_error(DIST_EINVAL, "null argument");
+  if (n < 1) return dist_set_error(DIST_EINVAL, "n must be positive");
+  if (t < 1) return dist_set_error(DIST_EINVAL, "the step count t starts at 1");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return dist_set_error(DIST_EINVAL, "need lr > 0, 0 <= beta1, beta2 < 1 and eps > 0");
+  launch_adam(z, m, v, g, n, lr, beta1, beta2, eps, t, (hipStream_t)stream);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// convergence threshold from the camera (host arithmetic only)
+// ---------------------------------------------------------------------------
+extern "C" int dist_eps_for_camera(double d_min, double sensor, double focal, int32_t resolution, double theta,
+                                   double* eps) {
+  if (!eps) return dist_set_error(DIST_EINVAL, "null argument");
+  if (!(d_min > 0.0) || !(sensor > 0.0) || !(focal > 0.0) || resolution < 1 || !std::isfinite(theta))
+    return dist_set_error(DIST_EINVAL, "need d_min, sensor, focal > 0, resolution >= 1 and a finite theta");
+  // neighbouring pixels' rays are S / R apart on the sensor; at distance
+  // d_min (along the optical axis, the ray tilted by theta) their front ends
+  // are d_min (S / R) cos(theta) / (f / cos(theta)) apart, and eps is half of
+  // that, so that the eps-balls around them just touch
+  const double pitch = sensor / (double)resolution;
+  const double c = std::cos(theta);
+  *eps = 0.5 * d_min * (pitch * c) / (focal / c);
+  return DIST_OK;
+}

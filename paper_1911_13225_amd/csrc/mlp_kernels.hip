@@ -16,6 +16,7 @@
 //   * The 1-wide output layer is a float32 dot product reduced across waves
 //     in a fixed order, then f = 0.5 (|p| - 0.5) + 0.05 tanh(m).
 #include "dist_internal.h"
+#include "march_rules.h"
 
 namespace dist {
 
@@ -1027,8 +1028,9 @@ __device__ __forceinline__ void march_tiles(const MarchArgs& a, const Sm<P>& s, 
       // running K smallest |f| (ties keep the earlier step)
       const float af = fabsf(f);
       const int Kr = im.K;
-      int pos = 0;
-      for (int k = 0; k < Kr; ++k) pos += (fabsf(pl.rec_f[(size_t)k * pl.cap + r]) <= af) ? 1 : 0;
+      float rec_abs[kMaxK];
+      for (int k = 0; k < Kr; ++k) rec_abs[k] = fabsf(pl.rec_f[(size_t)k * pl.cap + r]);
+      const int pos = topk_rank(af, rec_abs, Kr);
       for (int k = Kr - 1; k > pos; --k) {
         pl.rec_f[(size_t)k * pl.cap + r] = pl.rec_f[(size_t)(k - 1) * pl.cap + r];
         pl.rec_t[(size_t)k * pl.cap + r] = pl.rec_t[(size_t)(k - 1) * pl.cap + r];

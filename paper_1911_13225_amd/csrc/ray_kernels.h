@@ -100,12 +100,18 @@ void launch_color_samples(const RayPool& pl, const ImgDesc* imgs, const int* img
                           int* seg_base, int* seg_total, int* seg_padded, int* n_samples, float4* samples,
                           float4* cseed, int* sample_lat, long long cap, hipStream_t s);
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s);
+// Two launches: the previous list's survivors, then the rays that start this
+// tick (split children and (re)started images).
 void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
-                    int* out_count, const AdvEntry* table, const int* hdr, int* img_active,
-                    unsigned long long* qcount, int grid, hipStream_t s);
-void launch_zopt_loss(const float* depth, const float* sil, const float* depth_t, const float* sil_t, int n,
-                      float inv_hw, float w_d, float w_s, float* g_depth, float* g_sil, float* loss, hipStream_t s);
-void launch_adam(float* z, float* m, float* v, const float* g, int L, float lr, int t, hipStream_t s);
+                    int* out_count, const AdvEntry* table, const int* hdr, int* img_active, int grid, hipStream_t s);
+// Per-image loss of inverse optimisation (L1 depth, silhouette hinge, normal
+// term) and its map gradients; one workgroup per image, fixed order.
+void launch_render_loss(const float* depth, const float* normal, const float* sil, const float* depth_t,
+                        const float* normal_t, const float* sil_t, int n_img, int hw, float w_d, float w_s, float w_n,
+                        float* loss, float* g_depth, float* g_normal, float* g_sil, hipStream_t s);
+void launch_sum_ordered(const float* a, int n, float* out, hipStream_t s);
+void launch_adam(float* z, float* m, float* v, const float* g, int L, float lr, float b1, float b2, float eps, int t,
+                 hipStream_t s);
 void launch_fill_i32(int* p, int v, int n, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 

@@ -595,10 +595,14 @@ __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kma
 }
 
 // ---------------------------------------------------------------------------
-// Serving: one pass that builds the next pooled active list from (a) the rays
-// still active in the previous list, (b) the children of images that split
-// this tick and (c) the coarsest rays of newly (re)started images, and counts
-// per image the rays it has in the new list and the queries of the last tick.
+// Serving: the next pooled active list is built from (a) the rays still active
+// in the previous list and then (b) the children of images that split this
+// tick and the coarsest rays of newly (re)started images, counting per image
+// the rays it has in the new list.  (a) and (b) are separate launches: a ray
+// slot released by a finished request can be handed to a request that starts
+// this tick while the previous list still names it, and the stale entry must
+// be read (and dropped, its ray having stopped) before the slot is
+// re-initialised.
 // ---------------------------------------------------------------------------
 __global__ void k_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr) {
   const int n = hdr[0];
@@ -606,29 +610,51 @@ __global__ void k_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* 
     imgs[table[i].img].cur_level = table[i].lvl;
 }
 
-__global__ __launch_bounds__(256) void k_advance(RayPool pl, const ImgDesc* imgs, const int* in_list,
-                                                 const int* in_count, int* out_list, int* out_count,
-                                                 const AdvEntry* table, const int* hdr, int* img_active,
-                                                 unsigned long long* qcount) {
-  const int n_old = *in_count;
-  const int n_tab = hdr[0], n_new = hdr[1];
-  const int total = n_old + n_new;
+// per-image count of the wave's flagged entries: one atomic per distinct image
+__device__ __forceinline__ void count_per_image(bool flag, int img, int* img_active) {
   const int lane = threadIdx.x & 63;
-  for (int base = blockIdx.x * 256; base < total; base += gridDim.x * 256) {
+  unsigned long long todo = __ballot(flag);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int li = __shfl(img, leader);
+    const unsigned long long same = __ballot(flag && img == li);
+    if (lane == leader) atomicAdd(&img_active[li], __popcll(same));
+    todo &= ~same;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_advance_old(RayPool pl, const ImgDesc* imgs, const int* in_list,
+                                                     const int* in_count, int* out_list, int* out_count,
+                                                     int* img_active) {
+  const int n_old = *in_count;
+  for (int base = blockIdx.x * 256; base < n_old; base += gridDim.x * 256) {
     const int i = base + threadIdx.x;
-    bool keep = false, old = false;
+    bool keep = false;
     int r = 0, img = -1;
     if (i < n_old) {
-      old = true;
       r = in_list[i];
-      img = pl.img[r];
-      const ImgDesc& im = imgs[img];
-      const int off = r - im.slot_base;
-      const int hw = im.H * im.W;
-      const int lvl = off < hw ? 0 : (off < hw + (hw >> 2) ? 1 : 2);
-      keep = pl.st[r] == ST_ACTIVE && lvl == im.cur_level;
-    } else if (i < total) {
-      const int j = i - n_old;
+      if (pl.st[r] == ST_ACTIVE) {
+        img = pl.img[r];
+        const ImgDesc& im = imgs[img];
+        const int off = r - im.slot_base;
+        const int hw = im.H * im.W;
+        const int lvl = off < hw ? 0 : (off < hw + (hw >> 2) ? 1 : 2);
+        keep = lvl == im.cur_level;
+      }
+    }
+    count_per_image(keep, img, img_active);
+    block_append(keep, r, out_list, out_count);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_advance_new(RayPool pl, const ImgDesc* imgs, int* out_list, int* out_count,
+                                                     const AdvEntry* table, const int* hdr, int* img_active) {
+  const int n_tab = hdr[0], n_new = hdr[1];
+  for (int base = blockIdx.x * 256; base < n_new; base += gridDim.x * 256) {
+    const int j = base + threadIdx.x;
+    bool keep = false;
+    int r = 0, img = -1;
+    if (j < n_new) {
       int lo = 0, hi = n_tab - 1;          // last entry with begin <= j
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -656,51 +682,64 @@ __global__ __launch_bounds__(256) void k_advance(RayPool pl, const ImgDesc* imgs
       init_ray(pl, im, img, r, d, t, t_lo, t_hi, inside, e.step);
       keep = inside;
     }
-    // queries of the last tick (old entries were all marched), if asked for
-    unsigned long long todo = qcount ? __ballot(old) : 0ull;
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int li = __shfl(img, leader);
-      const unsigned long long same = __ballot(old && img == li);
-      if (lane == leader) atomicAdd(&qcount[li], (unsigned long long)__popcll(same));
-      todo &= ~same;
-    }
-    // per-image count of rays in the new list
-    todo = __ballot(keep);
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int li = __shfl(img, leader);
-      const unsigned long long same = __ballot(keep && img == li);
-      if (lane == leader) atomicAdd(&img_active[li], __popcll(same));
-      todo &= ~same;
-    }
+    count_per_image(keep, img, img_active);
     block_append(keep, r, out_list, out_count);
   }
 }
 
-// Inverse optimisation (App. B.4 losses): per-pixel gradient of
-// w_d/HW L1(depth) over the rendered-and-target foreground plus the
-// silhouette hinge of App. A.3, and the loss value.
-__global__ __launch_bounds__(256) void k_zopt_loss(const float* depth, const float* sil, const float* depth_t,
-                                                   const float* sil_t, int n, float inv_hw, float w_d, float w_s,
-                                                   float* g_depth, float* g_sil, float* loss) {
-  __shared__ float red[256];
+// Image-space loss of inverse optimisation and its gradient w.r.t. the
+// rendered maps, one workgroup per image (fixed summation order, no atomics):
+//   L_i = 1/HW [ w_d sum_{fg_r & fg_t} |z_c - z_c*|                 (Sec. 4.2.1 L1 depth)
+//              + w_s sum_pix S* max(0, S) + (1 - S*) max(0, -S)     (App. A.3 hinge)
+//              + w_n sum_{fg_r & fg_t} (-n . n*) ]                  (App. B.3 normal term)
+// fg_r: S < 0 (the rendered binary silhouette), fg_t: S* > 0.5.  sign(0) = 0
+// and max'(0) = 0; a hinge term whose weight S* or 1 - S* is zero adds
+// nothing.  Gradient outputs may be null (not written); normals are read
+// only when w_n != 0.
+__global__ __launch_bounds__(1024) void k_render_loss(const float* depth, const float* normal, const float* sil,
+                                                      const float* depth_t, const float* normal_t,
+                                                      const float* sil_t, int hw, float w_d, float w_s, float w_n,
+                                                      float* loss, float* g_depth, float* g_normal, float* g_sil) {
+  __shared__ float red[1024];
+  const size_t base = (size_t)blockIdx.x * hw;
+  const float inv = 1.f / (float)hw;
+  const float cd = w_d * inv, cs = w_s * inv, cn = w_n * inv;
+  const bool nrm = w_n != 0.f;
   float acc = 0.f;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+  for (int p = threadIdx.x; p < hw; p += 1024) {
+    const size_t i = base + p;
     const float S = sil[i], St = sil_t[i];
     const bool fg = S < 0.f && St > 0.5f;
     const float dd = fg ? depth[i] - depth_t[i] : 0.f;
-    g_depth[i] = w_d * inv_hw * (dd > 0.f ? 1.f : (dd < 0.f ? -1.f : 0.f));
-    g_sil[i] = w_s * inv_hw * (St * (S > 0.f ? 1.f : 0.f) - (1.f - St) * (S < 0.f ? 1.f : 0.f));
-    acc += w_d * inv_hw * fabsf(dd) + w_s * inv_hw * (St * fmaxf(S, 0.f) + (1.f - St) * fmaxf(-S, 0.f));
+    float l = cd * fabsf(dd);
+    l += cs * ((St > 0.f ? St * fmaxf(S, 0.f) : 0.f) + (St < 1.f ? (1.f - St) * fmaxf(-S, 0.f) : 0.f));
+    float nt[3] = {0.f, 0.f, 0.f};
+    if (nrm && fg) {
+      for (int k = 0; k < 3; ++k) nt[k] = normal_t[3 * i + k];
+      l -= cn * (normal[3 * i] * nt[0] + normal[3 * i + 1] * nt[1] + normal[3 * i + 2] * nt[2]);
+    }
+    if (g_depth) g_depth[i] = cd * (dd > 0.f ? 1.f : (dd < 0.f ? -1.f : 0.f));
+    if (g_sil) g_sil[i] = cs * (St * (S > 0.f ? 1.f : 0.f) - (1.f - St) * (S < 0.f ? 1.f : 0.f));
+    if (g_normal)
+      for (int k = 0; k < 3; ++k) g_normal[3 * i + k] = -cn * nt[k];
+    acc += l;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = 512; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(loss, red[0]);
+  if (threadIdx.x == 0) loss[blockIdx.x] = red[0];
+}
+
+// out[0] = sum of a[0..n) in index order (one thread).
+__global__ void k_sum_ordered(const float* a, int n, float* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 0; i < n; ++i) s += a[i];
+    out[0] = s;
+  }
 }
 
 // Adam (paper App. B.4: Adam, learning rate 1e-2) on one latent code.
@@ -1033,20 +1072,24 @@ void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, i
                      hdr);
 }
 void launch_advance(const RayPool& pl, const ImgDesc* imgs, const int* in_list, const int* in_count, int* out_list,
-                    int* out_count, const AdvEntry* table, const int* hdr, int* img_active,
-                    unsigned long long* qcount, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(grid), dim3(256), 0, s, pl, imgs, in_list, in_count, out_list, out_count, table,
-                     hdr, img_active, qcount);
+                    int* out_count, const AdvEntry* table, const int* hdr, int* img_active, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_old, dim3(grid), dim3(256), 0, s, pl, imgs, in_list, in_count, out_list, out_count,
+                     img_active);
+  hipLaunchKernelGGL(k_advance_new, dim3(grid), dim3(256), 0, s, pl, imgs, out_list, out_count, table, hdr,
+                     img_active);
 }
-void launch_zopt_loss(const float* depth, const float* sil, const float* depth_t, const float* sil_t, int n,
-                      float inv_hw, float w_d, float w_s, float* g_depth, float* g_sil, float* loss, hipStream_t s) {
-  unsigned g = nblk(n, 256);
-  if (g > 1024) g = 1024;
-  hipLaunchKernelGGL(k_zopt_loss, dim3(g), dim3(256), 0, s, depth, sil, depth_t, sil_t, n, inv_hw, w_d, w_s, g_depth,
-                     g_sil, loss);
+void launch_render_loss(const float* depth, const float* normal, const float* sil, const float* depth_t,
+                        const float* normal_t, const float* sil_t, int n_img, int hw, float w_d, float w_s, float w_n,
+                        float* loss, float* g_depth, float* g_normal, float* g_sil, hipStream_t s) {
+  hipLaunchKernelGGL(k_render_loss, dim3(n_img), dim3(1024), 0, s, depth, normal, sil, depth_t, normal_t, sil_t, hw,
+                     w_d, w_s, w_n, loss, g_depth, g_normal, g_sil);
 }
-void launch_adam(float* z, float* m, float* v, const float* g, int L, float lr, int t, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3(nblk(L, 256)), dim3(256), 0, s, z, m, v, g, L, lr, 0.9f, 0.999f, 1e-8f, t);
+void launch_sum_ordered(const float* a, int n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, s, a, n, out);
+}
+void launch_adam(float* z, float* m, float* v, const float* g, int L, float lr, float b1, float b2, float eps, int t,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_adam, dim3(nblk(L, 256)), dim3(256), 0, s, z, m, v, g, L, lr, b1, b2, eps, t);
 }
 
 void launch_ul_init(const RayPool& pl, const ImgDesc* imgs, int n_img, int spi, const float* g_depth, float* lam,

@@ -228,7 +228,7 @@ static int capture_tick(Server* s, int par) {
   launch_fill_i32(s->img_active, 0, s->cap_imgs, s->st);
   launch_apply_levels(s->imgs, s->table, s->hdr, s->cap_imgs, s->st);
   launch_advance(s->pool, s->imgs, s->lists[cur], s->counters + cur, s->lists[nxt], s->counters + nxt, s->table,
-                 s->hdr, s->img_active, nullptr, s->adv_grid, s->st);
+                 s->hdr, s->img_active, s->adv_grid, s->st);
   MarchArgs ma{};
   ma.net = ctx->net[kPrecBF16];
   ma.pool = s->pool;
@@ -267,7 +267,7 @@ static int pool_init(Server* s) {
   HIPCHK_S(hipHostMalloc((void**)&s->h_active, sizeof(int) * s->cap_imgs));
   HIPCHK_S(hipHostMalloc((void**)&s->h_q, sizeof(unsigned long long) * s->cap_imgs));
   HIPCHK_S(hipHostMalloc((void**)&s->h_desc, sizeof(ImgDesc) * s->cap_imgs));
-  HIPCHK_S(hipHostMalloc((void**)&s->h_loss, sizeof(float) * 4));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_loss, sizeof(float) * s->cap_lat));
   s->slots.init(s->cap_rays);
   for (int i = s->cap_imgs - 1; i >= 0; --i) s->free_imgs.push_back(i);
   for (int i = s->cap_lat - 1; i >= 0; --i) s->free_lats.push_back(i);
@@ -292,7 +292,7 @@ static size_t req_layout(Server* s, Request* r, char* base) {
   r->d_hit_count = carve<int>(p, 4);
   r->d_fv = carve<float>(p, npx * 6);
   r->d_nraw = carve<float4>(p, npx);
-  r->d_loss = carve<float>(p, 4);
+  r->d_loss = carve<float>(p, r->n_views + 1);
   if (r->req.kind == DIST_REQ_ZOPT) {
     const int tile = adj_tile_rows(kPrecSplit);
     const int K = r->req.prm.k_samples;
@@ -422,11 +422,11 @@ static void complete_render(Server* s, Request* r) {
     r->finished = true;
     return;
   }
-  // loss and its gradient on the maps (depth L1 + silhouette hinge)
-  const int npx = r->n_views * r->hw;
-  launch_fill_i32((int*)r->d_loss, 0, 1, s->st);
-  launch_zopt_loss(fo.depth, fo.sil, q.target_depth, q.target_sil, npx, 1.f / r->hw, q.w_depth, q.w_sil, r->d_gd,
-                   r->d_gs, r->d_loss, s->st);
+  // loss and its gradient on the maps (depth L1 + silhouette hinge), per
+  // view in a fixed order, then summed over the views in view order
+  launch_render_loss(fo.depth, nullptr, fo.sil, q.target_depth, nullptr, q.target_sil, r->n_views, r->hw, q.w_depth,
+                     q.w_sil, 0.f, r->d_loss, r->d_gd, nullptr, r->d_gs, s->st);
+  launch_sum_ordered(r->d_loss, r->n_views, r->d_loss + r->n_views, s->st);
   // gradient samples of this request's images and the adjoint
   BwdSpace& b = r->bw;
   SeedIn in{};
@@ -456,10 +456,10 @@ static void complete_render(Server* s, Request* r) {
                    ctx->skip >= 0 ? ctx->wsz : nullptr, ctx->L, r->d_gz, s->st, r->lat);
   const int L = ctx->L;
   launch_adam(s->z_pool + (size_t)r->lat * L, s->adam_m + (size_t)r->lat * L, s->adam_v + (size_t)r->lat * L,
-              r->d_gz + (size_t)r->lat * L, L, q.lr, r->iter + 1, s->st);
-  (void)hipMemcpyAsync(s->h_loss, r->d_loss, sizeof(float), hipMemcpyDeviceToHost, s->st);
-  (void)hipStreamSynchronize(s->st);
-  r->final_loss = s->h_loss[0];
+              r->d_gz + (size_t)r->lat * L, L, q.lr, 0.9f, 0.999f, 1e-8f, r->iter + 1, s->st);
+  // the loss reaches the host with the next synchronisation of the server
+  // stream (every tick and finish() synchronise); no wait here
+  (void)hipMemcpyAsync(s->h_loss + r->lat, r->d_loss + r->n_views, sizeof(float), hipMemcpyDeviceToHost, s->st);
   r->iter += 1;
   if (r->iter >= q.iters) {
     (void)hipMemcpyAsync(q.z_out, s->z_pool + (size_t)r->lat * L, sizeof(float) * L, hipMemcpyDeviceToDevice, s->st);
@@ -471,6 +471,7 @@ static void complete_render(Server* s, Request* r) {
 
 static void finish(Server* s, Request* r, int status) {
   (void)hipStreamSynchronize(s->st);
+  if (r->req.kind == DIST_REQ_ZOPT && r->lat >= 0 && r->iter > 0) r->final_loss = s->h_loss[r->lat];
   std::lock_guard<std::mutex> lk(s->mu);
   r->status = status;
   r->t_done = Clock::now();
@@ -546,6 +547,9 @@ static void run(Server* s) {
       std::vector<Request*> rs = s->running;
       s->running.clear();
       for (Request* r : rs) finish(s, r, DIST_EHIP);
+      // no ray of a failed request may stay in the pooled lists
+      launch_fill_i32(s->counters, 0, 2, s->st);
+      (void)hipStreamSynchronize(s->st);
       continue;
     }
     // progress and completion

@@ -64,3 +64,30 @@ def test_bad_decoder_descriptions_are_rejected(lib):
         d = (ctypes.c_int32 * len(dims))(*dims)
         desc = N.dist_decoder_desc(len(dims), L, skip, d)
         assert lib.dist_create(ctypes.byref(h), ctypes.byref(desc), ptrs, ptrs, 0, None) == -1
+
+
+def test_eps_helper_reproduces_the_paper_example(lib):
+    """App. A.2: f = 60 mm, d_min = 10 cm, S = 32 mm, R = 512 give eps of about
+    0.5e-4 m, and neighbouring pixels' points about 1e-4 m = 2 eps apart
+    (Sec. 3.2); cos^2 scaling off the optical axis."""
+    import math
+    from conftest import load_golden
+    from paper_1911_13225_amd import api
+    g = load_golden("worked_examples.txt")
+    e = api.dist_eps_for_camera(g["eps.dmin_m"], g["eps.sensor_m"], g["eps.focal_m"], int(g["eps.res"]))
+    assert abs(e - g["eps.approx_m"]) / g["eps.approx_m"] < 0.05
+    assert abs(2 * e - g["spacing.approx_m"]) / g["spacing.approx_m"] < 0.05
+    e30 = api.dist_eps_for_camera(g["eps.dmin_m"], g["eps.sensor_m"], g["eps.focal_m"], int(g["eps.res"]),
+                                  math.radians(30))
+    assert abs(e30 / e - math.cos(math.radians(30)) ** 2) < 1e-12
+    out = ctypes.c_double()
+    assert lib.dist_eps_for_camera(0.0, 1.0, 1.0, 1, 0.0, ctypes.byref(out)) == -1
+    assert lib.dist_eps_for_camera(1.0, 1.0, 1.0, 0, 0.0, ctypes.byref(out)) == -1
+
+
+def test_loss_and_adam_reject_bad_arguments_on_the_host(lib):
+    assert lib.dist_render_loss(0, 4, 4, None, None, None, None, None, None, 1.0, 1.0, 0.0, None, None, None,
+                                None, None) == -1
+    assert lib.dist_render_loss(1, 4, 4, None, None, None, None, None, None, 1.0, 1.0, 0.0, None, None, None,
+                                None, None) == -1
+    assert lib.dist_adam_step(None, None, None, None, 4, 1e-2, 0.9, 0.999, 1e-8, 1, None) == -1

@@ -7,7 +7,7 @@
 * Latent-code fitting (App. B.4: Adam, lr 1e-2; depth L1 x 10 + silhouette):
   the HIP path and the FP64 oracle each run their own 50-iteration fit from
   the same seeded start against the same oracle-rendered targets; the
-  gradients agree at the start and the two loss curves agree along the way.
+  gradients agree at the start and at the oracle's iterates later on.
 """
 import sys
 
@@ -114,7 +114,27 @@ def _fit_targets(spec, cams, prm):
     return dec, zs, pairs, dt, st
 
 
+def _gpu_gradient(ctx, cams, prm, z, dtt, stt):
+    """Loss and dL/dz of the latent fit through the library: render, device
+    loss, paper gradient."""
+    from paper_1911_13225_amd import api
+    out = api.dist_render_fwd(ctx, cams, z, prm, save=True)
+    loss, gd, _, gs = api.dist_render_loss(out["depth"], None, out["sil"], dtt, None, stt, w_d=10.0, w_s=1.0)
+    g = api.dist_render_bwd(ctx, out["saved"], gd, None, gs, n_latents=1)
+    out["saved"].free()
+    return float(loss.sum()), g
+
+
 def test_latent_fit_matches_oracle(ctx):
+    """Latent-code fitting (App. B.4: Adam, lr 1e-2; 10 L1 depth + silhouette).
+    The library's own loop (render, device loss, paper gradient, device Adam)
+    and the oracle's loop start from the same code: their losses and gradients
+    agree at the start and after the first step.  Adam's per-coordinate
+    normalisation then lets float32 and float64 runs drift apart (coordinates
+    with a near-zero gradient move by +-lr either way), so later the library's
+    gradient is checked where both sides take it at the same code: the oracle's
+    own iterate z_t at iterations 10 and 49 (the oracle never receives a value
+    computed by the library).  Both fits must reduce the loss tenfold."""
     from paper_1911_13225_amd import api
     spec = di.DEEPSDF_SPEC
     cams = di.random_sphere_cameras(2, 32, 32)
@@ -122,31 +142,28 @@ def test_latent_fit_matches_oracle(ctx):
                          want_normals=0)
     dec, zs, pairs, dt, st = _fit_targets(spec, cams, prm)
     z0 = di.make_latents(1, spec.latent_dim, sigma=0.01, base_seed=1000)
-    iters, checks = 50, (0, 1, 10, 49)
-
-    # HIP path: DistRender + torch Adam
-    z = torch.tensor(z0, device="cuda", requires_grad=True)
-    opt = torch.optim.Adam([z], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    iters, checks = 50, (10, 49)
     dtt = torch.tensor(dt.astype(np.float32), device="cuda")
     stt = torch.tensor(st.astype(np.float32), device="cuda")
-    nz = torch.zeros(dtt.shape + (3,), device="cuda")
-    loss_g, g0_gpu = {}, None
-    for it in range(iters):
-        depth, normal, sil, _ = api.DistRender.apply(z, ctx, cams, prm)
-        L = api.render_loss(depth, nz, sil, dtt, nz, stt, w_d=10.0, w_s=1.0, w_n=0.0)
-        opt.zero_grad()
-        L.backward()
-        if it == 0:
-            g0_gpu = z.grad.detach().double().cpu().numpy()[0]
-        loss_g[it] = float(L.detach())
-        opt.step()
-    zg = z.detach().double().cpu().numpy()
 
-    # oracle: its own render, loss gradient, backward and Adam in float64
+    # library loop
+    z = torch.tensor(z0, device="cuda")
+    m = torch.zeros_like(z)
+    v = torch.zeros_like(z)
+    loss_g, g_gpu = {}, {}
+    for it in range(iters):
+        L, g = _gpu_gradient(ctx, cams, prm, z, dtt, stt)
+        loss_g[it] = L
+        if it in (0, 1):
+            g_gpu[it] = g.double().cpu().numpy()[0]
+        api.dist_adam_step(z, m, v, g, it + 1, lr=1e-2)
+    torch.cuda.synchronize()
+
+    # oracle loop: its own render, loss gradient, backward and Adam in float64
     zo = z0.astype(np.float64).copy()
-    m = np.zeros_like(zo)
-    v = np.zeros_like(zo)
-    loss_o, g0_or = {}, None
+    mo = np.zeros_like(zo)
+    vo = np.zeros_like(zo)
+    loss_o, g_or, z_or = {}, {}, {}
     for it in range(iters):
         rs = O.render(dec, zo, cams, pairs, prm)
         grads, L = [], 0.0
@@ -155,26 +172,27 @@ def test_latent_fit_matches_oracle(ctx):
             grads.append((gd, gn, gs))
             L += l
         g, _, _ = O.backward(dec, zo, rs, pairs, prm, grads, want_theta=False)
-        if it == 0:
-            g0_or = g[0]
-        loss_o[it] = L
-        zo, m, v = O.adam_step(zo, g, m, v, it + 1)
+        g_or[it], z_or[it], loss_o[it] = g[0], zo.copy(), L
+        zo, mo, vo = O.adam_step(zo, g, mo, vo, it + 1)
 
-    rel0 = np.linalg.norm(g0_gpu - g0_or) / np.linalg.norm(g0_or)
-    dz_g = np.linalg.norm(zg - zs) / np.linalg.norm(z0 - zs)
-    dz_o = np.linalg.norm(zo - zs) / np.linalg.norm(z0 - zs)
-    _log("latent fit: gradient at start rel", rel0)
-    for it in checks:
-        _log("  it", it, "loss hip", loss_g[it], "oracle", loss_o[it])
-    _log("  |z - z*| / |z0 - z*|: hip", dz_g, "oracle", dz_o)
+    rel0 = np.linalg.norm(g_gpu[0] - g_or[0]) / np.linalg.norm(g_or[0])
+    _log("latent fit: gradient at start rel", rel0, "loss hip", loss_g[0], "oracle", loss_o[0])
     assert rel0 <= 1e-3
-    # the same start and first step; Adam's per-coordinate normalisation then
-    # lets float32 and float64 runs drift apart (coordinates with near-zero
-    # gradient move by +-lr either way), so later the curves are only required
-    # to fit equally well
     assert abs(loss_g[0] - loss_o[0]) <= 1e-4 * loss_o[0]
-    assert abs(loss_g[1] - loss_o[1]) <= 1e-3 * loss_o[0]
-    assert abs(loss_g[10] - loss_o[10]) <= 2e-2 * loss_o[0]
+    # the first Adam step moves every coordinate by lr sign(g): the same code
+    # on both sides wherever the two gradients agree in sign
+    if np.array_equal(np.sign(g_gpu[0]), np.sign(g_or[0])):
+        rel1 = np.linalg.norm(g_gpu[1] - g_or[1]) / np.linalg.norm(g_or[1])
+        _log("  gradient after one step rel", rel1)
+        assert rel1 <= 1e-3
+    for it in checks:
+        Lg, g = _gpu_gradient(ctx, cams, prm, torch.tensor(z_or[it].astype(np.float32), device="cuda"), dtt, stt)
+        g = g.double().cpu().numpy()[0]
+        rel = np.linalg.norm(g - g_or[it]) / np.linalg.norm(g_or[it])
+        _log("  at the oracle's z of iteration", it, "gradient rel", rel, "loss hip", Lg, "oracle", loss_o[it])
+        assert rel <= 1e-3
+        assert abs(Lg - loss_o[it]) <= 1e-3 * loss_o[0]
+    _log("  loss at the end: hip", loss_g[iters - 1], "oracle", loss_o[iters - 1])
     assert loss_g[iters - 1] <= 0.1 * loss_g[0] and loss_o[iters - 1] <= 0.1 * loss_o[0]
 
 

@@ -345,6 +345,7 @@ def test_render_bf16_batch():
     out = _gpu_render(spec, cams, Z, prm)
     dec = oracle_decoder(spec)
     tot_px, tot_mis, worst = 0, 0, 0.0
+    all_err, excluded = [], 0
     for i in range(4):
         v, l = i // 2, i % 2
         o = O.render(dec, Z, cams, [(v, l)], prm)[0]
@@ -354,6 +355,8 @@ def test_render_bf16_batch():
         cosv = np.abs(np.sum(D * o.normal, axis=-1))
         wc = both & (cosv >= 0.25)
         err = np.abs(o.depth[wc] - g["depth"][wc])
+        all_err.append(np.abs(o.depth[both] - g["depth"][both]))
+        excluded += int(both.sum() - wc.sum())
         mis = int(((o.sil < 0) != (g["sil"] < 0)).sum())
         ln = np.linalg.norm(o.nraw[wc], axis=-1)
         dn = (np.linalg.norm(o.normal[wc] - g["normal"][wc], axis=-1) * ln).max()
@@ -363,14 +366,25 @@ def test_render_bf16_batch():
         worst = max(worst, float(err.max()))
         tot_px += H * H
         tot_mis += mis
+    # every hit both renders agree on, grazing ones included: reported, and
+    # the share beyond the 2e-3 bound kept small
+    e = np.concatenate(all_err)
+    _log("  all hits in both:", e.size, "max", float(e.max()), "p99.9", float(np.percentile(e, 99.9)),
+         "above 2e-3:", int((e > 2e-3).sum()), "excluded as grazing:", excluded)
     assert worst <= 2e-3
+    assert (e > 2e-3).mean() <= 1e-2
     assert tot_mis <= max(2, tot_px // 1000)
 
 
 # ----------------------------------------------------------------------------
 # backward (paper gradient), free running
 # ----------------------------------------------------------------------------
-def _grad_case(spec, prm, H, n_views, n_lat, w_n):
+def _grad_case(spec, prm, H, n_views, n_lat, w_n, w_d=10.0, w_s=1.0, sil_hits=False):
+    """Free-running dL/dz of a loss on the oracle's maps: the GPU backward of
+    its own render against the oracle's backward of the oracle's render, with
+    the seeds of the oracle's loss (no GPU value enters the oracle).  With
+    sil_hits the seeds are instead +-1e-3 dL/dS on every oracle hit pixel
+    (the silhouette term where |f| < eps at the minimum-|f| query)."""
     from paper_1911_13225_amd import api
     cams = [di.front_camera(H, H)] if n_views == 1 else di.random_sphere_cameras(n_views, H, H)
     Z = di.make_latents(n_lat, spec.latent_dim, sigma=0.05)
@@ -379,10 +393,15 @@ def _grad_case(spec, prm, H, n_views, n_lat, w_n):
     dec = oracle_decoder(spec)
     pairs = [(i // n_lat, i % n_lat) for i in range(n_views * n_lat)]
     renders = O.render(dec, Z, cams, pairs, prm)
+    rng = np.random.Generator(np.random.PCG64(17))
     grads, gd, gn, gs = [], [], [], []
     for r, (v, l) in zip(renders, pairs):
         dt, nt, stt = di.sphere_target_maps(cams[v], 0.5)
-        _, g_d, g_n, g_s = O.loss_and_grads(r, dt, nt, stt, w_d=10.0, w_s=1.0, w_n=w_n)
+        _, g_d, g_n, g_s = O.loss_and_grads(r, dt, nt, stt, w_d=w_d, w_s=w_s, w_n=w_n)
+        if sil_hits:
+            g_d = np.zeros_like(g_d)
+            g_n = np.zeros_like(g_n)
+            g_s = np.where(r.status == O.HIT, rng.choice([-1e-3, 1e-3], size=r.status.shape), 0.0)
         grads.append((g_d, g_n, g_s))
         gd.append(g_d)
         gn.append(g_n)
@@ -409,17 +428,36 @@ def test_backward_fp32(case):
     assert rel <= 1e-3
 
 
-@pytest.mark.parametrize("spec,w_n", [(di.DEEPSDF_SPEC, 1.0), (di.C1_SPEC, 0.0)], ids=["deepsdf", "c1"])
-def test_backward_bf16(spec, w_n):
-    """Free running against the oracle: depth + silhouette + normal loss on
-    the DeepSDF decoder (0.7% measured); depth + silhouette on the 128-wide
-    decoder, whose 8-wave kernels split their rows into two groups of column
-    sums (0.4% measured; its normal term, a difference of two bf16 VJPs scaled
-    by 1/(2 delta), measures 1.05% and is checked against the recompute by
-    test_backward_saved_masks_match_recompute)."""
+@pytest.mark.parametrize("case", ["mixed", "depth", "silhouette", "normal", "silhouette_at_hits"])
+def test_backward_fp32_per_term(case):
+    """Each term of the loss on its own, float32 path (DeepSDF decoder)."""
+    spec = di.DEEPSDF_SPEC
+    prm = cfg_params("c2", precision=0)
+    w = {"mixed": (10.0, 1.0, 1.0), "depth": (10.0, 0.0, 0.0), "silhouette": (0.0, 1.0, 0.0),
+         "normal": (0.0, 0.0, 1.0), "silhouette_at_hits": (0.0, 0.0, 0.0)}[case]
+    rel, g, go = _grad_case(spec, prm, 48, 2, 2, w[2], w_d=w[0], w_s=w[1], sil_hits=case == "silhouette_at_hits")
+    _log("backward fp32 term", case, "rel", rel, "|g|", np.linalg.norm(go))
+    assert rel <= 1e-3
+
+
+BF16_TERM_CASES = [
+    ("deepsdf", "mixed"), ("deepsdf", "depth"), ("deepsdf", "silhouette"), ("deepsdf", "normal"),
+    ("deepsdf", "silhouette_at_hits"),
+    ("c1", "mixed"), ("c1", "depth+silhouette"), ("c1", "normal"), ("c1", "silhouette_at_hits"),
+]
+
+
+@pytest.mark.parametrize("dec_name,case", BF16_TERM_CASES, ids=[f"{a}-{b}" for a, b in BF16_TERM_CASES])
+def test_backward_bf16_per_term(dec_name, case):
+    """Free running against the oracle, bf16 path, each loss term on its own
+    and the benchmark's mix (10 L1 depth + silhouette + normal).  The 128-wide
+    decoder's 8-wave kernels split their rows into two groups of column sums."""
+    spec = di.DEEPSDF_SPEC if dec_name == "deepsdf" else di.C1_SPEC
     prm = cfg_params("c3", precision=1)
-    rel, g, go = _grad_case(spec, prm, 48, 2, 2, w_n)
-    _log("backward bf16 rel", rel)
+    w = {"mixed": (10.0, 1.0, 1.0), "depth": (10.0, 0.0, 0.0), "silhouette": (0.0, 1.0, 0.0),
+         "normal": (0.0, 0.0, 1.0), "depth+silhouette": (10.0, 1.0, 0.0), "silhouette_at_hits": (0.0, 0.0, 0.0)}[case]
+    rel, g, go = _grad_case(spec, prm, 48, 2, 2, w[2], w_d=w[0], w_s=w[1], sil_hits=case == "silhouette_at_hits")
+    _log("backward bf16", dec_name, case, "rel", rel, "|g|", np.linalg.norm(go))
     assert rel <= 1e-2
 
 

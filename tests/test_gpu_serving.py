@@ -143,3 +143,134 @@ def test_admission_refuses_requests_beyond_the_budget():
         assert e.value.code == -1
     finally:
         c.close()
+
+
+def _oracle_fit(dec, cams, pairs, prm, z0, dt, st, iters, lr=1e-2):
+    """The oracle's latent fit: render -> loss_and_grads -> backward -> Adam."""
+    from oracle import dist_oracle as O
+    zo = z0.astype(np.float64).copy()
+    m = np.zeros_like(zo)
+    v = np.zeros_like(zo)
+    losses, gs, renders = [], [], []
+    for it in range(iters):
+        rs = O.render(dec, zo[None], cams, pairs, prm)
+        grads, L = [], 0.0
+        for r, d_t, s_t in zip(rs, dt, st):
+            l, g_d, g_n, g_s = O.loss_and_grads(r, d_t, np.zeros(d_t.shape + (3,)), s_t, w_d=10.0, w_s=1.0)
+            grads.append((g_d, g_n, g_s))
+            L += l
+        g = O.backward(dec, zo[None], rs, pairs, prm, grads, want_theta=False)[0][0]
+        losses.append(L)
+        gs.append(g)
+        renders.append(rs)
+        zo, m, v = O.adam_step(zo, g, m, v, it + 1, lr=lr)
+    return zo, losses, gs, renders
+
+
+def test_served_zopt_matches_oracle_loop(ctx):
+    """A served latent-optimisation job (bf16 march, split-precision recompute,
+    device loss, adjoint and Adam) against the oracle's own loop from the same
+    start and targets.
+
+    Adam is invariant to the scale of the gradient and its first step moves
+    every coordinate by lr sign(g), so the code it returns checks the
+    gradient's direction coordinate by coordinate: after one iteration every
+    coordinate whose oracle gradient is clear of the bf16 gradient error
+    (|g_j| > 5% of max |g|) must have moved by exactly -lr sign(g_j), and none
+    by more than lr.  After three iterations those coordinates (clear at every
+    iteration, one sign) must agree with the oracle's code to 0.3 lr (each
+    step is lr m/sqrt(v), a ratio of gradients that agree to a few percent per
+    coordinate), and every coordinate to 2 lr per step.  The loss the job
+    reports is the loss of its last render: it must equal the loss of the maps
+    it returned (float32 summation order), and the oracle's loss at the same
+    iteration up to what the bf16 render tolerances allow, w_d 2e-3 per
+    foreground pixel plus w_s 2e-3 per pixel inside the unit sphere, per H W."""
+    from paper_1911_13225_amd import api, _native as N
+    from _common import oracle_decoder
+    spec = di.DEEPSDF_SPEC
+    dec = oracle_decoder(spec)
+    H = 32
+    cams = di.random_sphere_cameras(2, H, H, base_seed=2100)
+    pairs = [(0, 0), (1, 0)]
+    prm = _prm(want_normals=0)
+    from oracle import dist_oracle as O
+    zs = di.make_latents(1, 256, sigma=0.1, base_seed=3000)
+    tg = O.render(dec, zs, cams, pairs, prm)
+    dt = np.stack([np.where(np.isfinite(t.depth), t.depth, 0.0) for t in tg]).astype(np.float32)
+    st = np.stack([(t.sil < 0).astype(np.float32) for t in tg])
+    z0 = di.make_latents(1, 256, sigma=0.01, base_seed=1000)[0]
+    td, ts = torch.tensor(dt, device="cuda"), torch.tensor(st, device="cuda")
+    lr = 1e-2
+    for iters in (1, 3):
+        _log("served z-opt vs oracle loop, iterations", iters)
+        req = api.ServeRequest(N.REQ_ZOPT, cams, torch.tensor(z0, device="cuda"), prm, want_normals=False,
+                               targets=(td, ts), iters=iters, lr=lr)
+        api.dist_submit(ctx, req)
+        res = api.dist_poll(ctx, req, 120_000_000)
+        assert res is not None and res["status"] == 0
+        zo, losses, grads, renders = _oracle_fit(dec, cams, pairs, prm, z0, dt.astype(np.float64),
+                                                 st.astype(np.float64), iters, lr)
+        zg = req.z_out.double().cpu().numpy()
+        # the reported loss is that of the returned maps (last iteration)
+        depth, sil = req.depth.double().cpu().numpy(), req.sil.double().cpu().numpy()
+        fg = (sil < 0) & (st > 0.5)
+        L_maps = (10.0 * np.abs(np.where(fg, depth - dt, 0.0)).sum()
+                  + (st * np.maximum(sil, 0) + (1 - st) * np.maximum(-sil, 0)).sum()) / (H * H)
+        _log("  final loss", res["final_loss"], "of its maps", L_maps, "oracle", losses[-1])
+        assert abs(res["final_loss"] - L_maps) <= 1e-5 * L_maps
+        n_fg = sum(int((r.status == O.HIT).sum()) for r in renders[-1])
+        n_in = sum(int((r.status != O.MISS).sum()) for r in renders[-1])
+        bound = (10.0 * 2e-3 * n_fg + 2e-3 * n_in) / (H * H)
+        assert abs(res["final_loss"] - losses[-1]) <= bound, (res["final_loss"], losses[-1], bound)
+        gmax = [np.abs(g).max() for g in grads]
+        clear = np.all([np.abs(g) > 0.05 * m for g, m in zip(grads, gmax)], axis=0)
+        clear &= np.all([np.sign(g) == np.sign(grads[0]) for g in grads], axis=0)
+        assert clear.sum() >= 10
+        dz = zg - z0.astype(np.float64)
+        if iters == 1:
+            np.testing.assert_allclose(dz[clear], -lr * np.sign(grads[0][clear]), rtol=1e-4, atol=0)
+            assert np.all(np.abs(dz) <= lr * (1 + 1e-4))
+        else:
+            err = np.abs(zg - zo)
+            _log("  |z - z_oracle| on", int(clear.sum()), "clear coordinates: max", err[clear].max() / lr, "lr")
+            assert np.all(err[clear] <= 0.3 * lr)
+            assert np.all(err <= 2 * lr * iters)
+
+
+def test_slot_reuse_after_a_request_ends_by_max_steps():
+    """A request that stops at max_steps leaves its stopped rays in the last
+    pooled list; a request of another resolution admitted into the freed ray
+    slots at the next tick must render exactly as it does alone."""
+    from paper_1911_13225_amd import api, _native as N
+    spec = di.C1_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    budget = 18 << 20           # a pool of 65536 ray slots: A or B, never both
+
+    def b_request():
+        cams = di.random_sphere_cameras(1, 224, 224, base_seed=2300)
+        z = torch.tensor(di.make_latents(1, 64, sigma=0.02, base_seed=5300)[0], device="cuda")
+        return api.ServeRequest(N.REQ_RENDER, cams, z, _prm(c2f_levels=2), want_normals=True)
+
+    c = api.Context.from_spec(spec, Ws, bs, hbm_budget=budget)
+    try:
+        alone = b_request()
+        api.dist_submit(c, alone)
+        assert api.dist_poll(c, alone, 60_000_000)["status"] == 0
+        cams_a = di.random_sphere_cameras(3, 128, 128, base_seed=2400)
+        za = torch.tensor(di.make_latents(1, 64, sigma=0.02, base_seed=5400)[0], device="cuda")
+        a = api.ServeRequest(N.REQ_RENDER, cams_a, za, _prm(c2f_levels=0, max_steps=4), want_normals=False)
+        b = b_request()
+        api.dist_submit(c, a)
+        api.dist_submit(c, b)
+        ra = api.dist_poll(c, a, 60_000_000)
+        rb = api.dist_poll(c, b, 60_000_000)
+        assert ra["status"] == 0 and rb["status"] == 0
+        n_unconv = int((a.status == 4).sum())
+        _log("slot reuse: A rays stopped at max_steps", n_unconv)
+        assert n_unconv > 1000
+        assert torch.equal(alone.depth, b.depth)
+        assert torch.equal(alone.sil, b.sil)
+        assert torch.equal(alone.status, b.status)
+        assert torch.equal(alone.normal, b.normal)
+    finally:
+        c.close()
