@@ -117,6 +117,21 @@ class Decoder:
             delta = g_h * (pre[l - 1] > 0.0)
         return gZ, gW, gb
 
+    def relu_margin(self, Z, P):
+        """Smallest |pre-activation| over all hidden units at each point [n].
+
+        A ReLU pattern is an integer decision taken in floating point: the
+        derivative of f jumps when a unit crosses zero, so a gradient sample
+        whose margin is below the rounding error of its point (or of the
+        arithmetic) is ill-conditioned, and two correct implementations may
+        disagree there by a finite amount."""
+        Z = np.asarray(Z, np.float64)
+        P = np.asarray(P, np.float64)
+        if P.shape[0] == 0:
+            return np.zeros(0)
+        _, _, pre = self.layer_inputs(Z, P, keep=True)
+        return np.min(np.stack([np.abs(a).min(axis=1) for a in pre[:-1]], axis=1), axis=1)
+
     def sdf_grad_p(self, Z, P, seeds):
         """seeds_i * grad_p f(P_i, Z_i) [n,3]: the spatial gradient of f through
         the residual term 0.5 |p| and the point columns of layer 0 and of the
@@ -606,6 +621,32 @@ def gradient_samples(r: Render, prm, g_depth, g_normal, g_sil):
             pts.append(p - e)
             seeds.append(-gnr[:, i] / (2.0 * delta))
     return np.concatenate(pts, 0), np.concatenate(seeds, 0)
+
+
+def sample_relu_margin(dec: Decoder, z, r: Render, prm) -> np.ndarray:
+    """[H,W] smallest ReLU margin (Decoder.relu_margin) over every point at
+    which the paper gradient of a pixel may evaluate the decoder: its K
+    minimum-|f| records (the first is also the silhouette sample) and, for
+    hits, the six central-difference queries around c + d v (Sec. 3.3, 3.4).
+    Background pixels without samples get +inf."""
+    n = r.H * r.W
+    out = np.full(n, np.inf)
+    st = r.status.reshape(-1)
+    c = r.c
+    for j in range(int(prm.k_samples)):
+        sel = (st != MISS) & np.isfinite(r.rec_absf[j])
+        P = c[None, :] + r.rec_t[j, sel, None] * r.dirs[sel]
+        mg = dec.relu_margin(np.broadcast_to(z, (P.shape[0], z.shape[0])), P)
+        out[sel] = np.minimum(out[sel], mg)
+    if int(prm.want_normals):
+        hit = st == HIT
+        p = c[None, :] + r.dist.reshape(-1)[hit, None] * r.dirs[hit]
+        zz = np.broadcast_to(z, (p.shape[0], z.shape[0]))
+        for i in range(3):
+            e = np.zeros(3)
+            e[i] = float(prm.normal_delta)
+            out[hit] = np.minimum(out[hit], np.minimum(dec.relu_margin(zz, p + e), dec.relu_margin(zz, p - e)))
+    return out.reshape(r.H, r.W)
 
 
 def backward(dec: Decoder, Z, renders: Sequence[Render], pairs, prm, grads, want_theta=True):

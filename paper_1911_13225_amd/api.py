@@ -313,8 +313,8 @@ def dist_render_loss(depth, normal, sil, depth_t, normal_t, sil_t, w_d=10.0, w_s
     d, s, dt, st = [x.detach().float().contiguous() for x in (depth, sil, depth_t, sil_t)]
     n_img, H, W = d.shape
     use_n = float(w_n) != 0.0
-    nr = normal.detach().float().contiguous() if use_n else None
-    ntr = normal_t.detach().float().contiguous() if use_n else None
+    nr = normal.detach().float().contiguous() if use_n and normal is not None else None
+    ntr = normal_t.detach().float().contiguous() if use_n and normal_t is not None else None
     loss = torch.empty(n_img, device=d.device)
     gd = torch.empty_like(d) if want_grad else None
     gs = torch.empty_like(d) if want_grad else None

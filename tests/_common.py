@@ -59,3 +59,27 @@ def compare_render(o, g, eps, mu=2e-5, depth_tol=1e-4):
                 sil_max=float(ds.max()) if ds.size else 0.0,
                 sil_mismatch=int((fg_o != fg_g).sum()), hits=int((st_o == 1).sum()),
                 flip_idx=np.nonzero(flips)[0])
+
+
+def well_conditioned(dec, z, r, prm, depth_t=None, sil_t=None, mu_march=2e-5, mu_relu=1e-6, mu_f=1e-6,
+                     mu_res=1e-5):
+    """[H,W] bool: pixels whose paper gradient is a well-conditioned function
+    of the render, judged from the oracle alone (no GPU value enters).
+
+    A pixel is kept when every floating-point decision its gradient depends
+    on is farther from its threshold than the rounding of a float32 path can
+    move it: the march decisions (status, step count; ``Render.margin``), the
+    ReLU patterns at every gradient sample (``O.sample_relu_margin``), the
+    sign of f at the minimum-|f| query (silhouette seed) and, given a target
+    depth, the sign of the depth residual."""
+    from oracle import dist_oracle as O
+    keep = r.margin > mu_march
+    if mu_relu > 0:
+        keep &= O.sample_relu_margin(dec, z, r, prm) > mu_relu
+    f0 = r.rec_f[0].reshape(r.H, r.W)
+    keep &= (r.status == O.MISS) | (np.abs(f0) > mu_f)
+    if depth_t is not None:
+        fg = (r.sil < 0) & ((np.asarray(sil_t) > 0.5) if sil_t is not None else True)
+        res = np.where(fg, r.depth - np.where(fg, depth_t, 0.0), np.inf)
+        keep &= ~fg | (np.abs(res) > mu_res)
+    return keep
