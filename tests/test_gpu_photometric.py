@@ -5,8 +5,9 @@ a procedurally textured sphere), so the comparison is of the loss itself: the
 total to 1e-5 relative, dL/d(depth) per pixel to 1e-4 of its largest value on
 all but 0.1% of the pixels (float32 and float64 may take a visibility or
 footprint decision differently at a boundary).  End to end, the tracer's
-depth, the loss and the paper's backward give dL/dz within 2e-2 of the
-oracle's free-running pipeline.
+depth (float32), the loss and the paper's backward give the loss within 1e-4
+and dL/dz within 1e-3 (the float32 dL/dz bound) of the oracle's free-running
+pipeline.
 """
 import sys
 
@@ -87,8 +88,8 @@ def test_photometric_pipeline_gradient_matches_oracle():
     out["saved"].free()
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     _log("photometric loss", float(loss.item()), "oracle", L_o, "dL/dz rel", rel)
-    assert abs(float(loss.item()) - L_o) <= 1e-2 * L_o
-    assert rel <= 2e-2
+    assert abs(float(loss.item()) - L_o) <= 1e-4 * L_o
+    assert rel <= 1e-3
 
 
 def test_photometric_invalid_arguments():
