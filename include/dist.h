@@ -350,6 +350,21 @@ int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
                   const float* z, int32_t n_latents, int64_t n, int32_t precision,
                   float* f, void* stream);
 
+/* The decoder query of dist_sdf_eval without any allocation, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, result and
+ * errors as dist_sdf_eval; its one scratch buffer (the per-latent folded
+ * biases) is a fixed 1 MiB array per GPU that the library takes at
+ * dist_create and keeps until the process ends, so n_latents * (width of
+ * layer 0 + width of the skip layer) must fit 262144 floats (256 latents for
+ * the DeepSDF decoder; larger requests return DIST_EINVAL).  The context's
+ * device must be current.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (two streams, two threads, two contexts) race and
+ * must be serialised by the caller.  No timing hooks are recorded. */
+int dist_sdf_eval_noalloc(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
+                          const float* z, int32_t n_latents, int64_t n, int32_t precision,
+                          float* f, void* stream);
+
 /* Vector-Jacobian product of the decoder at detached points (the per-sample
  * term of Eq. 2): g_z[l] = sum_{i: latent_ids[i] = l} seeds[i] df(points[i],
  * z_l)/dz_l, and optionally the weight gradient.  precision DIST_FP32

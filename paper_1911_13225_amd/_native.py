@@ -90,6 +90,8 @@ _SIGS = [
                                            ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     ("dist_saved_free", ctypes.c_int, [_P]),
     ("dist_sdf_eval", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P, _P]),
+    ("dist_sdf_eval_noalloc", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P,
+                                             _P]),
     ("dist_sdf_vjp", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P,
                                     ctypes.POINTER(_P), ctypes.POINTER(_P), _P]),
     ("dist_submit", ctypes.c_int, [_P, ctypes.POINTER(dist_request), ctypes.POINTER(ctypes.c_uint64)]),

@@ -264,6 +264,15 @@ def dist_sdf_eval(ctx: Context, points: torch.Tensor, latent_ids: torch.Tensor, 
     return f
 
 
+def dist_sdf_eval_noalloc(ctx: Context, points: torch.Tensor, latent_ids: torch.Tensor, z: torch.Tensor,
+                          precision: int, out: torch.Tensor):
+    """dist_sdf_eval into the caller's `out` [n] with no allocation anywhere:
+    inputs must already be contiguous float32 / int32 device tensors."""
+    check(ctx.lib.dist_sdf_eval_noalloc(ctx.handle, _ptr(points), _ptr(latent_ids), _ptr(z), z.shape[0],
+                                        points.shape[0], int(precision), _ptr(out), _stream()))
+    return out
+
+
 def dist_sdf_vjp(ctx: Context, points, latent_ids, seeds, z, precision: int, want_theta: bool = False):
     n = points.shape[0]
     g_z = torch.empty(z.shape[0], ctx.latent_dim, device=points.device)

@@ -45,6 +45,37 @@ int dist_set_error(int code, const char* fmt, ...) {
   } while (0)
 
 extern "C" const char* dist_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free decoder query (dist_sdf_eval_noalloc): the
+// per-latent folded biases live in this array instead of a workspace.  Each
+// GPU holds its own copy for the life of the process.  Host code must never
+// pass `scratch` itself to a kernel (on the host it is only a stand-in
+// symbol): its device address is taken once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchFloats = size_t(1) << 18;   // 1 MiB per GPU
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Resolve the scratch address on `device`, which must be the current device.
+static int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return dist_set_error(DIST_EINVAL, "device %d is beyond the %d devices the scratch table covers", device,
+                          kMaxScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return DIST_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return dist_set_error(DIST_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                          hipGetErrorString(e));
+  g_scratch_ptr[device] = (float*)ptr;
+  return DIST_OK;
+}
+
 extern "C" const char* dist_version(void) { return "dist-mi355x 0.1 (gfx950)"; }
 
 // ---------------------------------------------------------------------------
@@ -259,6 +290,7 @@ extern "C" int dist_create(dist_ctx** out, const dist_decoder_desc* desc, const 
       }
     }
   }
+  if (rc == DIST_OK) rc = scratch_setup(ctx->device);
   if (rc != DIST_OK) { dist_destroy(ctx); return rc; }
   *out = ctx;
   return DIST_OK;
@@ -1432,6 +1464,49 @@ extern "C" int dist_sdf_eval(dist_ctx* ctx, const float* points, const int32_t* 
   }
   ws_put(ctx, w);
   return rc;
+}
+
+extern "C" int dist_sdf_eval_noalloc(dist_ctx* ctx, const float* points, const int32_t* latent_ids, const float* z,
+                                     int32_t n_latents, int64_t n, int32_t precision, float* f, void* stream) {
+  if (!ctx) return dist_set_error(DIST_EINVAL, "null argument");
+  if (ctx->n_out != 1) return dist_set_error(DIST_EINVAL, "a colour network has no signed distance");
+  if (n == 0) return DIST_OK;                       // nothing is read or written
+  if (!points || !latent_ids || !z || !f) return dist_set_error(DIST_EINVAL, "null argument");
+  if (n < 0 || n > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "n out of range");
+  if (n_latents < 1) return dist_set_error(DIST_EINVAL, "n_latents must be positive");
+  if (precision < 0 || precision > 2) return dist_set_error(DIST_EINVAL, "bad precision");
+  const size_t per_lat = (size_t)ctx->wpad[0] + (ctx->skip >= 0 ? (size_t)ctx->wpad[ctx->skip] : 0);
+  if ((size_t)n_latents * per_lat > kNoAllocScratchFloats)
+    return dist_set_error(DIST_EINVAL, "n_latents = %d exceeds the allocation-free scratch (%zu floats: at most %zu "
+                          "latents for this decoder)", n_latents, kNoAllocScratchFloats,
+                          kNoAllocScratchFloats / per_lat);
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != ctx->device)
+    return dist_set_error(DIST_EINVAL, "the context's device (%d) must be current (device %d is)", ctx->device, dev);
+  float* sp = g_scratch_ptr[dev];
+  if (!sp) return dist_set_error(DIST_EHIP, "the scratch of device %d was not set up", dev);
+  hipStream_t st = (hipStream_t)stream;
+  // the folded biases overwrite their whole range, so nothing needs clearing
+  float* b0 = sp;
+  float* bS = sp + (size_t)n_latents * ctx->wpad[0];
+  launch_fold_bias(ctx->bf[0], ctx->w0z, z, n_latents, ctx->L, ctx->out_dims[0], ctx->wpad[0], b0, st);
+  if (ctx->skip >= 0)
+    launch_fold_bias(ctx->bf[ctx->skip], ctx->wsz, z, n_latents, ctx->L, ctx->out_dims[ctx->skip],
+                     ctx->wpad[ctx->skip], bS, st);
+  EvalArgs ea{};
+  ea.net = ctx->net[precision];
+  ea.bias0_lat = b0;
+  ea.biasS_lat = ctx->skip >= 0 ? bS : b0;
+  ea.mode = 0;
+  ea.pts = points;
+  ea.lat = latent_ids;
+  ea.n = n;
+  ea.n_lat = n_latents;
+  ea.f_out = f;
+  launch_eval(precision, ea, mlp_grid(ctx, n, precision), st);
+  HIPCHK(hipGetLastError());
+  return DIST_OK;
 }
 
 extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* latent_ids, const float* seeds,
