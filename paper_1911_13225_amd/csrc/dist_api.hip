@@ -728,15 +728,17 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
   ma.bias0_lat = w->bias0_lat;
   ma.biasS_lat = w->biasS_lat;
   ma.qcount = w->qcount;
-  for (int n = 0; n < prm->max_steps; ++n) {
-    const int lv = std::max(L - n / 3, 0);
+  ma.t_hist = t_hist;
+  // steps before the last coarse-to-fine split: one launch per step, every
+  // image splitting after the same steps
+  for (int n = 0; n < 3 * L; ++n) {
+    const int lv = L - n / 3;
     const long long rays = (long long)n_img * (hw >> (2 * lv));
     ma.list = w->list[n & 1];
     ma.count = w->counters + n;
-    ma.t_hist = t_hist ? t_hist + (size_t)n * w->pool.cap : nullptr;
-    // every image splits after the same steps: then the children replace the
-    // rays, otherwise the march step appends its survivors to the next list
-    const bool split = n % 3 == 2 && lv > 0;
+    // at a split the children replace the rays, otherwise the march step
+    // appends its survivors to the next list
+    const bool split = n % 3 == 2;
     int* nxt = w->list[(n + 1) & 1];
     int* ncnt = w->counters + n + 1;
     ma.next_list = split ? nullptr : nxt;
@@ -748,6 +750,23 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
     }
     if (split)
       launch_split(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * (lv - 1)), lv - 1, n + 1, nxt, ncnt, st);
+  }
+  // full resolution: every remaining step in one launch; the rays of the
+  // step's list are claimed into per-workgroup rings carved from the other
+  // list (grid and ring size bounded by its capacity)
+  {
+    const int n = 3 * L;
+    const long long cap = w->pool.cap;
+    const int grid = (int)std::max(1LL, std::min<long long>(ctx->n_cu, cap / 256));
+    ma.list = w->list[n & 1];
+    ma.count = w->counters + n;
+    ma.next_list = w->list[(n + 1) & 1];
+    ma.next_count = nullptr;
+    ma.claim = w->counters + n + 1;
+    ma.ring_cap = (int)std::min<long long>(4096, cap / grid);
+    ma.rows_done = (ctx->timing && ctx->d_rows) ? ctx->d_rows + 0 : nullptr;
+    TimedLaunch tl(ctx, 0, st);
+    launch_march_ring(prec, ma, grid, st);
   }
   HIPCHK(hipGetLastError());
   return DIST_OK;

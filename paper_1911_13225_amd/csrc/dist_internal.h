@@ -96,7 +96,10 @@ struct MarchArgs {
   // builds the next list itself, e.g. at a coarse-to-fine split)
   int* next_list;
   int* next_count;
-  float* t_hist;                   // per ray slot: t of this step (or null)
+  float* t_hist;                   // [max_steps][pool.cap]: t of each ray at each of its steps (or null)
+  unsigned long long* rows_done;   // k_march_ring: queries made, added at the end (or null)
+  int* claim;                      // k_march_ring: rays of `list` claimed so far (starts at 0)
+  int ring_cap;                    // k_march_ring: ring slots per workgroup in next_list
 };
 
 struct EvalArgs {
@@ -178,6 +181,8 @@ size_t adj_mask_words(int precision, const NetDev& net);   // per workgroup
 hipError_t mlp_setup(int precision, const NetDev& net);    // raise LDS limits
 
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t s);
+// every remaining step in one launch (rays claimed from list into per-workgroup rings in next_list)
+void launch_march_ring(int precision, const MarchArgs& a, int grid, hipStream_t s);
 void launch_eval(int precision, const EvalArgs& a, int grid, hipStream_t s);
 // recompute-and-VJP: precision kPrecSplit or kPrecF32 (no bf16 variant; other
 // values launch nothing); VJP from saved masks: any precision

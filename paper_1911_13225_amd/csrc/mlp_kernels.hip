@@ -991,91 +991,112 @@ __device__ __forceinline__ void wg_append(bool flag, int value, int* list, int* 
 // ---------------------------------------------------------------------------
 // March step (Alg. 1 with aggressive steps, convergence and escape; Sec. 3.2)
 // ---------------------------------------------------------------------------
+// Load the rays of one tile: row i < k takes ray slot rid_of(i), the other
+// rows of the M-row tile stay idle (rid -1).  With a history buffer the
+// ray's t is recorded at its own step (t_hist[n][slot], stride pool.cap).
+template <int P, int M, class RidOf>
+__device__ __forceinline__ void march_load(const MarchArgs& a, const Sm<P>& s, int k, RidOf rid_of) {
+  const int tid = threadIdx.x;
+  if (tid < M) {
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    int lt = 0, r = -1;
+    if (tid < k) {
+      r = rid_of(tid);
+      const ImgDesc& im = a.imgs[a.pool.img[r]];
+      const float4 d = a.pool.d[r];
+      p = make_float4(fmaf(d.w, d.x, im.c[0]), fmaf(d.w, d.y, im.c[1]), fmaf(d.w, d.z, im.c[2]), 0.f);
+      lt = im.latent;
+      if (a.t_hist) a.t_hist[(size_t)a.pool.n[r] * a.pool.cap + r] = d.w;
+    }
+    s.pts[tid] = p;
+    s.lat[tid] = lt;
+    s.rid[tid] = r;
+  }
+  __syncthreads();
+}
+
+// One decoder query per loaded row and the march epilogue: running top-K of
+// |f|, convergence (|f| < eps, Eq. 1), the step limit, the aggressive step
+// t += alpha f and the unit-sphere escape test.  Returns whether this
+// thread's ray is still ACTIVE; the queries are counted per image.
+template <int P, int M>
+__device__ __forceinline__ bool march_eval(const MarchArgs& a, const Sm<P>& s) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wn = mlp_forward<P, kFwdWaves<P>, M, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
+  bool still = false;
+  if (tid < M && s.rid[tid] >= 0) {
+    float m = a.net.blast;
+    for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
+    const float4 p = s.pts[tid];
+    const float f = sdf_from_m(p, m);
+    const int r = s.rid[tid];
+    const RayPool& pl = a.pool;
+    const ImgDesc& im = a.imgs[pl.img[r]];
+    const int n = pl.n[r];
+    float4 d = pl.d[r];
+    const float t = d.w;
+    // running K smallest |f| (ties keep the earlier step)
+    const float af = fabsf(f);
+    const int Kr = im.K;
+    float rec_abs[kMaxK];
+    for (int k = 0; k < Kr; ++k) rec_abs[k] = fabsf(pl.rec_f[(size_t)k * pl.cap + r]);
+    const int pos = topk_rank(af, rec_abs, Kr);
+    for (int k = Kr - 1; k > pos; --k) {
+      pl.rec_f[(size_t)k * pl.cap + r] = pl.rec_f[(size_t)(k - 1) * pl.cap + r];
+      pl.rec_t[(size_t)k * pl.cap + r] = pl.rec_t[(size_t)(k - 1) * pl.cap + r];
+      pl.rec_n[(size_t)k * pl.cap + r] = pl.rec_n[(size_t)(k - 1) * pl.cap + r];
+    }
+    if (pos < Kr) {
+      pl.rec_f[(size_t)pos * pl.cap + r] = f;
+      pl.rec_t[(size_t)pos * pl.cap + r] = t;
+      pl.rec_n[(size_t)pos * pl.cap + r] = (uint8_t)n;
+    }
+    pl.flast[r] = f;
+    uint8_t st;
+    if (!(af == af) || af == INFINITY) {
+      st = ST_UNCONVERGED;                   // non-finite query: stop the ray
+    } else if (af < im.eps) {
+      st = ST_HIT;
+    } else if (n == im.max_steps - 1) {
+      st = ST_UNCONVERGED;
+    } else {
+      const float tn = fmaf(im.alpha, f, t);
+      const float2 b = pl.b[r];
+      st = (tn > b.y || tn < b.x) ? ST_ESCAPED : ST_ACTIVE;
+      d.w = tn;
+      pl.d[r] = d;
+    }
+    pl.st[r] = st;
+    pl.n[r] = (uint8_t)(n + 1);
+    still = st == ST_ACTIVE;
+  }
+  if (a.qcount && tid < M) {
+    // queries of this tile per image, one atomic per distinct image in a wave
+    const int r = s.rid[tid];
+    const bool valid = r >= 0;
+    const int img = valid ? a.pool.img[r] : -1;
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int li = __shfl(img, leader);
+      const unsigned long long same = __ballot(valid && img == li);
+      if (lane == leader) atomicAdd(&a.qcount[li], (unsigned long long)__popcll(same));
+      todo &= ~same;
+    }
+  }
+  return still;
+}
+
+// One march step over the active list: M-row tiles, the survivors appended to
+// the next list (compaction fused into the step).
 template <int P, int M>
 __device__ __forceinline__ void march_tiles(const MarchArgs& a, const Sm<P>& s, int count) {
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   for (int tile = blockIdx.x; tile * M < count; tile += gridDim.x) {
-    if (tid < M) {
-      const int idx = tile * M + tid;
-      float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-      int lt = 0, r = -1;
-      if (idx < count) {
-        r = a.list[idx];
-        const ImgDesc& im = a.imgs[a.pool.img[r]];
-        const float4 d = a.pool.d[r];
-        p = make_float4(fmaf(d.w, d.x, im.c[0]), fmaf(d.w, d.y, im.c[1]), fmaf(d.w, d.z, im.c[2]), 0.f);
-        lt = im.latent;
-        if (a.t_hist) a.t_hist[r] = d.w;
-      }
-      s.pts[tid] = p;
-      s.lat[tid] = lt;
-      s.rid[tid] = r;
-    }
-    __syncthreads();
-    const int wn = mlp_forward<P, kFwdWaves<P>, M, false, false>(a.net, a.bias0_lat, a.biasS_lat, s, tid, MaskRef{});
-    bool still = false;
-    if (tid < M && s.rid[tid] >= 0) {
-      float m = a.net.blast;
-      for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
-      const float4 p = s.pts[tid];
-      const float f = sdf_from_m(p, m);
-      const int r = s.rid[tid];
-      const RayPool& pl = a.pool;
-      const ImgDesc& im = a.imgs[pl.img[r]];
-      const int n = pl.n[r];
-      float4 d = pl.d[r];
-      const float t = d.w;
-      // running K smallest |f| (ties keep the earlier step)
-      const float af = fabsf(f);
-      const int Kr = im.K;
-      float rec_abs[kMaxK];
-      for (int k = 0; k < Kr; ++k) rec_abs[k] = fabsf(pl.rec_f[(size_t)k * pl.cap + r]);
-      const int pos = topk_rank(af, rec_abs, Kr);
-      for (int k = Kr - 1; k > pos; --k) {
-        pl.rec_f[(size_t)k * pl.cap + r] = pl.rec_f[(size_t)(k - 1) * pl.cap + r];
-        pl.rec_t[(size_t)k * pl.cap + r] = pl.rec_t[(size_t)(k - 1) * pl.cap + r];
-        pl.rec_n[(size_t)k * pl.cap + r] = pl.rec_n[(size_t)(k - 1) * pl.cap + r];
-      }
-      if (pos < Kr) {
-        pl.rec_f[(size_t)pos * pl.cap + r] = f;
-        pl.rec_t[(size_t)pos * pl.cap + r] = t;
-        pl.rec_n[(size_t)pos * pl.cap + r] = (uint8_t)n;
-      }
-      pl.flast[r] = f;
-      uint8_t st;
-      if (!(af == af) || af == INFINITY) {
-        st = ST_UNCONVERGED;                   // non-finite query: stop the ray
-      } else if (af < im.eps) {
-        st = ST_HIT;
-      } else if (n == im.max_steps - 1) {
-        st = ST_UNCONVERGED;
-      } else {
-        const float tn = fmaf(im.alpha, f, t);
-        const float2 b = pl.b[r];
-        st = (tn > b.y || tn < b.x) ? ST_ESCAPED : ST_ACTIVE;
-        d.w = tn;
-        pl.d[r] = d;
-      }
-      pl.st[r] = st;
-      pl.n[r] = (uint8_t)(n + 1);
-      still = st == ST_ACTIVE;
-    }
-    // compaction fused into the step: survivors form the next active list
+    const int k = min(M, count - tile * M);
+    march_load<P, M>(a, s, k, [&](int i) { return a.list[tile * M + i]; });
+    const bool still = march_eval<P, M>(a, s);
     if (a.next_list) wg_append<kFwdWaves<P> * 64>(still, still ? s.rid[tid] : 0, a.next_list, a.next_count);
-    if (a.qcount && tid < M) {
-      // queries of this step per image, one atomic per distinct image in a wave
-      const int r = s.rid[tid];
-      const bool valid = r >= 0;
-      const int img = valid ? a.pool.img[r] : -1;
-      unsigned long long todo = __ballot(valid);
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int li = __shfl(img, leader);
-        const unsigned long long same = __ballot(valid && img == li);
-        if (lane == leader) atomicAdd(&a.qcount[li], (unsigned long long)__popcll(same));
-        todo &= ~same;
-      }
-    }
     __syncthreads();
   }
 }
@@ -1098,6 +1119,90 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
     march_tiles<P, Cfg<P>::M>(a, s, count);
   }
 }
+
+// Offset of this thread among the workgroup's threads with flag set (thread
+// order) and their total, without atomics.
+template <int NT>
+__device__ __forceinline__ int wg_prefix(bool flag, int* total) {
+  __shared__ int pcnt[NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(flag);
+  if (lane == 0) pcnt[w] = __popcll(bal);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < NT / 64; ++i) {
+    const int c = pcnt[i];
+    off += i < w ? c : 0;
+    tot += c;
+  }
+  __syncthreads();                     // pcnt is rewritten by the next call
+  *total = tot;
+  return off + __popcll(bal & ((1ull << lane) - 1ull));
+}
+
+// Every remaining step of the march in one launch (after the last
+// coarse-to-fine split).  Each ray's trajectory depends on that ray alone, so
+// the rays need not advance in lockstep: every workgroup keeps a ring of rays
+// in its own region of a spare list (ring_cap slots), marches tiles of up to
+// M of them and puts the survivors back at the ring's end.  While it holds
+// fewer than 2M live rays it claims more from the input list (one atomic per
+// claim of up to 1024), so workgroups that draw short rays take more of them
+// and the grid stays busy until the input is spent.  No step waits for the
+// slowest tile of the grid, and tiles stay full until a workgroup has fewer
+// than M live rays.  A ring never overflows: claims are capped by its free
+// slots and a ray returns only after leaving it.  Every ray stops within
+// max_steps queries and a workgroup leaves once a claim returns nothing and
+// its ring is empty, so every workgroup leaves the loop.
+template <int P>
+__global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_eu(kFwdWaves<P> / 4, kFwdWaves<P> / 4))) void k_march_ring(MarchArgs a) {
+  constexpr int M = Cfg<P>::M, NT = kFwdWaves<P> * 64;
+  __shared__ int claim_lds[2];
+  Sm<P> s(dyn_smem, a.net.kmax);
+  const int tid = threadIdx.x;
+  const int n0 = *a.count, RC = a.ring_cap;
+  int* ring = a.next_list + (size_t)blockIdx.x * RC;
+  int head = 0, tail = 0, live = 0;
+  bool more = true;
+  long long rows = 0;
+  while (true) {
+    if (more && live < 2 * M) {
+      if (tid == 0) {
+        const int want = min(1024, RC - live);
+        const int st = atomicAdd(a.claim, want);
+        claim_lds[0] = st;
+        claim_lds[1] = max(0, min(want, n0 - st));
+      }
+      __syncthreads();
+      const int st = claim_lds[0], got = claim_lds[1];
+      for (int i = tid; i < got; i += NT) ring[(tail + i) % RC] = a.list[st + i];
+      tail += got;
+      live += got;
+      more = got > 0;
+      __syncthreads();
+    }
+    if (live == 0) break;
+    const int k = min(M, live);
+    auto rid_of = [&](int i) { return ring[(head + i) % RC]; };
+    bool still;
+    if (P == kPrecBF16 && k <= 64) {
+      march_load<P, 64>(a, s, k, rid_of);
+      still = march_eval<P, 64>(a, s);
+    } else {
+      march_load<P, M>(a, s, k, rid_of);
+      still = march_eval<P, M>(a, s);
+    }
+    int tot;
+    const int pos = wg_prefix<NT>(still, &tot);
+    if (still) ring[(tail + pos) % RC] = s.rid[tid];
+    head += k;
+    tail += tot;
+    live += tot - k;
+    rows += k;
+    __syncthreads();
+  }
+  if (tid == 0 && a.rows_done && rows) atomicAdd(a.rows_done, (unsigned long long)rows);
+}
+
 // ---------------------------------------------------------------------------
 // Plain decoder queries (explicit points, or the 6-point normal stencil)
 // ---------------------------------------------------------------------------
@@ -1501,6 +1606,7 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
   } while (0)
 
 void launch_march(int precision, const MarchArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_march, a); }
+void launch_march_ring(int precision, const MarchArgs& a, int grid, hipStream_t st) { DIST_DISPATCH(k_march_ring, a); }
 void launch_color(int precision, const ColorArgs& a, int grid, hipStream_t st) {
   const size_t sm = mlp_smem_bytes(precision, a.net);
   if (precision == 1) hipLaunchKernelGGL(k_color<1>, dim3(grid), dim3(kFwdWaves<1> * 64), sm, st, a);
