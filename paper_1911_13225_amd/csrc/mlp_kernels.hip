@@ -3,8 +3,10 @@
 //
 // Layout of one tile (M rows = rays, 8 waves):
 //   * The activation tile lives in LDS, row-major [M][kmax] (bf16 or f32),
-//     16-byte chunks XOR-swizzled by (row & 15) so that the MFMA operand reads
-//     and the epilogue writes are bank-conflict free.
+//     each row padded by one 16-byte chunk: consecutive rows then start 4
+//     banks apart, so the MFMA operand reads (32 rows, one chunk each) and
+//     the epilogue writes are bank-conflict free, and a k-step's operand is a
+//     lane's row base plus an immediate offset (no per-step address work).
 //   * Hidden layers are computed as D[n][m] = sum_k W[n][k] act[m][k] with the
 //     weights as the MFMA A operand (pre-packed fragments streamed from L2)
 //     and the activations as the B operand (from LDS).  An accumulator lane
@@ -60,7 +62,7 @@ __host__ __device__ inline int fwd_threads(int P) { return (P == 0 ? 4 : 8) * 64
 __host__ __device__ inline size_t smem_bytes_for(int P, int kmax, int nout = 1) {
   const int M = rows_for(P);
   const int ES = P == 1 ? 2 : 4;
-  return (size_t)M * kmax * ES + (size_t)M * (16 + 4 + 4 + 4 + 4) + (size_t)8 * M * 4 * nout;
+  return (size_t)M * (kmax * ES + 16) + (size_t)M * (16 + 4 + 4 + 4 + 4) + (size_t)8 * M * 4 * nout;
 }
 
 template <int P> struct Sm {
@@ -74,7 +76,7 @@ template <int P> struct Sm {
   int rowb;
   __device__ Sm(char* base, int kmax) {
     constexpr int M = Cfg<P>::M;
-    rowb = kmax * Cfg<P>::ES;
+    rowb = kmax * Cfg<P>::ES + 16;            // one chunk of padding per row
     act = base;
     size_t off = (size_t)M * rowb;
     pts = (float4*)(base + off); off += (size_t)M * 16;
@@ -85,7 +87,7 @@ template <int P> struct Sm {
     part = (float*)(base + off);
   }
   __device__ __forceinline__ char* chunk(int m, int ch) const {
-    return act + (size_t)m * rowb + ((ch ^ (m & 15)) << 4);
+    return act + (size_t)m * rowb + (ch << 4);
   }
 };
 
@@ -216,14 +218,9 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
   int wrow[NTW];                 // byte offset of fragment (n-tile nt0 + j, k-step 0)
 #pragma unroll
   for (int j = 0; j < NTW; ++j) wrow[j] = (nt0 + j) * ksteps * 1024;
-  const char* arow[MTW];
-  int sw[MTW];
+  const char* arow[MTW];          // the lane's row and half of the k-step (chunk 2 ks + g)
 #pragma unroll
-  for (int i = 0; i < MTW; ++i) {
-    const int m = (mt0 + i) * 32 + r;
-    arow[i] = s.act + (size_t)m * s.rowb;
-    sw[i] = m & 15;
-  }
+  for (int i = 0; i < MTW; ++i) arow[i] = s.act + (size_t)((mt0 + i) * 32 + r) * s.rowb + 16 * g;
   Pipe<bf16x8, MTW, NTW, D> p;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -232,17 +229,17 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
     __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
   }
 #pragma unroll
-  for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const bf16x8*)(arow[i] + (((g) ^ sw[i]) << 4));
+  for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const bf16x8*)arow[i];
   constexpr int U = D < 2 ? 2 : D;
-  // one k-step: the next step's activation fragments, this step's MFMAs and,
-  // with pf, the weight fragments D steps ahead
+  // one k-step: the next step's activation fragments (the block's row bases
+  // ab plus an immediate; after the layer's last step this reads one chunk
+  // past K, still inside the tile, and the value is not used), this step's
+  // MFMAs and, with pf, the weight fragments D steps ahead
+  const char* ab[MTW];
   auto step = [&](int ks, int d, bool pf) {
     const int sl = d % D, cb = d & 1, nb = cb ^ 1;
-    {
-      const int kn = min(ks + 1, ksteps - 1);     // unconditional (the last one is redundant)
 #pragma unroll
-      for (int i = 0; i < MTW; ++i) p.b[nb][i] = *(const bf16x8*)(arow[i] + (((2 * kn + g) ^ sw[i]) << 4));
-    }
+    for (int i = 0; i < MTW; ++i) p.b[nb][i] = *(const bf16x8*)(ab[i] + 32 * (d + 1));
 #pragma unroll
     for (int i = 0; i < MTW; ++i)
 #pragma unroll
@@ -258,8 +255,12 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
   // the last block requests no weights past the end
   for (int k0 = 0; k0 < ksteps - U; k0 += U) {
 #pragma unroll
+    for (int i = 0; i < MTW; ++i) ab[i] = arow[i] + 32 * k0;
+#pragma unroll
     for (int d = 0; d < U; ++d) step(k0 + d, d, true);
   }
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) ab[i] = arow[i] + 32 * (ksteps - U);
 #pragma unroll
   for (int d = 0; d < U; ++d) step(ksteps - U + d, d, d + D < U);
   mfma_drain();
@@ -278,14 +279,9 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
   int wrow[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) wrow[j] = (nt0 + j) * ksteps * 1024;
-  const char* arow[MTW];
-  int sw[MTW];
+  const char* arow[MTW];          // the lane's row and half of the k-step (hi chunk 2 (2 ks + g), lo next)
 #pragma unroll
-  for (int i = 0; i < MTW; ++i) {
-    const int m = (mt0 + i) * 32 + r;
-    arow[i] = s.act + (size_t)m * s.rowb;
-    sw[i] = m & 15;
-  }
+  for (int i = 0; i < MTW; ++i) arow[i] = s.act + (size_t)((mt0 + i) * 32 + r) * s.rowb + 32 * g;
   Pipe<bf16x8, MTW, NTW, D> ph, pl;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -298,19 +294,17 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
   }
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
-    ph.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g) ^ sw[i]) << 4));
-    if constexpr (X3) pl.b[0][i] = *(const bf16x8*)(arow[i] + (((2 * g + 1) ^ sw[i]) << 4));
+    ph.b[0][i] = *(const bf16x8*)arow[i];
+    if constexpr (X3) pl.b[0][i] = *(const bf16x8*)(arow[i] + 16);
   }
   constexpr int U = D < 2 ? 2 : D;
+  const char* ab[MTW];           // the block's row bases (see gemm_bf16)
   auto step = [&](int ks, int d, bool pf) {
     const int sl = d % D, cb = d & 1, nb = cb ^ 1;
-    {
-      const int c = 2 * (2 * min(ks + 1, ksteps - 1) + g);
 #pragma unroll
-      for (int i = 0; i < MTW; ++i) {
-        ph.b[nb][i] = *(const bf16x8*)(arow[i] + ((c ^ sw[i]) << 4));
-        if constexpr (X3) pl.b[nb][i] = *(const bf16x8*)(arow[i] + (((c + 1) ^ sw[i]) << 4));
-      }
+    for (int i = 0; i < MTW; ++i) {
+      ph.b[nb][i] = *(const bf16x8*)(ab[i] + 64 * (d + 1));
+      if constexpr (X3) pl.b[nb][i] = *(const bf16x8*)(ab[i] + 64 * (d + 1) + 16);
     }
     // the next step's LDS reads go out before this step's MFMAs (left to
     // itself the scheduler sinks them below, exposing their latency)
@@ -336,8 +330,12 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
   };
   for (int k0 = 0; k0 < ksteps - U; k0 += U) {
 #pragma unroll
+    for (int i = 0; i < MTW; ++i) ab[i] = arow[i] + 64 * k0;
+#pragma unroll
     for (int d = 0; d < U; ++d) step(k0 + d, d, true);
   }
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) ab[i] = arow[i] + 64 * (ksteps - U);
 #pragma unroll
   for (int d = 0; d < U; ++d) step(ksteps - U + d, d, d + D < U);
   mfma_drain();
@@ -352,14 +350,9 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
   int wrow[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) wrow[j] = (nt0 + j) * ksteps * 1024;
-  const char* arow[MTW];
-  int sw[MTW];
+  const char* arow[MTW];          // the lane's row and half of the k-step (chunk 2 ks + g)
 #pragma unroll
-  for (int i = 0; i < MTW; ++i) {
-    const int m = (mt0 + i) * 32 + r;
-    arow[i] = s.act + (size_t)m * s.rowb;
-    sw[i] = m & 15;
-  }
+  for (int i = 0; i < MTW; ++i) arow[i] = s.act + (size_t)((mt0 + i) * 32 + r) * s.rowb + 16 * g;
   Pipe<f32x4, MTW, NTW, D> p;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -368,19 +361,18 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
     __builtin_amdgcn_sched_barrier(0);     // prologue loads stay in stage order
   }
 #pragma unroll
-  for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const f32x4*)(arow[i] + (((g) ^ sw[i]) << 4));
+  for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const f32x4*)arow[i];
   constexpr int U = D < 2 ? 2 : D;
   for (int k0 = 0; k0 < ksteps; k0 += U) {
+    const char* ab[MTW];         // the block's row bases (see gemm_bf16)
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) ab[i] = arow[i] + 32 * k0;
 #pragma unroll
     for (int d = 0; d < U; ++d) {
       const int ks = k0 + d, sl = d % D;
       const int cb = d & 1, nb = cb ^ 1;
-      {
-        const int kn = min(ks + 1, ksteps - 1);
 #pragma unroll
-        for (int i = 0; i < MTW; ++i)
-          p.b[nb][i] = *(const f32x4*)(arow[i] + (((2 * kn + g) ^ sw[i]) << 4));
-      }
+      for (int i = 0; i < MTW; ++i) p.b[nb][i] = *(const f32x4*)(ab[i] + 32 * (d + 1));
 #pragma unroll
       for (int sidx = 0; sidx < 4; ++sidx)
 #pragma unroll
