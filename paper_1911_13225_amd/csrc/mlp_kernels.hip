@@ -102,6 +102,23 @@ __device__ __forceinline__ int opaque(int x) {
 }
 
 
+// ReLU mask bits of a tile row: word w of layer l of row m is at
+// p[row * rs + l * ls + w], with row = m (per-workgroup scratch) or, with rid,
+// the row's sample index kept in s.rid (masks saved per sample; rows with a
+// negative index are not stored).
+struct MaskRef {
+  unsigned* p;
+  int rs, ls;
+  bool rid;
+};
+
+template <int P>
+__device__ __forceinline__ int mask_row(const MaskRef& mk, const Sm<P>& s, int m) { return mk.rid ? s.rid[m] : m; }
+
+__device__ __forceinline__ size_t mask_at(const MaskRef& mk, int row, int layer, int w) {
+  return (size_t)row * mk.rs + (size_t)layer * mk.ls + w;
+}
+
 // ---------------------------------------------------------------------------
 // Layer 0: h0 = relu(W0_p p + (b0 + W0_z z)), float32 VALU, written to LDS.
 // ---------------------------------------------------------------------------
@@ -109,9 +126,13 @@ __device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p
 
 // Each thread owns one chunk of EPC output features (its W0_p columns stay in
 // registers) and walks the rows of the tile; N0 / EPC divides NT.
-template <int P, int NT, int MR, bool CAP>
+// With MASK the ReLU bits of layer 0 are stored like those of the other
+// layers (a word holds 32 features, i.e. 32 / EPC neighbouring lanes' chunks,
+// combined across those lanes), so the backward reads them instead of
+// recomputing W0_p p + b0.
+template <int P, int NT, int MR, bool CAP, bool MASK = false>
 __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_,
-                                            float* hcap, int rstride) {
+                                            float* hcap, int rstride, const MaskRef& mk = MaskRef{}) {
   const int tid = opaque(tid_);
   constexpr int M = MR, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
@@ -138,6 +159,18 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         v[e + u] = fmaxf(fmaf(wx[e + u], p.x, fmaf(wy[e + u], p.y, fmaf(wz[e + u], p.z, bb[u]))), 0.f);
+    }
+    if constexpr (MASK) {
+      // v > 0 exactly when the pre-activation is > 0 (the ReLU keeps it)
+      constexpr int CPW = 32 / EPC;            // chunks per mask word
+      unsigned bits = 0;
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) bits |= (v[e] > 0.f ? 1u : 0u) << e;
+      bits <<= EPC * (ch % CPW);
+#pragma unroll
+      for (int o = 1; o < CPW; o <<= 1) bits |= __shfl_xor(bits, o);
+      const int row = mask_row(mk, s, m);
+      if (ch % CPW == 0 && row >= 0) mk.p[mask_at(mk, row, 0, ch / CPW)] = bits;
     }
     if constexpr (CAP) {
 #pragma unroll
@@ -396,23 +429,6 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
 // ---------------------------------------------------------------------------
 // EP_VJP_NOGP: the VJP without the point-gradient partials (compiled out)
 enum { EP_ACT = 0, EP_LAST = 1, EP_ACT_MASK = 2, EP_LAST_ADJ = 3, EP_VJP = 4, EP_VJP_NOGP = 5 };
-
-// ReLU mask bits of a tile row: word w of layer l of row m is at
-// p[row * rs + l * ls + w], with row = m (per-workgroup scratch) or, with rid,
-// the row's sample index kept in s.rid (masks saved per sample; rows with a
-// negative index are not stored).
-struct MaskRef {
-  unsigned* p;
-  int rs, ls;
-  bool rid;
-};
-
-template <int P>
-__device__ __forceinline__ int mask_row(const MaskRef& mk, const Sm<P>& s, int m) { return mk.rid ? s.rid[m] : m; }
-
-__device__ __forceinline__ size_t mask_at(const MaskRef& mk, int row, int layer, int w) {
-  return (size_t)row * mk.rs + (size_t)layer * mk.ls + w;
-}
 
 struct EpCtx {
   const float* bias;        // per-layer bias (non-skip) or null
@@ -683,43 +699,18 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
 }
 
 // VJP through one layer: acc = W^T delta for the output of layer ec.layer;
-// apply that layer's ReLU mask (recomputed in float32 for layer 0, whose
-// pre-activation is the same expression layer0_fill evaluates).
-template <int P, int MTW, int NTW, int WN, bool L0, bool CAP, bool GP>
+// apply that layer's ReLU mask, as the forward stored it (layer 0 included).
+template <int P, int MTW, int NTW, int WN, bool CAP, bool GP>
 __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x16 (&acc)[MTW][NTW], const Sm<P>& s,
                                        int nt0, int mt0, int mg, int nw, int lane, const unsigned (&mb)[MTW][NTW]) {
   const int r = lane & 31, g = lane >> 5;
-  const int N0 = net.wpad[0];
 #pragma unroll
   for (int i = 0; i < MTW; ++i) {
     const int m = (mt0 + i) * 32 + r;
-    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float* b0l = nullptr;
-    if constexpr (L0) {
-      p = s.pts[m];
-      b0l = ec.bias0_lat + (size_t)s.lat[m] * N0;
-    }
 #pragma unroll
     for (int j = 0; j < NTW; ++j) {
-      unsigned bits;
-      if constexpr (L0) {
-        bits = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int n = feat(nt0, j, q, g);
-          const float4 wx = ld4(net.w0p + n), wy = ld4(net.w0p + N0 + n), wz = ld4(net.w0p + 2 * N0 + n);
-          const float4 b = ld4(b0l + n);
-          const float pre[4] = {fmaf(wx.x, p.x, fmaf(wy.x, p.y, fmaf(wz.x, p.z, b.x))),
-                                fmaf(wx.y, p.x, fmaf(wy.y, p.y, fmaf(wz.y, p.z, b.y))),
-                                fmaf(wx.z, p.x, fmaf(wy.z, p.y, fmaf(wz.z, p.z, b.z))),
-                                fmaf(wx.w, p.x, fmaf(wy.w, p.y, fmaf(wz.w, p.z, b.w)))};
-#pragma unroll
-          for (int e = 0; e < 4; ++e) bits |= pos_bit(pre[e]) << (8 * q + e);
-        }
-      } else {
-        // the lane's features are bits 8q + 4g + e of the stored word
-        bits = mb[i][j] >> (4 * g);
-      }
+      // the lane's features are bits 8q + 4g + e of the stored word
+      const unsigned bits = mb[i][j] >> (4 * g);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -853,9 +844,7 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
     for (int i = 0; i < MTW; ++i)
 #pragma unroll
       for (int j = 0; j < NTW; ++j)
-        mb[i][j] = ec.layer != 0
-                       ? ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, (mt0 + i) * 32 + r), 0), ec.layer, nt0 + j)]
-                       : 0u;
+        mb[i][j] = ec.mk.p[mask_at(ec.mk, max(mask_row(ec.mk, s, (mt0 + i) * 32 + r), 0), ec.layer, nt0 + j)];
   };
   if constexpr (VJP && EARLY) load_masks();
   if constexpr (VJP) acc_mfma_start<P, MTW, NTW>(acc, nullptr, nt0, lane);
@@ -877,8 +866,7 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   if constexpr (VJP) {
     constexpr bool GP = MODE == EP_VJP;
     if constexpr (!EARLY) load_masks();
-    if (ec.layer == 0) ep_vjp<P, MTW, NTW, WN, true, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
-    else ep_vjp<P, MTW, NTW, WN, false, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
+    ep_vjp<P, MTW, NTW, WN, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
   }
   __syncthreads();
 }
@@ -931,7 +919,7 @@ template <int P, int NW, int MR, bool ADJ, bool CAP, int NOUT = 1>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
                                            const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr) {
   const int rstride = (net.nl - 1) * net.kmax;
-  layer0_fill<P, NW * 64, MR, CAP>(net, bias0_lat, s, tid, hcap, rstride);
+  layer0_fill<P, NW * 64, MR, CAP, ADJ>(net, bias0_lat, s, tid, hcap, rstride, mk);
   __syncthreads();
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
