@@ -278,6 +278,14 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
 #pragma unroll
       for (int j = 0; j < NTW; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(p.a[sl][j], p.b[cb][i], acc[i][j], 0, 0, 0);
+    // the next step's LDS reads spread among this step's MFMAs, one before
+    // each group of NTW (left to itself the scheduler sinks them all below
+    // the MFMAs and the next step waits for them; measured 2% faster)
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);      // one LDS read
+      __builtin_amdgcn_sched_group_barrier(0x008, NTW, 0);    // NTW MFMAs
+    }
     if (pf) {
 #pragma unroll
       for (int j = 0; j < NTW; ++j) p.a[sl][j] = ld_frag<bf16x8>(rs, voff, wrow[j] + (ks + D) * 1024);
