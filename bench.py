@@ -179,6 +179,46 @@ def gradient_variants(w, reps=2):
     return res
 
 
+def theta_run(w, reps=2):
+    """dL/dtheta of the benchmark's loss on the 32-image bf16 launch: the
+    backward with weight gradients (recompute and VJP of every sample row with
+    h and Delta captured in bf16, then one GEMM per layer over the rows),
+    against the same backward to z alone.  Reports the captured rows and the
+    weight-gradient GEMM rate (2 x rows x every layer's weights, a lower bound
+    on the work of that call, over its time)."""
+    import torch
+    from paper_1911_13225_amd import api
+    Z = w["Z"]
+    out = api.dist_render_fwd(w["ctx"], w["cams"], Z, w["prm"], save=True)
+    dt, nt, st = w["targets"]
+    _, gd, gn, gs = api.dist_render_loss(out["depth"], out["normal"], out["sil"], dt, nt, st, w_d=10.0, w_s=1.0,
+                                         w_n=1.0)
+    n = Z.shape[0]
+    res = {}
+    for name, theta in (("z_only", False), ("with_theta", True)):
+        api.dist_render_bwd(w["ctx"], out["saved"], gd, gn, gs, n_latents=n, want_theta=theta)
+        torch.cuda.synchronize()
+        api.dist_timing_enable(w["ctx"], True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            api.dist_render_bwd(w["ctx"], out["saved"], gd, gn, gs, n_latents=n, want_theta=theta)
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(1e3 * (time.perf_counter() - t0) / reps, 2)
+        launches, ms, rows = api.dist_timing_read(w["ctx"], 2)
+        api.dist_timing_enable(w["ctx"], False)
+        if theta:
+            res["rows"] = int(rows // max(reps, 1))
+    out["saved"].free()
+    weights = 1_835_520   # multiply-adds of one row through every layer's weights (z and p columns included)
+    extra = res["with_theta_ms"] - res["z_only_ms"]
+    res["weight_gradient_gflop"] = round(2 * weights * res["rows"] / 1e9, 1)
+    res["extra_ms_over_z_only"] = round(extra, 2)
+    res["weight_gradient_tflops_over_extra"] = round(2 * weights * res["rows"] / (extra * 1e-3) / 1e12, 1) if extra > 0 else None
+    res["note"] = ("rows = recomputed sample rows (depth/silhouette records and the six stencil queries of every "
+                   "hit with a normal seed); the captured h and Delta are bfloat16")
+    return res
+
+
 def color_run(w, reps=3):
     """The colour network (the geometry layout on 512-wide shape + texture
     codes, three outputs) at the hits of the benchmark workload's render:
@@ -583,6 +623,9 @@ def main():
         log("[bench] gradient variants on the same workload")
         res["gradient_variants"] = gradient_variants(w)
         log("[bench] gradient variants", res["gradient_variants"])
+        log("[bench] weight gradient on the same workload")
+        res["weight_gradient"] = theta_run(w)
+        log("[bench] weight gradient", res["weight_gradient"])
         log("[bench] colour network at the hits of the same workload")
         res["color"] = color_run(w)
         log("[bench] colour", res["color"])

@@ -117,6 +117,19 @@ struct ColorSpace {
   BwdSpace* bw = nullptr;
 };
 
+// Capture of one chunk of weight-gradient rows (see run_theta): h and Delta
+// of every hidden layer, the row factor, z / point / 1 per row, feature-major
+// in the capture type of the adjoint precision; per-slice results of the
+// contraction.
+struct ThetaSpace {
+  void* mem = nullptr;
+  size_t bytes = 0;
+  int rows = 0, prec = -1;
+  float *hbuf = nullptr, *dbuf = nullptr, *gmbuf = nullptr;
+  void *zrows = nullptr, *prows = nullptr, *ones = nullptr;
+  float* slices = nullptr;                 // per-slice GEMM results [slice][out][in]
+};
+
 struct dist_ctx {
   int device = 0;
   int n_out = 1;                    // 1: signed distance network, 3: colour network
@@ -146,6 +159,9 @@ struct dist_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> tev[kTimeClasses];
   size_t tev_used[kTimeClasses] = {0, 0, 0, 0};
   unsigned long long* d_rows = nullptr;   // device accumulators of processed rows [kTimeClasses]
+  // weight gradient: capture buffers of one chunk of rows (kept for the
+  // context's life)
+  struct ThetaSpace* theta = nullptr;
 };
 
 // Event pair around one launch of kernel class k (no-op unless timing is on).

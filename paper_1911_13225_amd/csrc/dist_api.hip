@@ -323,6 +323,10 @@ extern "C" int dist_destroy(dist_ctx* ctx) {
     ctx_free(ctx, ctx->col->mem, ctx->col->bytes);
     delete ctx->col;
   }
+  if (ctx->theta) {
+    ctx_free(ctx, ctx->theta->mem, ctx->theta->bytes);
+    delete ctx->theta;
+  }
   for (auto& o : ctx->owned) ctx_free(ctx, o.first, o.second);
   delete ctx;
   return DIST_OK;
@@ -996,31 +1000,114 @@ __global__ void k_zero_f32(float* p, long long n) {
 // Weight gradient: adjoint over chunks of tiles capturing h and Delta per row,
 // then one fixed-order accumulation kernel per layer.  Synchronises once to
 // read the number of samples.
+// Weight gradient (Sec. 3.4: dL/dtheta = sum over samples of seed * df/dtheta
+// at the detached points).  Per layer, dW_l = sum_rows Delta_l (x) x_l and
+// db_l = sum_rows Delta_l, where Delta_l is the row's seed times dm/d(pre-
+// activation of layer l) and x_l the layer's input ([h] for hidden layers,
+// [z, p] for layer 0, [h, z, p] for the skip layer).  The recompute-and-VJP
+// kernel captures h and Delta of every row of a chunk, feature-major
+// (bfloat16 on the bf16 paths, float32 on the float32 path); each layer's
+// contraction over the chunk's rows runs on MFMA (k_dw).  The contraction is
+// long (up to 65,536 rows) and the output small (a layer's weights), so the
+// rows are cut into slices of kThetaSlice that run in parallel, and the
+// slices' results are added into g_W / g_b in slice order: the sum order is
+// fixed, so the result is reproducible bit for bit.  The capture buffers
+// belong to the context and are reused; the one host synchronisation reads
+// the sample count that sizes the chunk loop.
+static constexpr int kThetaChunkRows = 65536;
+static constexpr int kThetaSlice = 2048;
+
+// C[n][k] (row stride ldc) += sum over slices s (in order) of P[s][n][k].
+__global__ void k_slice_sum(const float* __restrict__ P, int S, int k_in, int n_out, float* C, int ldc) {
+  const long long total = (long long)k_in * n_out;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    for (int sl = 0; sl < S; ++sl) acc += P[sl * total + i];
+    const long long n = i / k_in, k = i - n * k_in;
+    C[n * ldc + k] += acc;
+  }
+}
+
+static int theta_space(dist_ctx* ctx, int prec, int rows) {
+  ThetaSpace*& t = ctx->theta;
+  if (t && t->prec == prec && t->rows >= rows) return DIST_OK;
+  if (t) {
+    ctx_free(ctx, t->mem, t->bytes);
+    delete t;
+    t = nullptr;
+  }
+  const size_t es = prec == kPrecF32 ? 4 : 2;
+  const size_t nfeat = (size_t)(ctx->nl - 1) * ctx->kmax;
+  const size_t al = 256;
+  auto up = [&](size_t x) { return (x + al - 1) / al * al; };
+  const size_t hb = up(rows * nfeat * es), gb = up(rows * es), zb = up((size_t)rows * ctx->L * es),
+               pb = up((size_t)rows * 4 * es);
+  size_t wmax = 0;
+  for (int l = 0; l < ctx->nl; ++l) wmax = std::max(wmax, (size_t)ctx->out_dims[l] * ctx->in_dims[l]);
+  const size_t sb = up((size_t)(kThetaChunkRows / kThetaSlice) * wmax * 4);
+  ThetaSpace* n = new ThetaSpace();
+  n->bytes = 2 * hb + 2 * gb + zb + pb + sb;
+  int rc = ctx_alloc(ctx, &n->mem, n->bytes);
+  if (rc) {
+    delete n;
+    return rc;
+  }
+  char* m = (char*)n->mem;
+  n->hbuf = (float*)m;
+  n->dbuf = (float*)(m + hb);
+  n->gmbuf = (float*)(m + 2 * hb);
+  n->ones = m + 2 * hb + gb;
+  n->zrows = m + 2 * hb + 2 * gb;
+  n->prows = m + 2 * hb + 2 * gb + zb;
+  n->slices = (float*)(m + 2 * hb + 2 * gb + zb + pb);
+  n->rows = rows;
+  n->prec = prec;
+  t = n;
+  return DIST_OK;
+}
+
+// C[n][k] (row-major, ldc) += sum_r D[n][r] X[k][r] over `rows` rows, D and X
+// feature-major with feature stride R, in slices of kThetaSlice rows (rows is
+// a multiple of it, or below one slice).
+static void dw_rows(dist_ctx* ctx, int prec, int n_out, int k_in, int rows, int R, const void* D, const void* X,
+                    float* C, int ldc, hipStream_t st) {
+  if (n_out <= 0 || k_in <= 0 || rows <= 0) return;
+  const int S = rows >= kThetaSlice ? rows / kThetaSlice : 1;
+  const int K = rows / S;
+  float* P = ctx->theta->slices;
+  launch_dw(prec, D, X, R, n_out, k_in, K, S, P, st);
+  const long long total = (long long)k_in * n_out;
+  hipLaunchKernelGGL(k_slice_sum, dim3((int)std::min<long long>((total + 255) / 256, 4096)), dim3(256), 0, st, P, S,
+                     k_in, n_out, C, ldc);
+}
+
 static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const float* z, float* const* g_W,
                      float* const* g_b, hipStream_t st) {
   for (int l = 0; l < ctx->nl; ++l)
     if (!g_W[l] || !g_b[l]) return dist_set_error(DIST_EINVAL, "null weight-gradient pointer for layer %d", l);
-  int ns = 0;
-  HIPCHK(hipMemcpyAsync(&ns, b->n_samples, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
   for (int l = 0; l < ctx->nl; ++l) {
     hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, st, g_W[l],
                        (long long)ctx->out_dims[l] * ctx->in_dims[l]);
     hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, st, g_b[l], (long long)ctx->out_dims[l]);
   }
+  int ns = 0;
+  HIPCHK(hipMemcpyAsync(&ns, b->n_samples, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   const int tile = b->tile;
   const int tiles = ns / tile;
   if (tiles == 0) return DIST_OK;
-  const int chunk = std::max(1, std::min(tiles, 32768 / tile));
-  const size_t rows = (size_t)chunk * tile;
-  const size_t rstride = (size_t)(ctx->nl - 1) * ctx->kmax;
-  const size_t bytes = rows * rstride * 4 * 2 + rows * 4 + 1024;
-  void* mem = nullptr;
-  int rc = ctx_alloc(ctx, &mem, bytes);
+  const int chunk = std::max(1, std::min(tiles, kThetaChunkRows / tile));
+  // contraction rows per chunk: whole slices (rows past the chunk's samples are zero)
+  auto gemm_rows_of = [](int valid) {
+    return valid >= kThetaSlice ? (valid + kThetaSlice - 1) / kThetaSlice * kThetaSlice : valid;
+  };
+  const int R = gemm_rows_of(chunk * tile);
+  int rc = theta_space(ctx, prec, R);
   if (rc) return rc;
-  float* hbuf = (float*)mem;
-  float* dbuf = hbuf + rows * rstride;
-  float* gmbuf = dbuf + rows * rstride;
+  ThetaSpace* t = ctx->theta;
+  const int es = prec == kPrecF32 ? 4 : 2;
+  const int kmax = ctx->kmax;
+  auto at = [&](const void* base, size_t off) { return (const void*)((const char*)base + off * es); };
   AdjArgs aa{};
   aa.net = ctx->net[prec];
   aa.bias0_lat = w->bias0_lat;
@@ -1030,44 +1117,39 @@ static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const f
   aa.n_samples = b->n_samples;
   aa.mask_ws = b->mask_ws;
   aa.partial = b->partial;
-  aa.hbuf = hbuf;
-  aa.dbuf = dbuf;
-  aa.gmbuf = gmbuf;
+  aa.hbuf = t->hbuf;
+  aa.dbuf = t->dbuf;
+  aa.gmbuf = t->gmbuf;
+  aa.cap_rows = R;
+  const int L = ctx->L, nl = ctx->nl;
   for (int t0 = 0; t0 < tiles; t0 += chunk) {
     const int t1 = std::min(tiles, t0 + chunk);
+    const int valid = (t1 - t0) * tile;
+    const int rows = gemm_rows_of(valid);
     aa.tile_begin = t0;
     aa.tile_end = t1;
     {
-      TimedLaunch tl(ctx, 2, st);
+      // the rows of every chunk, counted once (all samples)
+      TimedLaunch tl(ctx, 2, st, t0 == 0 ? b->n_samples : nullptr, 1);
       launch_adjoint(prec, aa, std::max(1, std::min(t1 - t0, ctx->n_cu)), st);
     }
-    for (int l = 0; l < ctx->nl; ++l) {
-      DwArgs d{};
-      d.layer = l;
-      d.nl = ctx->nl;
-      d.skip = ctx->skip;
-      d.L = ctx->L;
-      d.nh = l > 0 ? ctx->out_dims[l - 1] : 0;
-      d.kmax = ctx->kmax;
-      d.rstride = (int)rstride;
-      d.rows = (t1 - t0) * tile;
-      d.out = ctx->out_dims[l];
-      d.in = ctx->in_dims[l];
-      d.hbuf = hbuf;
-      d.dbuf = dbuf;
-      d.gmbuf = gmbuf;
-      d.pts = b->samples + (size_t)t0 * tile;
-      d.lat = b->sample_lat + (size_t)t0 * tile;
-      d.z = z;
-      d.gW = g_W[l];
-      d.gb = g_b[l];
-      launch_dw(d, st);
+    launch_theta_rows(prec, b->samples + (size_t)t0 * tile, b->sample_lat + (size_t)t0 * tile, z, L, valid, R,
+                      t->zrows, t->prows, t->ones, t->hbuf, t->dbuf, t->gmbuf, (nl - 1) * kmax, st);
+    for (int l = 0; l < nl; ++l) {
+      const int out = ctx->out_dims[l], in = ctx->in_dims[l];
+      // Delta of this layer: captured for hidden layers, the row factor gm for the output layer
+      const void* D = l < nl - 1 ? at(t->dbuf, (size_t)l * kmax * R) : (const void*)t->gmbuf;
+      const int nh = l == 0 ? 0 : ctx->out_dims[l - 1];       // width of the h part of the input
+      if (nh > 0) dw_rows(ctx, prec, out, nh, rows, R, D, at(t->hbuf, (size_t)(l - 1) * kmax * R), g_W[l], in, st);
+      if (l == 0 || l == ctx->skip) {
+        dw_rows(ctx, prec, out, L, rows, R, D, t->zrows, g_W[l] + nh, in, st);
+        dw_rows(ctx, prec, out, 3, rows, R, D, t->prows, g_W[l] + nh + L, in, st);
+      }
+      dw_rows(ctx, prec, out, 1, rows, R, D, t->ones, g_b[l], 1, st);
     }
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
-  ctx_free(ctx, mem, bytes);
-  return DIST_OK;
+  return rc;
 }
 
 static int cs_get(dist_ctx* ctx, Workspace* w, long long cap_samples, long long cap_pix = 0) {

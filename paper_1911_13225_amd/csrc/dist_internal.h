@@ -135,11 +135,14 @@ struct AdjArgs {
   float* partial;                  // [tile][2][2][kmax] column sums (S0, Sskip) x m-groups
   // weight gradient (optional): tiles [tile_begin, tile_end) write, per row,
   // h_l (post-ReLU) and Delta_l = seed * dm/d(pre-activation of layer l) for
-  // every hidden layer, [row][nl-1][kmax], plus the row's seed factor gm
+  // every hidden layer, feature-major [nl-1][kmax][cap_rows], plus the row's
+  // seed factor gm, in the capture type (float32 in the float32 kernel,
+  // bfloat16 otherwise)
   float* hbuf;
   float* dbuf;
   float* gmbuf;
   int tile_begin, tile_end;
+  int cap_rows;                    // rows of the capture chunk (feature-major: element (l kmax + n) cap_rows + row)
   // VJP from saved masks (k_vjp_saved): samples [n_begin[0], n_samples[0]),
   // each with its stencil index in sample_idx; masks and 1 - tanh^2 as
   // written by the forward's stencil queries
@@ -161,18 +164,19 @@ struct AdjArgs {
 constexpr int kPrecF32 = 0, kPrecBF16 = 1, kPrecSplit = 2;
 constexpr int kGpSlots = 8;          // point-gradient partial slots per sample (one per wave)
 
-struct DwArgs {
-  int layer, nl, skip, L, nh, kmax, rstride, rows, out, in;
-  const float* hbuf;
-  const float* dbuf;
-  const float* gmbuf;
-  const float4* pts;
-  const int* lat;
-  const float* z;
-  float* gW;
-  float* gb;
-};
-void launch_dw(const DwArgs& a, hipStream_t s);
+// Inputs of the weight gradient that the capture does not hold, per captured
+// row, feature-major like the capture (R rows per feature): z of its latent
+// [L][R], its point [4][R] (x, y, z, 0) and a 1 [R] (for the bias sums), in
+// the capture type of `precision` (float32 for 0, bfloat16 otherwise); rows
+// in [valid, R) are zeros, and so are the captured h and Delta there.
+void launch_theta_rows(int precision, const float4* pts, const int* lat, const float* z, int L, int valid, int R,
+                       void* zrows, void* prows, void* ones, float* hbuf, float* dbuf, float* gmbuf, int n_feat,
+                       hipStream_t s);
+// Weight-gradient contraction over rows: for each slice sl of K rows (S
+// slices), P[sl][n][k] = sum_r D[n][r] X[k][r] over the slice, for n < n_out,
+// k < k_in, with D and X feature-major (feature stride R, capture type).
+void launch_dw(int precision, const void* D, const void* X, int R, int n_out, int k_in, int K, int S, float* P,
+               hipStream_t s);
 
 int mlp_tile_rows(int precision);                 // rays per MLP tile
 int adj_tile_rows(int precision);                 // samples per adjoint tile

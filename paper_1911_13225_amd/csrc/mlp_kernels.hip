@@ -120,6 +120,47 @@ __device__ __forceinline__ size_t mask_at(const MaskRef& mk, int row, int layer,
 }
 
 // ---------------------------------------------------------------------------
+// Weight-gradient capture (h and Delta of every row and hidden layer, and the
+// row factor): float32 elements in the float32 kernels, bfloat16 in the
+// others.  The layout is feature-major, element (row r, layer l, feature n) at
+// (l kmax + n) R + r for a chunk of R rows, so that the contraction over rows
+// reads 8 consecutive rows of one feature as one MFMA operand.  The capture
+// arrays are typed float; offsets are in elements of the capture type.
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ float* cap_ptr(float* base, size_t off) {
+  if constexpr (P == 0) return base + off;
+  else return (float*)((bf16*)base + off);
+}
+// features n..n+3 of row m, below a base that holds the layer and the tile's first row
+template <int P>
+__device__ __forceinline__ void cap4(float* base, int m, int n, int R, float a, float b, float c, float d) {
+  const size_t o = (size_t)n * R + m;
+  if constexpr (P == 0) {
+    base[o] = a;
+    base[o + R] = b;
+    base[o + 2 * (size_t)R] = c;
+    base[o + 3 * (size_t)R] = d;
+  } else {
+    bf16* q = (bf16*)base;
+    q[o] = (bf16)a;
+    q[o + R] = (bf16)b;
+    q[o + 2 * (size_t)R] = (bf16)c;
+    q[o + 3 * (size_t)R] = (bf16)d;
+  }
+}
+template <int P>
+__device__ __forceinline__ float cap_get(const float* base, size_t off) {
+  if constexpr (P == 0) return base[off];
+  else return (float)((const bf16*)base)[off];
+}
+template <int P>
+__device__ __forceinline__ void cap_put(float* base, size_t off, float v) {
+  if constexpr (P == 0) base[off] = v;
+  else ((bf16*)base)[off] = (bf16)v;
+}
+
+// ---------------------------------------------------------------------------
 // Layer 0: h0 = relu(W0_p p + (b0 + W0_z z)), float32 VALU, written to LDS.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p; }
@@ -175,7 +216,7 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
     if constexpr (CAP) {
 #pragma unroll
       for (int e = 0; e < EPC; e += 4)
-        *(float4*)(hcap + (size_t)m * rstride + n + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+        cap4<P>(hcap, m, n + e, rstride, v[e], v[e + 1], v[e + 2], v[e + 3]);
     }
     if constexpr (P == 1) {
       bf16x8 w;
@@ -452,9 +493,9 @@ struct EpCtx {
   int which;                // 0: S0, 1: Sskip, -1: none
   bool write_act;
   int kmax;
-  float* hrow;              // weight-gradient capture: h of this layer, row stride rstride (or null)
+  float* hrow;              // weight-gradient capture: h of this layer from the tile's first row (or null)
   float* drow;              // weight-gradient capture: Delta of this layer (or null)
-  int rstride;
+  int rstride;              // rows of the capture chunk (feature stride)
   float* gp;                // camera gradient: per-row point-gradient partials [row][kGpSlots][3] (or null)
   int gp_row0;              // global row index of the tile's first row
   bool gp_accum;            // add to the partials (the skip layer wrote them first)
@@ -622,8 +663,8 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
         }
         store4_relu<P>(s, m, n, g, x);
         if constexpr (CAP)
-          *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) =
-              make_float4(fmaxf(x[0], 0.f), fmaxf(x[1], 0.f), fmaxf(x[2], 0.f), fmaxf(x[3], 0.f));
+          cap4<P>(ec.hrow, m, n, ec.rstride, fmaxf(x[0], 0.f), fmaxf(x[1], 0.f), fmaxf(x[2], 0.f),
+                  fmaxf(x[3], 0.f));
       }
       if constexpr (MASK) {
         bits <<= 4 * g;
@@ -683,7 +724,7 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
         // the seed of the output layer (a single output; a colour network
         // builds its seed from the three channels after the forward)
         if constexpr (ADJ && NOUT == 1) store4<P>(s, m, n, g, v, true);
-        if constexpr (CAP) *(float4*)(ec.hrow + (size_t)m * ec.rstride + n) = make_float4(h[0], h[1], h[2], h[3]);
+        if constexpr (CAP) cap4<P>(ec.hrow, m, n, ec.rstride, h[0], h[1], h[2], h[3]);
       }
     }
 #pragma unroll
@@ -734,9 +775,8 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
         const float w = s.gm[m];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          *(float4*)(ec.drow + (size_t)m * ec.rstride + feat(nt0, j, q, g)) =
-              make_float4(w * acc[i][j][4 * q], w * acc[i][j][4 * q + 1], w * acc[i][j][4 * q + 2],
-                          w * acc[i][j][4 * q + 3]);
+          cap4<P>(ec.drow, m, feat(nt0, j, q, g), ec.rstride, w * acc[i][j][4 * q],
+                  w * acc[i][j][4 * q + 1], w * acc[i][j][4 * q + 2], w * acc[i][j][4 * q + 3]);
       }
     }
   }
@@ -922,20 +962,21 @@ __device__ __forceinline__ EpCtx fwd_ctx(const NetDev& net, const float* biasS_l
 // Forward through all hidden layers; leaves the output-layer partial sums in
 // s.part and returns the number of partial groups.  ADJ records the ReLU masks
 // and the output-layer seed for the adjoint; CAP keeps float32 copies of every
-// hidden activation in hcap for the weight gradient.
+// hidden activation in hcap (the capture from the tile's first row, chunk
+// rows capR) for the weight gradient.
 template <int P, int NW, int MR, bool ADJ, bool CAP, int NOUT = 1>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
-                                           const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr) {
-  const int rstride = (net.nl - 1) * net.kmax;
-  layer0_fill<P, NW * 64, MR, CAP, ADJ>(net, bias0_lat, s, tid, hcap, rstride, mk);
+                                           const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr,
+                                           int capR = 0) {
+  layer0_fill<P, NW * 64, MR, CAP, ADJ>(net, bias0_lat, s, tid, hcap, capR, mk);
   __syncthreads();
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
     EpCtx ec = fwd_ctx(net, biasS_lat, l);
     ec.mk = mk;
     if constexpr (CAP) {
-      ec.hrow = hcap + (size_t)l * net.kmax;
-      ec.rstride = rstride;
+      ec.hrow = cap_ptr<P>(hcap, (size_t)l * net.kmax * capR);
+      ec.rstride = capR;
     }
     // the skip layer is never the last hidden layer (skip <= nl - 3)
     if (l == net.nl - 2)
@@ -1273,8 +1314,8 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
     ec.gp_row0 = tile * Cfg<P>::M;
     ec.gp_accum = (l - 1 == 0) && net.skip >= 1;   // the skip layer comes first in this loop
     if constexpr (CAP) {
-      ec.drow = a.dbuf + row0 * rstride + (size_t)(l - 1) * net.kmax;
-      ec.rstride = rstride;
+      ec.drow = cap_ptr<P>(a.dbuf, (size_t)(l - 1) * net.kmax * a.cap_rows + row0);
+      ec.rstride = a.cap_rows;
     }
     layer<P, NW, Cfg<P>::M, GP ? EP_VJP : EP_VJP_NOGP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
   }
@@ -1297,10 +1338,10 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
   const MaskRef mk{a.mask_ws + (size_t)blockIdx.x * (size_t)(net.nl) * M * ntmax, ntmax, M * ntmax, false};
   const bool theta = a.hbuf != nullptr;
   const int t_end = theta ? min(a.tile_end, (count + M - 1) / M) : (count + M - 1) / M;
-  const int rstride = (net.nl - 1) * net.kmax;
+  const int rstride = a.cap_rows;             // capture chunk rows (feature stride)
   for (int tile = (theta ? a.tile_begin : 0) + blockIdx.x; tile < t_end; tile += gridDim.x) {
     const size_t row0 = theta ? (size_t)(tile - a.tile_begin) * M : 0;
-    float* hcap = theta ? a.hbuf + row0 * rstride : nullptr;
+    float* hcap = theta ? cap_ptr<P>(a.hbuf, row0) : nullptr;
     if (tid < M) {
       const int idx = tile * M + tid;
       const float4 smp = a.samples[idx];
@@ -1309,14 +1350,15 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
       s.lat[tid] = a.sample_lat[idx];
     }
     __syncthreads();
-    const int wn = theta ? mlp_forward<P, kAdjWaves, Cfg<P>::M, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap)
+    const int wn = theta ? mlp_forward<P, kAdjWaves, Cfg<P>::M, true, true>(net, a.bias0_lat, a.biasS_lat, s, tid, mk, hcap,
+                                                                            rstride)
                          : mlp_forward<P, kAdjWaves, Cfg<P>::M, true, false>(net, a.bias0_lat, a.biasS_lat, s, tid, mk);
     if (tid < M) {
       float m = net.blast;
       for (int w = 0; w < wn; ++w) m += s.part[w * M + tid];
       const float th = tanhf(m);
       s.gm[tid] = s.fval[tid] * 0.05f * (1.f - th * th);
-      if (theta) a.gmbuf[row0 + tid] = s.gm[tid];
+      if (theta) cap_put<P>(a.gmbuf, row0 + tid, s.gm[tid]);
     }
     __syncthreads();
     if (theta) {
@@ -1324,8 +1366,8 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
       const int ll = net.nl - 2, W = net.wpad[ll];
       for (int i = tid; i < M * W; i += kAdjWaves * 64) {
         const int m = i / W, n = i - m * W;
-        const size_t o = (row0 + m) * rstride + (size_t)ll * net.kmax + n;
-        a.dbuf[o] = a.hbuf[o] > 0.f ? s.gm[m] * net.wlast[n] : 0.f;
+        const size_t o = ((size_t)ll * net.kmax + n) * rstride + row0 + m;
+        cap_put<P>(a.dbuf, o, cap_get<P>(a.hbuf, o) > 0.f ? s.gm[m] * net.wlast[n] : 0.f);
       }
     }
     float* part = a.partial + (size_t)tile * 4 * net.kmax;
@@ -1485,56 +1527,6 @@ __global__ __launch_bounds__(kBwdWaves * 64) __attribute__((amdgpu_waves_per_eu(
 // in_l is [z, p] for layer 0, [h, z, p] for the skip layer, h_{l-1} otherwise;
 // for the output layer Delta is the row's seed factor gm and in = h_{nl-2}.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float dw_in(const DwArgs& a, int r, int k) {
-  const size_t base = (size_t)r * a.rstride;
-  const int L = a.L;
-  if (a.layer == 0) {
-    if (k < L) return a.z[(size_t)a.lat[r] * L + k];
-    return (&a.pts[r].x)[k - L];
-  }
-  if (a.layer == a.skip) {
-    if (k < a.nh) return a.hbuf[base + (size_t)(a.layer - 1) * a.kmax + k];
-    if (k < a.nh + L) return a.z[(size_t)a.lat[r] * L + (k - a.nh)];
-    return (&a.pts[r].x)[k - a.nh - L];
-  }
-  return a.hbuf[base + (size_t)(a.layer - 1) * a.kmax + k];
-}
-
-__device__ __forceinline__ float dw_delta(const DwArgs& a, int r, int n) {
-  if (a.layer == a.nl - 1) return a.gmbuf[r];
-  return a.dbuf[(size_t)r * a.rstride + (size_t)a.layer * a.kmax + n];
-}
-
-__global__ __launch_bounds__(256) void k_dw(DwArgs a) {
-  __shared__ float Ds[32][17];
-  __shared__ float Is[32][17];
-  const int n0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
-  const int tn = threadIdx.x >> 4, tk = threadIdx.x & 15;
-  const int n = n0 + tn, k = k0 + tk;
-  float acc = 0.f, accb = 0.f;
-  for (int r0 = 0; r0 < a.rows; r0 += 32) {
-    for (int i = threadIdx.x; i < 32 * 16; i += 256) {
-      const int rr = i >> 4, c = i & 15;
-      const int r = r0 + rr;
-      Ds[rr][c] = (r < a.rows && n0 + c < a.out) ? dw_delta(a, r, n0 + c) : 0.f;
-      Is[rr][c] = (r < a.rows && k0 + c < a.in) ? dw_in(a, r, k0 + c) : 0.f;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < 32; ++rr) {
-      acc = fmaf(Ds[rr][tn], Is[rr][tk], acc);
-      accb += Ds[rr][tn];
-    }
-    __syncthreads();
-  }
-  if (n < a.out && k < a.in) a.gW[(size_t)n * a.in + k] += acc;
-  if (blockIdx.x == 0 && tk == 0 && n < a.out) a.gb[n] += accb;
-}
-
-void launch_dw(const DwArgs& a, hipStream_t st) {
-  dim3 grid((a.in + 15) / 16, (a.out + 15) / 16);
-  hipLaunchKernelGGL(k_dw, grid, dim3(256), 0, st, a);
-}
 
 // ---------------------------------------------------------------------------
 // Host-side helpers
@@ -1545,6 +1537,147 @@ int adj_tile_rows(int precision) { return mlp_tile_rows(precision); }
 size_t mlp_smem_bytes(int precision, const NetDev& net) { return smem_bytes_for(precision, net.kmax, net.nout); }
 size_t adj_mask_words(int precision, const NetDev& net) {
   return (size_t)net.nl * mlp_tile_rows(precision) * (net.kmax / 32);
+}
+
+// Per captured row, feature-major (R rows per feature): z of its latent, its
+// point and a 1, in the capture type; for the rows in [valid, R) that only pad
+// the contraction to whole slices, zeros there and in the captured h, Delta
+// and row factor.
+template <class T>
+__global__ void k_theta_rows(const float4* __restrict__ pts, const int* __restrict__ lat, const float* __restrict__ z,
+                             int L, int valid, int R, T* zrows, T* prows, T* ones, T* hbuf, T* dbuf, T* gmbuf,
+                             int n_feat) {
+  const long long step = (long long)gridDim.x * blockDim.x, t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (long long i = t0; i < (long long)L * R; i += step) {
+    const int j = (int)(i / R), r = (int)(i - (long long)j * R);
+    zrows[i] = (T)(r < valid ? z[(size_t)lat[r] * L + j] : 0.f);
+  }
+  for (long long r = t0; r < R; r += step) {
+    const bool ok = r < valid;
+    const float4 p = ok ? pts[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    prows[r] = (T)p.x;
+    prows[R + r] = (T)p.y;
+    prows[2 * (long long)R + r] = (T)p.z;
+    prows[3 * (long long)R + r] = (T)0.f;
+    ones[r] = (T)(ok ? 1.f : 0.f);
+    if (!ok) gmbuf[r] = (T)0.f;
+  }
+  const int pad = R - valid;
+  for (long long i = t0; i < (long long)n_feat * pad; i += step) {
+    const long long f = i / pad, r = valid + (i - f * pad);
+    hbuf[f * R + r] = (T)0.f;
+    dbuf[f * R + r] = (T)0.f;
+  }
+}
+
+void launch_theta_rows(int precision, const float4* pts, const int* lat, const float* z, int L, int valid, int R,
+                       void* zrows, void* prows, void* ones, float* hbuf, float* dbuf, float* gmbuf, int n_feat,
+                       hipStream_t st) {
+  const long long total = (long long)std::max(L, 1) * R;
+  const int grid = (int)std::min<long long>((total + 255) / 256, 4096);
+  if (precision == 0)
+    hipLaunchKernelGGL(k_theta_rows<float>, dim3(grid), dim3(256), 0, st, pts, lat, z, L, valid, R, (float*)zrows,
+                       (float*)prows, (float*)ones, hbuf, dbuf, gmbuf, n_feat);
+  else
+    hipLaunchKernelGGL(k_theta_rows<bf16>, dim3(grid), dim3(256), 0, st, pts, lat, z, L, valid, R, (bf16*)zrows,
+                       (bf16*)prows, (bf16*)ones, (bf16*)hbuf, (bf16*)dbuf, (bf16*)gmbuf, n_feat);
+}
+
+// Weight-gradient contraction over the captured rows (Sec. 3.4: dW_l = sum
+// over samples of Delta_l x_l^T): P[sl][n][k] = sum over slice sl's K rows of
+// D[n][r] X[k][r], D and X feature-major with feature stride R.  A workgroup
+// of 4 waves owns a 128 (n) x 128 (k) block; a wave computes 64 x 64 of it as
+// 2 x 2 MFMA tiles whose A operand is 8 consecutive rows of one D feature and
+// B operand 8 consecutive rows of one X feature (bf16: 32x32x16; float32:
+// 32x32x2 over float4 loads of 4 rows, the rows paired (i, i + 4): any pairing
+// of the contraction index gives the same sum).  Reads past n_out or k_in are
+// clamped to the last feature and their outputs dropped.
+template <int P>
+__global__ __launch_bounds__(256) void k_dw(const void* __restrict__ D, const void* __restrict__ X, int R, int n_out,
+                                            int k_in, int K, float* __restrict__ Pout) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ln = lane & 31, g = lane >> 5;
+  const int nb = blockIdx.x * 128 + (wave & 1) * 64, kb = blockIdx.y * 128 + (wave >> 1) * 64;
+  const size_t r0 = (size_t)blockIdx.z * K;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+  int na[2], kx[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    na[i] = min(nb + 32 * i + ln, n_out - 1);
+    kx[i] = min(kb + 32 * i + ln, k_in - 1);
+  }
+  if constexpr (P != 0) {
+    const bf16* a[2] = {(const bf16*)D + (size_t)na[0] * R + r0 + 8 * g, (const bf16*)D + (size_t)na[1] * R + r0 + 8 * g};
+    const bf16* b[2] = {(const bf16*)X + (size_t)kx[0] * R + r0 + 8 * g, (const bf16*)X + (size_t)kx[1] * R + r0 + 8 * g};
+    bf16x8 av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      av[i] = *(const bf16x8*)a[i];
+      bv[i] = *(const bf16x8*)b[i];
+    }
+    for (int r = 16; r <= K; r += 16) {
+      bf16x8 an[2], bn[2];
+      const int rn = min(r, K - 16);                 // the last load repeats (in bounds, unused)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        an[i] = *(const bf16x8*)(a[i] + rn);
+        bn[i] = *(const bf16x8*)(b[i] + rn);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = an[i];
+        bv[i] = bn[i];
+      }
+    }
+  } else {
+    const float* a[2] = {(const float*)D + (size_t)na[0] * R + r0 + 4 * g, (const float*)D + (size_t)na[1] * R + r0 + 4 * g};
+    const float* b[2] = {(const float*)X + (size_t)kx[0] * R + r0 + 4 * g, (const float*)X + (size_t)kx[1] * R + r0 + 4 * g};
+    for (int r = 0; r < K; r += 8) {
+      float4 av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = *(const float4*)(a[i] + r);
+        bv[i] = *(const float4*)(b[i] + r);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+  mfma_drain();
+  float* out = Pout + (size_t)blockIdx.z * n_out * k_in;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int n = nb + 32 * i + 8 * q + 4 * g + e, k = kb + 32 * j + ln;
+          if (n < n_out && k < k_in) out[(size_t)n * k_in + k] = acc[i][j][4 * q + e];
+        }
+}
+
+void launch_dw(int precision, const void* D, const void* X, int R, int n_out, int k_in, int K, int S, float* P,
+               hipStream_t st) {
+  const dim3 grid((n_out + 127) / 128, (k_in + 127) / 128, S);
+  if (precision == 0) hipLaunchKernelGGL(k_dw<0>, grid, dim3(256), 0, st, D, X, R, n_out, k_in, K, P);
+  else hipLaunchKernelGGL(k_dw<1>, grid, dim3(256), 0, st, D, X, R, n_out, k_in, K, P);
 }
 
 template <int P>
