@@ -483,7 +483,17 @@ def zopt_run(iters=200, n_views=4, H=256, precision=1):
     d0 = float((z - zs).norm())
     m = torch.zeros_like(z)
     v = torch.zeros_like(z)
-    curve = {}
+    checks = (0, 1, 10, 50, 100, iters - 1)
+    curve, image = {}, {}
+
+    def image_fit(o):
+        # the fit in image space: mean |depth error| where both are foreground,
+        # and the intersection over union of the two silhouettes
+        fr, ft = o["sil"] < 0, st > 0.5
+        both = fr & ft
+        derr = float((o["depth"] - dt).abs()[both].mean()) if bool(both.any()) else None
+        iou = float(both.sum()) / max(float((fr | ft).sum()), 1.0)
+        return {"depth_abs_err_fg": round(derr, 6) if derr is not None else None, "silhouette_iou": round(iou, 5)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(iters):
@@ -491,19 +501,22 @@ def zopt_run(iters=200, n_views=4, H=256, precision=1):
         loss, gd, _, gs = api.dist_render_loss(out["depth"], None, out["sil"], dt, None, st, w_d=10.0, w_s=1.0)
         g = api.dist_render_bwd(ctx, out["saved"], gd, None, gs, n_latents=1)
         out["saved"].free()
-        api.dist_adam_step(z, m, v, g, it + 1, lr=1e-2)
-        if it in (0, 1, 10, 50, 100, iters - 1):
+        if it in checks:
             curve[it] = round(float(loss.sum()), 6)
+            image[it] = image_fit(out)
+            image[it]["z_dist_rel"] = round(float((z - zs).norm()) / d0, 4)
+        api.dist_adam_step(z, m, v, g, it + 1, lr=1e-2)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     out = api.dist_render_fwd(ctx, cams, z, prm)
-    fg = (out["sil"] < 0) & (st > 0.5)
-    derr = float((out["depth"] - dt).abs()[fg].mean()) if bool(fg.any()) else None
+    final = image_fit(out)
     ctx.close()
     return {"iters": iters, "views": n_views, "resolution": H, "precision": "bf16" if precision else "fp32",
-            "its_per_s": round(iters / sec, 2), "loss": curve,
+            "its_per_s": round(iters / sec, 2), "loss": curve, "image_space": image, "final": final,
             "z_dist_rel": {"start": 1.0, "end": round(float((z - zs).norm()) / d0, 4)},
-            "final_depth_abs_err_fg": derr}
+            "note": "a random decoder's latent is not identifiable from four depth maps: the fit converges in "
+                    "image space (depth error, silhouette IoU) while z wanders; Adam at a fixed lr 1e-2 "
+                    "oscillates near the fit (App. B.4 schedule)"}
 
 
 def photometric_run(iters=50, n_views=8, H=112, precision=1):
@@ -680,7 +693,15 @@ def main():
     if not a.no_cpu:
         log("[bench] cpu baseline (oracle) and per-output error of the bf16 launch on its pixels")
         res["cpu_baseline"] = cpu_baseline(gpu_maps)
+    # every context is closed (its serving thread joined) before the result is
+    # printed; the process then leaves without the interpreter's teardown, so
+    # nothing outlives the script
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
     print(json.dumps(res), flush=True)
+    sys.stderr.flush()
+    os._exit(0)
 
 
 if __name__ == "__main__":
