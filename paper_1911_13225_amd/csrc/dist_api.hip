@@ -997,9 +997,6 @@ __global__ void k_zero_f32(float* p, long long n) {
     p[i] = 0.f;
 }
 
-// Weight gradient: adjoint over chunks of tiles capturing h and Delta per row,
-// then one fixed-order accumulation kernel per layer.  Synchronises once to
-// read the number of samples.
 // Weight gradient (Sec. 3.4: dL/dtheta = sum over samples of seed * df/dtheta
 // at the detached points).  Per layer, dW_l = sum_rows Delta_l (x) x_l and
 // db_l = sum_rows Delta_l, where Delta_l is the row's seed times dm/d(pre-
@@ -1007,25 +1004,39 @@ __global__ void k_zero_f32(float* p, long long n) {
 // [z, p] for layer 0, [h, z, p] for the skip layer).  The recompute-and-VJP
 // kernel captures h and Delta of every row of a chunk, feature-major
 // (bfloat16 on the bf16 paths, float32 on the float32 path); each layer's
-// contraction over the chunk's rows runs on MFMA (k_dw).  The contraction is
-// long (up to 65,536 rows) and the output small (a layer's weights), so the
-// rows are cut into slices of kThetaSlice that run in parallel, and the
-// slices' results are added into g_W / g_b in slice order: the sum order is
-// fixed, so the result is reproducible bit for bit.  The capture buffers
-// belong to the context and are reused; the one host synchronisation reads
-// the sample count that sizes the chunk loop.
+// contraction over the chunk's rows runs on MFMA (one k_dw launch per layer
+// and chunk, every input segment and the bias in it).  The contraction is
+// long (all samples) and the output small (a layer's weights), so the rows of
+// a chunk are cut into slices of kThetaSlice that run in parallel; slice s of
+// every chunk adds to its own partial, and one launch per layer sums the
+// partials in slice order into g_W / g_b: the sum order is fixed, so the
+// result is reproducible bit for bit.  The capture and partial buffers belong
+// to the context and are reused; the one host synchronisation reads the
+// sample count that sizes the chunk loop.
 static constexpr int kThetaChunkRows = 65536;
 static constexpr int kThetaSlice = 2048;
+static constexpr int kThetaSlices = kThetaChunkRows / kThetaSlice;
+static_assert(kThetaSlice % kDwRows == 0, "slices are whole LDS blocks of the contraction");
 
-// C[n][k] (row stride ldc) += sum over slices s (in order) of P[s][n][k].
-__global__ void k_slice_sum(const float* __restrict__ P, int S, int k_in, int n_out, float* C, int ldc) {
-  const long long total = (long long)k_in * n_out;
+// g_W[n][k] = sum over slices s (in order) of P[s][n][k] for k < k_in, and
+// g_b[n] the same sum of column k_in.
+__global__ void k_slice_sum(const float* __restrict__ P, int S, int n_out, int k_in, float* __restrict__ gW,
+                            float* __restrict__ gb) {
+  const int ldp = k_in + 1;
+  const long long total = (long long)n_out * ldp;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
     float acc = 0.f;
     for (int sl = 0; sl < S; ++sl) acc += P[sl * total + i];
-    const long long n = i / k_in, k = i - n * k_in;
-    C[n * ldc + k] += acc;
+    const long long n = i / ldp, k = i - n * ldp;
+    if (k < k_in) gW[n * k_in + k] = acc;
+    else gb[n] = acc;
   }
+}
+
+static size_t theta_partials(const dist_ctx* ctx) {
+  size_t f = 0;
+  for (int l = 0; l < ctx->nl; ++l) f += (size_t)ctx->out_dims[l] * (ctx->in_dims[l] + 1);
+  return f * kThetaSlices;
 }
 
 static int theta_space(dist_ctx* ctx, int prec, int rows) {
@@ -1042,9 +1053,7 @@ static int theta_space(dist_ctx* ctx, int prec, int rows) {
   auto up = [&](size_t x) { return (x + al - 1) / al * al; };
   const size_t hb = up(rows * nfeat * es), gb = up(rows * es), zb = up((size_t)rows * ctx->L * es),
                pb = up((size_t)rows * 4 * es);
-  size_t wmax = 0;
-  for (int l = 0; l < ctx->nl; ++l) wmax = std::max(wmax, (size_t)ctx->out_dims[l] * ctx->in_dims[l]);
-  const size_t sb = up((size_t)(kThetaChunkRows / kThetaSlice) * wmax * 4);
+  const size_t sb = up(theta_partials(ctx) * 4);
   ThetaSpace* n = new ThetaSpace();
   n->bytes = 2 * hb + 2 * gb + zb + pb + sb;
   int rc = ctx_alloc(ctx, &n->mem, n->bytes);
@@ -1066,42 +1075,32 @@ static int theta_space(dist_ctx* ctx, int prec, int rows) {
   return DIST_OK;
 }
 
-// C[n][k] (row-major, ldc) += sum_r D[n][r] X[k][r] over `rows` rows, D and X
-// feature-major with feature stride R, in slices of kThetaSlice rows (rows is
-// a multiple of it, or below one slice).
-static void dw_rows(dist_ctx* ctx, int prec, int n_out, int k_in, int rows, int R, const void* D, const void* X,
-                    float* C, int ldc, hipStream_t st) {
-  if (n_out <= 0 || k_in <= 0 || rows <= 0) return;
-  const int S = rows >= kThetaSlice ? rows / kThetaSlice : 1;
-  const int K = rows / S;
-  float* P = ctx->theta->slices;
-  launch_dw(prec, D, X, R, n_out, k_in, K, S, P, st);
-  const long long total = (long long)k_in * n_out;
-  hipLaunchKernelGGL(k_slice_sum, dim3((int)std::min<long long>((total + 255) / 256, 4096)), dim3(256), 0, st, P, S,
-                     k_in, n_out, C, ldc);
-}
-
 static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const float* z, float* const* g_W,
                      float* const* g_b, hipStream_t st) {
   for (int l = 0; l < ctx->nl; ++l)
     if (!g_W[l] || !g_b[l]) return dist_set_error(DIST_EINVAL, "null weight-gradient pointer for layer %d", l);
-  for (int l = 0; l < ctx->nl; ++l) {
-    hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, st, g_W[l],
-                       (long long)ctx->out_dims[l] * ctx->in_dims[l]);
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, st, g_b[l], (long long)ctx->out_dims[l]);
-  }
   int ns = 0;
   HIPCHK(hipMemcpyAsync(&ns, b->n_samples, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const int tile = b->tile;
   const int tiles = ns / tile;
-  if (tiles == 0) return DIST_OK;
+  if (tiles == 0) {
+    for (int l = 0; l < ctx->nl; ++l) {
+      hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, st, g_W[l],
+                         (long long)ctx->out_dims[l] * ctx->in_dims[l]);
+      hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, st, g_b[l], (long long)ctx->out_dims[l]);
+    }
+    HIPCHK(hipGetLastError());
+    return DIST_OK;
+  }
   const int chunk = std::max(1, std::min(tiles, kThetaChunkRows / tile));
   // contraction rows per chunk: whole slices (rows past the chunk's samples are zero)
   auto gemm_rows_of = [](int valid) {
     return valid >= kThetaSlice ? (valid + kThetaSlice - 1) / kThetaSlice * kThetaSlice : valid;
   };
   const int R = gemm_rows_of(chunk * tile);
+  if (R % kCapBlock != 0 || tile != kCapBlock || (prec != kPrecF32 && R % kDwRows != 0))
+    return dist_set_error(DIST_EINVAL, "weight-gradient chunk of %d rows is not whole blocks", R);
   int rc = theta_space(ctx, prec, R);
   if (rc) return rc;
   ThetaSpace* t = ctx->theta;
@@ -1122,10 +1121,48 @@ static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const f
   aa.gmbuf = t->gmbuf;
   aa.cap_rows = R;
   const int L = ctx->L, nl = ctx->nl;
+  // per layer: its partials and the input segments of its contraction
+  std::vector<DwArgs> da(nl);
+  {
+    size_t off = 0;
+    for (int l = 0; l < nl; ++l) {
+      DwArgs& d = da[l];
+      d.D = l < nl - 1 ? at(t->dbuf, (size_t)l * kmax * R) : (const void*)t->gmbuf;
+      d.FD = l < nl - 1 ? kmax : 1;
+      d.R = R;
+      d.n_out = ctx->out_dims[l];
+      d.k_in = ctx->in_dims[l];
+      d.ldp = d.k_in + 1;
+      d.P = t->slices + off;
+      off += (size_t)kThetaSlices * d.n_out * d.ldp;
+      int e = 0;
+      // a segment: its base, the features it contributes and its features per capture block
+      auto seg = [&](const void* p, int n, int F) {
+        d.x.p[d.x.nseg] = p;
+        d.x.F[d.x.nseg] = F;
+        e += n;
+        d.x.end[d.x.nseg++] = e;
+      };
+      const int nh = l == 0 ? 0 : ctx->out_dims[l - 1];       // width of the h part of the input
+      if (nh > 0) seg(at(t->hbuf, (size_t)(l - 1) * kmax * R), nh, kmax);
+      if (l == 0 || l == ctx->skip) {
+        seg(t->zrows, L, L);
+        seg(t->prows, 3, 4);
+      }
+      if (prec == kPrecF32) seg(t->ones, 1, 1);
+      if (e != d.k_in + (prec == kPrecF32 ? 1 : 0))
+        return dist_set_error(DIST_EINVAL, "layer %d input segments cover %d of %d features", l, e, d.k_in);
+      d.kcols = e;
+      d.bias = prec == kPrecF32 ? 0 : 1;
+    }
+  }
+  int S0 = 0;
   for (int t0 = 0; t0 < tiles; t0 += chunk) {
     const int t1 = std::min(tiles, t0 + chunk);
     const int valid = (t1 - t0) * tile;
     const int rows = gemm_rows_of(valid);
+    const int S = rows >= kThetaSlice ? rows / kThetaSlice : 1;
+    if (t0 == 0) S0 = S;
     aa.tile_begin = t0;
     aa.tile_end = t1;
     {
@@ -1134,19 +1171,19 @@ static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const f
       launch_adjoint(prec, aa, std::max(1, std::min(t1 - t0, ctx->n_cu)), st);
     }
     launch_theta_rows(prec, b->samples + (size_t)t0 * tile, b->sample_lat + (size_t)t0 * tile, z, L, valid, R,
-                      t->zrows, t->prows, t->ones, t->hbuf, t->dbuf, t->gmbuf, (nl - 1) * kmax, st);
+                      t->zrows, t->prows, t->ones, t->hbuf, t->dbuf, t->gmbuf, nl - 1, kmax, st);
     for (int l = 0; l < nl; ++l) {
-      const int out = ctx->out_dims[l], in = ctx->in_dims[l];
-      // Delta of this layer: captured for hidden layers, the row factor gm for the output layer
-      const void* D = l < nl - 1 ? at(t->dbuf, (size_t)l * kmax * R) : (const void*)t->gmbuf;
-      const int nh = l == 0 ? 0 : ctx->out_dims[l - 1];       // width of the h part of the input
-      if (nh > 0) dw_rows(ctx, prec, out, nh, rows, R, D, at(t->hbuf, (size_t)(l - 1) * kmax * R), g_W[l], in, st);
-      if (l == 0 || l == ctx->skip) {
-        dw_rows(ctx, prec, out, L, rows, R, D, t->zrows, g_W[l] + nh, in, st);
-        dw_rows(ctx, prec, out, 3, rows, R, D, t->prows, g_W[l] + nh + L, in, st);
-      }
-      dw_rows(ctx, prec, out, 1, rows, R, D, t->ones, g_b[l], 1, st);
+      DwArgs d = da[l];
+      d.S = S;
+      d.K = rows / S;
+      d.acc = t0 > 0;
+      launch_dw(prec, d, st);
     }
+  }
+  for (int l = 0; l < nl; ++l) {
+    const long long total = (long long)da[l].n_out * da[l].ldp;
+    hipLaunchKernelGGL(k_slice_sum, dim3((int)std::min<long long>((total + 255) / 256, 4096)), dim3(256), 0, st,
+                       da[l].P, S0, da[l].n_out, da[l].k_in, g_W[l], g_b[l]);
   }
   HIPCHK(hipGetLastError());
   return rc;

@@ -165,18 +165,44 @@ constexpr int kPrecF32 = 0, kPrecBF16 = 1, kPrecSplit = 2;
 constexpr int kGpSlots = 8;          // point-gradient partial slots per sample (one per wave)
 
 // Inputs of the weight gradient that the capture does not hold, per captured
-// row, feature-major like the capture (R rows per feature): z of its latent
-// [L][R], its point [4][R] (x, y, z, 0) and a 1 [R] (for the bias sums), in
-// the capture type of `precision` (float32 for 0, bfloat16 otherwise); rows
-// in [valid, R) are zeros, and so are the captured h and Delta there.
+// row, in the capture's blocked layout (kCapBlock rows per block, a block's
+// features contiguous): z of its latent (L features), its point (4: x, y, z,
+// 0) and a 1 (for the float32 bias column), in the capture type of
+// `precision` (float32 for 0, bfloat16 otherwise); rows in [valid, R) are
+// zeros, and so are the captured h, Delta and row factor there.  valid and R
+// are multiples of kCapBlock.
 void launch_theta_rows(int precision, const float4* pts, const int* lat, const float* z, int L, int valid, int R,
-                       void* zrows, void* prows, void* ones, float* hbuf, float* dbuf, float* gmbuf, int n_feat,
-                       hipStream_t s);
-// Weight-gradient contraction over rows: for each slice sl of K rows (S
-// slices), P[sl][n][k] = sum_r D[n][r] X[k][r] over the slice, for n < n_out,
-// k < k_in, with D and X feature-major (feature stride R, capture type).
-void launch_dw(int precision, const void* D, const void* X, int R, int n_out, int k_in, int K, int S, float* P,
-               hipStream_t s);
+                       void* zrows, void* prows, void* ones, float* hbuf, float* dbuf, float* gmbuf, int n_layers,
+                       int kmax, hipStream_t s);
+// Weight-gradient contraction over rows (k_dw_bf16 / k_dw_f32): for each
+// slice sl of K rows (S slices), P[sl][n][k] (+)= sum_r D[n][r] X_k[r] over
+// the slice, for n < n_out, k < kcols, with D and the input features X in
+// the capture's blocked layout (rows in blocks of kCapBlock, a block's
+// features contiguous, capture type).
+constexpr int kCapBlock = 64;                                // rows per capture block (a recompute tile)
+struct DwX {
+  const void* p[4];          // segment bases (feature 0, block 0 of the segment)
+  int end[4];                // cumulative feature counts
+  int F[4];                  // features per capture block of the segment (its block stride / kCapBlock)
+  int nseg;
+};
+struct DwArgs {
+  const void* D;             // Delta, blocked like the capture
+  int FD;                    // features per capture block of D
+  DwX x;                     // input features in input order
+  int R;                     // feature stride in elements
+  int n_out, k_in;           // weight shape; column k_in of a partial holds the bias
+  int kcols;                 // columns the GEMM computes (k_in, or k_in + 1 with a ones segment)
+  int bias;                  // bf16: the first column block also sums the Delta rows into column k_in
+  int K, S;                  // rows per slice (a multiple of kDwRows on the bf16 path), slices
+  int acc;                   // add to the partials instead of overwriting them
+  int ldp;                   // row stride of a partial (k_in + 1)
+  float* P;                  // partials [S][n_out][ldp]
+};
+constexpr int kDwRows = kCapBlock;                           // rows per LDS block (bf16): one capture block
+constexpr int kDwLd = kDwRows + 8;                           // LDS elements per staged feature
+constexpr size_t kDwLds = (size_t)2 * 2 * 128 * kDwLd * 2;  // two buffers of both 128-feature tiles
+void launch_dw(int precision, const DwArgs& a, hipStream_t s);
 
 int mlp_tile_rows(int precision);                 // rays per MLP tile
 int adj_tile_rows(int precision);                 // samples per adjoint tile

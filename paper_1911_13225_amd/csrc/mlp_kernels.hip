@@ -122,11 +122,16 @@ __device__ __forceinline__ size_t mask_at(const MaskRef& mk, int row, int layer,
 // ---------------------------------------------------------------------------
 // Weight-gradient capture (h and Delta of every row and hidden layer, and the
 // row factor): float32 elements in the float32 kernels, bfloat16 in the
-// others.  The layout is feature-major, element (row r, layer l, feature n) at
-// (l kmax + n) R + r for a chunk of R rows, so that the contraction over rows
-// reads 8 consecutive rows of one feature as one MFMA operand.  The capture
-// arrays are typed float; offsets are in elements of the capture type.
-// ---------------------------------------------------------------------------
+// others.  The layout is blocked feature-major: rows go in blocks of
+// kCapBlock (a tile of the recompute), and element (row r, layer l, feature
+// n) of a chunk of R rows is at l kmax R + ((r / kCapBlock) kmax + n)
+// kCapBlock + r % kCapBlock.  A feature's rows of one block are contiguous,
+// so the contraction over rows reads 8 consecutive rows of one feature as one
+// MFMA operand, and a block holds every feature of its rows in one piece: a
+// tile writes its capture as one contiguous region and the contraction
+// streams its blocks sequentially.  The capture arrays are typed float;
+// offsets are in elements of the capture type.
+static_assert(Cfg<0>::M == kCapBlock && Cfg<2>::M == kCapBlock, "a recompute tile is one capture block");
 template <int P>
 __device__ __forceinline__ float* cap_ptr(float* base, size_t off) {
   if constexpr (P == 0) return base + off;
@@ -158,6 +163,60 @@ template <int P>
 __device__ __forceinline__ void cap_put(float* base, size_t off, float v) {
   if constexpr (P == 0) base[off] = v;
   else ((bf16*)base)[off] = (bf16)v;
+}
+
+// Capture of a whole tile from LDS, after the barrier that ends a layer: the
+// tile's M rows of the layer's first W features, from one plane of the
+// activation tile (split bf16: the hi chunks, or the lo chunks where an
+// epilogue put the values to capture; float32: the tile itself, each row
+// scaled by gm[row] when given).  A thread gathers 8 rows (bf16) or 4 rows
+// (float32) of 4 neighbouring features and writes each feature's run of rows
+// as one 16-byte store; consecutive threads take consecutive runs of one
+// feature, so a wave writes whole 128-byte lines.
+template <int P>
+__device__ __forceinline__ void cap_tile(const Sm<P>& s, int plane, float* base, int R, int W, const float* gm) {
+  constexpr int M = Cfg<P>::M;
+  const int nt = blockDim.x;
+  if constexpr (P == 2) {
+    constexpr int G = M / 8;
+    for (int it = threadIdx.x; it < (W / 4) * G; it += nt) {
+      const int a = it % G, n = 4 * (it / G);
+      uint2 r[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) r[i] = *(const uint2*)(s.chunk(8 * a + i, 2 * (n >> 3) + plane) + 2 * (n & 7));
+      bf16* dst = (bf16*)base + (size_t)n * R + 8 * a;
+      auto lo2 = [](unsigned x, unsigned y) { return (x & 0xffffu) | (y << 16); };
+      auto hi2 = [](unsigned x, unsigned y) { return (x >> 16) | (y & 0xffff0000u); };
+      uint4 o;
+      o = make_uint4(lo2(r[0].x, r[1].x), lo2(r[2].x, r[3].x), lo2(r[4].x, r[5].x), lo2(r[6].x, r[7].x));
+      *(uint4*)dst = o;
+      o = make_uint4(hi2(r[0].x, r[1].x), hi2(r[2].x, r[3].x), hi2(r[4].x, r[5].x), hi2(r[6].x, r[7].x));
+      *(uint4*)(dst + (size_t)R) = o;
+      o = make_uint4(lo2(r[0].y, r[1].y), lo2(r[2].y, r[3].y), lo2(r[4].y, r[5].y), lo2(r[6].y, r[7].y));
+      *(uint4*)(dst + 2 * (size_t)R) = o;
+      o = make_uint4(hi2(r[0].y, r[1].y), hi2(r[2].y, r[3].y), hi2(r[4].y, r[5].y), hi2(r[6].y, r[7].y));
+      *(uint4*)(dst + 3 * (size_t)R) = o;
+    }
+  } else if constexpr (P == 0) {
+    constexpr int G = M / 4;
+    for (int it = threadIdx.x; it < (W / 4) * G; it += nt) {
+      const int a = it % G, c = it / G;
+      float4 r[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        r[i] = *(const float4*)s.chunk(4 * a + i, c);
+        if (gm) {
+          const float w = gm[4 * a + i];
+          r[i] = make_float4(w * r[i].x, w * r[i].y, w * r[i].z, w * r[i].w);
+        }
+      }
+      float* dst = base + (size_t)(4 * c) * R + 4 * a;
+      *(float4*)dst = make_float4(r[0].x, r[1].x, r[2].x, r[3].x);
+      *(float4*)(dst + (size_t)R) = make_float4(r[0].y, r[1].y, r[2].y, r[3].y);
+      *(float4*)(dst + 2 * (size_t)R) = make_float4(r[0].z, r[1].z, r[2].z, r[3].z);
+      *(float4*)(dst + 3 * (size_t)R) = make_float4(r[0].w, r[1].w, r[2].w, r[3].w);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -212,11 +271,6 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
       for (int o = 1; o < CPW; o <<= 1) bits |= __shfl_xor(bits, o);
       const int row = mask_row(mk, s, m);
       if (ch % CPW == 0 && row >= 0) mk.p[mask_at(mk, row, 0, ch / CPW)] = bits;
-    }
-    if constexpr (CAP) {
-#pragma unroll
-      for (int e = 0; e < EPC; e += 4)
-        cap4<P>(hcap, m, n + e, rstride, v[e], v[e + 1], v[e + 2], v[e + 3]);
     }
     if constexpr (P == 1) {
       bf16x8 w;
@@ -662,9 +716,6 @@ __device__ __forceinline__ void ep_act(const EpCtx& ec, f32x16 (&acc)[MTW][NTW],
           for (int e = 0; e < 4; ++e) bits |= pos_bit(x[e]) << (8 * q + e);   // the lane's half: << 4g below
         }
         store4_relu<P>(s, m, n, g, x);
-        if constexpr (CAP)
-          cap4<P>(ec.hrow, m, n, ec.rstride, fmaxf(x[0], 0.f), fmaxf(x[1], 0.f), fmaxf(x[2], 0.f),
-                  fmaxf(x[3], 0.f));
       }
       if constexpr (MASK) {
         bits <<= 4 * g;
@@ -724,7 +775,9 @@ __device__ __forceinline__ void ep_last(const NetDev& net, const EpCtx& ec, f32x
         // the seed of the output layer (a single output; a colour network
         // builds its seed from the three channels after the forward)
         if constexpr (ADJ && NOUT == 1) store4<P>(s, m, n, g, v, true);
-        if constexpr (CAP) cap4<P>(ec.hrow, m, n, ec.rstride, h[0], h[1], h[2], h[3]);
+        if constexpr (CAP && P == 2)
+          *(bf16x4*)(s.chunk(m, 2 * (n >> 3) + 1) + 8 * g) = bf16x4{(bf16)h[0], (bf16)h[1], (bf16)h[2], (bf16)h[3]};
+        if constexpr (CAP && P == 0) cap4<P>(ec.hrow, m, n, ec.rstride, h[0], h[1], h[2], h[3]);
       }
     }
 #pragma unroll
@@ -764,19 +817,22 @@ __device__ __forceinline__ void ep_vjp(const NetDev& net, const EpCtx& ec, f32x1
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[i][j][4 * q + e] = keep_if(acc[i][j][4 * q + e], bits, 8 * q + e);
-      if (ec.write_act) {
+      if (ec.write_act || (CAP && P == 0)) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           float v[4] = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
           store4<P>(s, m, feat(nt0, j, q, g), g, v, true);
         }
       }
-      if constexpr (CAP) {
+      if constexpr (CAP && P == 2) {
         const float w = s.gm[m];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          cap4<P>(ec.drow, m, feat(nt0, j, q, g), ec.rstride, w * acc[i][j][4 * q],
-                  w * acc[i][j][4 * q + 1], w * acc[i][j][4 * q + 2], w * acc[i][j][4 * q + 3]);
+        for (int q = 0; q < 4; ++q) {
+          const int n = feat(nt0, j, q, g);
+          *(bf16x4*)(s.chunk(m, 2 * (n >> 3) + 1) + 8 * g) =
+              bf16x4{(bf16)(w * acc[i][j][4 * q]), (bf16)(w * acc[i][j][4 * q + 1]), (bf16)(w * acc[i][j][4 * q + 2]),
+                     (bf16)(w * acc[i][j][4 * q + 3])};
+        }
       }
     }
   }
@@ -917,6 +973,14 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
     ep_vjp<P, MTW, NTW, WN, CAP, GP>(net, ec, acc, s, nt0, mt0, mg, nw, lane, mb);
   }
   __syncthreads();
+  if constexpr (CAP) {
+    // weight-gradient capture of the layer's output width from the tile; the
+    // next layer's epilogue rewrites the tile only after its GEMM's barrier
+    constexpr int N = WN * NTW * 32;
+    if constexpr (MODE == EP_ACT || MODE == EP_ACT_MASK) cap_tile<P>(s, 0, ec.hrow, ec.rstride, N, nullptr);
+    if constexpr ((MODE == EP_LAST || MODE == EP_LAST_ADJ) && P == 2) cap_tile<P>(s, 1, ec.hrow, ec.rstride, N, nullptr);
+    if constexpr (VJP) cap_tile<P>(s, P == 2 ? 1 : 0, ec.drow, ec.rstride, N, P == 0 ? s.gm : nullptr);
+  }
 }
 
 // One layer of output width N and contracted width K; returns the number of
@@ -970,13 +1034,14 @@ __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0
                                            int capR = 0) {
   layer0_fill<P, NW * 64, MR, CAP, ADJ>(net, bias0_lat, s, tid, hcap, capR, mk);
   __syncthreads();
+  if constexpr (CAP) cap_tile<P>(s, 0, hcap, kCapBlock, net.wpad[0], nullptr);
   int wn = 4;
   for (int l = 1; l <= net.nl - 2; ++l) {
     EpCtx ec = fwd_ctx(net, biasS_lat, l);
     ec.mk = mk;
     if constexpr (CAP) {
       ec.hrow = cap_ptr<P>(hcap, (size_t)l * net.kmax * capR);
-      ec.rstride = capR;
+      ec.rstride = kCapBlock;
     }
     // the skip layer is never the last hidden layer (skip <= nl - 3)
     if (l == net.nl - 2)
@@ -1298,7 +1363,7 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
 // factor s.gm where the column sums are taken).
 template <int P, int NW, bool CAP, bool GP = true>
 __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, const MaskRef& mk, float* part,
-                                           size_t row0, int rstride, int tile) {
+                                           size_t blk0, int rstride, int tile) {
   const NetDev& net = a.net;
   for (int l = net.nl - 2; l >= 1; --l) {
     EpCtx ec{};
@@ -1314,8 +1379,8 @@ __device__ __forceinline__ void vjp_layers(const AdjArgs& a, const Sm<P>& s, con
     ec.gp_row0 = tile * Cfg<P>::M;
     ec.gp_accum = (l - 1 == 0) && net.skip >= 1;   // the skip layer comes first in this loop
     if constexpr (CAP) {
-      ec.drow = cap_ptr<P>(a.dbuf, (size_t)(l - 1) * net.kmax * a.cap_rows + row0);
-      ec.rstride = a.cap_rows;
+      ec.drow = cap_ptr<P>(a.dbuf, (size_t)(l - 1) * net.kmax * a.cap_rows + blk0);
+      ec.rstride = kCapBlock;
     }
     layer<P, NW, Cfg<P>::M, GP ? EP_VJP : EP_VJP_NOGP, CAP>(net, ec, s, net.wpT[l], nullptr, net.kpad[l], net.wpad[l]);
   }
@@ -1340,8 +1405,9 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
   const int t_end = theta ? min(a.tile_end, (count + M - 1) / M) : (count + M - 1) / M;
   const int rstride = a.cap_rows;             // capture chunk rows (feature stride)
   for (int tile = (theta ? a.tile_begin : 0) + blockIdx.x; tile < t_end; tile += gridDim.x) {
-    const size_t row0 = theta ? (size_t)(tile - a.tile_begin) * M : 0;
-    float* hcap = theta ? cap_ptr<P>(a.hbuf, row0) : nullptr;
+    const size_t row0 = theta ? (size_t)(tile - a.tile_begin) * M : 0;   // first row in the chunk
+    const size_t blk0 = row0 * net.kmax;                                  // the tile's capture block
+    float* hcap = theta ? cap_ptr<P>(a.hbuf, blk0) : nullptr;
     if (tid < M) {
       const int idx = tile * M + tid;
       const float4 smp = a.samples[idx];
@@ -1365,13 +1431,13 @@ __global__ __launch_bounds__(kAdjWaves * 64) __attribute__((amdgpu_waves_per_eu(
       // Delta of the last hidden layer: gm * w_last * [h > 0]
       const int ll = net.nl - 2, W = net.wpad[ll];
       for (int i = tid; i < M * W; i += kAdjWaves * 64) {
-        const int m = i / W, n = i - m * W;
-        const size_t o = ((size_t)ll * net.kmax + n) * rstride + row0 + m;
+        const int n = i / M, m = i - n * M;          // consecutive threads: consecutive rows of a feature
+        const size_t o = (size_t)ll * net.kmax * rstride + blk0 + (size_t)n * kCapBlock + m;
         cap_put<P>(a.dbuf, o, cap_get<P>(a.hbuf, o) > 0.f ? s.gm[m] * net.wlast[n] : 0.f);
       }
     }
     float* part = a.partial + (size_t)tile * 4 * net.kmax;
-    if (theta) vjp_layers<P, kAdjWaves, true>(a, s, mk, part, row0, rstride, tile);
+    if (theta) vjp_layers<P, kAdjWaves, true>(a, s, mk, part, blk0, rstride, tile);
     else vjp_layers<P, kAdjWaves, false>(a, s, mk, part, 0, 0, tile);
   }
 }
@@ -1539,127 +1605,277 @@ size_t adj_mask_words(int precision, const NetDev& net) {
   return (size_t)net.nl * mlp_tile_rows(precision) * (net.kmax / 32);
 }
 
-// Per captured row, feature-major (R rows per feature): z of its latent, its
-// point and a 1, in the capture type; for the rows in [valid, R) that only pad
-// the contraction to whole slices, zeros there and in the captured h, Delta
-// and row factor.
+// Per captured row, in the blocked layout of the capture (features of a
+// kCapBlock-row block contiguous): z of its latent, its point (and a 0) and a
+// 1, in the capture type; for the rows in [valid, R) that only pad the
+// contraction to whole slices, zeros there and in the captured h, Delta and
+// row factor (whole blocks: valid is a multiple of kCapBlock).
 template <class T>
 __global__ void k_theta_rows(const float4* __restrict__ pts, const int* __restrict__ lat, const float* __restrict__ z,
                              int L, int valid, int R, T* zrows, T* prows, T* ones, T* hbuf, T* dbuf, T* gmbuf,
-                             int n_feat) {
+                             int n_layers, int kmax) {
   const long long step = (long long)gridDim.x * blockDim.x, t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  constexpr int B = kCapBlock;
   for (long long i = t0; i < (long long)L * R; i += step) {
-    const int j = (int)(i / R), r = (int)(i - (long long)j * R);
+    // i walks the blocked layout: block b, feature j, row r % B
+    const long long b = i / ((long long)L * B);
+    const int j = (int)(i / B % L), r = (int)(b * B + i % B);
     zrows[i] = (T)(r < valid ? z[(size_t)lat[r] * L + j] : 0.f);
   }
   for (long long r = t0; r < R; r += step) {
     const bool ok = r < valid;
     const float4 p = ok ? pts[r] : make_float4(0.f, 0.f, 0.f, 0.f);
-    prows[r] = (T)p.x;
-    prows[R + r] = (T)p.y;
-    prows[2 * (long long)R + r] = (T)p.z;
-    prows[3 * (long long)R + r] = (T)0.f;
+    T* pr = prows + (r / B) * 4 * B + r % B;
+    pr[0] = (T)p.x;
+    pr[B] = (T)p.y;
+    pr[2 * B] = (T)p.z;
+    pr[3 * B] = (T)0.f;
     ones[r] = (T)(ok ? 1.f : 0.f);
     if (!ok) gmbuf[r] = (T)0.f;
   }
-  const int pad = R - valid;
-  for (long long i = t0; i < (long long)n_feat * pad; i += step) {
-    const long long f = i / pad, r = valid + (i - f * pad);
-    hbuf[f * R + r] = (T)0.f;
-    dbuf[f * R + r] = (T)0.f;
+  // padding blocks of every layer: one contiguous range per layer
+  const long long per = (long long)(R - valid) * kmax;
+  for (long long i = t0; i < (long long)n_layers * per; i += step) {
+    const long long l = i / per, o = l * kmax * R + (long long)valid * kmax + (i - l * per);
+    hbuf[o] = (T)0.f;
+    dbuf[o] = (T)0.f;
   }
 }
 
 void launch_theta_rows(int precision, const float4* pts, const int* lat, const float* z, int L, int valid, int R,
-                       void* zrows, void* prows, void* ones, float* hbuf, float* dbuf, float* gmbuf, int n_feat,
-                       hipStream_t st) {
+                       void* zrows, void* prows, void* ones, float* hbuf, float* dbuf, float* gmbuf, int n_layers,
+                       int kmax, hipStream_t st) {
   const long long total = (long long)std::max(L, 1) * R;
   const int grid = (int)std::min<long long>((total + 255) / 256, 4096);
   if (precision == 0)
     hipLaunchKernelGGL(k_theta_rows<float>, dim3(grid), dim3(256), 0, st, pts, lat, z, L, valid, R, (float*)zrows,
-                       (float*)prows, (float*)ones, hbuf, dbuf, gmbuf, n_feat);
+                       (float*)prows, (float*)ones, hbuf, dbuf, gmbuf, n_layers, kmax);
   else
     hipLaunchKernelGGL(k_theta_rows<bf16>, dim3(grid), dim3(256), 0, st, pts, lat, z, L, valid, R, (bf16*)zrows,
-                       (bf16*)prows, (bf16*)ones, (bf16*)hbuf, (bf16*)dbuf, (bf16*)gmbuf, n_feat);
+                       (bf16*)prows, (bf16*)ones, (bf16*)hbuf, (bf16*)dbuf, (bf16*)gmbuf, n_layers, kmax);
 }
 
 // Weight-gradient contraction over the captured rows (Sec. 3.4: dW_l = sum
-// over samples of Delta_l x_l^T): P[sl][n][k] = sum over slice sl's K rows of
-// D[n][r] X[k][r], D and X feature-major with feature stride R.  A workgroup
-// of 4 waves owns a 128 (n) x 128 (k) block; a wave computes 64 x 64 of it as
-// 2 x 2 MFMA tiles whose A operand is 8 consecutive rows of one D feature and
-// B operand 8 consecutive rows of one X feature (bf16: 32x32x16; float32:
-// 32x32x2 over float4 loads of 4 rows, the rows paired (i, i + 4): any pairing
-// of the contraction index gives the same sum).  Reads past n_out or k_in are
-// clamped to the last feature and their outputs dropped.
-template <int P>
-__global__ __launch_bounds__(256) void k_dw(const void* __restrict__ D, const void* __restrict__ X, int R, int n_out,
-                                            int k_in, int K, float* __restrict__ Pout) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ln = lane & 31, g = lane >> 5;
-  const int nb = blockIdx.x * 128 + (wave & 1) * 64, kb = blockIdx.y * 128 + (wave >> 1) * 64;
-  const size_t r0 = (size_t)blockIdx.z * K;
+// over samples of Delta_l x_l^T, db_l = sum of Delta_l): for each slice sl of
+// K rows, P[sl][n][k] = sum over the slice's rows r of D[n][r] X[k][r], with
+// D and X feature-major (feature stride R).  The input features X of a layer
+// are up to four segments in input order (h, z, p, and on the float32 path a
+// ones row that yields the bias column).  With acc set the slice adds to the
+// partial it holds from the previous chunk; every slice is owned by one
+// workgroup per launch, so the sum order is fixed.  Slices are mapped to
+// workgroups so that all tiles of one slice run on one XCD (workgroups are
+// dealt to the 8 XCDs round robin) and share its L2 for the slice's rows.
+// input feature k: its rows of block 0 and the block stride (elements)
+__device__ __forceinline__ const char* dw_feature(const DwX& x, int k, int es, int& bstride) {
+  const void* b = x.p[0];
+  int base = 0, F = x.F[0];
+  if (x.nseg > 1 && k >= x.end[0]) { b = x.p[1]; base = x.end[0]; F = x.F[1]; }
+  if (x.nseg > 2 && k >= x.end[1]) { b = x.p[2]; base = x.end[1]; F = x.F[2]; }
+  if (x.nseg > 3 && k >= x.end[2]) { b = x.p[3]; base = x.end[2]; F = x.F[3]; }
+  bstride = F * kCapBlock;
+  return (const char*)b + (size_t)(k - base) * kCapBlock * es;
+}
+
+// workgroup -> (tile of the output, slice), all tiles of a slice on one XCD
+__device__ __forceinline__ void dw_block(int T, int S, int& tile, int& slice) {
+  const int id = blockIdx.x;
+  if (S % 8 == 0) {
+    const int x = id & 7, y = id >> 3;
+    slice = (y / T) * 8 + x;
+    tile = y % T;
+  } else {
+    slice = id / T;
+    tile = id % T;
+  }
+}
+
+__device__ __forceinline__ void dw_put(const DwArgs& a, float* P, int n, int k, float v) {
+  float* d = P + (size_t)n * a.ldp + k;
+  *d = a.acc ? *d + v : v;
+}
+
+// bf16: a workgroup of 4 waves owns a 128 (n) x 128 (k) block.  Blocks of
+// kDwRows rows of both operands are staged in LDS (feature-major, one padded
+// row of kDwLd elements per feature) with 16-byte loads, 8 lanes per 128-byte
+// feature row, double buffered: the next block's loads are in flight while
+// the MFMAs run on the current one.  Each wave computes 64 x 64 as 2 x 2
+// 32x32x16 tiles whose A operand is 8 rows of one Delta feature and B
+// operand 8 rows of one input feature.  The workgroups of the first k-block
+// column also sum the staged Delta rows: the bias column (k_in) of the
+// partial.  Features past n_out or kcols are clamped to the last one and
+// their outputs dropped.
+__global__ __launch_bounds__(256, 2) void k_dw_bf16(DwArgs a) {
+  bf16* lds = (bf16*)dyn_smem;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, ln = lane & 31, g = lane >> 5;
+  const int Tn = (a.n_out + 127) / 128, Tk = (a.kcols + 127) / 128;
+  int tile, slice;
+  dw_block(Tn * Tk, a.S, tile, slice);
+  const int n0 = (tile % Tn) * 128, k0 = (tile / Tn) * 128;
+  const size_t r0 = (size_t)slice * a.K;
+  const int rc = t & 7, fl = t >> 3;
+  const bf16* ga[4];
+  const bf16* gx[4];
+  int sx[4];                              // block strides of the input features (segments differ)
+  const int sa = a.FD * kCapBlock;
+  const size_t b0 = r0 / kCapBlock;       // the slice's first block
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int n = min(n0 + fl + 32 * i, a.n_out - 1), k = min(k0 + fl + 32 * i, a.kcols - 1);
+    ga[i] = (const bf16*)a.D + b0 * sa + (size_t)n * kCapBlock + 8 * rc;
+    gx[i] = (const bf16*)dw_feature(a.x, k, 2, sx[i]);
+    gx[i] += b0 * sx[i] + 8 * rc;
+  }
+  const bool bias = k0 == 0 && a.bias;
+  float bs[4] = {0.f, 0.f, 0.f, 0.f};
+  // three register sets: the loads of blocks b + 2 and b + 3 are in flight
+  // while block b is multiplied from LDS and block b + 1 is staged (HBM
+  // latency under load needs about that many bytes in flight per CU)
+  constexpr int NS = 3;
+  bf16x8 ra[NS][4], rx[NS][4];
+  auto gload = [&](int set, int blk) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ra[set][i] = *(const bf16x8*)(ga[i] + (size_t)blk * sa);
+      rx[set][i] = *(const bf16x8*)(gx[i] + (size_t)blk * sx[i]);
+    }
+  };
+  auto stage = [&](int set, int buf) {
+    bf16* A = lds + (size_t)buf * 2 * 128 * kDwLd;
+    bf16* X = A + 128 * kDwLd;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      *(bf16x8*)(A + (fl + 32 * i) * kDwLd + 8 * rc) = ra[set][i];
+      *(bf16x8*)(X + (fl + 32 * i) * kDwLd + 8 * rc) = rx[set][i];
+    }
+    if (bias) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bs[i] += (float)ra[set][i][e];
+    }
+  };
   f32x16 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
-  int na[2], kx[2];
+  const int wn = wave & 1, wk = wave >> 1;
+  const int nblk = a.K / kDwRows;
+  auto mma = [&](int buf) {
+    const bf16* A = lds + (size_t)buf * 2 * 128 * kDwLd;
+    const bf16* X = A + 128 * kDwLd;
+#pragma unroll
+    for (int ks = 0; ks < kDwRows / 16; ++ks) {
+      bf16x8 av[2], xv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = *(const bf16x8*)(A + (64 * wn + 32 * i + ln) * kDwLd + 16 * ks + 8 * g);
+        xv[i] = *(const bf16x8*)(X + (64 * wk + 32 * i + ln) * kDwLd + 16 * ks + 8 * g);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], xv[j], acc[i][j], 0, 0, 0);
+    }
+  };
+  // block b sits in register set b % NS, then in LDS buffer b % 2.  The loads
+  // are issued unconditionally (past the last block they repeat it, in
+  // bounds and unused): a conditional load would make the wait for an older
+  // set count it as absent and drain everything in flight.
+  auto step = [&](int blk, int set, int buf) {
+    gload(set, min(blk + NS, nblk - 1));
+    // the loads go out before the MFMAs (left to itself the scheduler sinks
+    // them below the wait for the older sets)
+    __builtin_amdgcn_sched_barrier(0);
+    mma(buf);
+    __builtin_amdgcn_sched_barrier(0);
+    if (blk + 1 < nblk) stage((set + 1) % NS, buf ^ 1);
+    __syncthreads();
+  };
+#pragma unroll
+  for (int u = 0; u < NS; ++u) gload(u, min(u, nblk - 1));
+  stage(0, 0);
+  __syncthreads();
+  int blk = 0;
+  for (; blk + 6 <= nblk; blk += 6) {
+#pragma unroll
+    for (int u = 0; u < 6; ++u) step(blk + u, u % NS, u & 1);
+  }
+#pragma unroll
+  for (int u = 0; u < 6; ++u)                     // the last nblk % 6 blocks (register sets indexed statically)
+    if (blk + u < nblk) step(blk + u, u % NS, u & 1);
+  mfma_drain();
+  float* P = a.P + (size_t)slice * a.n_out * a.ldp;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int n = n0 + 64 * wn + 32 * i + 8 * q + 4 * g + e, k = k0 + 64 * wk + 32 * j + ln;
+          if (n < a.n_out && k < a.kcols) dw_put(a, P, n, k, acc[i][j][4 * q + e]);
+        }
+  if (bias) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float x = bs[i];
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      const int n = n0 + fl + 32 * i;
+      if (rc == 0 && n < a.n_out) dw_put(a, P, n, a.k_in, x);
+    }
+  }
+}
+
+// float32: the operands are read straight from memory (float4 of 4 rows per
+// lane), a workgroup of 4 waves owns 128 x 128 and a wave 64 x 64 as 2 x 2
+// 32x32x2 tiles, the rows paired (i, i + 4) (any pairing of the contraction
+// index gives the same sum); the bias comes from the ones segment.
+__global__ __launch_bounds__(256) void k_dw_f32(DwArgs a) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ln = lane & 31, g = lane >> 5;
+  const int Tn = (a.n_out + 127) / 128, Tk = (a.kcols + 127) / 128;
+  int tile, slice;
+  dw_block(Tn * Tk, a.S, tile, slice);
+  const int nb = (tile % Tn) * 128 + (wave & 1) * 64, kb = (tile / Tn) * 128 + (wave >> 1) * 64;
+  const size_t r0 = (size_t)slice * a.K;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+  const float* pa[2];
+  const float* pb[2];
+  int sb[2];
+  const int sa = a.FD * kCapBlock;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    na[i] = min(nb + 32 * i + ln, n_out - 1);
-    kx[i] = min(kb + 32 * i + ln, k_in - 1);
+    pa[i] = (const float*)a.D + (size_t)min(nb + 32 * i + ln, a.n_out - 1) * kCapBlock + 4 * g;
+    pb[i] = (const float*)dw_feature(a.x, min(kb + 32 * i + ln, a.kcols - 1), 4, sb[i]) + 4 * g;
   }
-  if constexpr (P != 0) {
-    const bf16* a[2] = {(const bf16*)D + (size_t)na[0] * R + r0 + 8 * g, (const bf16*)D + (size_t)na[1] * R + r0 + 8 * g};
-    const bf16* b[2] = {(const bf16*)X + (size_t)kx[0] * R + r0 + 8 * g, (const bf16*)X + (size_t)kx[1] * R + r0 + 8 * g};
-    bf16x8 av[2], bv[2];
+  for (int r = 0; r < a.K; r += 8) {
+    const size_t blk = (r0 + r) / kCapBlock, w = (r0 + r) % kCapBlock;
+    float4 av[2], bv[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      av[i] = *(const bf16x8*)a[i];
-      bv[i] = *(const bf16x8*)b[i];
+      av[i] = *(const float4*)(pa[i] + blk * sa + w);
+      bv[i] = *(const float4*)(pb[i] + blk * sb[i] + w);
     }
-    for (int r = 16; r <= K; r += 16) {
-      bf16x8 an[2], bn[2];
-      const int rn = min(r, K - 16);                 // the last load repeats (in bounds, unused)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        an[i] = *(const bf16x8*)(a[i] + rn);
-        bn[i] = *(const bf16x8*)(b[i] + rn);
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        av[i] = an[i];
-        bv[i] = bn[i];
-      }
-    }
-  } else {
-    const float* a[2] = {(const float*)D + (size_t)na[0] * R + r0 + 4 * g, (const float*)D + (size_t)na[1] * R + r0 + 4 * g};
-    const float* b[2] = {(const float*)X + (size_t)kx[0] * R + r0 + 4 * g, (const float*)X + (size_t)kx[1] * R + r0 + 4 * g};
-    for (int r = 0; r < K; r += 8) {
-      float4 av[2], bv[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        av[i] = *(const float4*)(a[i] + r);
-        bv[i] = *(const float4*)(b[i] + r);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
-        }
-    }
   }
   mfma_drain();
-  float* out = Pout + (size_t)blockIdx.z * n_out * k_in;
+  float* P = a.P + (size_t)slice * a.n_out * a.ldp;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1669,15 +1885,15 @@ __global__ __launch_bounds__(256) void k_dw(const void* __restrict__ D, const vo
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int n = nb + 32 * i + 8 * q + 4 * g + e, k = kb + 32 * j + ln;
-          if (n < n_out && k < k_in) out[(size_t)n * k_in + k] = acc[i][j][4 * q + e];
+          if (n < a.n_out && k < a.kcols) dw_put(a, P, n, k, acc[i][j][4 * q + e]);
         }
 }
 
-void launch_dw(int precision, const void* D, const void* X, int R, int n_out, int k_in, int K, int S, float* P,
-               hipStream_t st) {
-  const dim3 grid((n_out + 127) / 128, (k_in + 127) / 128, S);
-  if (precision == 0) hipLaunchKernelGGL(k_dw<0>, grid, dim3(256), 0, st, D, X, R, n_out, k_in, K, P);
-  else hipLaunchKernelGGL(k_dw<1>, grid, dim3(256), 0, st, D, X, R, n_out, k_in, K, P);
+void launch_dw(int precision, const DwArgs& a, hipStream_t st) {
+  const int T = ((a.n_out + 127) / 128) * ((a.kcols + 127) / 128);
+  const dim3 grid(T * a.S);
+  if (precision == 0) hipLaunchKernelGGL(k_dw_f32, grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_dw_bf16, grid, dim3(256), kDwLds, st, a);
 }
 
 template <int P>
@@ -1703,7 +1919,11 @@ hipError_t mlp_setup(int precision, const NetDev& net) {
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_color_adjoint<0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   }
-  if (precision == 1) return setup_p<1>(bytes);
+  if (precision == 1) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_dw_bf16, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kDwLds);
+    if (e != hipSuccess) return e;
+    return setup_p<1>(bytes);
+  }
   if (precision == 2) return setup_p<2>(bytes);
   return setup_p<0>(bytes);
 }
