@@ -367,11 +367,17 @@ int dist_sdf_eval_noalloc(dist_ctx* ctx, const float* points, const int32_t* lat
 
 /* Vector-Jacobian product of the decoder at detached points (the per-sample
  * term of Eq. 2): g_z[l] = sum_{i: latent_ids[i] = l} seeds[i] df(points[i],
- * z_l)/dz_l, and optionally the weight gradient.  precision DIST_FP32
- * (float32 throughout) or DIST_BF16 / DIST_BF16X3 (split-bf16 recompute,
- * bf16 back-propagation).  Synchronises the host (it stages the grouping of
- * samples by latent).  With n = 0, g_z (and g_W, g_b) are zeroed and points,
- * latent_ids and seeds may be NULL. */
+ * z_l)/dz_l, and optionally the weight gradient.  points device [n, 3],
+ * latent_ids device int32 [n] (ids outside [0, n_latents) are clamped to
+ * that range, as in dist_sdf_eval), seeds device [n], z device [n_latents,
+ * latent_dim], g_z device [n_latents, latent_dim]; g_W / g_b as for
+ * dist_render_bwd.  precision DIST_FP32 (float32 throughout) or DIST_BF16 /
+ * DIST_BF16X3 (split-bf16 recompute, bf16 back-propagation).  The samples
+ * are grouped by latent on the device (a stable sort, so the sum order is
+ * fixed and the result reproducible bit for bit); the call is stream-ordered
+ * and does not synchronise the host, except with g_W, where it reads the
+ * sample count once to size its chunk loop.  With n = 0, g_z (and g_W, g_b)
+ * are zeroed and points, latent_ids and seeds may be NULL. */
 int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
                  const float* seeds, const float* z, int32_t n_latents, int64_t n,
                  int32_t precision, float* g_z, float* const* g_W, float* const* g_b,

@@ -17,7 +17,8 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdist.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["mlp_kernels.hip", "ray_kernels.hip", "dist_api.hip", "serve.hip", "photo_kernels.hip"]
+SOURCES = ["mlp_kernels.hip", "ray_kernels.hip", "dist_api.hip", "serve.hip", "photo_kernels.hip",
+           "sample_group.hip"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
     # code-object v5 loads in the HIP runtime that ships with PyTorch as well

@@ -63,6 +63,19 @@ struct CamSpace {
 // Buffers of the gradient through the unrolled march: the ray parameter of
 // every ray slot at every step (kept by the forward) and the per-slot adjoint
 // of t.
+// Scratch of the device-side grouping of explicit samples by latent
+// (dist_sdf_vjp): sort keys and values, per-latent counts and starts, and the
+// sort's temporary storage.
+struct GroupSpace {
+  char* mem = nullptr;
+  size_t bytes = 0;
+  int cap_n = 0, cap_lat = 0;
+  size_t temp_bytes = 0;
+  int *keys_in = nullptr, *vals_in = nullptr, *keys_out = nullptr, *vals_out = nullptr;
+  int *cnt = nullptr, *start = nullptr;
+  void* temp = nullptr;
+};
+
 struct UnrollSpace {
   char* mem = nullptr;
   size_t bytes = 0;
@@ -100,6 +113,7 @@ struct Workspace {
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   BwdSpace* bw = nullptr;
+  GroupSpace* gs = nullptr;
 };
 
 // Buffers of a colour network's calls (folded biases, hit list, backward).

@@ -527,6 +527,10 @@ static void ws_destroy(dist_ctx* ctx, Workspace* w) {
     ctx_free(ctx, w->us->mem, w->us->bytes);
     delete w->us;
   }
+  if (w->gs) {
+    ctx_free(ctx, w->gs->mem, w->gs->bytes);
+    delete w->gs;
+  }
   delete w;
 }
 
@@ -593,6 +597,36 @@ static int ns_get(dist_ctx* ctx, Workspace* w, long long cap_samples, size_t wor
   n->mask = (unsigned*)n->mem;
   n->dtanh = (float*)(n->mem + mbytes);
   w->ns = n;
+  return DIST_OK;
+}
+
+// Scratch of the device grouping of cap_n explicit samples over cap_lat latents.
+static int gs_get(dist_ctx* ctx, Workspace* w, int cap_n, int cap_lat) {
+  GroupSpace* g = w->gs;
+  if (g && g->cap_n >= cap_n && g->cap_lat >= cap_lat) return DIST_OK;
+  if (g) {
+    ctx_free(ctx, g->mem, g->bytes);
+    delete g;
+    w->gs = nullptr;
+  }
+  g = new GroupSpace();
+  g->cap_n = std::max(cap_n, 1);
+  g->cap_lat = std::max(cap_lat, 1);
+  g->temp_bytes = group_temp_bytes(g->cap_n, g->cap_lat);
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t kb = up((size_t)g->cap_n * 4), lb = up((size_t)g->cap_lat * 4);
+  g->bytes = 4 * kb + 2 * lb + up(g->temp_bytes);
+  int rc = ctx_alloc(ctx, (void**)&g->mem, g->bytes);
+  if (rc != DIST_OK) { delete g; return rc; }
+  char* m = g->mem;
+  g->keys_in = (int*)m;
+  g->vals_in = (int*)(m + kb);
+  g->keys_out = (int*)(m + 2 * kb);
+  g->vals_out = (int*)(m + 3 * kb);
+  g->cnt = (int*)(m + 4 * kb);
+  g->start = (int*)(m + 4 * kb + lb);
+  g->temp = m + 4 * kb + 2 * lb;
+  w->gs = g;
   return DIST_OK;
 }
 
@@ -1659,69 +1693,53 @@ extern "C" int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* l
   if ((g_W == nullptr) != (g_b == nullptr)) return dist_set_error(DIST_EINVAL, "pass both g_W and g_b, or neither");
   precision = adj_prec(precision);
   hipStream_t st = (hipStream_t)stream;
-  HIPCHK(hipStreamSynchronize(st));
-  std::vector<float> hp(3 * n), hs(n);
-  std::vector<int> hl(n);
-  if (n) {
-    HIPCHK(hipMemcpy(hp.data(), points, 12 * n, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(hs.data(), seeds, 4 * n, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(hl.data(), latent_ids, 4 * n, hipMemcpyDeviceToHost));
-  }
-  for (int64_t i = 0; i < n; ++i)
-    if (hl[i] < 0 || hl[i] >= n_latents) return dist_set_error(DIST_EINVAL, "latent id out of range");
   const int tile = adj_tile_rows(precision);
-  // group by latent (stable), pad each group to a multiple of the tile
-  std::vector<std::vector<int64_t>> groups(n_latents);
-  for (int64_t i = 0; i < n; ++i) groups[hl[i]].push_back(i);
-  std::vector<int> sb(n_latents), stt(n_latents), sp(n_latents);
-  long long pos = 0;
-  for (int l = 0; l < n_latents; ++l) {
-    sb[l] = (int)pos;
-    stt[l] = (int)groups[l].size();
-    sp[l] = (int)((groups[l].size() + tile - 1) / tile * tile);
-    pos += sp[l];
-  }
-  std::vector<float> smp(4 * std::max<long long>(pos, 1), 0.f);
-  std::vector<int> slat(std::max<long long>(pos, 1), 0);
-  for (int l = 0; l < n_latents; ++l) {
-    for (int k = 0; k < sp[l]; ++k) {
-      const long long o = sb[l] + k;
-      slat[o] = l;
-      if (k < stt[l]) {
-        const int64_t i = groups[l][k];
-        smp[4 * o] = hp[3 * i];
-        smp[4 * o + 1] = hp[3 * i + 1];
-        smp[4 * o + 2] = hp[3 * i + 2];
-        smp[4 * o + 3] = hs[i];
-      }
-    }
-  }
+  // per-latent segments padded to whole tiles: at most n + n_latents (tile - 1) slots
+  const long long cap = n + (long long)n_latents * (tile - 1);
+  if (cap > (1LL << 31) - 1) return dist_set_error(DIST_EINVAL, "too many samples and latents");
   Workspace* w = nullptr;
   int rc = ws_get(ctx, 1, 1, 1, n_latents, 1, &w);
   if (rc) return rc;
-  const int grid = mlp_grid(ctx, std::max<long long>(pos, 1), precision);
-  rc = bw_get(ctx, w, (int)std::max<long long>(pos, tile), 1, n_latents, tile,
+  const int grid = mlp_grid(ctx, std::max<long long>(cap, 1), precision);
+  rc = bw_get(ctx, w, (int)std::max<long long>(cap, tile), 1, n_latents, tile,
               adj_mask_words(precision, ctx->net[precision]) * grid);
+  if (!rc) rc = gs_get(ctx, w, (int)n, n_latents);
   if (rc) { ws_put(ctx, w); return rc; }
   BwdSpace* b = w->bw;
-  int np = (int)pos;
+  GroupSpace* gsp = w->gs;
   rc = fold_biases(ctx, w, z, n_latents, st);
   if (!rc) {
-    if (pos) {
-      HIPCHK(hipMemcpyAsync(b->samples, smp.data(), 16 * pos, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(b->sample_lat, slat.data(), 4 * pos, hipMemcpyHostToDevice, st));
-    }
-    HIPCHK(hipMemcpyAsync(b->seg_base, sb.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(b->seg_total, stt.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(b->seg_padded, sp.data(), 4 * n_latents, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(b->n_samples, &np, 4, hipMemcpyHostToDevice, st));
+    GroupArgs ga{};
+    ga.pts = points;
+    ga.seeds = seeds;
+    ga.lat = latent_ids;
+    ga.n = (int)n;
+    ga.n_lat = n_latents;
+    ga.tile = tile;
+    ga.keys_in = gsp->keys_in;
+    ga.vals_in = gsp->vals_in;
+    ga.keys_out = gsp->keys_out;
+    ga.vals_out = gsp->vals_out;
+    ga.cnt = gsp->cnt;
+    ga.start = gsp->start;
+    ga.temp = gsp->temp;
+    ga.temp_bytes = gsp->temp_bytes;
+    ga.samples = b->samples;
+    ga.sample_lat = b->sample_lat;
+    ga.seg_base = b->seg_base;
+    ga.seg_total = b->seg_total;
+    ga.seg_padded = b->seg_padded;
+    ga.n_samples = b->n_samples;
+    hipError_t e = group_samples(ga, st);
+    if (e != hipSuccess) rc = dist_set_error(DIST_EHIP, "grouping the samples by latent failed: %s", hipGetErrorString(e));
+  }
+  if (!rc) {
     if (g_W) {
       rc = run_theta(ctx, w, b, precision, z, g_W, g_b, st);
       if (!rc) rc = reduce_only(ctx, b, n_latents, g_z, st);
     } else {
       rc = run_adjoint_and_reduce(ctx, w, b, precision, n_latents, g_z, false, st);
     }
-    HIPCHK(hipStreamSynchronize(st));
   }
   ws_put(ctx, w);
   return rc;

@@ -236,4 +236,26 @@ void launch_pack_w(int precision, bool transpose, const float* W, int out, int i
 void launch_fold_bias(const float* b, const float* Wz, const float* z, int n_lat, int L, int nout,
                       int npad, float* dst, hipStream_t s);
 
+// Grouping of n explicit samples (points [n][3], seeds [n], latent ids [n],
+// clamped to [0, n_lat)) into per-latent segments padded to whole tiles of
+// the recompute-and-VJP kernel, in sample order within a latent (a stable
+// radix sort): samples / sample_lat, seg_base / seg_total / seg_padded per
+// latent and the padded total n_samples.  Scratch: keys and values (in and
+// out, n each), cnt and start (n_lat each) and temp (temp_bytes, at least
+// group_temp_bytes(n, n_lat)).  Stream-ordered, no host synchronisation.
+struct GroupArgs {
+  const float* pts;
+  const float* seeds;
+  const int32_t* lat;
+  int n, n_lat, tile;
+  int *keys_in, *vals_in, *keys_out, *vals_out, *cnt, *start;
+  void* temp;
+  size_t temp_bytes;
+  float4* samples;
+  int* sample_lat;
+  int *seg_base, *seg_total, *seg_padded, *n_samples;
+};
+size_t group_temp_bytes(int n, int n_lat);
+hipError_t group_samples(const GroupArgs& g, hipStream_t s);
+
 }  // namespace dist

@@ -153,6 +153,35 @@ def test_zero_gradients_and_empty_batches(ctx):
     assert float(gz.abs().max()) == 0.0
 
 
+def test_sdf_vjp_device_grouping(ctx):
+    """The VJP entry point groups its samples by latent on the device (stable
+    sort, per-latent segments padded to whole tiles): each latent's gradient
+    equals, bit for bit, that of a call holding only its own samples; ids
+    outside [0, n_latents) are clamped; a repeated call is identical."""
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    g = np.random.default_rng(11)
+    n, L = 1000, 3
+    P = torch.tensor(g.uniform(-0.6, 0.6, (n, 3)).astype(np.float32), device="cuda")
+    ids = g.integers(0, L, n).astype(np.int32)
+    seeds = torch.tensor(g.normal(size=n).astype(np.float32), device="cuda")
+    Z = torch.tensor(di.make_latents(L, spec.latent_dim), device="cuda")
+    for prec in (0, 1):
+        lat = torch.tensor(ids, device="cuda")
+        gz = api.dist_sdf_vjp(ctx, P, lat, seeds, Z, prec)
+        assert torch.equal(gz, api.dist_sdf_vjp(ctx, P, lat, seeds, Z, prec))
+        for l in range(L):
+            sel = torch.tensor(np.nonzero(ids == l)[0], device="cuda")
+            one = api.dist_sdf_vjp(ctx, P[sel], torch.zeros(len(sel), dtype=torch.int32, device="cuda"), seeds[sel],
+                                   Z[l:l + 1].contiguous(), prec)
+            assert torch.equal(gz[l], one[0]), (prec, l)
+        wild = ids.copy()
+        wild[ids == 0] = -5
+        wild[ids == L - 1] = L + 7
+        gw = api.dist_sdf_vjp(ctx, P, torch.tensor(wild, device="cuda"), seeds, Z, prec)
+        assert torch.equal(gw, gz)
+
+
 def test_invalid_arguments_are_rejected(ctx):
     from paper_1911_13225_amd import api, _native as N
     spec = di.DEEPSDF_SPEC
