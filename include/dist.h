@@ -439,7 +439,8 @@ int dist_poll(dist_ctx* ctx, uint64_t ticket, dist_result* res, int64_t timeout_
  * kernel: 0 = march step (decoder + march update), 1 = plain decoder queries
  * (normals, dist_sdf_eval), 2 = adjoint (backward recompute + VJP),
  * 3 = VJP of the normal-stencil samples from the ReLU masks the forward
- * saved (no recompute). */
+ * saved (no recompute), 4 = weight-gradient contraction over the captured
+ * rows (one launch per layer and chunk; rows are not counted). */
 typedef struct {
   int64_t launches;
   double ms;

@@ -101,7 +101,8 @@ def dist_timing_enable(ctx: Context, on: bool = True):
 
 
 def dist_timing_read(ctx: Context, kernel: int):
-    """(launches, milliseconds, rows) of kernel class 0 march, 1 eval, 2 adjoint, 3 VJP from saved masks."""
+    """(launches, milliseconds, rows) of kernel class 0 march, 1 eval, 2 adjoint, 3 VJP from saved masks,
+    4 weight-gradient contraction (rows not counted)."""
     t = N.dist_kernel_time()
     check(ctx.lib.dist_timing_read(ctx.handle, int(kernel), ctypes.byref(t)))
     return int(t.launches), float(t.ms), int(t.rows)

@@ -15,8 +15,8 @@ struct Server;
 }
 
 // kernel classes of dist_timing_read: march, decoder queries, adjoint with
-// recompute, VJP from saved masks
-constexpr int kTimeClasses = 4;
+// recompute, VJP from saved masks, weight-gradient contraction
+constexpr int kTimeClasses = 5;
 
 // Buffers of one backward pass (gradient samples and partial sums).
 struct BwdSpace {

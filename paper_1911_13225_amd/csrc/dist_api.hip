@@ -1211,6 +1211,7 @@ static int run_theta(dist_ctx* ctx, Workspace* w, BwdSpace* b, int prec, const f
       d.S = S;
       d.K = rows / S;
       d.acc = t0 > 0;
+      TimedLaunch tl(ctx, 4, st);
       launch_dw(prec, d, st);
     }
   }
