@@ -15,16 +15,19 @@
 //
 // Admission is limited by free ray slots, image/latent slots and the
 // context's HBM budget (request buffers are charged against it); a request
-// waits in the queue until resources free up.
-#include <chrono>
-#include <condition_variable>
+// waits in the queue until resources free up.  The queue, tickets, admission
+// bookkeeping, the coarse-to-fine tick table and the completion / failure /
+// cancellation paths are the device-independent core in sched_core.h; this
+// file is its HIP backend (pool, captured tick, per-request buffers, outputs,
+// loss, gradient and optimiser step).
 #include <cstring>
 #include <deque>
 #include <map>
-#include <thread>
+#include <memory>
 #include <vector>
 
 #include "ray_kernels.h"
+#include "sched_core.h"
 #include "serve.h"
 
 namespace dist {
@@ -34,49 +37,9 @@ int validate_camera_ext(const dist_camera& c, const dist_trace_params* p);
 void fill_desc_ext(ImgDesc& d, const dist_camera& c, const dist_trace_params* p, int latent, int slot_base,
                    int out_base);
 
-using Clock = std::chrono::steady_clock;
-
-// First-fit allocator of contiguous ray-slot ranges.
-struct SlotAlloc {
-  std::map<int, int> free_;     // begin -> count
-  void init(int cap) { free_.clear(); free_[0] = cap; }
-  int alloc(int n) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        const int b = it->first, c = it->second;
-        free_.erase(it);
-        if (c > n) free_[b + n] = c - n;
-        return b;
-      }
-    }
-    return -1;
-  }
-  void release(int b, int n) {
-    auto it = free_.emplace(b, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-};
-
-struct Request {
-  uint64_t ticket = 0;
+struct Request : sched::Job {
   dist_request req{};
   std::vector<dist_camera> cams;
-  int H = 0, W = 0, hw = 0, n_views = 0, levels = 0, spi = 0;
-  // pool resources
-  int slot_base = -1;
-  std::vector<int> imgs;        // pool image slots (view order)
-  int lat = -1;
   // device buffers of this request (one block from the server cache)
   char* mem = nullptr;
   size_t mem_bytes = 0;
@@ -86,29 +49,12 @@ struct Request {
   float4* d_nraw = nullptr;
   int *d_hits = nullptr, *d_hit_count = nullptr;
   BwdSpace bw;
-  // progress
-  int step = 0, iter = 0;
-  std::vector<char> img_done;
-  bool finished = false;       // render / optimisation complete (scheduler thread)
-  bool done = false;           // result published (under the server lock)
-  int status = DIST_OK;
-  int64_t queries = 0;
-  float final_loss = 0.f;
-  Clock::time_point t_submit, t_done;
 };
 
-struct Server {
+struct Server : sched::Backend {
   dist_ctx* ctx = nullptr;
   hipStream_t st = nullptr;
-  std::thread th;
-  std::mutex mu;
-  std::condition_variable cv_sub, cv_done;
-  bool stop = false;
-  std::deque<Request*> pending;
-  std::map<uint64_t, Request*> tickets;
-  std::vector<Request*> running;
-  uint64_t next_ticket = 1;
-  int max_pending = 4096;
+  std::unique_ptr<sched::Core> core;
   // pool
   int cap_rays = 0, cap_imgs = 0, cap_lat = 0;
   char* mem = nullptr;
@@ -129,15 +75,23 @@ struct Server {
   unsigned long long* h_q = nullptr;
   ImgDesc* h_desc = nullptr;
   float* h_loss = nullptr;
-  SlotAlloc slots;
-  std::vector<int> free_imgs, free_lats;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   int parity = 0;
   int adv_grid = 1024;
   // request buffer cache (size -> blocks), charged against the budget
   std::multimap<size_t, char*> cache;
-  std::string init_error;
-  int init_rc = DIST_OK;
+
+  // the scheduler core's device steps (scheduler thread only)
+  bool acquire(sched::Job* j) override;
+  void release(sched::Job* j) override;
+  void begin(sched::Job* j) override;
+  int tick(const std::vector<sched::TickEntry>& table, int n_new) override;
+  int active(int img) const override { return h_active[img]; }
+  int64_t queries(int img) const override { return (int64_t)h_q[img]; }
+  void complete(sched::Job* j) override;
+  void settle(sched::Job* j) override;
+  void drop_rays() override;
+  void thread_init() override { (void)hipSetDevice(ctx->device); }
 };
 
 static size_t ray_bytes() {
@@ -268,9 +222,6 @@ static int pool_init(Server* s) {
   HIPCHK_S(hipHostMalloc((void**)&s->h_q, sizeof(unsigned long long) * s->cap_imgs));
   HIPCHK_S(hipHostMalloc((void**)&s->h_desc, sizeof(ImgDesc) * s->cap_imgs));
   HIPCHK_S(hipHostMalloc((void**)&s->h_loss, sizeof(float) * s->cap_lat));
-  s->slots.init(s->cap_rays);
-  for (int i = s->cap_imgs - 1; i >= 0; --i) s->free_imgs.push_back(i);
-  for (int i = s->cap_lat - 1; i >= 0; --i) s->free_lats.push_back(i);
   HIPCHK_S(hipStreamSynchronize(s->st));
   for (int par = 0; par < 2; ++par) {
     rc = capture_tick(s, par);
@@ -320,21 +271,24 @@ static size_t req_layout(Server* s, Request* r, char* base) {
   return (size_t)(p - base) + 256;
 }
 
-static void release(Server* s, Request* r) {
-  if (r->slot_base >= 0) s->slots.release(r->slot_base, r->n_views * r->spi);
-  r->slot_base = -1;
-  for (int i : r->imgs) s->free_imgs.push_back(i);
-  r->imgs.clear();
-  if (r->lat >= 0) s->free_lats.push_back(r->lat);
-  r->lat = -1;
-  buf_put(s, r->mem, r->mem_bytes);
+// Device buffers of a request: one block from the cache, carved.
+bool Server::acquire(sched::Job* j) {
+  Request* r = static_cast<Request*>(j);
+  r->mem_bytes = req_layout(this, r, nullptr);
+  if (buf_get(this, r->mem_bytes, &r->mem) != DIST_OK) return false;
+  req_layout(this, r, r->mem);
+  return true;
+}
+
+void Server::release(sched::Job* j) {
+  Request* r = static_cast<Request*>(j);
+  buf_put(this, r->mem, r->mem_bytes);
   r->mem = nullptr;
 }
 
-// Start (or restart, for the next z-opt iteration) the render of a request.
-static void start_render(Server* s, Request* r) {
-  r->step = 0;
-  std::fill(r->img_done.begin(), r->img_done.end(), 0);
+// Fold the request's latent into the pooled per-latent biases: the start of
+// every render (the first, and each z-opt iteration's).
+static void fold_latent(Server* s, Request* r) {
   const int L = s->ctx->L;
   const float* z = s->z_pool + (size_t)r->lat * L;
   launch_fold_bias(s->ctx->bf[0], s->ctx->w0z, z, 1, L, s->ctx->out_dims[0], s->ctx->wpad[0],
@@ -344,48 +298,30 @@ static void start_render(Server* s, Request* r) {
                      s->ctx->wpad[s->ctx->skip], s->biasS + (size_t)r->lat * s->ctx->wpad[s->ctx->skip], s->st);
 }
 
-static bool try_admit(Server* s, Request* r) {
-  const int need = r->n_views * r->spi;
-  if ((int)s->free_imgs.size() < r->n_views || s->free_lats.empty()) return false;
-  r->mem_bytes = req_layout(s, r, nullptr);
-  if (buf_get(s, r->mem_bytes, &r->mem) != DIST_OK) return false;
-  const int base = s->slots.alloc(need);
-  if (base < 0) {
-    buf_put(s, r->mem, r->mem_bytes);
-    r->mem = nullptr;
-    return false;
-  }
-  r->slot_base = base;
-  req_layout(s, r, r->mem);
-  r->lat = s->free_lats.back();
-  s->free_lats.pop_back();
-  r->imgs.resize(r->n_views);
+// The request holds its ray slots, image slots and latent slot: descriptors,
+// latent code, optimiser state, first render.
+void Server::begin(sched::Job* j) {
+  Request* r = static_cast<Request*>(j);
   for (int v = 0; v < r->n_views; ++v) {
-    r->imgs[v] = s->free_imgs.back();
-    s->free_imgs.pop_back();
+    ImgDesc& d = h_desc[r->imgs[v]];
+    fill_desc_ext(d, r->cams[v], &r->req.prm, r->lat, r->slot_base + v * r->spi, v * r->hw);
+    (void)hipMemcpyAsync(imgs + r->imgs[v], &d, sizeof(ImgDesc), hipMemcpyHostToDevice, st);
   }
-  // descriptors and the latent code
-  for (int v = 0; v < r->n_views; ++v) {
-    ImgDesc& d = s->h_desc[r->imgs[v]];
-    fill_desc_ext(d, r->cams[v], &r->req.prm, r->lat, base + v * r->spi, v * r->hw);
-    (void)hipMemcpyAsync(s->imgs + r->imgs[v], &d, sizeof(ImgDesc), hipMemcpyHostToDevice, s->st);
-  }
-  (void)hipMemcpyAsync(r->d_imgs, r->imgs.data(), sizeof(int) * r->n_views, hipMemcpyHostToDevice, s->st);
-  for (int v = 0; v < r->n_views; ++v) launch_fill_u64(s->qcount + r->imgs[v], 1, s->st);
-  const int L = s->ctx->L;
-  (void)hipMemcpyAsync(s->z_pool + (size_t)r->lat * L, r->req.z, sizeof(float) * L, hipMemcpyDeviceToDevice, s->st);
-  launch_fill_i32((int*)(s->adam_m + (size_t)r->lat * L), 0, L, s->st);
-  launch_fill_i32((int*)(s->adam_v + (size_t)r->lat * L), 0, L, s->st);
+  (void)hipMemcpyAsync(r->d_imgs, r->imgs.data(), sizeof(int) * r->n_views, hipMemcpyHostToDevice, st);
+  for (int v = 0; v < r->n_views; ++v) launch_fill_u64(qcount + r->imgs[v], 1, st);
+  const int L = ctx->L;
+  (void)hipMemcpyAsync(z_pool + (size_t)r->lat * L, r->req.z, sizeof(float) * L, hipMemcpyDeviceToDevice, st);
+  launch_fill_i32((int*)(adam_m + (size_t)r->lat * L), 0, L, st);
+  launch_fill_i32((int*)(adam_v + (size_t)r->lat * L), 0, L, st);
   // the synchronisation below makes the pinned descriptors reusable
-  (void)hipStreamSynchronize(s->st);
-  r->img_done.assign(r->n_views, 0);
-  start_render(s, r);
-  return true;
+  (void)hipStreamSynchronize(st);
+  fold_latent(this, r);
 }
 
 // Outputs, normals and (z-opt) loss + gradient + Adam for a finished render.
-static void complete_render(Server* s, Request* r) {
-  dist_ctx* ctx = s->ctx;
+void Server::complete(sched::Job* j) {
+  Request* r = static_cast<Request*>(j);
+  Server* s = this;
   const dist_request& q = r->req;
   const bool zopt = q.kind == DIST_REQ_ZOPT;
   const bool last = !zopt || r->iter + 1 >= q.iters;
@@ -465,132 +401,43 @@ static void complete_render(Server* s, Request* r) {
     (void)hipMemcpyAsync(q.z_out, s->z_pool + (size_t)r->lat * L, sizeof(float) * L, hipMemcpyDeviceToDevice, s->st);
     r->finished = true;
   } else {
-    start_render(s, r);
+    r->restart();
+    fold_latent(s, r);
   }
 }
 
-static void finish(Server* s, Request* r, int status) {
-  (void)hipStreamSynchronize(s->st);
-  if (r->req.kind == DIST_REQ_ZOPT && r->lat >= 0 && r->iter > 0) r->final_loss = s->h_loss[r->lat];
-  std::lock_guard<std::mutex> lk(s->mu);
-  r->status = status;
-  r->t_done = Clock::now();
-  r->finished = true;
-  release(s, r);
-  r->done = true;
-  s->cv_done.notify_all();
+// The request's device work has drained; a z-opt request's last loss is on
+// the host.
+void Server::settle(sched::Job* j) {
+  Request* r = static_cast<Request*>(j);
+  (void)hipStreamSynchronize(st);
+  if (r->req.kind == DIST_REQ_ZOPT && r->lat >= 0 && r->iter > 0) r->final_loss = h_loss[r->lat];
 }
 
-static void run(Server* s) {
-  dist_ctx* ctx = s->ctx;
-  (void)hipSetDevice(ctx->device);
-  while (true) {
-    // admission
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      if (s->stop) break;
-      if (s->running.empty() && s->pending.empty()) {
-        s->cv_sub.wait(lk, [&] { return s->stop || !s->pending.empty(); });
-        if (s->stop) break;
-      }
-    }
-    while (true) {
-      Request* r = nullptr;
-      {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->pending.empty()) break;
-        r = s->pending.front();
-      }
-      if (!try_admit(s, r)) break;
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->pending.pop_front();
-      s->running.push_back(r);
-    }
-    if (s->running.empty()) {
-      std::this_thread::sleep_for(std::chrono::microseconds(200));
-      continue;
-    }
-    // the tick's table of images that start rays
-    int n_tab = 0, n_new = 0;
-    for (Request* r : s->running) {
-      const int L = r->levels;
-      int lvl = -1, split = 0;
-      if (r->step == 0) {
-        lvl = L;
-      } else if (r->step % 3 == 0 && r->step / 3 <= L) {
-        lvl = L - r->step / 3;
-        split = 1;
-      }
-      if (lvl < 0) continue;
-      for (int v = 0; v < r->n_views; ++v) {
-        AdvEntry& e = s->h_table[n_tab++];
-        e.img = r->imgs[v];
-        e.lvl = lvl;
-        e.step = r->step;
-        e.split = split;
-        e.begin = n_new;
-        e.count = (r->H >> lvl) * (r->W >> lvl);
-        n_new += e.count;
-      }
-    }
-    s->h_hdr[0] = n_tab;
-    s->h_hdr[1] = n_new;
-    if (n_tab) (void)hipMemcpyAsync(s->table, s->h_table, sizeof(AdvEntry) * n_tab, hipMemcpyHostToDevice, s->st);
-    (void)hipMemcpyAsync(s->hdr, s->h_hdr, sizeof(int) * 2, hipMemcpyHostToDevice, s->st);
-    hipError_t e = hipGraphLaunch(s->exec[s->parity], s->st);
-    s->parity ^= 1;
-    (void)hipMemcpyAsync(s->h_active, s->img_active, sizeof(int) * s->cap_imgs, hipMemcpyDeviceToHost, s->st);
-    (void)hipMemcpyAsync(s->h_q, s->qcount, sizeof(unsigned long long) * s->cap_imgs, hipMemcpyDeviceToHost, s->st);
-    hipError_t e2 = hipStreamSynchronize(s->st);
-    if (e != hipSuccess || e2 != hipSuccess) {
-      // runtime failure: fail every running request
-      std::vector<Request*> rs = s->running;
-      s->running.clear();
-      for (Request* r : rs) finish(s, r, DIST_EHIP);
-      // no ray of a failed request may stay in the pooled lists
-      launch_fill_i32(s->counters, 0, 2, s->st);
-      (void)hipStreamSynchronize(s->st);
-      continue;
-    }
-    // progress and completion
-    std::vector<Request*> keep;
-    for (Request* r : s->running) {
-      r->step += 1;
-      bool all = true;
-      for (int v = 0; v < r->n_views; ++v) {
-        const int img = r->imgs[v];
-        if (!r->img_done[v]) {
-          const bool no_more_splits = r->step > 3 * r->levels;
-          if (r->step >= r->req.prm.max_steps || (no_more_splits && s->h_active[img] == 0)) r->img_done[v] = 1;
-        }
-        all = all && r->img_done[v];
-      }
-      if (!all) {
-        keep.push_back(r);
-        continue;
-      }
-      complete_render(s, r);
-      if (r->finished) {
-        long long q = 0;
-        for (int img : r->imgs) q += (long long)s->h_q[img];
-        r->queries = q;
-        finish(s, r, DIST_OK);
-      } else {
-        keep.push_back(r);
-      }
-    }
-    s->running.swap(keep);
+// One tick: the table of images that start rays, the captured graph (clear
+// counters, apply level changes, advance, march), then the per-image active
+// and query counts back on the host.
+int Server::tick(const std::vector<sched::TickEntry>& tab, int n_new) {
+  const int n_tab = (int)tab.size();
+  for (int i = 0; i < n_tab; ++i) {
+    const sched::TickEntry& t = tab[i];
+    h_table[i] = AdvEntry{t.img, t.lvl, t.step, t.split, t.begin, t.count};
   }
-  // cancel what is left
-  std::vector<Request*> rest;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    rest = s->running;
-    for (Request* r : s->pending) rest.push_back(r);
-    s->running.clear();
-    s->pending.clear();
-  }
-  for (Request* r : rest) finish(s, r, DIST_ECANCELLED);
+  h_hdr[0] = n_tab;
+  h_hdr[1] = n_new;
+  if (n_tab) (void)hipMemcpyAsync(table, h_table, sizeof(AdvEntry) * n_tab, hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(hdr, h_hdr, sizeof(int) * 2, hipMemcpyHostToDevice, st);
+  hipError_t e = hipGraphLaunch(exec[parity], st);
+  parity ^= 1;
+  (void)hipMemcpyAsync(h_active, img_active, sizeof(int) * cap_imgs, hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h_q, qcount, sizeof(unsigned long long) * cap_imgs, hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  return (e != hipSuccess || e2 != hipSuccess) ? DIST_EHIP : DIST_OK;
+}
+
+void Server::drop_rays() {
+  launch_fill_i32(counters, 0, 2, st);
+  (void)hipStreamSynchronize(st);
 }
 
 }  // namespace dist
@@ -605,14 +452,11 @@ void serve_shutdown(dist_ctx* ctx) {
     ctx->server = nullptr;
   }
   if (!s) return;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-  }
-  s->cv_sub.notify_all();
-  if (s->th.joinable()) s->th.join();
+  // jobs still queued or running end DIST_ECANCELLED; then the core and every
+  // request it still holds go
+  s->core->shutdown();
   (void)hipStreamSynchronize(s->st);
-  for (auto& kv : s->tickets) delete kv.second;
+  s->core.reset();
   for (int p = 0; p < 2; ++p)
     if (s->exec[p]) (void)hipGraphExecDestroy(s->exec[p]);
   for (auto& kv : s->cache) ctx_free(ctx, kv.second, kv.first);
@@ -639,7 +483,8 @@ static Server* get_server(dist_ctx* ctx, int* rc) {
     delete s;
     return nullptr;
   }
-  s->th = std::thread(run, s);
+  s->core.reset(new sched::Core(s, s->cap_rays, s->cap_imgs, s->cap_lat, 4096));
+  s->core->start();
   ctx->server = s;
   return s;
 }
@@ -671,13 +516,15 @@ extern "C" int dist_submit(dist_ctx* ctx, const dist_request* req, uint64_t* tic
   r->req = *req;
   r->cams.assign(req->cams, req->cams + req->n_views);
   r->req.cams = r->cams.data();
+  r->kind = req->kind;
   r->H = H;
   r->W = W;
   r->hw = H * W;
   r->n_views = req->n_views;
   r->levels = req->prm.c2f_levels;
   r->spi = slots_per_image(r->hw, r->levels);
-  r->t_submit = Clock::now();
+  r->max_steps = req->prm.max_steps;
+  r->iters = req->kind == DIST_REQ_ZOPT ? req->iters : 1;
   if ((long long)r->n_views * r->spi > s->cap_rays) {
     delete r;
     return dist_set_error(DIST_ENOMEM, "request needs more ray slots than the pool holds");
@@ -687,16 +534,9 @@ extern "C" int dist_submit(dist_ctx* ctx, const dist_request* req, uint64_t* tic
     delete r;
     return dist_set_error(DIST_ENOMEM, "request can never fit the HBM budget (%zu bytes needed)", need);
   }
-  std::lock_guard<std::mutex> lk(s->mu);
-  if ((int)s->pending.size() >= s->max_pending) {
-    delete r;
-    return dist_set_error(DIST_EBUSY, "serving queue full");
-  }
-  r->ticket = s->next_ticket++;
-  s->tickets[r->ticket] = r;
-  s->pending.push_back(r);
-  *ticket = r->ticket;
-  s->cv_sub.notify_all();
+  rc = s->core->submit(r, ticket);
+  if (rc == DIST_EBUSY) return dist_set_error(DIST_EBUSY, "serving queue full");
+  if (rc) return dist_set_error(rc, "the server is shutting down");
   return DIST_OK;
 }
 
@@ -708,21 +548,7 @@ extern "C" int dist_poll(dist_ctx* ctx, uint64_t ticket, dist_result* res, int64
     s = ctx->server;
   }
   if (!s) return dist_set_error(DIST_ENOTFOUND, "unknown ticket");
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->tickets.find(ticket);
-  if (it == s->tickets.end()) return dist_set_error(DIST_ENOTFOUND, "unknown ticket");
-  Request* r = it->second;
-  auto done = [&] { return r->done; };
-  if (!done()) {
-    if (timeout_us == 0) return DIST_PENDING;
-    if (timeout_us < 0) s->cv_done.wait(lk, done);
-    else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) return DIST_PENDING;
-  }
-  res->status = r->status;
-  res->latency_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(r->t_done - r->t_submit).count();
-  res->queries = r->queries;
-  res->final_loss = r->final_loss;
-  s->tickets.erase(it);
-  delete r;
-  return DIST_OK;
+  const int rc = s->core->poll(ticket, res, timeout_us);
+  if (rc == DIST_ENOTFOUND) return dist_set_error(DIST_ENOTFOUND, "unknown ticket");
+  return rc;
 }
