@@ -49,12 +49,17 @@ extern "C" {
  *                "Initialization"): background, no queries.
  *   ESCAPED      the ray left the unit sphere while marching: background.
  *   UNCONVERGED  max_steps reached without convergence: background (the
- *                erosion effect of App. A.2).                                */
+ *                erosion effect of App. A.2).
+ *   ERROR        a query returned a non-finite signed distance (NaN or
+ *                infinity: the decoder's weights or codes are not finite):
+ *                the ray stops, background, no gradient samples; a served
+ *                request with such a ray ends with DIST_ENUMERIC.           */
 #define DIST_ACTIVE       0
 #define DIST_HIT          1
 #define DIST_MISS         2
 #define DIST_ESCAPED      3
 #define DIST_UNCONVERGED  4
+#define DIST_ERROR        5
 
 /* ---- precision ----------------------------------------------------------- */
 #define DIST_FP32  0   /* every decoder product in float32                       */
@@ -149,7 +154,9 @@ int dist_destroy(dist_ctx* ctx);
  *   sil      soft silhouette: min|f| - eps along the pixel's ray, or
  *            (distance of the ray from the origin) - 1 for rays that miss
  *            the unit sphere; negative means foreground (Sec. 3.3, App. A.3)
- *   status   uint8 DIST_HIT / DIST_MISS / DIST_ESCAPED / DIST_UNCONVERGED
+ *   status   uint8 DIST_HIT / DIST_MISS / DIST_ESCAPED / DIST_UNCONVERGED /
+ *            DIST_ERROR (the call stays stream-ordered and returns DIST_OK:
+ *            a non-finite query is reported per pixel, here)
  *   nsteps   uint8 number of global marching steps taken (0 for MISS)
  *   queries  device int64 [n_images]: decoder queries spent marching
  * saved: if non-NULL receives the state dist_render_bwd needs; the caller

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_PKG, "libdist.so")
 DIST_OK, DIST_PENDING = 0, 1
 ERRORS = {-1: "DIST_EINVAL", -2: "DIST_ENOMEM", -3: "DIST_EBUSY", -4: "DIST_ENOTFOUND",
           -5: "DIST_ECANCELLED", -6: "DIST_EHIP", -7: "DIST_ENUMERIC"}
-ACTIVE, HIT, MISS, ESCAPED, UNCONVERGED = 0, 1, 2, 3, 4
+ACTIVE, HIT, MISS, ESCAPED, UNCONVERGED, ERROR = 0, 1, 2, 3, 4, 5
+DIST_ENUMERIC = -7
 FP32, BF16 = 0, 1
 REQ_RENDER, REQ_ZOPT = 0, 1
 

@@ -21,7 +21,7 @@ constexpr int kMaxLayers = 12;
 constexpr int kMaxK = 4;
 constexpr int kMaxWidth = 512;
 
-enum : uint8_t { ST_ACTIVE = 0, ST_HIT = 1, ST_MISS = 2, ST_ESCAPED = 3, ST_UNCONVERGED = 4 };
+enum : uint8_t { ST_ACTIVE = 0, ST_HIT = 1, ST_MISS = 2, ST_ESCAPED = 3, ST_UNCONVERGED = 4, ST_ERROR = 5 };
 
 // One rendered image: camera, latent, tracing parameters and ray-slot bases.
 struct ImgDesc {
@@ -92,6 +92,7 @@ struct MarchArgs {
   const int* list;                 // active ray slots
   const int* count;                // number of entries in list
   unsigned long long* qcount;      // per-image decoder queries (or null)
+  int* ecount;                     // per-image count of non-finite queries (or null)
   // rays still ACTIVE after the step are appended here (null: the caller
   // builds the next list itself, e.g. at a coarse-to-fine split)
   int* next_list;

@@ -1148,7 +1148,8 @@ __device__ __forceinline__ bool march_eval(const MarchArgs& a, const Sm<P>& s) {
     pl.flast[r] = f;
     uint8_t st;
     if (!(af == af) || af == INFINITY) {
-      st = ST_UNCONVERGED;                   // non-finite query: stop the ray
+      st = ST_ERROR;                         // non-finite query: stop the ray, report it
+      if (a.ecount) atomicAdd(&a.ecount[pl.img[r]], 1);
     } else if (af < im.eps) {
       st = ST_HIT;
     } else if (n == im.max_steps - 1) {

@@ -177,6 +177,8 @@ __global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* img
       const float b = im.c[0] * d.x + im.c[1] * d.y + im.c[2] * d.z;
       const float cc = im.c[0] * im.c[0] + im.c[1] * im.c[1] + im.c[2] * im.c[2];
       sil = ray_origin_distance(cc, b) - 1.f;
+    } else if (st == ST_ERROR) {
+      sil = INFINITY;                      // a non-finite query: background
     } else {
       sil = fabsf(pl.rec_f[r]) - im.eps;
     }
@@ -225,7 +227,7 @@ __device__ __forceinline__ PixSamples pixel_samples(const RayPool& pl, const Img
                                                     const SeedIn& in) {
   PixSamples ps{0, 0, 0};
   const uint8_t st = pl.st[r];
-  if (st == ST_MISS) return ps;
+  if (st == ST_MISS || st == ST_ERROR) return ps;     // no samples on a ray that met a non-finite query
   const float gd = in.g_depth ? in.g_depth[q] : 0.f;
   const float gs = in.g_sil ? in.g_sil[q] : 0.f;
   if (in.hit_mode) {
@@ -782,7 +784,7 @@ __global__ void k_fill_u64(unsigned long long* p, int n) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float ul_seed(const RayPool& pl, const ImgDesc& im, int r, int pix, const UlIn& in) {
   const uint8_t st = pl.st[r];
-  if (st == ST_MISS) return 0.f;
+  if (st == ST_MISS || st == ST_ERROR) return 0.f;
   const int last = (int)pl.n[r] - 1;
   if (in.step > last) return 0.f;
   const bool term = in.step == last;

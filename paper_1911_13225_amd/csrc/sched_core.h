@@ -76,6 +76,7 @@ struct Job {
   int step = 0, iter = 0;
   std::vector<char> img_done;
   bool finished = false;        // render / optimisation complete
+  int error = DIST_OK;          // set by the backend: the job ends with this code (e.g. DIST_ENUMERIC)
   // published result (under mu)
   bool done = false;
   int status = DIST_OK;
@@ -110,7 +111,8 @@ struct Backend {
   virtual int active(int img) const = 0;
   virtual int64_t queries(int img) const = 0;
   // every image of j is done: outputs (render) or loss, gradient and the
-  // optimiser step (z-opt); sets j->finished, or restarts the job's render
+  // optimiser step (z-opt); sets j->finished, or restarts the job's render;
+  // may set j->error (the job then ends with that code)
   virtual void complete(Job* j) = 0;
   // before j's result is published: its device work has drained and
   // j->final_loss is set
@@ -234,7 +236,7 @@ class Core {
     if (j->slot_base >= 0) be_->settle(j);
     release(j);
     std::lock_guard<std::mutex> lk(mu_);
-    j->status = status;
+    j->status = status == DIST_OK && j->error != DIST_OK ? j->error : status;
     j->t_done = Clock::now();
     j->finished = true;
     j->done = true;

@@ -67,12 +67,14 @@ struct Server : sched::Backend {
   int* hdr = nullptr;            // [0] entries, [1] new rays
   int* img_active = nullptr;
   unsigned long long* qcount = nullptr;
+  int* ecount = nullptr;         // per image slot: queries that returned a non-finite f
   float *z_pool = nullptr, *bias0 = nullptr, *biasS = nullptr, *adam_m = nullptr, *adam_v = nullptr;
   // pinned staging
   AdvEntry* h_table = nullptr;
   int* h_hdr = nullptr;
   int* h_active = nullptr;
   unsigned long long* h_q = nullptr;
+  int* h_err = nullptr;
   ImgDesc* h_desc = nullptr;
   float* h_loss = nullptr;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -165,6 +167,7 @@ static size_t pool_layout(Server* s, char* base) {
   s->hdr = carve<int>(p, 4);
   s->img_active = carve<int>(p, s->cap_imgs);
   s->qcount = carve<unsigned long long>(p, s->cap_imgs);
+  s->ecount = carve<int>(p, s->cap_imgs);
   const int L = s->ctx->L;
   s->z_pool = carve<float>(p, (size_t)s->cap_lat * L);
   s->bias0 = carve<float>(p, (size_t)s->cap_lat * kMaxWidth);
@@ -192,6 +195,7 @@ static int capture_tick(Server* s, int par) {
   ma.list = s->lists[nxt];
   ma.count = s->counters + nxt;
   ma.qcount = s->qcount;          // queries counted where they are made
+  ma.ecount = s->ecount;          // and non-finite ones
   launch_march(kPrecBF16, ma, ctx->n_cu, s->st);
   hipGraph_t g = nullptr;
   HIPCHK_S(hipStreamEndCapture(s->st, &g));
@@ -220,6 +224,7 @@ static int pool_init(Server* s) {
   HIPCHK_S(hipHostMalloc((void**)&s->h_hdr, sizeof(int) * 4));
   HIPCHK_S(hipHostMalloc((void**)&s->h_active, sizeof(int) * s->cap_imgs));
   HIPCHK_S(hipHostMalloc((void**)&s->h_q, sizeof(unsigned long long) * s->cap_imgs));
+  HIPCHK_S(hipHostMalloc((void**)&s->h_err, sizeof(int) * s->cap_imgs));
   HIPCHK_S(hipHostMalloc((void**)&s->h_desc, sizeof(ImgDesc) * s->cap_imgs));
   HIPCHK_S(hipHostMalloc((void**)&s->h_loss, sizeof(float) * s->cap_lat));
   HIPCHK_S(hipStreamSynchronize(s->st));
@@ -308,7 +313,10 @@ void Server::begin(sched::Job* j) {
     (void)hipMemcpyAsync(imgs + r->imgs[v], &d, sizeof(ImgDesc), hipMemcpyHostToDevice, st);
   }
   (void)hipMemcpyAsync(r->d_imgs, r->imgs.data(), sizeof(int) * r->n_views, hipMemcpyHostToDevice, st);
-  for (int v = 0; v < r->n_views; ++v) launch_fill_u64(qcount + r->imgs[v], 1, st);
+  for (int v = 0; v < r->n_views; ++v) {
+    launch_fill_u64(qcount + r->imgs[v], 1, st);
+    launch_fill_i32(ecount + r->imgs[v], 0, 1, st);
+  }
   const int L = ctx->L;
   (void)hipMemcpyAsync(z_pool + (size_t)r->lat * L, r->req.z, sizeof(float) * L, hipMemcpyDeviceToDevice, st);
   launch_fill_i32((int*)(adam_m + (size_t)r->lat * L), 0, L, st);
@@ -354,7 +362,11 @@ void Server::complete(sched::Job* j) {
     launch_normals(s->pool, s->imgs, r->d_hits, r->d_hit_count, r->n_views * r->hw, r->d_fv, q.prm.normal_delta,
                    q.normal, r->d_nraw, s->st);
   }
-  if (!zopt) {
+  // a query of this render returned a non-finite f: the request ends with
+  // DIST_ENUMERIC (its maps show the rays as DIST_ERROR; no optimiser step)
+  for (int img : r->imgs)
+    if (h_err[img] > 0) r->error = DIST_ENUMERIC;
+  if (!zopt || r->error != DIST_OK) {
     r->finished = true;
     return;
   }
@@ -431,6 +443,7 @@ int Server::tick(const std::vector<sched::TickEntry>& tab, int n_new) {
   parity ^= 1;
   (void)hipMemcpyAsync(h_active, img_active, sizeof(int) * cap_imgs, hipMemcpyDeviceToHost, st);
   (void)hipMemcpyAsync(h_q, qcount, sizeof(unsigned long long) * cap_imgs, hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(h_err, ecount, sizeof(int) * cap_imgs, hipMemcpyDeviceToHost, st);
   hipError_t e2 = hipStreamSynchronize(st);
   return (e != hipSuccess || e2 != hipSuccess) ? DIST_EHIP : DIST_OK;
 }
@@ -465,6 +478,7 @@ void serve_shutdown(dist_ctx* ctx) {
   (void)hipHostFree(s->h_hdr);
   (void)hipHostFree(s->h_active);
   (void)hipHostFree(s->h_q);
+  (void)hipHostFree(s->h_err);
   (void)hipHostFree(s->h_desc);
   (void)hipHostFree(s->h_loss);
   if (s->st) (void)hipStreamDestroy(s->st);

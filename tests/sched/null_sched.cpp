@@ -45,6 +45,7 @@ struct NullBackend : Backend {
   std::map<uint64_t, int> life_of;
   size_t budget, used = 0;
   int acquire_calls = 0, fail_acquire_every = 0, ticks = 0, fail_tick_at = -1;
+  int numeric_every = 0;                   // every n-th ticket's render meets a non-finite query
   bool block = false;
   int tick_failures = 0, max_running_imgs = 0;
 
@@ -110,6 +111,11 @@ struct NullBackend : Backend {
   int64_t queries(int img) const override { return q[img]; }
   void complete(Job* j) override {
     CHECK(j->imgs.size() == (size_t)j->n_views);
+    if (numeric_every && j->ticket % numeric_every == 0) {
+      j->error = DIST_ENUMERIC;
+      j->finished = true;
+      return;
+    }
     if (j->kind == DIST_REQ_ZOPT) {
       ++j->iter;
       if (j->iter >= j->iters) j->finished = true;
@@ -316,11 +322,35 @@ static void tickfail() {
   CHECK(be.used == 0 && be.ranges.empty());
 }
 
+// A job whose render met a non-finite query ends with DIST_ENUMERIC; the
+// others complete.
+static void numeric() {
+  NullBackend be(16, (size_t)16 << 20);
+  be.numeric_every = 3;
+  Core core(&be, 1 << 16, 16, 16, 4096);
+  core.start();
+  std::mt19937 g(9);
+  std::vector<uint64_t> tks;
+  for (int i = 0; i < 30; ++i) {
+    uint64_t tk = 0;
+    CHECK(core.submit(make_job(g, i % 2 ? DIST_REQ_ZOPT : DIST_REQ_RENDER), &tk) == DIST_OK);
+    tks.push_back(tk);
+  }
+  for (uint64_t tk : tks) {
+    dist_result r{};
+    CHECK(core.poll(tk, &r, -1) == DIST_OK);
+    CHECK(r.status == (tk % 3 == 0 ? DIST_ENUMERIC : DIST_OK));
+  }
+  core.shutdown();
+  CHECK(be.used == 0 && be.ranges.empty());
+}
+
 int main(int argc, char** argv) {
   const std::string s = argc > 1 ? argv[1] : "all";
   if (s == "mixed" || s == "all") { mixed(); std::printf("ok mixed\n"); }
   if (s == "busy" || s == "all") { busy(); std::printf("ok busy\n"); }
   if (s == "cancel" || s == "all") { cancel(); std::printf("ok cancel\n"); }
   if (s == "tickfail" || s == "all") { tickfail(); std::printf("ok tickfail\n"); }
+  if (s == "numeric" || s == "all") { numeric(); std::printf("ok numeric\n"); }
   return 0;
 }

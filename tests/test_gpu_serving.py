@@ -274,3 +274,45 @@ def test_slot_reuse_after_a_request_ends_by_max_steps():
         assert torch.equal(alone.normal, b.normal)
     finally:
         c.close()
+
+
+def test_non_finite_queries_are_reported():
+    """A decoder whose output layer holds a NaN returns a non-finite f at
+    every query: the forward marks every ray that meets the unit sphere
+    DIST_ERROR (background, depth +inf, silhouette +inf, no gradient samples,
+    so dL/dz is zero), and a served render or z-opt request ends with
+    DIST_ENUMERIC."""
+    from paper_1911_13225_amd import api, _native as N
+    spec = di.DEEPSDF_SPEC
+    Ws, bs = di.make_decoder(spec, seed=0)
+    Ws = [w.copy() for w in Ws]
+    Ws[-1][0, 7] = np.nan
+    c = api.Context.from_spec(spec, Ws, bs)
+    try:
+        cams = [di.front_camera(32, 32)]
+        Z = torch.tensor(di.make_latents(1, spec.latent_dim), device="cuda")
+        for prec in (0, 1):
+            _log("non-finite decoder: forward and backward, precision", prec)
+            out = api.dist_render_fwd(c, cams, Z, _prm(precision=prec, c2f_levels=0), save=True)
+            st = out["status"].cpu().numpy()
+            assert set(np.unique(st).tolist()) <= {N.ERROR, N.MISS} and (st == N.ERROR).any()
+            assert bool(torch.isinf(out["depth"]).all()) and bool((out["sil"] > 0).all())
+            err = torch.tensor(st == N.ERROR, device="cuda")
+            assert bool(torch.isinf(out["sil"][err]).all())
+            ones = torch.ones_like(out["depth"])
+            g = api.dist_render_bwd(c, out["saved"], ones, torch.ones_like(out["normal"]), ones, n_latents=1)
+            out["saved"].free()
+            assert float(g.abs().max()) == 0.0
+        _log("non-finite decoder: served render and z-opt")
+        r = api.ServeRequest(N.REQ_RENDER, cams, Z[0], _prm(c2f_levels=0), want_normals=True)
+        api.dist_submit(c, r)
+        res = api.dist_poll(c, r, 60_000_000)
+        assert res is not None and res["status"] == N.DIST_ENUMERIC
+        assert bool((r.status == N.ERROR).any())
+        tgt = (torch.full((1, 32, 32), 1.5, device="cuda"), torch.ones(1, 32, 32, device="cuda"))
+        q = api.ServeRequest(N.REQ_ZOPT, cams, Z[0], _prm(c2f_levels=0), want_normals=False, targets=tgt, iters=3)
+        api.dist_submit(c, q)
+        res = api.dist_poll(c, q, 60_000_000)
+        assert res is not None and res["status"] == N.DIST_ENUMERIC
+    finally:
+        c.close()

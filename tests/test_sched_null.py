@@ -3,7 +3,8 @@ ray slots / images / latents, the coarse-to-fine tick table, completion,
 failure and cancellation) on a null device, on the CPU, built with
 ThreadSanitizer: DIST_EBUSY when the queue is full, DIST_ENOTFOUND for
 unknown or already-read tickets, DIST_ECANCELLED at shutdown, DIST_EHIP for
-every job running across a failed tick, injected allocation failures, and
+every job running across a failed tick, DIST_ENUMERIC for a job the device
+flags, injected allocation failures, and
 exclusive ownership of every image slot and ray-slot range."""
 import os
 import shutil
@@ -29,7 +30,7 @@ def binary(tmp_path_factory):
     return out
 
 
-@pytest.mark.parametrize("scenario", ["mixed", "busy", "cancel", "tickfail"])
+@pytest.mark.parametrize("scenario", ["mixed", "busy", "cancel", "tickfail", "numeric"])
 def test_scheduler_core_on_a_null_device(binary, scenario):
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66 second_deadlock_stack=1")
     r = subprocess.run([binary, scenario], capture_output=True, text=True, timeout=240, env=env)
