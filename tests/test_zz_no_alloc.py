@@ -5,6 +5,9 @@ Both run the same kernels on the same folded biases, so their outputs must be
 identical bit for bit.  Two calls in a row, the second with fewer points and
 fewer latents, check that the shared scratch array keeps no state that
 matters from one call to the next; a request beyond the scratch is refused.
+Captured in a HIP graph (the callers it is for), a call replays to the eager
+result bit for bit, with eager work between the replays, and follows its
+inputs when they change in place.
 """
 import ctypes
 import sys
@@ -78,4 +81,40 @@ def test_noalloc_eval_refuses_beyond_the_scratch():
     api.dist_sdf_eval_noalloc(ctx, P, ids, Z, 1, out)
     ref = api.dist_sdf_eval(ctx, P, ids, Z, 1)
     assert torch.equal(out, ref)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp32", "bf16", "split"])
+def test_noalloc_eval_replays_in_a_captured_graph(precision):
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    ctx = gpu_ctx(spec)
+    P, ids, Z = _inputs(4000, 5, spec.latent_dim, 21)
+    out = torch.full((4000,), float("nan"), device="cuda")
+    ref = api.dist_sdf_eval(ctx, P, ids, Z, precision)
+    # one call outside the capture first, on the stream the capture will use
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        api.dist_sdf_eval_noalloc(ctx, P, ids, Z, precision, out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    _log("graph capture, precision", precision)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        api.dist_sdf_eval_noalloc(ctx, P, ids, Z, precision, out)
+    for k in range(4):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+    # the graph reads its inputs where they are: change them in place
+    P.mul_(0.9)
+    Z.mul_(1.1)
+    ref2 = api.dist_sdf_eval(ctx, P, ids, Z, precision)
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref2)
+    del g
     ctx.close()
