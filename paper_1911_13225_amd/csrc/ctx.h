@@ -132,9 +132,10 @@ struct ColorSpace {
 };
 
 // Capture of one chunk of weight-gradient rows (see run_theta): h and Delta
-// of every hidden layer, the row factor, z / point / 1 per row, feature-major
-// in the capture type of the adjoint precision; per-slice results of the
-// contraction.
+// of every hidden layer, the row factor, z / point / 1 per row, in the
+// blocked layout of the capture (see mlp_kernels.hip) and the capture type of
+// the adjoint precision; the slice partials of the contraction, accumulated
+// across chunks.
 struct ThetaSpace {
   void* mem = nullptr;
   size_t bytes = 0;

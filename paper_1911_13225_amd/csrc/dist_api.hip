@@ -1036,8 +1036,9 @@ __global__ void k_zero_f32(float* p, long long n) {
 // db_l = sum_rows Delta_l, where Delta_l is the row's seed times dm/d(pre-
 // activation of layer l) and x_l the layer's input ([h] for hidden layers,
 // [z, p] for layer 0, [h, z, p] for the skip layer).  The recompute-and-VJP
-// kernel captures h and Delta of every row of a chunk, feature-major
-// (bfloat16 on the bf16 paths, float32 on the float32 path); each layer's
+// kernel captures h and Delta of every row of a chunk in the blocked
+// feature-major layout of the capture (64-row blocks, a block's features
+// contiguous; bfloat16 on the bf16 paths, float32 on the float32 path); each layer's
 // contraction over the chunk's rows runs on MFMA (one k_dw launch per layer
 // and chunk, every input segment and the bias in it).  The contraction is
 // long (all samples) and the output small (a layer's weights), so the rows of

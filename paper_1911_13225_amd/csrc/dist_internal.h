@@ -136,14 +136,14 @@ struct AdjArgs {
   float* partial;                  // [tile][2][2][kmax] column sums (S0, Sskip) x m-groups
   // weight gradient (optional): tiles [tile_begin, tile_end) write, per row,
   // h_l (post-ReLU) and Delta_l = seed * dm/d(pre-activation of layer l) for
-  // every hidden layer, feature-major [nl-1][kmax][cap_rows], plus the row's
+  // every hidden layer, blocked [nl-1][cap_rows / 64][kmax][64], plus the row's
   // seed factor gm, in the capture type (float32 in the float32 kernel,
   // bfloat16 otherwise)
   float* hbuf;
   float* dbuf;
   float* gmbuf;
   int tile_begin, tile_end;
-  int cap_rows;                    // rows of the capture chunk (feature-major: element (l kmax + n) cap_rows + row)
+  int cap_rows;                    // rows of the capture chunk (element l kmax cap_rows + (row / 64 kmax + n) 64 + row % 64)
   // VJP from saved masks (k_vjp_saved): samples [n_begin[0], n_samples[0]),
   // each with its stencil index in sample_idx; masks and 1 - tanh^2 as
   // written by the forward's stencil queries

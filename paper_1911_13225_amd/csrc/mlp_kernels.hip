@@ -1659,7 +1659,8 @@ void launch_theta_rows(int precision, const float4* pts, const int* lat, const f
 // Weight-gradient contraction over the captured rows (Sec. 3.4: dW_l = sum
 // over samples of Delta_l x_l^T, db_l = sum of Delta_l): for each slice sl of
 // K rows, P[sl][n][k] = sum over the slice's rows r of D[n][r] X[k][r], with
-// D and X feature-major (feature stride R).  The input features X of a layer
+// D and X in the capture's blocked layout (64-row blocks, a block's features
+// contiguous, each segment with its own features per block).  The input features X of a layer
 // are up to four segments in input order (h, z, p, and on the float32 path a
 // ones row that yields the bias column).  With acc set the slice adds to the
 // partial it holds from the previous chunk; every slice is owned by one
