@@ -166,6 +166,40 @@ def test_sdf_vjp_weights(spec, prec, tol):
         assert rw <= tol and rb <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)], ids=["fp32", "bf16"])
+def test_sdf_vjp_weights_multi_chunk(prec, tol):
+    """Weight and bias gradients over 140,000 samples: three chunks of the
+    contraction (two of 65,536 rows and a ragged one), whose slice partials
+    accumulate across chunks, against the oracle (small decoder).  Among 36 M
+    ReLU decisions some pre-activations lie within float32 rounding of zero,
+    and one flipped unit moves a random-sign sum of this length by ~1e-4, so
+    the samples whose smallest |pre-activation| (oracle) is below 1e-5 get a
+    zero seed on both sides."""
+    from paper_1911_13225_amd import api
+    spec = di.C1_SPEC
+    ctx = ctx_for(spec)
+    dec = oracle_decoder(spec)
+    n = 140_000
+    Z = di.make_latents(3, spec.latent_dim, sigma=0.1)
+    P = _rand_points(n, 23, -0.6, 0.6)
+    rng = np.random.Generator(np.random.PCG64(24))
+    seeds = rng.standard_normal(n).astype(np.float32)
+    lat = rng.integers(0, 3, n).astype(np.int32)
+    keep = dec.relu_margin(Z[lat].astype(np.float64), P.astype(np.float64)) > 1e-5
+    seeds = np.where(keep, seeds, 0.0).astype(np.float32)
+    _log("vjp weights, multi-chunk, precision", prec, "samples", n, "kept", int(keep.sum()))
+    assert keep.mean() > 0.95
+    g, gW, gb = api.dist_sdf_vjp(ctx, torch.tensor(P, device="cuda"), torch.tensor(lat, device="cuda"),
+                                 torch.tensor(seeds, device="cuda"), torch.tensor(Z, device="cuda"), prec,
+                                 want_theta=True)
+    _, oW, ob = dec.sdf_vjp(Z[lat].astype(np.float64), P.astype(np.float64), seeds.astype(np.float64))
+    for l in range(len(oW)):
+        rw = np.linalg.norm(gW[l].cpu().numpy() - oW[l]) / np.linalg.norm(oW[l])
+        rb = np.linalg.norm(gb[l].cpu().numpy() - ob[l]) / max(np.linalg.norm(ob[l]), 1e-30)
+        _log("  layer", l, "dW rel", rw, "db rel", rb)
+        assert rw <= tol and rb <= tol
+
+
 # ----------------------------------------------------------------------------
 # forward render, FP32
 # ----------------------------------------------------------------------------
