@@ -230,9 +230,9 @@ __device__ __forceinline__ float4 ld4(const float* p) { return *(const float4*)p
 // layers (a word holds 32 features, i.e. 32 / EPC neighbouring lanes' chunks,
 // combined across those lanes), so the backward reads them instead of
 // recomputing W0_p p + b0.
-template <int P, int NT, int MR, bool CAP, bool MASK = false>
+template <int P, int NT, int MR, bool MASK = false>
 __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias0_lat, const Sm<P>& s, int tid_,
-                                            float* hcap, int rstride, const MaskRef& mk = MaskRef{}) {
+                                            const MaskRef& mk = MaskRef{}) {
   const int tid = opaque(tid_);
   constexpr int M = MR, EPC = Cfg<P>::EPC;
   const int N0 = net.wpad[0];
@@ -1032,7 +1032,7 @@ template <int P, int NW, int MR, bool ADJ, bool CAP, int NOUT = 1>
 __device__ __forceinline__ int mlp_forward(const NetDev& net, const float* bias0_lat, const float* biasS_lat,
                                            const Sm<P>& s, int tid, const MaskRef& mk, float* hcap = nullptr,
                                            int capR = 0) {
-  layer0_fill<P, NW * 64, MR, CAP, ADJ>(net, bias0_lat, s, tid, hcap, capR, mk);
+  layer0_fill<P, NW * 64, MR, ADJ>(net, bias0_lat, s, tid, mk);
   __syncthreads();
   if constexpr (CAP) cap_tile<P>(s, 0, hcap, kCapBlock, net.wpad[0], nullptr);
   int wn = 4;
