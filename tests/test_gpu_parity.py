@@ -691,3 +691,46 @@ def test_full_size_c2_sampled_pixels():
     assert np.all(g["sil"][hit] < 0)
     assert np.all(np.isfinite(g["depth"][hit]))
     assert np.all(np.isinf(g["depth"][~hit]))
+
+
+@pytest.mark.parametrize("prec,depth_tol", [(0, 1e-4), (1, 2e-3)], ids=["fp32", "bf16"])
+def test_max_image_size_sampled_pixels(prec, depth_tol):
+    """The largest image the boundary accepts (2048 x 2048 = 2^22 pixels),
+    coarse-to-fine from 512 x 512: 200 sampled pixels traced one by one by the
+    oracle agree in status, step count and depth (flips only where the oracle's
+    decision margin is below 2e-5 in float32, 1e-3 in bf16); the backward runs
+    at that size and stays finite; one pixel more per side is refused."""
+    from paper_1911_13225_amd import api, _native as N
+    spec = di.DEEPSDF_SPEC
+    prm = cfg_params("c2", precision=prec)
+    H = 2048
+    cam = di.front_camera(H, H)
+    Z = di.make_latents(1, spec.latent_dim)
+    ctx = ctx_for(spec)
+    out = api.dist_render_fwd(ctx, [cam], torch.tensor(Z, device="cuda"), prm, save=True)
+    torch.cuda.synchronize()
+    g = _np(out, 0)
+    rng = np.random.Generator(np.random.PCG64(31))
+    pix = rng.choice(H * H, 200, replace=False)
+    o = O.render(oracle_decoder(spec), Z, [cam], [(0, 0)], prm, pixels=[pix])[0]
+    st_o, st_g = o.status.reshape(-1)[pix], g["status"].reshape(-1)[pix]
+    ns_o, ns_g = o.nsteps.reshape(-1)[pix], g["nsteps"].reshape(-1)[pix]
+    same = (st_o == st_g) & (ns_o == ns_g)
+    flips = ~same
+    _log("max size, precision", prec, ": hits", int((st_o == 1).sum()), "flips", int(flips.sum()),
+         "queries", int(out["queries"][0]))
+    assert np.all(o.margin.reshape(-1)[pix][flips] < (2e-5 if prec == 0 else 1e-3))
+    assert flips.sum() <= (1 if prec == 0 else 4)
+    h = same & (st_o == 1)
+    assert h.sum() > 20
+    assert np.abs(o.depth.reshape(-1)[pix][h] - g["depth"].reshape(-1)[pix][h]).max() <= depth_tol
+    hit = g["status"] == 1
+    assert np.all(g["sil"][hit] < 0) and np.all(np.isfinite(g["depth"][hit]))
+    # backward over every pixel of the largest image
+    gd = torch.where(out["status"] == 1, torch.full_like(out["depth"], 1e-6), torch.zeros_like(out["depth"]))
+    gz = api.dist_render_bwd(ctx, out["saved"], gd, None, torch.full_like(out["sil"], 1e-6), n_latents=1)
+    out["saved"].free()
+    assert bool(torch.isfinite(gz).all()) and float(gz.abs().max()) > 0
+    with pytest.raises(N.DistError) as e:
+        api.dist_render_fwd(ctx, [di.front_camera(H + 4, H + 4)], torch.tensor(Z, device="cuda"), prm)
+    assert e.value.code == -1
