@@ -144,7 +144,8 @@ int dist_destroy(dist_ctx* ctx);
 /* Forward render (paper Sec. 3): sphere-trace n_images images, image i
  * being the pair (view pairs[2i], latent pairs[2i+1]).  pairs may be NULL,
  * meaning all n_views x n_latents pairs with image i = (i / n_latents,
- * i % n_latents).  All views must share H and W.
+ * i % n_latents).  All views must share H and W; 1 <= n_images <= 65535
+ * (an image is one row of the per-image launch grids) and H W <= 2^22.
  *   cams     host [n_views]
  *   z        device [n_latents, latent_dim]
  * Outputs (device, caller-owned, each may be NULL), per image [H, W](x3):
@@ -308,7 +309,8 @@ int dist_photometric_loss(const dist_camera* cams, int32_t n_views,
  * fg_r is the rendered silhouette (sil < 0), fg_t the target's (sil_t > 0.5);
  * sign(0) = 0 and max'(0) = 0; a hinge term whose weight sil_t or 1 - sil_t is
  * zero adds nothing (so a target depth off its silhouette is never read).
- *   depth, sil, depth_t, sil_t   device [n_images][H][W] (sil_t in [0, 1])
+ *   depth, sil, depth_t, sil_t   device [n_images][H][W] (sil_t in [0, 1]);
+ *                                1 <= n_images <= 65535, H W <= 2^22
  *   normal, normal_t             device [n_images][H][W][3]; read only when
  *                                w_normal != 0 (then both are required)
  *   loss                         device [n_images], overwritten

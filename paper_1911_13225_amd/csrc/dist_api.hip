@@ -871,7 +871,7 @@ extern "C" int dist_render_fwd(dist_ctx* ctx, const dist_camera* cams, int32_t n
   if (ctx->n_out != 1) return dist_set_error(DIST_EINVAL, "a colour network does not render geometry");
   if (n_views < 1 || n_latents < 1) return dist_set_error(DIST_EINVAL, "n_views and n_latents must be positive");
   const int n_img = pairs ? n_images : n_views * n_latents;
-  if (n_img < 1 || n_img > 65536) return dist_set_error(DIST_EINVAL, "n_images must be in [1, 65536]");
+  if (n_img < 1 || n_img > kMaxImages) return dist_set_error(DIST_EINVAL, "n_images must be in [1, %d]", kMaxImages);
   const int H = cams[0].H, W = cams[0].W;
   for (int v = 0; v < n_views; ++v) {
     if (cams[v].H != H || cams[v].W != W) return dist_set_error(DIST_EINVAL, "all views must share H and W");
@@ -1754,7 +1754,7 @@ extern "C" int dist_render_loss(int32_t n_images, int32_t H, int32_t W, const fl
                                 const float* sil, const float* depth_t, const float* normal_t, const float* sil_t,
                                 float w_depth, float w_sil, float w_normal, float* loss, float* g_depth,
                                 float* g_normal, float* g_sil, void* stream) {
-  if (n_images < 1 || n_images > 65536) return dist_set_error(DIST_EINVAL, "n_images must be in [1, 65536]");
+  if (n_images < 1 || n_images > kMaxImages) return dist_set_error(DIST_EINVAL, "n_images must be in [1, %d]", kMaxImages);
   if (H < 1 || W < 1 || (long long)H * W > (1 << 22))
     return dist_set_error(DIST_EINVAL, "H and W must be positive (at most 4M pixels per image)");
   if (!depth || !sil || !depth_t || !sil_t || !loss) return dist_set_error(DIST_EINVAL, "null argument");

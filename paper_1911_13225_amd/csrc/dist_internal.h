@@ -164,6 +164,7 @@ struct AdjArgs {
 // bfloat16 (x = hi + lo, products hi*hi + lo*hi + hi*lo, float32 accumulation).
 constexpr int kPrecF32 = 0, kPrecBF16 = 1, kPrecSplit = 2;
 constexpr int kGpSlots = 8;          // point-gradient partial slots per sample (one per wave)
+constexpr int kMaxImages = 65535;    // images per call: one row each of the per-image launch grids (gridDim.y)
 
 // Inputs of the weight gradient that the capture does not hold, per captured
 // row, in the capture's blocked layout (kCapBlock rows per block, a block's

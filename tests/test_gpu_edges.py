@@ -182,6 +182,39 @@ def test_sdf_vjp_device_grouping(ctx):
         assert torch.equal(gw, gz)
 
 
+def test_many_small_images_in_one_launch(ctx):
+    """4,096 images of 8 x 8 (64 views x 64 latents) in one launch: every
+    per-image grid row and descriptor is used; sampled images agree with the
+    oracle in status and step count and, on hits, in depth; 65,536 images are
+    refused (an image is one row of the per-image launch grids)."""
+    from paper_1911_13225_amd import api, _native as N
+    spec = di.C1_SPEC
+    c = api.Context.from_spec(spec, *di.make_decoder(spec, seed=0))
+    try:
+        cams = di.random_sphere_cameras(64, 8, 8)
+        Z = di.make_latents(64, spec.latent_dim)
+        prm = _prm(precision=0, c2f_levels=1, want_normals=0)
+        out = api.dist_render_fwd(c, cams, torch.tensor(Z, device="cuda"), prm)
+        assert out["depth"].shape[0] == 4096
+        dec = O.Decoder(spec, *di.make_decoder(spec, seed=0))
+        for i in (0, 1, 2047, 4095):
+            v, l = i // 64, i % 64
+            o = O.render(dec, Z, cams, [(v, l)], prm)[0]
+            st = out["status"][i].cpu().numpy()
+            ns = out["nsteps"][i].cpu().numpy()
+            same = (o.status == st) & (o.nsteps == ns)
+            assert np.all(same | (o.margin < 2e-5)), i
+            h = same & (st == 1)
+            if h.any():
+                assert np.abs(o.depth[h] - out["depth"][i].cpu().numpy()[h]).max() <= 1e-4
+        with pytest.raises(N.DistError) as e:
+            api.dist_render_fwd(c, di.random_sphere_cameras(256, 4, 4), torch.tensor(
+                di.make_latents(256, spec.latent_dim), device="cuda"), _prm(precision=0, c2f_levels=0))
+        assert e.value.code == -1
+    finally:
+        c.close()
+
+
 def test_invalid_arguments_are_rejected(ctx):
     from paper_1911_13225_amd import api, _native as N
     spec = di.DEEPSDF_SPEC
