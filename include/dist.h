@@ -405,7 +405,10 @@ int dist_sdf_vjp(dist_ctx* ctx, const float* points, const int32_t* latent_ids,
  *   ZOPT: target_depth/target_sil device [n_views, H, W] (sil in {0,1}),
  *         iters Adam iterations with learning rate lr (paper App. B.4:
  *         Adam, 1e-2), loss w_depth * L1 depth + w_sil * silhouette hinge
- *         (App. A.3), z_out device [latent_dim]. */
+ *         (App. A.3), z_out device [latent_dim].
+ * A request whose render meets a non-finite signed distance ends with
+ * status DIST_ENUMERIC; a z-opt request then stops optimising and leaves
+ * z_out unwritten. */
 typedef struct {
   int32_t kind;
   int32_t n_views;
