@@ -769,6 +769,7 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
   ma.t_hist = t_hist;
   // steps before the last coarse-to-fine split: one launch per step, every
   // image splitting after the same steps
+  int* tail_cnt = w->counters + prm->max_steps + 5;
   for (int n = 0; n < 3 * L; ++n) {
     const int lv = L - n / 3;
     const long long rays = (long long)n_img * (hw >> (2 * lv));
@@ -786,8 +787,12 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
       // the bf16 march may choose 64-row tiles, so size its grid by those
       launch_march(prec, ma, mlp_grid(ctx, rays, prec == kPrecBF16 ? kPrecSplit : prec), st);
     }
+    // the last split orders the full-resolution list for the one-launch
+    // march: children of rays still marching first, the others from the
+    // list's end
     if (split)
-      launch_split(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * (lv - 1)), lv - 1, n + 1, nxt, ncnt, st);
+      launch_split(w->pool, w->imgs, w->imgs_list, n_img, hw >> (2 * (lv - 1)), lv - 1, n + 1, nxt, ncnt, st,
+                   lv == 1 ? tail_cnt : nullptr, w->pool.cap);
   }
   // full resolution: every remaining step in one launch; the rays of the
   // step's list are claimed into per-workgroup rings carved from the other
@@ -798,6 +803,8 @@ int run_trace(dist_ctx* ctx, Workspace* w, int n_img, int hw, const dist_trace_p
     const int grid = (int)std::max(1LL, std::min<long long>(ctx->n_cu, cap / 256));
     ma.list = w->list[n & 1];
     ma.count = w->counters + n;
+    ma.count_tail = L > 0 ? tail_cnt : nullptr;
+    ma.tail_end = w->pool.cap;
     ma.next_list = w->list[(n + 1) & 1];
     ma.next_count = nullptr;
     ma.claim = w->counters + n + 1;

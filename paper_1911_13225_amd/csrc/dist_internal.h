@@ -91,6 +91,10 @@ struct MarchArgs {
   const float* biasS_lat;          // [n_lat][wpad_skip]
   const int* list;                 // active ray slots
   const int* count;                // number of entries in list
+  // k_march_ring: a second run of *count_tail entries stored backwards from
+  // list[tail_end - 1], taken after the first (or null)
+  const int* count_tail;
+  int tail_end;
   unsigned long long* qcount;      // per-image decoder queries (or null)
   int* ecount;                     // per-image count of non-finite queries (or null)
   // rays still ACTIVE after the step are appended here (null: the caller

@@ -1127,8 +1127,8 @@ __device__ __forceinline__ bool march_eval(const MarchArgs& a, const Sm<P>& s) {
     const RayPool& pl = a.pool;
     const ImgDesc& im = a.imgs[pl.img[r]];
     const int n = pl.n[r];
-    float4 d = pl.d[r];
-    const float t = d.w;
+    float* dw = reinterpret_cast<float*>(pl.d) + 4 * (size_t)r + 3;   // t, the ray's distance
+    const float t = *dw;
     // running K smallest |f| (ties keep the earlier step)
     const float af = fabsf(f);
     const int Kr = im.K;
@@ -1158,8 +1158,7 @@ __device__ __forceinline__ bool march_eval(const MarchArgs& a, const Sm<P>& s) {
       const float tn = fmaf(im.alpha, f, t);
       const float2 b = pl.b[r];
       st = (tn > b.y || tn < b.x) ? ST_ESCAPED : ST_ACTIVE;
-      d.w = tn;
-      pl.d[r] = d;
+      *dw = tn;
     }
     pl.st[r] = st;
     pl.n[r] = (uint8_t)(n + 1);
@@ -1241,8 +1240,11 @@ __device__ __forceinline__ int wg_prefix(bool flag, int* total) {
 // in its own region of a spare list (ring_cap slots), marches tiles of up to
 // M of them and puts the survivors back at the ring's end.  While it holds
 // fewer than 2M live rays it claims more from the input list (one atomic per
-// claim of up to 1024), so workgroups that draw short rays take more of them
-// and the grid stays busy until the input is spent.  No step waits for the
+// claim of up to 256), so workgroups that draw short rays take more of them
+// and the grid stays busy until the input is spent.  Small claims keep the
+// last fresh rays spread over many workgroups: with claims of 1024 the
+// workgroups that claimed last still marched hundreds of rays after the
+// others had run dry (3% of the march).  No step waits for the
 // slowest tile of the grid, and tiles stay full until a workgroup has fewer
 // than M live rays.  A ring never overflows: claims are capped by its free
 // slots and a ray returns only after leaving it.  Every ray stops within
@@ -1254,7 +1256,7 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
   __shared__ int claim_lds[2];
   Sm<P> s(dyn_smem, a.net.kmax);
   const int tid = threadIdx.x;
-  const int n0 = *a.count, RC = a.ring_cap;
+  const int nh = *a.count, n0 = nh + (a.count_tail ? *a.count_tail : 0), RC = a.ring_cap;
   int* ring = a.next_list + (size_t)blockIdx.x * RC;
   int head = 0, tail = 0, live = 0;
   bool more = true;
@@ -1262,14 +1264,17 @@ __global__ __launch_bounds__(kFwdWaves<P> * 64) __attribute__((amdgpu_waves_per_
   while (true) {
     if (more && live < 2 * M) {
       if (tid == 0) {
-        const int want = min(1024, RC - live);
+        const int want = min(256, RC - live);
         const int st = atomicAdd(a.claim, want);
         claim_lds[0] = st;
         claim_lds[1] = max(0, min(want, n0 - st));
       }
       __syncthreads();
       const int st = claim_lds[0], got = claim_lds[1];
-      for (int i = tid; i < got; i += NT) ring[(tail + i) % RC] = a.list[st + i];
+      for (int i = tid; i < got; i += NT) {
+        const int j = st + i;
+        ring[(tail + i) % RC] = j < nh ? a.list[j] : a.list[a.tail_end - 1 - (j - nh)];
+      }
       tail += got;
       live += got;
       more = got > 0;

@@ -64,7 +64,8 @@ struct SplitList {
 void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_rays, int* list,
                        int* counter, hipStream_t s);
 void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_children,
-                  int child_lvl, int child_step, int* list, int* counter, hipStream_t s);
+                  int child_lvl, int child_step, int* list, int* counter, hipStream_t s,
+                  int* counter_tail = nullptr, int tail_end = 0);
 void launch_finalize(const RayPool& pl, const ImgDesc* imgs, const int* imgs_list, int n_img, int hw,
                      const FinalizeOut& o, hipStream_t s);
 void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, const int* hit_count, int max_hits,

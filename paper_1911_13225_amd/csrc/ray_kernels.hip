@@ -14,7 +14,7 @@ namespace dist {
 // Append `value` to list for every thread with flag set; one atomic per
 // 256-thread block.  Must be called by all threads of the block.  Returns the
 // list position of a flagged thread's entry (-1 for the others).
-__device__ __forceinline__ int block_append(bool flag, int value, int* list, int* counter) {
+__device__ __forceinline__ int block_append(bool flag, int value, int* list, int* counter, int dir = 1) {
   __shared__ int wcnt[4];
   __shared__ int base;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -29,7 +29,7 @@ __device__ __forceinline__ int block_append(bool flag, int value, int* list, int
   __syncthreads();
   int off = base;
   for (int i = 0; i < w; ++i) off += wcnt[i];
-  if (flag) list[off + within] = value;
+  if (flag) list[dir * (off + within)] = value;
   __syncthreads();
   return flag ? off + within : -1;
 }
@@ -115,15 +115,20 @@ __global__ __launch_bounds__(256) void k_init_level(RayPool pl, ImgDesc* imgs, c
 // four rays of level lvl.  A child starts from the parent's t clamped into its
 // own unit-sphere interval (from its own entry if the parent missed) and is
 // re-activated whatever the parent's state; its records start empty.
+// With counter_tail the list is filled from both ends: children of rays still
+// marching at the split (the ones that need the most further steps) from the
+// front, the others backwards from list[tail_end - 1], so a consumer that
+// takes the rays in order starts the long ones first.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_split(RayPool pl, ImgDesc* imgs, const int* imgs_list, int child_lvl,
-                                               int child_step, int* list, int* counter) {
+                                               int child_step, int* list, int* counter, int* counter_tail,
+                                               int tail_end) {
   const int img = imgs_list[blockIdx.y];
   const ImgDesc& im = imgs[img];
   const int Wl = im.W >> child_lvl, Hl = im.H >> child_lvl;
   const int Wp = im.W >> (child_lvl + 1);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool act = false;
+  bool act = false, marching = false;
   int r = 0;
   if (i < Wl * Hl) {
     const int V = i / Wl, U = i - V * Wl;
@@ -132,13 +137,20 @@ __global__ __launch_bounds__(256) void k_split(RayPool pl, ImgDesc* imgs, const 
     level_ray(im, child_lvl, U, V, d, xt, yt);
     const bool inside = sphere_interval(im, d, t_lo, t_hi);
     const int pr = im.slot_base + im.lvl_off[child_lvl + 1] + (V >> 1) * Wp + (U >> 1);
-    const float tp = pl.st[pr] == ST_MISS ? t_lo : pl.d[pr].w;
+    const uint8_t pst = pl.st[pr];
+    const float tp = pst == ST_MISS ? t_lo : pl.d[pr].w;
     const float t = fminf(fmaxf(tp, t_lo), t_hi);
     r = im.slot_base + im.lvl_off[child_lvl] + i;
     init_ray(pl, im, img, r, d, t, t_lo, t_hi, inside, child_step);
     act = inside;
+    marching = pst == ST_ACTIVE;
   }
-  block_append(act, r, list, counter);
+  if (counter_tail) {
+    block_append(act && marching, r, list, counter);
+    block_append(act && !marching, r, list + tail_end - 1, counter_tail, -1);
+  } else {
+    block_append(act, r, list, counter);
+  }
 }
 
 __global__ void k_set_level(ImgDesc* imgs, const int* imgs_list, int n, int lvl) {
@@ -979,10 +991,11 @@ void launch_init_level(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, i
                      counter);
 }
 void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_img, int max_children,
-                  int child_lvl, int child_step, int* list, int* counter, hipStream_t s) {
+                  int child_lvl, int child_step, int* list, int* counter, hipStream_t s, int* counter_tail,
+                  int tail_end) {
   if (n_img <= 0 || max_children <= 0) return;
   hipLaunchKernelGGL(k_split, dim3(nblk(max_children, 256), n_img), dim3(256), 0, s, pl, imgs, imgs_list,
-                     child_lvl, child_step, list, counter);
+                     child_lvl, child_step, list, counter, counter_tail, tail_end);
   hipLaunchKernelGGL(k_set_level, dim3(nblk(n_img, 256)), dim3(256), 0, s, imgs, imgs_list, n_img, child_lvl);
 }
 void launch_finalize(const RayPool& pl, const ImgDesc* imgs, const int* imgs_list, int n_img, int hw,
