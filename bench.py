@@ -297,7 +297,7 @@ def cpu_baseline(gpu_maps=None, seconds_target=15.0):
         rounds += 1
         for q in pix:
             seen[img][int(q)] = (r.status.reshape(-1)[q], r.depth.reshape(-1)[q], r.sil.reshape(-1)[q],
-                                 r.normal.reshape(-1, 3)[q], r.dirs[q])
+                                 r.normal.reshape(-1, 3)[q], r.dirs[q], float(np.linalg.norm(r.nraw.reshape(-1, 3)[q])))
     out = {"value": round(total_q / total_s, 1), "unit": "queries/s", "cores": int(cores), "kind": "oracle",
            "sample": f"{rounds} x {n_pix} random pixels of images {list(BASELINE_IMAGES)} of the 32-image "
                      f"workload (with their coarse-to-fine ancestors), FP64 fwd + normals + loss + backward; "
@@ -311,12 +311,14 @@ def per_output_error(seen, gpu_maps):
     """Per-output error of the GPU's bf16 maps against the oracle on the pixels
     the oracle traced: depth over pixels that are foreground in both (all of
     them, and the well-conditioned ones with |cos(ray, normal)| >= 0.25),
-    normals on the well-conditioned ones, binary silhouette mismatch over all
-    sampled pixels."""
-    dd, dd_wc, dn_wc, n_pix, mis = [], [], [], 0, 0
+    normals on the well-conditioned ones (unit normals, and as the tests bound
+    them: the unit-normal difference times the length of the central-difference
+    gradient, which normalising would otherwise amplify where that length is
+    small), binary silhouette mismatch over all sampled pixels."""
+    dd, dd_wc, dn_wc, dg_wc, n_pix, mis = [], [], [], [], 0, 0
     for img, px in seen.items():
         g = gpu_maps[img]
-        for q, (st, dep, sil, nrm, dvec) in px.items():
+        for q, (st, dep, sil, nrm, dvec, glen) in px.items():
             n_pix += 1
             mis += int((sil < 0) != (g["sil"][q] < 0))
             if st == 1 and g["status"][q] == 1:
@@ -325,14 +327,16 @@ def per_output_error(seen, gpu_maps):
                 if abs(float(np.dot(dvec, nrm))) >= 0.25:
                     dd_wc.append(e)
                     dn_wc.append(float(np.linalg.norm(nrm - g["normal"][q])))
+                    dg_wc.append(dn_wc[-1] * glen)
     dd = np.array(dd)
     res = {"pixels": n_pix, "hits_both": int(dd.size), "silhouette_mismatch_frac": round(mis / max(n_pix, 1), 6),
-           "tolerance": {"depth": 2e-3, "silhouette_mismatch_frac": 1e-3}}
+           "tolerance": {"depth": 2e-3, "silhouette_mismatch_frac": 1e-3, "normal_x_grad_len": 2e-3}}
     if dd.size:
         res["depth_all_hits"] = {"max": float(dd.max()), "p99_9": float(np.percentile(dd, 99.9)),
                                  "frac_above_2e-3": round(float((dd > 2e-3).mean()), 6)}
         res["depth_well_conditioned"] = {"n": len(dd_wc), "max": float(max(dd_wc)) if dd_wc else None}
         res["normal_well_conditioned_max"] = float(max(dn_wc)) if dn_wc else None
+        res["normal_x_grad_len_well_conditioned_max"] = float(max(dg_wc)) if dg_wc else None
     return res
 
 
