@@ -13,7 +13,9 @@ namespace dist {
 // ---------------------------------------------------------------------------
 // Append `value` to list for every thread with flag set; one atomic per
 // 256-thread block.  Must be called by all threads of the block.  Returns the
-// list position of a flagged thread's entry (-1 for the others).
+// list position of a flagged thread's entry (-1 for the others); the entry at
+// position i is stored at list[dir * i], so dir = -1 fills backwards from the
+// element `list` points at.
 __device__ __forceinline__ int block_append(bool flag, int value, int* list, int* counter, int dir = 1) {
   __shared__ int wcnt[4];
   __shared__ int base;
