@@ -298,13 +298,14 @@ __device__ __forceinline__ void layer0_fill(const NetDev& net, const float* bias
 // The k loop is software pipelined: weight fragments (from L2) are requested
 // D k-steps before use in a ring of D register sets, and the activation
 // fragments of the next k-step (from LDS) are requested one step ahead (a
-// double buffer, so the loop is unrolled by U = max(D, 2) steps).  Measured
-// per use: four steps ahead for the bf16 forward (the march), two for the
-// bf16 VJP, split bf16 and float32 (1-2% either way: fewer loads in flight
-// queue less in the texture units that carry them, too few expose the round
-// trip).  The last U steps request no weights past the end of the layer.
-// ksteps must be a multiple of U and at least U (the padded widths are
-// multiples of 128).
+// double buffer, so the loop is unrolled by U = max(D, 2) steps, an even
+// count).  Measured per use: four steps ahead for the bf16 forward (the
+// march) and for every VJP (the bf16 one and the split kernels' hi-product
+// one: 3-3.5% faster than two), two for the split forward and float32 (1-2%
+// either way: fewer loads in flight queue less in the texture units that
+// carry them, too few expose the round trip).  The
+// last U steps request no weights past the end of the layer.  ksteps must be
+// a multiple of U and at least U (the padded widths are multiples of 128).
 
 // Weight fragments are read with raw buffer loads: a scalar resource for the
 // layer's packed array (its byte size bounds every load), the lane's 16-byte
@@ -359,6 +360,7 @@ __device__ __forceinline__ void gemm_bf16(f32x16 (&acc)[MTW][NTW], const Sm<1>& 
 #pragma unroll
   for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const bf16x8*)arow[i];
   constexpr int U = D < 2 ? 2 : D;
+  static_assert(U % 2 == 0, "the activation double buffer alternates within a block of U steps");
   // one k-step: the next step's activation fragments (the block's row bases
   // ab plus an immediate; after the layer's last step this reads one chunk
   // past K, still inside the tile, and the value is not used), this step's
@@ -434,6 +436,7 @@ __device__ __forceinline__ void gemm_split(f32x16 (&acc)[MTW][NTW], const Sm<2>&
     if constexpr (X3) pl.b[0][i] = *(const bf16x8*)(arow[i] + 16);
   }
   constexpr int U = D < 2 ? 2 : D;
+  static_assert(U % 2 == 0, "the activation double buffer alternates within a block of U steps");
   const char* ab[MTW];           // the block's row bases (see gemm_bf16)
   auto step = [&](int ks, int d, bool pf) {
     const int sl = d % D, cb = d & 1, nb = cb ^ 1;
@@ -499,6 +502,7 @@ __device__ __forceinline__ void gemm_f32(f32x16 (&acc)[MTW][NTW], const Sm<0>& s
 #pragma unroll
   for (int i = 0; i < MTW; ++i) p.b[0][i] = *(const f32x4*)arow[i];
   constexpr int U = D < 2 ? 2 : D;
+  static_assert(U % 2 == 0, "the activation double buffer alternates within a block of U steps");
   for (int k0 = 0; k0 < ksteps; k0 += U) {
     const char* ab[MTW];         // the block's row bases (see gemm_bf16)
 #pragma unroll
@@ -955,9 +959,9 @@ __device__ __forceinline__ void layer_run(const NetDev& net, const EpCtx& ec, co
   else if constexpr (SKIP) acc_bias<P, MTW, NTW, true>(acc, ec, s, nt0, mt0, lane);
   else acc_mfma_start<P, MTW, NTW>(acc, net.bfrag[ec.layer], nt0, lane);
   if constexpr (P == 1) {
-    gemm_bf16<MTW, NTW, VJP ? 2 : 4>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane, nbytes);
+    gemm_bf16<MTW, NTW, 4>(acc, s, (const bf16x8*)wp, ksteps, nt0, mt0, lane, nbytes);
   } else if constexpr (P == 2) {
-    gemm_split<MTW, NTW, !VJP>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane,
+    gemm_split<MTW, NTW, !VJP, VJP ? 4 : 2>(acc, s, (const bf16x8*)wp, (const bf16x8*)wlo, ksteps, nt0, mt0, lane,
                                          nbytes);
   } else {
     gemm_f32<MTW, NTW>(acc, s, (const f32x4*)wp, ksteps, nt0, mt0, lane, nbytes);
