@@ -608,6 +608,29 @@ def test_backward_weights(precision, w_n, tol):
     assert worst <= tol
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "bf16"])
+def test_image_renders_the_same_alone_and_in_a_batch(precision):
+    """A ray's trajectory depends on that ray alone: an image rendered by itself
+    and inside a 16-image batch (other tiles, another list order after the
+    coarse-to-fine splits, other workgroups claiming its rays in the one-launch
+    march) gives the same maps bit for bit, with both coarse-to-fine depths."""
+    from paper_1911_13225_amd import api
+    spec = di.DEEPSDF_SPEC
+    ctx = ctx_for(spec)
+    cams = di.random_sphere_cameras(8, 64, 64)
+    Z = torch.tensor(di.make_latents(2, spec.latent_dim, sigma=0.05), device="cuda")
+    for c2f in (1, 2):
+        prm = cfg_params("c3", precision=precision, c2f_levels=c2f)
+        batch = api.dist_render_fwd(ctx, cams, Z, prm)
+        for i in (0, 7, 13):
+            alone = api.dist_render_fwd(ctx, cams, Z, prm, pairs=[(i // 2, i % 2)])
+            torch.cuda.synchronize()
+            _log("alone vs batch", precision, c2f, i, int(alone["queries"][0]), int(batch["queries"][i]))
+            for k in ("depth", "normal", "sil", "status", "nsteps"):
+                assert torch.equal(alone[k][0], batch[k][i]), (k, i, c2f)
+            assert int(alone["queries"][0]) == int(batch["queries"][i])
+
+
 def test_backward_is_deterministic():
     from paper_1911_13225_amd import api
     spec = di.DEEPSDF_SPEC
