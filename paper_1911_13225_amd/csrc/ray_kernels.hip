@@ -564,6 +564,8 @@ __global__ __launch_bounds__(256) void k_cam_reduce(RayPool pl, const ImgDesc* i
 // g_z[l] = W0_z^T S0 + Ws_z^T Ss with S = sum over the latent's tiles.  The
 // sum runs in two fixed-order passes: k_gz_fold adds each run of 64 tiles into
 // the run's first tile, k_gz_reduce adds the run heads.  Bitwise reproducible.
+// Both keep several tiles' loads in flight per thread (the chains are bound by
+// memory latency, not bandwidth) and add them in tile order.
 constexpr int kFold = 64;
 
 __global__ __launch_bounds__(512) void k_gz_fold(float* partial, int kmax, int tile, const int* seg_base,
@@ -575,8 +577,17 @@ __global__ __launch_bounds__(512) void k_gz_fold(float* partial, int kmax, int t
   const int c1 = min(c0 + kFold, nt);
   const int width = 4 * kmax;
   for (int i = threadIdx.x; i < width; i += blockDim.x) {
+    const float* p = partial + (size_t)(t0 + c0) * width + i;
     float a = 0.f;
-    for (int t = c0; t < c1; ++t) a += partial[(size_t)(t0 + t) * width + i];
+    int t = 0;
+    for (; t + 8 <= c1 - c0; t += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(t + u) * width];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += v[u];
+    }
+    for (; t < c1 - c0; ++t) a += p[(size_t)t * width];
     partial[(size_t)(t0 + c0) * width + i] = a;
   }
 }
@@ -591,7 +602,26 @@ __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kma
   const int t0 = seg_base[l] / tile, nt = seg_padded[l] / tile;
   for (int n = threadIdx.x; n < 512; n += blockDim.x) {
     float a = 0.f, b = 0.f;
-    for (int c = 0; c < nt; c += kFold) {
+    int c = 0;
+    for (; c + 4 * kFold <= nt; c += 4 * kFold) {
+      float va[4][2], vb[4][2];            // four run heads (up to two row groups each) in flight
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float* pt = partial + (size_t)(t0 + c + u * kFold) * 4 * kmax;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          va[u][g] = (g < mg0 && n < w0) ? pt[g * kmax + n] : 0.f;
+          vb[u][g] = (Wsz && g < mgs && n < ws) ? pt[(2 + g) * kmax + n] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        for (int g = 0; g < mg0; ++g) a += va[u][g];
+        if (Wsz)
+          for (int g = 0; g < mgs; ++g) b += vb[u][g];
+      }
+    }
+    for (; c < nt; c += kFold) {
       const float* pt = partial + (size_t)(t0 + c) * 4 * kmax;
       for (int g = 0; g < mg0; ++g) a += (n < w0) ? pt[g * kmax + n] : 0.f;
       if (Wsz)
