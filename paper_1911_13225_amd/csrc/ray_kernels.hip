@@ -563,7 +563,8 @@ __global__ __launch_bounds__(256) void k_cam_reduce(RayPool pl, const ImgDesc* i
 
 // g_z[l] = W0_z^T S0 + Ws_z^T Ss with S = sum over the latent's tiles.  The
 // sum runs in two fixed-order passes: k_gz_fold adds each run of 64 tiles into
-// the run's first tile, k_gz_reduce adds the run heads.  Bitwise reproducible.
+// the run's first tile, k_gz_reduce adds the run heads and applies W_z^T.
+// Bitwise reproducible.
 // Both keep several tiles' loads in flight per thread (the chains are bound by
 // memory latency, not bandwidth) and add them in tile order.
 constexpr int kFold = 64;
@@ -592,22 +593,32 @@ __global__ __launch_bounds__(512) void k_gz_fold(float* partial, int kmax, int t
   }
 }
 
-__global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base,
-                                                   const int* seg_padded, int w0, int mg0, const float* W0z,
-                                                   int ws, int mgs, const float* Wsz, int L, float* gz, int lat0,
-                                                   int accumulate) {
+// One workgroup per latent.  The run heads of a column are summed in two
+// halves (each in head order, added half 0 + half 1), and each output of the
+// latent code in four quarters of the contracted rows [W0_z; Ws_z] (each in
+// row order, added in quarter order), so every chain is short and the order
+// is fixed.
+__global__ __launch_bounds__(1024) void k_gz_reduce(const float* partial, int kmax, int tile, const int* seg_base,
+                                                    const int* seg_padded, int w0, int mg0, const float* W0z,
+                                                    int ws, int mgs, const float* Wsz, int L, float* gz, int lat0,
+                                                    int accumulate) {
   __shared__ float S0[512];
   __shared__ float Ss[512];
+  __shared__ float ph[2][2][512];
+  __shared__ float pq[4][256];
   const int l = lat0 + blockIdx.x;
   const int t0 = seg_base[l] / tile, nt = seg_padded[l] / tile;
-  for (int n = threadIdx.x; n < 512; n += blockDim.x) {
+  const int nheads = (nt + kFold - 1) / kFold;
+  {
+    const int half = threadIdx.x >> 9, n = threadIdx.x & 511;
+    const int h1 = half ? nheads : nheads / 2;
+    int h = half ? nheads / 2 : 0;
     float a = 0.f, b = 0.f;
-    int c = 0;
-    for (; c + 4 * kFold <= nt; c += 4 * kFold) {
+    for (; h + 4 <= h1; h += 4) {
       float va[4][2], vb[4][2];            // four run heads (up to two row groups each) in flight
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const float* pt = partial + (size_t)(t0 + c + u * kFold) * 4 * kmax;
+        const float* pt = partial + (size_t)(t0 + (h + u) * kFold) * 4 * kmax;
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
           va[u][g] = (g < mg0 && n < w0) ? pt[g * kmax + n] : 0.f;
@@ -621,22 +632,50 @@ __global__ __launch_bounds__(512) void k_gz_reduce(const float* partial, int kma
           for (int g = 0; g < mgs; ++g) b += vb[u][g];
       }
     }
-    for (; c < nt; c += kFold) {
-      const float* pt = partial + (size_t)(t0 + c) * 4 * kmax;
+    for (; h < h1; ++h) {
+      const float* pt = partial + (size_t)(t0 + h * kFold) * 4 * kmax;
       for (int g = 0; g < mg0; ++g) a += (n < w0) ? pt[g * kmax + n] : 0.f;
       if (Wsz)
         for (int g = 0; g < mgs; ++g) b += (n < ws) ? pt[(2 + g) * kmax + n] : 0.f;
     }
-    S0[n] = a;
-    Ss[n] = b;
+    ph[0][half][n] = a;
+    ph[1][half][n] = b;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+  if (threadIdx.x < 512) {
+    S0[threadIdx.x] = ph[0][0][threadIdx.x] + ph[0][1][threadIdx.x];
+    Ss[threadIdx.x] = ph[1][0][threadIdx.x] + ph[1][1][threadIdx.x];
+  }
+  __syncthreads();
+  const int q = threadIdx.x >> 8, jl = threadIdx.x & 255;
+  const int rows = w0 + (Wsz ? ws : 0);
+  const int r0 = q * rows / 4, r1 = (q + 1) * rows / 4;
+  for (int j0 = 0; j0 < L; j0 += 256) {
+    const int j = j0 + jl;
     float acc = 0.f;
-    for (int n = 0; n < w0; ++n) acc = fmaf(W0z[(size_t)n * L + j], S0[n], acc);
-    if (Wsz)
-      for (int n = 0; n < ws; ++n) acc = fmaf(Wsz[(size_t)n * L + j], Ss[n], acc);
-    gz[(size_t)l * L + j] = accumulate ? gz[(size_t)l * L + j] + acc : acc;
+    if (j < L) {
+      int r = r0;
+      for (; r + 8 <= r1; r += 8) {
+        float w[8], x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int rr = r + u;
+          w[u] = rr < w0 ? W0z[(size_t)rr * L + j] : Wsz[(size_t)(rr - w0) * L + j];
+          x[u] = rr < w0 ? S0[rr] : Ss[rr - w0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fmaf(w[u], x[u], acc);
+      }
+      for (; r < r1; ++r)
+        acc = fmaf(r < w0 ? W0z[(size_t)r * L + j] : Wsz[(size_t)(r - w0) * L + j], r < w0 ? S0[r] : Ss[r - w0], acc);
+    }
+    pq[q][jl] = acc;
+    __syncthreads();
+    if (q == 0 && j < L) {
+      const float v = ((pq[0][jl] + pq[1][jl]) + pq[2][jl]) + pq[3][jl];
+      gz[(size_t)l * L + j] = accumulate ? gz[(size_t)l * L + j] + v : v;
+    }
+    __syncthreads();
   }
 }
 
@@ -1111,7 +1150,7 @@ void launch_gz_reduce(float* partial, int kmax, int tile, int max_tiles, const i
                       const float* Wsz, int L, float* gz, hipStream_t s, int lat0, int accumulate) {
   hipLaunchKernelGGL(k_gz_fold, dim3(nblk(max_tiles, kFold), n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base,
                      seg_padded, lat0);
-  hipLaunchKernelGGL(k_gz_reduce, dim3(n_lat), dim3(512), 0, s, partial, kmax, tile, seg_base, seg_padded, w0, mg0,
+  hipLaunchKernelGGL(k_gz_reduce, dim3(n_lat), dim3(1024), 0, s, partial, kmax, tile, seg_base, seg_padded, w0, mg0,
                      W0z, ws, mgs, Wsz, L, gz, lat0, accumulate);
 }
 void launch_apply_levels(ImgDesc* imgs, const AdvEntry* table, const int* hdr, int max_entries, hipStream_t s) {

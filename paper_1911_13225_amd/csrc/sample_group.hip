@@ -81,9 +81,12 @@ static int key_bits(int n_lat) {
 size_t group_temp_bytes(int n, int n_lat) {
   size_t a = 0, b = 0;
   const int m = n > 0 ? n : 1;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const int*)nullptr, (int*)nullptr, (const int*)nullptr,
-                                     (int*)nullptr, m, 0, key_bits(n_lat));
-  hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int*)nullptr, (int*)nullptr, n_lat);
+  // a failed size query leaves its size at 0: the sort or scan then reports
+  // the short temporary buffer as an error, which group_samples returns
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const int*)nullptr, (int*)nullptr, (const int*)nullptr,
+                                         (int*)nullptr, m, 0, key_bits(n_lat)) != hipSuccess)
+    a = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, b, (const int*)nullptr, (int*)nullptr, n_lat) != hipSuccess) b = 0;
   return std::max(a, b) + 256;
 }
 
