@@ -12,12 +12,13 @@ namespace dist {
 // helpers
 // ---------------------------------------------------------------------------
 // Append `value` to list for every thread with flag set; one atomic per
-// 256-thread block.  Must be called by all threads of the block.  Returns the
+// block of NT threads.  Must be called by all threads of the block.  Returns the
 // list position of a flagged thread's entry (-1 for the others); the entry at
 // position i is stored at list[dir * i], so dir = -1 fills backwards from the
 // element `list` points at.
+template <int NT = 256>
 __device__ __forceinline__ int block_append(bool flag, int value, int* list, int* counter, int dir = 1) {
-  __shared__ int wcnt[4];
+  __shared__ int wcnt[NT / 64];
   __shared__ int base;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const unsigned long long m = __ballot(flag);
@@ -25,7 +26,9 @@ __device__ __forceinline__ int block_append(bool flag, int value, int* list, int
   if (lane == 0) wcnt[w] = __popcll(m);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) tot += wcnt[i];
     base = tot ? atomicAdd(counter, tot) : 0;
   }
   __syncthreads();
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(256) void k_init_level(RayPool pl, ImgDesc* imgs, c
 // front, the others backwards from list[tail_end - 1], so a consumer that
 // takes the rays in order starts the long ones first.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_split(RayPool pl, ImgDesc* imgs, const int* imgs_list, int child_lvl,
+__global__ __launch_bounds__(1024) void k_split(RayPool pl, ImgDesc* imgs, const int* imgs_list, int child_lvl,
                                                int child_step, int* list, int* counter, int* counter_tail,
                                                int tail_end) {
   const int img = imgs_list[blockIdx.y];
@@ -147,11 +150,12 @@ __global__ __launch_bounds__(256) void k_split(RayPool pl, ImgDesc* imgs, const 
     act = inside;
     marching = pst == ST_ACTIVE;
   }
+  // 1024-thread blocks: a quarter of the atomics on the list counters
   if (counter_tail) {
-    block_append(act && marching, r, list, counter);
-    block_append(act && !marching, r, list + tail_end - 1, counter_tail, -1);
+    block_append<1024>(act && marching, r, list, counter);
+    block_append<1024>(act && !marching, r, list + tail_end - 1, counter_tail, -1);
   } else {
-    block_append(act, r, list, counter);
+    block_append<1024>(act, r, list, counter);
   }
 }
 
@@ -1065,7 +1069,7 @@ void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_
                   int child_lvl, int child_step, int* list, int* counter, hipStream_t s, int* counter_tail,
                   int tail_end) {
   if (n_img <= 0 || max_children <= 0) return;
-  hipLaunchKernelGGL(k_split, dim3(nblk(max_children, 256), n_img), dim3(256), 0, s, pl, imgs, imgs_list,
+  hipLaunchKernelGGL(k_split, dim3(nblk(max_children, 1024), n_img), dim3(1024), 0, s, pl, imgs, imgs_list,
                      child_lvl, child_step, list, counter, counter_tail, tail_end);
   hipLaunchKernelGGL(k_set_level, dim3(nblk(n_img, 256)), dim3(256), 0, s, imgs, imgs_list, n_img, child_lvl);
 }
