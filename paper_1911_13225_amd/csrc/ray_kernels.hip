@@ -166,9 +166,9 @@ __global__ void k_set_level(ImgDesc* imgs, const int* imgs_list, int n, int lvl)
 
 // ---------------------------------------------------------------------------
 // Finalise level-0 rays into the output maps (Sec. 3.3, App. A.3).
-// grid: (blocks over H*W, n_images)
+// grid: (1024-pixel blocks over H*W, n_images); one list atomic per block
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* imgs, const int* imgs_list,
+__global__ __launch_bounds__(1024) void k_finalize(RayPool pl, const ImgDesc* imgs, const int* imgs_list,
                                                   FinalizeOut o) {
   const int img = imgs_list ? imgs_list[blockIdx.y] : blockIdx.y;
   const ImgDesc& im = imgs[img];
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_finalize(RayPool pl, const ImgDesc* img
     if (o.normal && !hit) { o.normal[3 * q] = 0.f; o.normal[3 * q + 1] = 0.f; o.normal[3 * q + 2] = 0.f; }
     if (o.nraw) o.nraw[q] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  const int h = block_append(hit && o.want_hits, r, o.hits, o.hit_count);
+  const int h = block_append<1024>(hit && o.want_hits, r, o.hits, o.hit_count);
   if (o.hit_pix && pix < hw) o.hit_pix[(size_t)im.out_base + pix] = h;
 }
 
@@ -1075,7 +1075,7 @@ void launch_split(const RayPool& pl, ImgDesc* imgs, const int* imgs_list, int n_
 }
 void launch_finalize(const RayPool& pl, const ImgDesc* imgs, const int* imgs_list, int n_img, int hw,
                      const FinalizeOut& o, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(nblk(hw, 256), n_img), dim3(256), 0, s, pl, imgs, imgs_list, o);
+  hipLaunchKernelGGL(k_finalize, dim3(nblk(hw, 1024), n_img), dim3(1024), 0, s, pl, imgs, imgs_list, o);
 }
 void launch_normals(const RayPool& pl, const ImgDesc* imgs, const int* hits, const int* hit_count, int max_hits,
                     const float* fv, float delta, float* normal, float4* nraw, hipStream_t s) {
