@@ -2063,7 +2063,16 @@ __global__ void k_fold_bias(const float* __restrict__ b, const float* __restrict
     acc = b[n];
     const float* w = Wz + (size_t)n * L;
     const float* zz = z + (size_t)l * L;
-    for (int j = 0; j < L; ++j) acc = fmaf(w[j], zz[j], acc);
+    int j = 0;
+    // 32 weights requested before the 32 products are summed in order
+    for (; j + 32 <= L; j += 32) {
+      float wv[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) wv[u] = w[j + u];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) acc = fmaf(wv[u], zz[j + u], acc);
+    }
+    for (; j < L; ++j) acc = fmaf(w[j], zz[j], acc);
   }
   dst[i] = acc;
 }
